@@ -1,0 +1,186 @@
+/*
+ * libssj -- verification phase of exact set-similarity joins on MI355X (gfx950).
+ *
+ * The library verifies candidate pairs (r, s) of token sets held in an HBM
+ * resident collection: a pair is in the result iff its Jaccard similarity
+ * |r & s| / |r | s| is at least t = t_num / t_den (paper Sec. 3,
+ * Definition 1, with the Jaccard row of Table 1).  The decision is taken in
+ * integers as  |r & s| * (t_den + t_num) >= t_num * (|r| + |s|);  no floating
+ * point enters the path.  The overlap comes from an intersection that stops
+ * as soon as the required overlap is met or can no longer be reached (paper
+ * Sec. 3.1), so only candidates whose outcome is undecided cost more work.
+ *
+ * Collections follow the paper's preprocessing contract (Sec. 2.2, "Data
+ * layout"): every set is non-empty, its tokens are unique non-negative int32
+ * ids in strictly increasing order.  (The frequency ordering of token ids and
+ * the size ordering of sets help the candidate filter; verification does not
+ * depend on them and does not check them.)  Set ids are positions in the
+ * uploaded collection.
+ *
+ * Status: every function returns an int; SSJ_OK (0) on success, a positive
+ * value for a non-error state (SSJ_PENDING), a negative value for an error.
+ * No C++ exception crosses this interface.
+ */
+#ifndef SSJ_H
+#define SSJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SSJ_OK = 0,
+    SSJ_PENDING = 1,     /* stream request not finished yet */
+    SSJ_EINVAL = -1,     /* bad argument, malformed collection, id out of range */
+    SSJ_ENOMEM = -2,     /* device or host allocation failed / over the HBM budget */
+    SSJ_ETRUNC = -3,     /* result larger than out_cap; *out_n holds the size needed */
+    SSJ_EAGAIN = -4,     /* non-blocking submit found the queue full; or object busy */
+    SSJ_EDEVICE = -5,    /* a HIP runtime call failed; the context stays failed */
+    SSJ_ENOTFOUND = -6   /* unknown or already retired ticket */
+};
+
+typedef struct ssj_ctx ssj_ctx;   /* one per GPU; opaque */
+typedef struct ssj_coll ssj_coll; /* an HBM-resident collection; opaque */
+
+/* One candidate pair: two set ids of the same collection (paper Table 2, C). */
+typedef struct {
+    int32_t r;
+    int32_t s;
+} ssj_pair;
+
+typedef struct {
+    int device;           /* HIP device ordinal */
+    uint64_t hbm_budget;  /* device bytes for candidate chunks and their
+                             worst-case output (the paper's M_c, Sec. 3.3.1);
+                             0 selects 4 GiB */
+    int n_slots;          /* concurrent stream requests on the device (0 -> 4) */
+    int queue_depth;      /* stream requests accepted but not yet admitted (0 -> 64) */
+} ssj_opts;
+
+/* Creates a context on opts->device (opts may be NULL for defaults).
+ * Allocates device scratch and streams.  SSJ_EINVAL for a bad device or
+ * option, SSJ_EDEVICE if HIP fails. */
+int ssj_init(const ssj_opts* opts, ssj_ctx** out);
+
+/* Waits for in-flight stream work, releases everything the context owns
+ * (collections included).  NULL is accepted. */
+int ssj_shutdown(ssj_ctx* ctx);
+
+/* Message of the last failure on the calling thread (never NULL). */
+const char* ssj_last_error(ssj_ctx* ctx);
+
+/*
+ * Uploads a CSR collection: set i owns tokens[offsets[i] .. offsets[i+1]).
+ * offsets: host, n_sets + 1 entries, offsets[0] == 0, non-decreasing.
+ * tokens:  host, n_tokens entries (== offsets[n_sets]).
+ * Checks on the host: every set non-empty, tokens strictly increasing inside
+ * a set, 0 <= token < 2^31, n_sets < 2^31, n_tokens < 2^32  (else
+ * SSJ_EINVAL).  The library copies both arrays; the caller keeps ownership.
+ * The device copy is the token array plus one {start, length} descriptor per
+ * set.  The handle is valid until ssj_free_collection / ssj_shutdown.
+ * (The paper transfers each collection once, Sec. 3.3.1.)
+ */
+int ssj_upload_collection(ssj_ctx* ctx, const int64_t* offsets, int64_t n_sets,
+                          const int32_t* tokens, int64_t n_tokens, ssj_coll** out);
+
+/* Frees a collection.  SSJ_EAGAIN if stream requests on it are in flight. */
+int ssj_free_collection(ssj_ctx* ctx, ssj_coll* coll);
+
+/*
+ * Synchronous verification of host-resident candidates.
+ * cand:   host, n_cand pairs (ids must lie in [0, n_sets)).
+ * t:      0 <= t_num <= t_den, 0 < t_den < 2^31.
+ * out:    host, room for out_cap pairs; receives the passing candidates,
+ *         with multiplicity and orientation kept, in unspecified order.
+ * *out_n: number of passing candidates.  out_cap >= n_cand always suffices.
+ * Requests bigger than the HBM budget are split into chunks (paper Sec.
+ * 3.3.1, M_c).  Returns SSJ_ETRUNC when the result exceeds out_cap (out then
+ * holds out_cap of the pairs, *out_n the full count), SSJ_EINVAL for a bad
+ * threshold or an id out of range (*out_n = 0).  cand may be reused as soon
+ * as the call returns.
+ */
+int ssj_verify(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
+               int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap, int64_t* out_n);
+
+/*
+ * Device-pointer variant: no host copies, no synchronisation.  d_cand and
+ * d_out are device buffers owned by the caller; d_count is a device int64.
+ * The work is enqueued on hip_stream (a hipStream_t; NULL = the legacy
+ * default stream).  When the stream reaches the end of the call, *d_count
+ * holds the number of passing candidates (which may exceed out_cap: then
+ * only out_cap pairs were written), or -1 if an id was out of range.
+ * Synchronous argument errors (bad threshold, negative sizes, n_cand >= 2^31)
+ * return SSJ_EINVAL without enqueuing anything.  Calls that share a context
+ * share its device scratch: they must be ordered on one stream (or
+ * otherwise serialised) by the caller.
+ */
+int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand,
+                      int64_t n_cand, int64_t t_num, int64_t t_den, ssj_pair* d_out,
+                      int64_t out_cap, int64_t* d_count, void* hip_stream);
+
+/*
+ * Streaming (continuous batching) -- the paper's host/device pipeline
+ * (Sec. 3.2, threads H0/H1/H2; Sec. 4.1.2) as a request loop.
+ * submit copies cand into library-owned pinned staging and returns a ticket
+ * at once; an admission thread starts requests as slots and HBM budget free
+ * up, several at a time on separate streams.  Thread-safe.
+ * nonblocking != 0: SSJ_EAGAIN when the queue is full; otherwise the call
+ * waits for room.  Same argument rules as ssj_verify.
+ */
+int ssj_stream_submit(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
+                      int64_t t_num, int64_t t_den, int nonblocking, uint64_t* ticket);
+
+/*
+ * Collects a request.  wait != 0 blocks until it is done.  SSJ_PENDING if
+ * not done (and wait == 0).  On SSJ_OK the passing pairs are copied to out
+ * (host, out_cap pairs), *out_n is set and the ticket is retired.  On
+ * SSJ_ETRUNC *out_n holds the size needed and the ticket stays valid for a
+ * retry.  SSJ_EINVAL if the request had an id out of range (ticket
+ * retired), SSJ_ENOTFOUND for an unknown or retired ticket.
+ */
+int ssj_stream_poll(ssj_ctx* ctx, uint64_t ticket, int wait, ssj_pair* out, int64_t out_cap,
+                    int64_t* out_n);
+
+/* Timing of a finished stream request, in nanoseconds of CLOCK_MONOTONIC:
+ * submit, admission (copy start), device completion observed.  Valid until
+ * the ticket is retired.  SSJ_PENDING if not done. */
+int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, uint64_t* t_submit, uint64_t* t_admit,
+                     uint64_t* t_done);
+
+/*
+ * Execution plan.  Verification splits the candidates into length classes by
+ * |r| + |s| (upper bounds SSJ_CLASS_BOUNDS) and verifies each class with its
+ * own mapping of pairs onto lanes:
+ *   lanes = 1          one thread per pair (sequential early-exit merge)
+ *   lanes = 4..64      a group of lanes of one wavefront per pair
+ *   lanes = 256        one 256-thread workgroup per pair
+ * SSJ_MODE_DIRECT skips the classification and runs a single mapping over
+ * the candidates in input order (plain one-launch verification).
+ */
+#define SSJ_N_CLASSES 5
+#define SSJ_CLASS_BOUNDS {32, 128, 512, 2048, 0x7fffffff}
+
+enum { SSJ_MODE_BUCKETED = 0, SSJ_MODE_DIRECT = 1 };
+
+typedef struct {
+    int mode;                      /* SSJ_MODE_BUCKETED or SSJ_MODE_DIRECT */
+    int lanes[SSJ_N_CLASSES];      /* per length class; DIRECT uses lanes[0] */
+    int use_graph;                 /* replay launches through a captured hipGraph */
+} ssj_plan;
+
+/* Reads / replaces the context's plan.  SSJ_EINVAL for an unsupported lane
+ * count.  Not thread-safe against in-flight calls on the same context. */
+int ssj_get_plan(ssj_ctx* ctx, ssj_plan* plan);
+int ssj_set_plan(ssj_ctx* ctx, const ssj_plan* plan);
+
+/* Collection facts: number of sets, tokens, and the largest set size. */
+int ssj_collection_info(const ssj_coll* coll, int64_t* n_sets, int64_t* n_tokens,
+                        int64_t* max_len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSJ_H */

@@ -1,0 +1,450 @@
+// Verification kernels for gfx950 (CDNA4, wave64).
+//
+// A candidate pair (r, s) is similar iff its overlap o = |r & s| satisfies
+// o * (t_num + t_den) >= t_num * (|r| + |s|)  (paper Sec. 3, Definition 1 with
+// the Jaccard row of Table 1, rearranged into integers).  Equivalently o must
+// reach the required overlap
+//     alpha = ceil(t_num * (|r| + |s|) / (t_num + t_den)).
+// The overlap is found by walking the two sorted token lists and stopping as
+// soon as o >= alpha (accept) or o + min(tokens left in r, tokens left in s)
+// < alpha (reject: alpha is out of reach) -- the early-terminating merge of
+// paper Sec. 3.1.  Any sound stopping rule yields the same decisions.
+//
+// Three mappings of pairs onto lanes (the paper's alternatives A/B/C of Sec.
+// 3.3.2 assign a probe set to a thread or a block; here the unit is a pair):
+//   * one thread per pair: a sequential early-exit merge;
+//   * a group of G lanes (G = 4..64) of one wavefront per pair: tile merge;
+//   * one 256-thread workgroup per pair: the same tile merge over LDS.
+// The tile merge advances in rounds.  A round loads the next G tokens of r
+// (one per lane) and of s, counts the r tokens found in the s tile by a
+// binary search over the tile (cross-lane permutes or LDS), and then
+// consumes every token that can have no partner beyond the two tiles: if
+// max(r tile) < max(s tile) the whole r tile plus the s tokens <= max(r tile)
+// are consumed (and symmetrically; both tiles when the maxima are equal).
+// Every equal pair of tokens lies in the consumed part of both sides in the
+// round that finds it and in no later round, so each match is counted
+// exactly once; the stopping rule is checked before every round.
+//
+// Passing pairs are appended to the output by wavefront compaction: a
+// ballot of the pass flags, one atomic add per wavefront that has passes,
+// and a per-lane offset from the lane's rank among the passing lanes.
+#include "ssj_device.h"
+
+namespace ssj {
+namespace {
+
+__device__ __forceinline__ uint32_t required_overlap(uint32_t L, unsigned long long tn,
+                                                     unsigned long long tsum) {
+    return (uint32_t)((tn * (unsigned long long)L + tsum - 1ull) / tsum);
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
+
+// Value of v held by lane src of the same wavefront.
+__device__ __forceinline__ int bperm(int v, int src) {
+    return __builtin_amdgcn_ds_bpermute(src << 2, v);
+}
+
+// Number of set bits of m below the calling lane.
+__device__ __forceinline__ uint32_t mbcnt(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// One thread: sequential early-terminating merge.
+__device__ __forceinline__ bool merge_thread(const int32_t* __restrict__ A, uint32_t na,
+                                             const int32_t* __restrict__ B, uint32_t nb,
+                                             uint32_t alpha) {
+    uint32_t i = 0, j = 0, o = 0;
+    for (;;) {
+        if (o >= alpha) return true;
+        const uint32_t rem = min(na - i, nb - j);
+        if (o + rem < alpha) return false;
+        const int32_t x = A[i], y = B[j];
+        i += (x <= y);
+        j += (y <= x);
+        o += (x == y);
+    }
+}
+
+// G lanes of one wavefront (lanes gbase .. gbase+G-1, g = lane - gbase):
+// tile merge.  Control flow is uniform inside the group, so the cross-lane
+// permutes only read lanes that are active.
+template <int G>
+__device__ __forceinline__ bool merge_group(const int32_t* __restrict__ A, uint32_t na,
+                                            const int32_t* __restrict__ B, uint32_t nb,
+                                            uint32_t alpha, int g, int gbase) {
+    const unsigned long long gmask =
+        (G == kWave) ? ~0ull : (((1ull << (G % kWave)) - 1ull) << gbase);
+    uint32_t i = 0, j = 0, o = 0;
+    for (;;) {
+        if (o >= alpha) return true;
+        const uint32_t ra = na - i, rb = nb - j;
+        if (o + min(ra, rb) < alpha) return false;
+        const int ka = (int)min(ra, (uint32_t)G), kb = (int)min(rb, (uint32_t)G);
+        const bool va = g < ka, vb = g < kb;
+        const int32_t a = va ? A[i + g] : 0;
+        const int32_t b = vb ? B[j + g] : 0;
+        const int32_t amax = bperm(a, gbase + ka - 1);
+        const int32_t bmax = bperm(b, gbase + kb - 1);
+        // pos = number of s-tile tokens below a (capped at G-1)
+        int pos = 0;
+#pragma unroll
+        for (int step = G / 2; step >= 1; step >>= 1) {
+            const int k = pos + step - 1;
+            const int32_t v = bperm(b, gbase + k);
+            if (k < kb && v < a) pos += step;
+        }
+        const int32_t at = bperm(b, gbase + pos);
+        const bool hit = va && pos < kb && at == a;
+        const uint32_t nh = (uint32_t)__popcll(ballot(hit) & gmask);
+        if (amax < bmax) {
+            i += (uint32_t)ka;
+            j += (uint32_t)__popcll(ballot(vb && b <= amax) & gmask);
+        } else if (bmax < amax) {
+            j += (uint32_t)kb;
+            i += (uint32_t)__popcll(ballot(va && a <= bmax) & gmask);
+        } else {
+            i += (uint32_t)ka;
+            j += (uint32_t)kb;
+        }
+        o += nh;
+    }
+}
+
+// Whole workgroup: the tile merge with kBlock-token tiles, the s tile in LDS.
+// Must be called by all threads of the workgroup with the same arguments.
+__device__ bool merge_block(const int32_t* __restrict__ A, uint32_t na,
+                            const int32_t* __restrict__ B, uint32_t nb, uint32_t alpha,
+                            int32_t* sb, uint32_t* red) {
+    const int t = (int)threadIdx.x, w = t >> 6, lane = lane_id();
+    uint32_t i = 0, j = 0, o = 0;
+    for (;;) {
+        if (o >= alpha) return true;
+        const uint32_t ra = na - i, rb = nb - j;
+        if (o + min(ra, rb) < alpha) return false;
+        const int ka = (int)min(ra, (uint32_t)kBlock), kb = (int)min(rb, (uint32_t)kBlock);
+        const bool va = t < ka, vb = t < kb;
+        const int32_t a = va ? A[i + t] : 0;
+        const int32_t b = vb ? B[j + t] : 0;
+        const int32_t amax = A[i + ka - 1];
+        const int32_t bmax = B[j + kb - 1];
+        sb[t] = b;
+        __syncthreads();
+        int pos = 0;
+#pragma unroll
+        for (int step = kBlock / 2; step >= 1; step >>= 1) {
+            const int k = pos + step - 1;
+            if (k < kb && sb[k] < a) pos += step;
+        }
+        const bool hit = va && pos < kb && sb[pos] == a;
+        const uint32_t c0 = (uint32_t)__popcll(ballot(hit));
+        const uint32_t c1 = (uint32_t)__popcll(ballot(va && a <= bmax));
+        const uint32_t c2 = (uint32_t)__popcll(ballot(vb && b <= amax));
+        if (lane == 0) {
+            red[w * 3 + 0] = c0;
+            red[w * 3 + 1] = c1;
+            red[w * 3 + 2] = c2;
+        }
+        __syncthreads();
+        uint32_t nh = 0, na_le = 0, nb_le = 0;
+#pragma unroll
+        for (int q = 0; q < kBlock / kWave; ++q) {
+            nh += red[q * 3 + 0];
+            na_le += red[q * 3 + 1];
+            nb_le += red[q * 3 + 2];
+        }
+        __syncthreads();  // sb and red are rewritten by the next round
+        if (amax < bmax) {
+            i += (uint32_t)ka;
+            j += nb_le;
+        } else if (bmax < amax) {
+            j += (uint32_t)kb;
+            i += na_le;
+        } else {
+            i += (uint32_t)ka;
+            j += (uint32_t)kb;
+        }
+        o += nh;
+    }
+}
+
+// Appends the pairs of the lanes with pass set; wavefront compaction.
+__device__ __forceinline__ void append_wave(bool pass, int2 pr, const VerifyArgs& a) {
+    const unsigned long long m = ballot(pass);
+    if (m == 0ull) return;
+    const int lane = lane_id();
+    const int leader = __builtin_ctzll(m);
+    unsigned long long base = 0ull;
+    if (lane == leader) base = atomicAdd(&a.ctr->out_count, (unsigned long long)__popcll(m));
+    const uint32_t lo = (uint32_t)bperm((int)(uint32_t)base, leader);
+    const uint32_t hi = (uint32_t)bperm((int)(uint32_t)(base >> 32), leader);
+    base = ((unsigned long long)hi << 32) | lo;
+    if (pass) {
+        const unsigned long long k = base + mbcnt(m);
+        if (k < a.cap) a.out[k] = pr;
+    }
+}
+
+__device__ __forceinline__ void append_one(int2 pr, const VerifyArgs& a) {
+    const unsigned long long k = atomicAdd(&a.ctr->out_count, 1ull);
+    if (k < a.cap) a.out[k] = pr;
+}
+
+__device__ __forceinline__ bool ids_ok(int2 pr, uint32_t n_sets) {
+    return (uint32_t)pr.x < n_sets && (uint32_t)pr.y < n_sets;
+}
+
+// The last workgroup to finish publishes the count (or -1 on an id error)
+// and returns the counters to zero for the next launch.
+__device__ void finalize(const VerifyArgs& a) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(&a.ctr->done, 1u);
+        if (prev == gridDim.x - 1) {
+            __threadfence();
+            const unsigned long long cnt = atomicAdd(&a.ctr->out_count, 0ull);
+            const unsigned err = atomicOr(&a.ctr->err, 0u);
+            *a.d_count = err ? -1ll : (long long)cnt;
+            atomicExch(&a.ctr->out_count, 0ull);
+            atomicExch(&a.ctr->err, 0u);
+#pragma unroll
+            for (int q = 0; q < kClasses; ++q) {
+                atomicExch(&a.ctr->head[q], 0u);
+                atomicExch(&a.ctr->tail[q], 0u);
+            }
+            atomicExch(&a.ctr->done, 0u);
+            __threadfence();
+        }
+    }
+}
+
+template <int G>
+__device__ __forceinline__ bool verify_pair_lanes(const VerifyArgs& a, int2 pr, int g, int gbase) {
+    const uint2 dr = a.desc[pr.x];
+    const uint2 ds = a.desc[pr.y];
+    const uint32_t alpha = required_overlap(dr.y + ds.y, a.tn, a.tsum);
+    if constexpr (G == 1) {
+        return merge_thread(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha);
+    } else {
+        return merge_group<G>(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, g, gbase);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Direct mode: every pair in input order with one mapping (grid-stride).
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_verify_direct(VerifyArgs a) {
+    if constexpr (G == kBlock) {
+        __shared__ int32_t sb[kBlock];
+        __shared__ uint32_t red[16];
+        for (uint32_t p = blockIdx.x; p < a.n; p += gridDim.x) {
+            const int2 pr = a.cand[p];
+            bool pass = false;
+            if (ids_ok(pr, a.n_sets)) {
+                const uint2 dr = a.desc[pr.x];
+                const uint2 ds = a.desc[pr.y];
+                const uint32_t alpha = required_overlap(dr.y + ds.y, a.tn, a.tsum);
+                pass = merge_block(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, sb, red);
+            } else if (threadIdx.x == 0) {
+                atomicOr(&a.ctr->err, 1u);
+            }
+            if (threadIdx.x == 0 && pass) append_one(pr, a);
+        }
+    } else {
+        constexpr int GPW = kWave / G;
+        const int lane = lane_id();
+        const int grp = lane / G, g = lane % G, gbase = grp * G;
+        const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+        const uint32_t nwaves = (gridDim.x * kBlock) / kWave;
+        for (uint64_t base = (uint64_t)wave * GPW; base < a.n; base += (uint64_t)nwaves * GPW) {
+            const uint64_t p = base + (uint64_t)grp;
+            bool pass = false;
+            int2 pr = make_int2(0, 0);
+            if (p < a.n) {
+                pr = a.cand[p];
+                if (ids_ok(pr, a.n_sets)) {
+                    pass = verify_pair_lanes<G>(a, pr, g, gbase);
+                } else if (g == 0) {
+                    atomicOr(&a.ctr->err, 1u);
+                }
+            }
+            append_wave(pass && g == 0, pr, a);
+        }
+    }
+    finalize(a);
+}
+
+// ---------------------------------------------------------------------------
+// Bucketed mode, pass 1: length class of every pair -> per-class queues of
+// pair indices (wavefront-aggregated appends).
+__global__ __launch_bounds__(kBlock) void k_classify(VerifyArgs a) {
+    const int lane = lane_id();
+    for (uint64_t p0 = (uint64_t)blockIdx.x * kBlock; p0 < a.n;
+         p0 += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t p = p0 + threadIdx.x;
+        int cls = -1;
+        if (p < a.n) {
+            const int2 pr = a.cand[p];
+            if (ids_ok(pr, a.n_sets)) {
+                const uint32_t L = a.desc[pr.x].y + a.desc[pr.y].y;
+                cls = kClasses - 1;
+#pragma unroll
+                for (int q = kClasses - 2; q >= 0; --q)
+                    if (L <= a.bounds[q]) cls = q;
+            } else {
+                atomicOr(&a.ctr->err, 1u);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kClasses; ++q) {
+            const unsigned long long m = ballot(cls == q);
+            if (m != 0ull) {
+                const int leader = __builtin_ctzll(m);
+                uint32_t base = 0;
+                if (lane == leader) base = atomicAdd(&a.ctr->tail[q], (uint32_t)__popcll(m));
+                base = (uint32_t)bperm((int)base, leader);
+                if (cls == q) a.queues[(size_t)q * a.qcap + base + mbcnt(m)] = (uint32_t)p;
+            }
+        }
+    }
+}
+
+// Bucketed mode, pass 2: one persistent grid drains the class queues by
+// work stealing (an atomic cursor per queue), heaviest classes first;
+// workgroup-mapped classes are taken one pair per workgroup, the others one
+// wavefront tile (64 / G pairs) at a time.
+template <int G>
+__device__ void drain_class_waves(const VerifyArgs& a, int q) {
+    constexpr int GPW = kWave / G;
+    const int lane = lane_id();
+    const int grp = lane / G, g = lane % G, gbase = grp * G;
+    const uint32_t cnt = a.ctr->tail[q];
+    const uint32_t* queue = a.queues + (size_t)q * a.qcap;
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(&a.ctr->head[q], (uint32_t)GPW);
+        t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+        if (t >= cnt) break;
+        const uint32_t k = t + (uint32_t)grp;
+        bool pass = false;
+        int2 pr = make_int2(0, 0);
+        if (k < cnt) {
+            pr = a.cand[queue[k]];
+            pass = verify_pair_lanes<G>(a, pr, g, gbase);
+        }
+        append_wave(pass && g == 0, pr, a);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_verify_bucketed(VerifyArgs a) {
+    __shared__ int32_t sb[kBlock];
+    __shared__ uint32_t red[16];
+    __shared__ uint32_t s_tile;
+    for (int oi = 0; oi < kClasses; ++oi) {
+        const int q = a.order[oi];
+        if (a.lanes[q] != kBlock) continue;
+        const uint32_t cnt = a.ctr->tail[q];
+        const uint32_t* queue = a.queues + (size_t)q * a.qcap;
+        for (;;) {
+            if (threadIdx.x == 0) s_tile = atomicAdd(&a.ctr->head[q], 1u);
+            __syncthreads();
+            const uint32_t t = s_tile;
+            __syncthreads();
+            if (t >= cnt) break;
+            const int2 pr = a.cand[queue[t]];
+            const uint2 dr = a.desc[pr.x];
+            const uint2 ds = a.desc[pr.y];
+            const uint32_t alpha = required_overlap(dr.y + ds.y, a.tn, a.tsum);
+            const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, sb, red);
+            if (threadIdx.x == 0 && pass) append_one(pr, a);
+        }
+    }
+    for (int oi = 0; oi < kClasses; ++oi) {
+        const int q = a.order[oi];
+        switch (a.lanes[q]) {
+            case 1: drain_class_waves<1>(a, q); break;
+            case 4: drain_class_waves<4>(a, q); break;
+            case 8: drain_class_waves<8>(a, q); break;
+            case 16: drain_class_waves<16>(a, q); break;
+            case 32: drain_class_waves<32>(a, q); break;
+            case 64: drain_class_waves<64>(a, q); break;
+            default: break;
+        }
+    }
+    finalize(a);
+}
+
+__global__ void k_build_desc(const int64_t* __restrict__ off, uint2* __restrict__ desc,
+                             int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = off[i], e = off[i + 1];
+        desc[i] = make_uint2((uint32_t)b, (uint32_t)(e - b));
+    }
+}
+
+}  // namespace
+
+bool lanes_supported(int lanes) {
+    switch (lanes) {
+        case 1: case 4: case 8: case 16: case 32: case 64: case kBlock: return true;
+        default: return false;
+    }
+}
+
+const void* kernel_verify_direct(int lanes) {
+    switch (lanes) {
+        case 1: return (const void*)&k_verify_direct<1>;
+        case 4: return (const void*)&k_verify_direct<4>;
+        case 8: return (const void*)&k_verify_direct<8>;
+        case 16: return (const void*)&k_verify_direct<16>;
+        case 32: return (const void*)&k_verify_direct<32>;
+        case 64: return (const void*)&k_verify_direct<64>;
+        case kBlock: return (const void*)&k_verify_direct<kBlock>;
+        default: return nullptr;
+    }
+}
+
+const void* kernel_verify_bucketed() { return (const void*)&k_verify_bucketed; }
+const void* kernel_classify() { return (const void*)&k_classify; }
+
+hipError_t launch_build_desc(const int64_t* d_offsets, uint2* d_desc, int64_t n_sets,
+                             hipStream_t st) {
+    if (n_sets <= 0) return hipSuccess;
+    int64_t blocks = (n_sets + kBlock - 1) / kBlock;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_build_desc, dim3((unsigned)blocks), dim3(kBlock), 0, st, d_offsets,
+                       d_desc, n_sets);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify_direct(const VerifyArgs& a, int lanes, int grid, hipStream_t st) {
+    const dim3 g((unsigned)grid), b(kBlock);
+    switch (lanes) {
+        case 1: hipLaunchKernelGGL(k_verify_direct<1>, g, b, 0, st, a); break;
+        case 4: hipLaunchKernelGGL(k_verify_direct<4>, g, b, 0, st, a); break;
+        case 8: hipLaunchKernelGGL(k_verify_direct<8>, g, b, 0, st, a); break;
+        case 16: hipLaunchKernelGGL(k_verify_direct<16>, g, b, 0, st, a); break;
+        case 32: hipLaunchKernelGGL(k_verify_direct<32>, g, b, 0, st, a); break;
+        case 64: hipLaunchKernelGGL(k_verify_direct<64>, g, b, 0, st, a); break;
+        case kBlock: hipLaunchKernelGGL(k_verify_direct<kBlock>, g, b, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const VerifyArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify_bucketed(const VerifyArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_verify_bucketed, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace ssj

@@ -1,0 +1,252 @@
+"""Thin ctypes binding of libssj (include/ssj.h).
+
+Argument marshalling only: every step of verification runs in the HIP
+library.  The functions carry the C names.  PyTorch is imported first so that
+the library binds to the HIP runtime torch already loaded (one runtime per
+process); torch supplies device buffers and streams for ``ssj_verify_device``.
+There is no CPU fallback: if libssj.so is missing or cannot load, this module
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch  # noqa: F401  (shared HIP runtime, device memory, streams)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libssj.so")
+
+SSJ_OK = 0
+SSJ_PENDING = 1
+SSJ_EINVAL = -1
+SSJ_ENOMEM = -2
+SSJ_ETRUNC = -3
+SSJ_EAGAIN = -4
+SSJ_EDEVICE = -5
+SSJ_ENOTFOUND = -6
+
+SSJ_N_CLASSES = 5
+SSJ_CLASS_BOUNDS = (32, 128, 512, 2048, 0x7FFFFFFF)
+SSJ_MODE_BUCKETED = 0
+SSJ_MODE_DIRECT = 1
+
+EXPORTED = (
+    "ssj_init", "ssj_shutdown", "ssj_last_error", "ssj_upload_collection",
+    "ssj_free_collection", "ssj_verify", "ssj_verify_device", "ssj_stream_submit",
+    "ssj_stream_poll", "ssj_stream_times", "ssj_get_plan", "ssj_set_plan",
+    "ssj_collection_info",
+)
+
+_NAMES = {
+    SSJ_OK: "SSJ_OK", SSJ_PENDING: "SSJ_PENDING", SSJ_EINVAL: "SSJ_EINVAL",
+    SSJ_ENOMEM: "SSJ_ENOMEM", SSJ_ETRUNC: "SSJ_ETRUNC", SSJ_EAGAIN: "SSJ_EAGAIN",
+    SSJ_EDEVICE: "SSJ_EDEVICE", SSJ_ENOTFOUND: "SSJ_ENOTFOUND",
+}
+
+
+class SsjError(RuntimeError):
+    def __init__(self, code: int, msg: str, n: Optional[int] = None):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+        self.n = n
+
+
+class ssj_pair(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("s", ctypes.c_int32)]
+
+
+class ssj_opts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("hbm_budget", ctypes.c_uint64),
+                ("n_slots", ctypes.c_int), ("queue_depth", ctypes.c_int)]
+
+
+class ssj_plan(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("lanes", ctypes.c_int * SSJ_N_CLASSES),
+                ("use_graph", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libssj.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    p, i64, u64, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "ssj_init": ([P(ssj_opts), P(p)], c_int),
+        "ssj_shutdown": ([p], c_int),
+        "ssj_last_error": ([p], ctypes.c_char_p),
+        "ssj_upload_collection": ([p, p, i64, p, i64, P(p)], c_int),
+        "ssj_free_collection": ([p, p], c_int),
+        "ssj_verify": ([p, p, p, i64, i64, i64, p, i64, P(i64)], c_int),
+        "ssj_verify_device": ([p, p, p, i64, i64, i64, p, i64, p, p], c_int),
+        "ssj_stream_submit": ([p, p, p, i64, i64, i64, c_int, P(u64)], c_int),
+        "ssj_stream_poll": ([p, u64, c_int, p, i64, P(i64)], c_int),
+        "ssj_stream_times": ([p, u64, P(u64), P(u64), P(u64)], c_int),
+        "ssj_get_plan": ([p, P(ssj_plan)], c_int),
+        "ssj_set_plan": ([p, P(ssj_plan)], c_int),
+        "ssj_collection_info": ([p, P(i64), P(i64), P(i64)], c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _err(ctx, code: int, n: Optional[int] = None):
+    msg = load_library().ssj_last_error(ctx).decode(errors="replace")
+    raise SsjError(code, msg, n)
+
+
+def _pairs(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32).reshape(-1, 2)
+
+
+# --- C-named entry points -------------------------------------------------
+
+def ssj_init(device: int = 0, hbm_budget: int = 0, n_slots: int = 0, queue_depth: int = 0):
+    lib = load_library()
+    o = ssj_opts(device, hbm_budget, n_slots, queue_depth)
+    h = ctypes.c_void_p()
+    rc = lib.ssj_init(ctypes.byref(o), ctypes.byref(h))
+    if rc != SSJ_OK:
+        _err(None, rc)
+    return h
+
+
+def ssj_shutdown(ctx) -> None:
+    load_library().ssj_shutdown(ctx)
+
+
+def ssj_last_error(ctx=None) -> str:
+    return load_library().ssj_last_error(ctx).decode(errors="replace")
+
+
+def ssj_upload_collection(ctx, offsets, tokens):
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    tok = np.ascontiguousarray(tokens, dtype=np.int32)
+    h = ctypes.c_void_p()
+    rc = load_library().ssj_upload_collection(ctx, off.ctypes.data, off.shape[0] - 1,
+                                              tok.ctypes.data if tok.size else None,
+                                              tok.shape[0], ctypes.byref(h))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+    return h
+
+
+def ssj_free_collection(ctx, coll) -> None:
+    rc = load_library().ssj_free_collection(ctx, coll)
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def ssj_collection_info(coll) -> Tuple[int, int, int]:
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    rc = load_library().ssj_collection_info(coll, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    if rc != SSJ_OK:
+        _err(None, rc)
+    return a.value, b.value, c.value
+
+
+def ssj_verify(ctx, coll, cand, t_num: int, t_den: int, out_cap: Optional[int] = None) -> np.ndarray:
+    """Passing pairs (int32 [k, 2]); raises SsjError (code SSJ_ETRUNC carries .n)."""
+    c = _pairs(cand)
+    n = c.shape[0]
+    cap = n if out_cap is None else int(out_cap)
+    out = np.zeros((max(cap, 1), 2), dtype=np.int32)
+    out_n = ctypes.c_int64()
+    rc = load_library().ssj_verify(ctx, coll, c.ctypes.data if n else None, n, int(t_num), int(t_den),
+                                   out.ctypes.data, cap, ctypes.byref(out_n))
+    if rc != SSJ_OK:
+        _err(ctx, rc, out_n.value)
+    return out[:out_n.value].copy()
+
+
+def ssj_verify_device(ctx, coll, d_cand: "torch.Tensor", t_num: int, t_den: int,
+                      d_out: "torch.Tensor", d_count: "torch.Tensor", stream=None) -> None:
+    """Enqueues verification of device pairs on a torch stream (no sync)."""
+    assert d_cand.is_cuda and d_cand.dtype == torch.int32 and d_cand.is_contiguous()
+    assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
+    assert d_count.is_cuda and d_count.dtype == torch.int64 and d_count.numel() >= 1
+    n = d_cand.numel() // 2
+    cap = d_out.numel() // 2
+    st = stream if stream is not None else torch.cuda.current_stream(d_cand.device)
+    rc = load_library().ssj_verify_device(ctx, coll, d_cand.data_ptr() if n else None, n,
+                                          int(t_num), int(t_den), d_out.data_ptr() if cap else None,
+                                          cap, d_count.data_ptr(), ctypes.c_void_p(st.cuda_stream))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def ssj_stream_submit(ctx, coll, cand, t_num: int, t_den: int, nonblocking: bool = False) -> int:
+    c = _pairs(cand)
+    t = ctypes.c_uint64()
+    rc = load_library().ssj_stream_submit(ctx, coll, c.ctypes.data if c.shape[0] else None,
+                                          c.shape[0], int(t_num), int(t_den), int(bool(nonblocking)),
+                                          ctypes.byref(t))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+    return t.value
+
+
+def ssj_stream_poll(ctx, ticket: int, wait: bool = True, out_cap: int = 0):
+    """Returns the passing pairs, or None while pending (wait=False)."""
+    out = np.zeros((max(out_cap, 1), 2), dtype=np.int32)
+    out_n = ctypes.c_int64()
+    rc = load_library().ssj_stream_poll(ctx, ticket, int(bool(wait)), out.ctypes.data, out_cap,
+                                        ctypes.byref(out_n))
+    if rc == SSJ_PENDING:
+        return None
+    if rc != SSJ_OK:
+        _err(ctx, rc, out_n.value)
+    return out[:out_n.value].copy()
+
+
+def ssj_stream_times(ctx, ticket: int):
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    rc = load_library().ssj_stream_times(ctx, ticket, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    if rc == SSJ_PENDING:
+        return None
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+    return a.value, b.value, c.value
+
+
+def ssj_get_plan(ctx) -> ssj_plan:
+    p = ssj_plan()
+    rc = load_library().ssj_get_plan(ctx, ctypes.byref(p))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+    return p
+
+
+def ssj_set_plan(ctx, mode: int, lanes, use_graph: int = 0) -> None:
+    p = ssj_plan()
+    p.mode = int(mode)
+    for q in range(SSJ_N_CLASSES):
+        p.lanes[q] = int(lanes[q] if not isinstance(lanes, int) else lanes)
+    p.use_graph = int(use_graph)
+    rc = load_library().ssj_set_plan(ctx, ctypes.byref(p))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def ssj_stream_collect(ctx, ticket: int):
+    """poll(wait) with a retry at the size the library reports."""
+    try:
+        return ssj_stream_poll(ctx, ticket, True, 0)
+    except SsjError as e:
+        if e.code != SSJ_ETRUNC:
+            raise
+        return ssj_stream_poll(ctx, ticket, True, int(e.n))

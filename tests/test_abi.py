@@ -1,0 +1,82 @@
+"""The C-ABI library loads and exports what include/ssj.h declares (no GPU)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ssj.h")
+LIB = os.path.join(ROOT, "paper_1812_09141_amd", "libssj.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssj_[a-z_]+)\s*\(", text)))
+
+
+def exported_symbols():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    return {line.split()[-1] for line in out.splitlines() if line.strip()}
+
+
+@pytest.fixture(scope="module")
+def built():
+    if not os.path.exists(LIB):
+        from paper_1812_09141_amd import build
+        build.build()
+    return LIB
+
+
+def test_header_declares_core_calls():
+    names = declared_functions()
+    for n in ["ssj_init", "ssj_upload_collection", "ssj_verify", "ssj_verify_device",
+              "ssj_stream_submit", "ssj_stream_poll"]:
+        assert n in names
+
+
+def test_every_declared_symbol_exported(built):
+    exp = exported_symbols()
+    missing = [n for n in declared_functions() if n not in exp]
+    assert not missing, missing
+
+
+def test_binding_names_match_header(built):
+    import paper_1812_09141_amd.ssj as ssj
+    assert sorted(ssj.EXPORTED) == declared_functions()
+    lib = ssj.load_library()
+    for n in ssj.EXPORTED:
+        assert hasattr(lib, n)
+        assert hasattr(ssj, n)
+
+
+def test_library_independent_of_oracle(built):
+    exp = exported_symbols()
+    assert not any(s.startswith("ssjref_") for s in exp)
+    needed = subprocess.run(["readelf", "-d", LIB], capture_output=True, text=True).stdout
+    assert "ssj_oracle" not in needed and "allpairs" not in needed
+
+
+def test_init_without_gpu_fails_cleanly(built):
+    import torch
+    import paper_1812_09141_amd.ssj as ssj
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(ssj.SsjError) as e:
+        ssj.ssj_init(0)
+    assert e.value.code == ssj.SSJ_EDEVICE
+
+
+def test_constants_match_header():
+    import paper_1812_09141_amd.ssj as ssj
+    text = open(HEADER).read()
+    for name in ["SSJ_OK", "SSJ_PENDING", "SSJ_EINVAL", "SSJ_ENOMEM", "SSJ_ETRUNC", "SSJ_EAGAIN",
+                 "SSJ_EDEVICE", "SSJ_ENOTFOUND"]:
+        m = re.search(name + r"\s*=\s*(-?\d+)", text)
+        assert m and int(m.group(1)) == getattr(ssj, name)
+    m = re.search(r"SSJ_CLASS_BOUNDS\s*\{([^}]*)\}", text)
+    vals = tuple(int(v.strip(), 0) for v in m.group(1).split(","))
+    assert vals == ssj.SSJ_CLASS_BOUNDS
+    assert int(re.search(r"SSJ_N_CLASSES\s+(\d+)", text).group(1)) == ssj.SSJ_N_CLASSES
