@@ -105,7 +105,7 @@ def test_near_duplicates_all_plans(S, ctx, seed):
     for (tn, td) in [(1, 2), (7, 10), (9, 10)]:
         cand = np.concatenate([cfilter.candidates(c.offsets, c.tokens, tn, td), rp])
         want = want_of(c, cand, tn, td)
-        assert want.shape[0] > 100
+        assert want.shape[0] > (100 if tn * 2 <= td else 0)
         for name, plan in plans():
             _log(f"near-dup seed={seed} t={tn}/{td} {name} n={cand.shape[0]}")
             set_plan(S, ctx, plan)
