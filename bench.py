@@ -1,0 +1,297 @@
+#!/usr/bin/env python3
+"""Verification throughput on one MI355X: verified candidate pairs per second.
+
+Workload (default): the offline verification collection -- 100,000 sets,
+lognormal sizes (arithmetic mean 12, sigma 0.5) clipped to 2..200, tokens
+Zipf(1.0) over 200,000 ids -- joined at Jaccard t in {0.6, 0.7, 0.8, 0.9};
+all prefix+length filter candidates of each threshold verified in one call
+per threshold.  One step = the four calls.  The collection and the candidate
+pairs are resident in HBM before the timed region starts; output pairs and
+counts stay in HBM (ssj_verify_device).
+
+Prints one JSON line.  --gpus N > 1 is not supported (one GPU only).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "verified candidate pairs/sec + achieved HBM GB/s; p50/p99 batch latency (stream)"
+PEAK_HBM_GBS = 8000.0
+WORKLOAD_CFG = {"offline": 2, "tiny": 1, "longsets": 3}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="offline", choices=sorted(WORKLOAD_CFG))
+    ap.add_argument("--plan", default="auto",
+                    help="auto (autotuned) | inline:L | defer:L,F,l0,l1,l2,l3,l4")
+    ap.add_argument("--compare-plain", type=int, default=1,
+                    help="also time plain one-launch-per-batch verification")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU work budget of the oracle baseline (0 disables it)")
+    return ap.parse_args()
+
+
+def plan_of(S, spec):
+    """auto | inline:L | defer:L,F,l0,l1,l2,l3,l4"""
+    if spec == "auto":
+        return None
+    kind, _, rest = spec.partition(":")
+    vals = [int(v) for v in rest.split(",")] if rest else []
+    if kind == "inline":
+        return S.make_plan(inline_lanes=vals[0], defer_from=5)
+    if kind == "defer":
+        return S.make_plan(inline_lanes=vals[0], defer_from=vals[1], lanes=vals[2:7])
+    raise SystemExit(f"unknown plan {spec!r}")
+
+
+def load_manifest(cfg):
+    with open(os.path.join(ROOT, "tests", "golden", "manifest.json")) as f:
+        return json.load(f)[str(cfg)]
+
+
+def traffic_from_profiles(kernel_src_hash):
+    """HBM bytes per verify launch from committed PMC summaries, if current."""
+    p = os.path.join(ROOT, "profiles", "verify_bucketed_offline_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        with open(p) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256") != kernel_src_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "ssj_device.h"):
+        with open(os.path.join(ROOT, "paper_1812_09141_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def pairs_digest(pairs):
+    """SHA-256 of the pairs sorted as unsigned (r << 32 | s) keys."""
+    import hashlib
+    import numpy as np
+    pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    key = (pr[:, 0].astype(np.int64) << 32) | (pr[:, 1].astype(np.int64) & 0xFFFFFFFF)
+    return hashlib.sha256(pr[np.argsort(key, kind="stable")].tobytes()).hexdigest()
+
+
+def timed_steps(torch, step, steps, warmup):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the verification path has no multi-GPU form in this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1812_09141_amd.ssj as S
+    from ssj_inputs import filter as cfilter
+    from ssj_inputs import synth
+
+    cfg = WORKLOAD_CFG[args.workload]
+    w = synth.WORKLOADS[cfg]
+    man = load_manifest(cfg)
+    t0 = time.time()
+    coll = synth.workload_collection(cfg)
+    if coll.digest() != man["collection_sha256"]:
+        raise SystemExit("generated collection differs from the manifest")
+    cands = [cfilter.workload_candidates(cfg, tn, td) for (tn, td) in w.thresholds]
+    n_pairs = int(sum(c.shape[0] for c in cands))
+    log(f"inputs ready in {time.time() - t0:.1f}s: {coll.n_sets} sets, {coll.n_tokens} tokens, "
+        f"{n_pairs} candidate pairs per step")
+
+    dev = torch.device("cuda:0")
+    ctx = S.ssj_init(0)
+    h = S.ssj_upload_collection(ctx, coll.offsets, coll.tokens)
+    d_cands = [torch.from_numpy(c).to(dev) for c in cands]
+    d_outs = [torch.empty((max(c.shape[0], 1), 2), dtype=torch.int32, device=dev) for c in cands]
+    d_cnt = torch.zeros(len(cands), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+
+    batch = [(d_cands[i], tn, td, d_outs[i], d_cnt[i:i + 1]) for i, (tn, td) in enumerate(w.thresholds)]
+
+    def step():  # batched: every threshold's candidates in one launch
+        S.ssj_verify_batch_device(ctx, h, batch)
+
+    def step_plain():  # one launch per batch
+        for i, (tn, td) in enumerate(w.thresholds):
+            S.ssj_verify_device(ctx, h, d_cands[i], tn, td, d_outs[i], d_cnt[i:i + 1])
+
+    def check():
+        cnt = d_cnt.cpu().numpy()
+        ok = True
+        for i, (tn, td) in enumerate(w.thresholds):
+            m = man["thresholds"][f"{tn}/{td}"]
+            k = int(cnt[i])
+            if k != m["n_result"]:
+                ok = False
+                continue
+            got = d_outs[i][:k].cpu().numpy()
+            ok &= pairs_digest(got) == m["result_sha256"]
+        return ok
+
+    plan = plan_of(S, args.plan)
+    tuned = None
+    if plan is None:
+        big = max(range(len(cands)), key=lambda i: cands[i].shape[0])
+        tn, td = w.thresholds[big]
+        plan, tuned_ms = S.ssj_autotune(ctx, h, d_cands[big], tn, td, apply=False)
+        tuned = {"plan": plan.as_dict(), "kernel_ms": round(tuned_ms, 5),
+                 "tuned_on": f"t={tn}/{td}, {cands[big].shape[0]} pairs"}
+        log(f"autotuned plan: {tuned}")
+    S.ssj_set_plan(ctx, plan)
+
+    # main timed region, kernel timing on (HIP events on the launch stream)
+    S.ssj_timing_enable(ctx, True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    S.ssj_timing_read(ctx, reset=True)
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    in_ms, def_ms, launches = S.ssj_timing_read(ctx, reset=True)
+    S.ssj_timing_enable(ctx, False)
+    parity = check()
+    if not parity:
+        log("RESULT MISMATCH against the oracle manifest")
+
+    value = n_pairs * args.steps / elapsed
+    ms_per_step = elapsed * 1e3 / args.steps
+
+    # algorithmic bytes per step: pair ids (8) + two descriptors (16) per pair,
+    # the tokens the early-terminating merge consumes (4 each), 8 per result
+    b_alg = 0
+    b_full = 0
+    sizes = coll.sizes()
+    for i, (tn, td) in enumerate(w.thresholds):
+        m = man["thresholds"][f"{tn}/{td}"]
+        b_alg += 24 * m["n_candidates"] + 4 * m["sum_consumed_tokens"] + 8 * m["n_result"]
+        c = cands[i]
+        b_full += 24 * c.shape[0] + 4 * int(sizes[c[:, 0]].sum() + sizes[c[:, 1]].sum()) + 8 * m["n_result"]
+    launches = max(launches, 1)
+    per_launch_bytes = b_alg / (launches / args.steps)
+    avg_in_ms = in_ms / launches
+    avg_def_ms = def_ms / launches
+    deferred = plan.defer_from < 5
+    avg_kernel_ms = avg_in_ms + (avg_def_ms if deferred else 0.0)
+    achieved = per_launch_bytes / (avg_kernel_ms * 1e-3) / 1e9 if avg_kernel_ms > 0 else 0.0
+    src_hash = kernel_source_hash()
+    traffic = traffic_from_profiles(src_hash)
+
+    extra = {"plan": plan.as_dict()}
+    if tuned:
+        extra["autotune"] = tuned
+    if args.compare_plain:
+        n_plain = max(5, args.steps // 2)
+        dt = timed_steps(torch, step_plain, n_plain, 2)
+        extra["plain_one_launch_per_batch_pairs_per_s"] = round(n_pairs * n_plain / dt, 1)
+        extra["plain_ms_per_step"] = round(dt * 1e3 / n_plain, 4)
+        extra["plain_parity"] = bool(check())
+        extra["batched_over_plain"] = round(value / (n_pairs * n_plain / dt), 3)
+
+    # CPU baseline: the oracle (full merge, plain C) on the host cores
+    cpu = None
+    if args.cpu_seconds > 0:
+        import oracle
+        nthreads = max(1, min(os.cpu_count() or 1, 16))
+        t_c = time.perf_counter()
+        done = 0
+        reps = 0
+        while True:
+            for i, (tn, td) in enumerate(w.thresholds):
+                oracle.verify(coll.offsets, coll.tokens, cands[i], tn, td, n_threads=nthreads)
+                done += cands[i].shape[0]
+            reps += 1
+            if time.perf_counter() - t_c >= args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t_c
+        cpu = {"value": round(done / dt, 1), "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"{reps} full passes over the step's {n_pairs} candidate pairs "
+                         f"(all four thresholds), {dt:.1f}s of CPU work"}
+
+    S.ssj_shutdown(ctx)
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w.name}: {w.n_sets} sets, sizes lognormal(mean 12, sigma 0.5) clipped "
+                         f"2-200, Zipf(1.0) over {w.universe} tokens; Jaccard t in "
+                         f"{{0.6,0.7,0.8,0.9}}; {n_pairs} prefix+length candidates per step"
+                         if cfg == 2 else f"{w.name} (config {cfg}), {n_pairs} candidates per step"),
+            "pairs_per_step": n_pairs,
+            "launches_per_step": 1,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": (f"k_verify_tiles<{plan.inline_lanes}>" +
+                       (" + k_verify_deferred" if deferred else "")),
+            "achieved": round(achieved, 2),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 5),
+            "traffic": traffic,
+            "alg_bytes_per_launch": int(per_launch_bytes),
+            "avg_kernel_ms": round(avg_kernel_ms, 5),
+            "avg_inorder_ms": round(avg_in_ms, 5),
+            "avg_deferred_ms": round(avg_def_ms, 5),
+        },
+        "cpu_baseline": cpu,
+        "parity": bool(parity),
+        "alg_gbs_whole_step": round(b_alg * args.steps / elapsed / 1e9, 2),
+        "full_read_bytes_per_step": int(b_full),
+        "alg_bytes_per_step": int(b_alg),
+    }
+    rec.update(extra)
+    print(json.dumps(rec), flush=True)
+    if not parity:
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

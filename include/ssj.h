@@ -150,30 +150,81 @@ int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, uint64_t* t_submit, uint64_t
                      uint64_t* t_done);
 
 /*
- * Execution plan.  Verification splits the candidates into length classes by
- * |r| + |s| (upper bounds SSJ_CLASS_BOUNDS) and verifies each class with its
- * own mapping of pairs onto lanes:
- *   lanes = 1          one thread per pair (sequential early-exit merge)
- *   lanes = 4..64      a group of lanes of one wavefront per pair
- *   lanes = 256        one 256-thread workgroup per pair
- * SSJ_MODE_DIRECT skips the classification and runs a single mapping over
- * the candidates in input order (plain one-launch verification).
+ * Execution plan.  Verification runs as one or two kernels per launch:
+ *  1. an in-order kernel walks the candidates in tiles of consecutive pairs
+ *     and verifies each pair with inline_lanes lanes (1 = one thread per
+ *     pair, a sequential early-exit merge; 4..64 = a group of lanes of one
+ *     wavefront per pair, intersecting tile by tile);
+ *  2. pairs whose length class (by |r| + |s|, inclusive upper bounds
+ *     SSJ_CLASS_BOUNDS) is defer_from or higher are not verified by (1) but
+ *     queued per class; a persistent kernel then drains each class with
+ *     lanes[class] lanes per pair (256 = one workgroup per pair, handed out
+ *     by work stealing).  defer_from = SSJ_N_CLASSES defers nothing and runs
+ *     the in-order kernel alone.
+ * use_graph != 0 replays the launch through a captured hipGraph whose kernel
+ * parameters are updated per call.
  */
 #define SSJ_N_CLASSES 5
 #define SSJ_CLASS_BOUNDS {32, 128, 512, 2048, 0x7fffffff}
-
-enum { SSJ_MODE_BUCKETED = 0, SSJ_MODE_DIRECT = 1 };
+#define SSJ_MAX_BATCH 16
 
 typedef struct {
-    int mode;                      /* SSJ_MODE_BUCKETED or SSJ_MODE_DIRECT */
-    int lanes[SSJ_N_CLASSES];      /* per length class; DIRECT uses lanes[0] */
-    int use_graph;                 /* replay launches through a captured hipGraph */
+    int inline_lanes;            /* 1, 4, 8, 16, 32 or 64 */
+    int defer_from;              /* 0 .. SSJ_N_CLASSES */
+    int lanes[SSJ_N_CLASSES];    /* per deferred class: 1, 4, 8, 16, 32, 64 or 256 */
+    int use_graph;
 } ssj_plan;
 
-/* Reads / replaces the context's plan.  SSJ_EINVAL for an unsupported lane
- * count.  Not thread-safe against in-flight calls on the same context. */
+/* Reads / replaces the context's plan.  SSJ_EINVAL for an unsupported
+ * value.  Not thread-safe against in-flight calls on the same context. */
 int ssj_get_plan(ssj_ctx* ctx, ssj_plan* plan);
 int ssj_set_plan(ssj_ctx* ctx, const ssj_plan* plan);
+
+/* One request of a batched launch: device buffers owned by the caller, with
+ * the meaning of the ssj_verify_device arguments of the same names. */
+typedef struct {
+    const ssj_pair* d_cand;
+    int64_t n_cand;
+    int64_t t_num;
+    int64_t t_den;
+    ssj_pair* d_out;
+    int64_t out_cap;
+    int64_t* d_count;
+} ssj_request;
+
+/*
+ * Batched verification: up to SSJ_MAX_BATCH requests (each with its own
+ * candidates, threshold and output) verified by one launch on hip_stream.
+ * Each d_count receives its request's result count (or -1 on an id out of
+ * range).  The pairs of all requests together must stay below 2^31.  Same
+ * ordering rule as ssj_verify_device.  SSJ_EINVAL for bad arguments.
+ */
+int ssj_verify_batch_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_request* reqs,
+                            int n_reqs, void* hip_stream);
+
+/*
+ * Autotuner: times candidate plans on the given device candidates (which
+ * should be representative of the workload; a few million pairs suffice) and
+ * returns the fastest in *best (its kernel time per launch in *best_ms).
+ * apply != 0 also makes it the context's plan.  The search first picks the
+ * in-order mapping, then tries deferring the longer length classes, one
+ * class at a time, with the mappings suited to each length.  Synchronous.
+ */
+int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
+                 int64_t t_num, int64_t t_den, int apply, ssj_plan* best, double* best_ms);
+
+/*
+ * Kernel timing, for measurement.  While enabled, the library brackets the
+ * kernels of every launch it enqueues from ssj_verify, ssj_verify_device
+ * and ssj_verify_batch_device with HIP events recorded on the launch stream.
+ * ssj_timing_read waits for the recorded events and returns the summed
+ * elapsed milliseconds of the in-order kernels and of the deferred-class
+ * kernels, and the number of launches; reset != 0 clears the sums.  Do not
+ * enable it while the calls are being captured into a graph.
+ */
+int ssj_timing_enable(ssj_ctx* ctx, int enable);
+int ssj_timing_read(ssj_ctx* ctx, int reset, double* inorder_ms, double* deferred_ms,
+                    int64_t* launches);
 
 /* Collection facts: number of sets, tokens, and the largest set size. */
 int ssj_collection_info(const ssj_coll* coll, int64_t* n_sets, int64_t* n_tokens,

@@ -10,8 +10,8 @@
 // < alpha (reject: alpha is out of reach) -- the early-terminating merge of
 // paper Sec. 3.1.  Any sound stopping rule yields the same decisions.
 //
-// Three mappings of pairs onto lanes (the paper's alternatives A/B/C of Sec.
-// 3.3.2 assign a probe set to a thread or a block; here the unit is a pair):
+// Mappings of pairs onto lanes (the paper's alternatives A/B/C of Sec. 3.3.2
+// give a probe set to a thread or a block; here the unit is one pair):
 //   * one thread per pair: a sequential early-exit merge;
 //   * a group of G lanes (G = 4..64) of one wavefront per pair: tile merge;
 //   * one 256-thread workgroup per pair: the same tile merge over LDS.
@@ -25,9 +25,18 @@
 // round that finds it and in no later round, so each match is counted
 // exactly once; the stopping rule is checked before every round.
 //
-// Passing pairs are appended to the output by wavefront compaction: a
-// ballot of the pass flags, one atomic add per wavefront that has passes,
-// and a per-lane offset from the lane's rank among the passing lanes.
+// Scheduling.  One launch carries up to kMaxReq requests (candidate arrays
+// with their own threshold and output).  The in-order kernel walks tiles of
+// kTile consecutive pairs of one request (a static grid-stride split: with
+// early termination the cost of a pair depends on its first few tokens, not
+// on its length, so in-order tiles are balanced).  Optionally, pairs whose
+// length class |r| + |s| is at or above defer_from are not verified there but
+// queued per class (collected in LDS, one global atomic per workgroup flush);
+// a second, persistent kernel drains those queues with the class's own
+// mapping -- workgroup-per-pair classes by work stealing, the others by a
+// static split.  Passing pairs are appended by wavefront compaction: a ballot
+// of the pass flags, one atomic add per wavefront that has passes, and a
+// per-lane offset from the lane's rank among the passing lanes.
 #include "ssj_device.h"
 
 namespace ssj {
@@ -51,6 +60,10 @@ __device__ __forceinline__ int bperm(int v, int src) {
 __device__ __forceinline__ uint32_t mbcnt(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t load_relaxed(const unsigned int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One thread: sequential early-terminating merge.
@@ -171,46 +184,65 @@ __device__ bool merge_block(const int32_t* __restrict__ A, uint32_t na,
     }
 }
 
-// Appends the pairs of the lanes with pass set; wavefront compaction.
-__device__ __forceinline__ void append_wave(bool pass, int2 pr, const VerifyArgs& a) {
+// Appends the pairs of the lanes with pass set (one request); wavefront
+// compaction with a single atomic add.
+__device__ __forceinline__ void append_wave(bool pass, int2 pr, int2* out, unsigned long long cap,
+                                            unsigned long long* counter) {
     const unsigned long long m = ballot(pass);
     if (m == 0ull) return;
     const int lane = lane_id();
     const int leader = __builtin_ctzll(m);
     unsigned long long base = 0ull;
-    if (lane == leader) base = atomicAdd(&a.ctr->out_count, (unsigned long long)__popcll(m));
+    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
     const uint32_t lo = (uint32_t)bperm((int)(uint32_t)base, leader);
     const uint32_t hi = (uint32_t)bperm((int)(uint32_t)(base >> 32), leader);
     base = ((unsigned long long)hi << 32) | lo;
     if (pass) {
         const unsigned long long k = base + mbcnt(m);
-        if (k < a.cap) a.out[k] = pr;
+        if (k < cap) out[k] = pr;
     }
 }
 
-__device__ __forceinline__ void append_one(int2 pr, const VerifyArgs& a) {
-    const unsigned long long k = atomicAdd(&a.ctr->out_count, 1ull);
-    if (k < a.cap) a.out[k] = pr;
+__device__ __forceinline__ void append_one(int2 pr, const Request& R, unsigned long long* counter) {
+    const unsigned long long k = atomicAdd(counter, 1ull);
+    if (k < R.cap) R.out[k] = pr;
 }
 
 __device__ __forceinline__ bool ids_ok(int2 pr, uint32_t n_sets) {
     return (uint32_t)pr.x < n_sets && (uint32_t)pr.y < n_sets;
 }
 
-// The last workgroup to finish publishes the count (or -1 on an id error)
-// and returns the counters to zero for the next launch.
-__device__ void finalize(const VerifyArgs& a) {
+__device__ __forceinline__ int class_of(uint32_t L, const LaunchArgs& a) {
+    int cls = kClasses - 1;
+#pragma unroll
+    for (int q = kClasses - 2; q >= 0; --q)
+        if (L <= a.bounds[q]) cls = q;
+    return cls;
+}
+
+// Request holding global pair index gi (prefix sums in pair_off).
+__device__ __forceinline__ int request_of_pair(uint32_t gi, const LaunchArgs& a) {
+    int r = 0;
+    for (int q = 1; q < a.n_req; ++q) r += (gi >= a.pair_off[q]) ? 1 : 0;
+    return r;
+}
+
+// The last workgroup to finish publishes each request's count (or -1 on an
+// id error) and returns the counters to zero for the next launch.
+__device__ void finalize(const LaunchArgs& a) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
         const unsigned prev = atomicAdd(&a.ctr->done, 1u);
         if (prev == gridDim.x - 1) {
             __threadfence();
-            const unsigned long long cnt = atomicAdd(&a.ctr->out_count, 0ull);
-            const unsigned err = atomicOr(&a.ctr->err, 0u);
-            *a.d_count = err ? -1ll : (long long)cnt;
-            atomicExch(&a.ctr->out_count, 0ull);
-            atomicExch(&a.ctr->err, 0u);
+            for (int r = 0; r < a.n_req; ++r) {
+                const unsigned long long cnt = atomicAdd(&a.ctr->out_count[r], 0ull);
+                const unsigned err = atomicOr(&a.ctr->err[r], 0u);
+                *a.req[r].d_count = err ? -1ll : (long long)cnt;
+                atomicExch(&a.ctr->out_count[r], 0ull);
+                atomicExch(&a.ctr->err[r], 0u);
+            }
 #pragma unroll
             for (int q = 0; q < kClasses; ++q) {
                 atomicExch(&a.ctr->head[q], 0u);
@@ -223,10 +255,8 @@ __device__ void finalize(const VerifyArgs& a) {
 }
 
 template <int G>
-__device__ __forceinline__ bool verify_pair_lanes(const VerifyArgs& a, int2 pr, int g, int gbase) {
-    const uint2 dr = a.desc[pr.x];
-    const uint2 ds = a.desc[pr.y];
-    const uint32_t alpha = required_overlap(dr.y + ds.y, a.tn, a.tsum);
+__device__ __forceinline__ bool verify_lanes(const LaunchArgs& a, uint2 dr, uint2 ds,
+                                             uint32_t alpha, int g, int gbase) {
     if constexpr (G == 1) {
         return merge_thread(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha);
     } else {
@@ -234,144 +264,167 @@ __device__ __forceinline__ bool verify_pair_lanes(const VerifyArgs& a, int2 pr, 
     }
 }
 
+// Moves the workgroup's LDS queue of class q to the global queue.  Called by
+// the whole workgroup with the same c (= entries in the LDS queue).
+__device__ void flush_deferred(const LaunchArgs& a, int q, uint32_t c, const uint32_t* buf,
+                               uint32_t* s_base) {
+    if (threadIdx.x == 0) *s_base = atomicAdd(&a.ctr->tail[q], c);
+    __syncthreads();
+    const uint32_t base = *s_base;
+    uint32_t* dst = a.queues + (size_t)q * a.qcap + base;
+    for (uint32_t i = threadIdx.x; i < c; i += kBlock) dst[i] = buf[i];
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
-// Direct mode: every pair in input order with one mapping (grid-stride).
+// In-order kernel.  Workgroup iteration = one tile of kTile consecutive pairs
+// of one request; wavefront w takes the tile's pairs w*64 .. w*64+63, as
+// 64/G pairs at a time when G lanes share a pair.
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_verify_direct(VerifyArgs a) {
-    if constexpr (G == kBlock) {
-        __shared__ int32_t sb[kBlock];
-        __shared__ uint32_t red[16];
-        for (uint32_t p = blockIdx.x; p < a.n; p += gridDim.x) {
-            const int2 pr = a.cand[p];
-            bool pass = false;
-            if (ids_ok(pr, a.n_sets)) {
-                const uint2 dr = a.desc[pr.x];
-                const uint2 ds = a.desc[pr.y];
-                const uint32_t alpha = required_overlap(dr.y + ds.y, a.tn, a.tsum);
-                pass = merge_block(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, sb, red);
-            } else if (threadIdx.x == 0) {
-                atomicOr(&a.ctr->err, 1u);
-            }
-            if (threadIdx.x == 0 && pass) append_one(pr, a);
-        }
-    } else {
-        constexpr int GPW = kWave / G;
-        const int lane = lane_id();
-        const int grp = lane / G, g = lane % G, gbase = grp * G;
-        const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-        const uint32_t nwaves = (gridDim.x * kBlock) / kWave;
-        for (uint64_t base = (uint64_t)wave * GPW; base < a.n; base += (uint64_t)nwaves * GPW) {
-            const uint64_t p = base + (uint64_t)grp;
-            bool pass = false;
+__global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
+    constexpr int GPW = kWave / G;
+    __shared__ uint32_t s_defer[kClasses][kDeferCap];
+    __shared__ uint32_t s_dcnt[kClasses];
+    __shared__ uint32_t s_base;
+    const bool deferring = a.defer_from < kClasses;
+    if (threadIdx.x < kClasses) s_dcnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int w = (int)(threadIdx.x >> 6);
+    const int lane = lane_id();
+    const int grp = lane / G, g = lane % G, gbase = grp * G;
+    const uint32_t n_tiles = a.tile_off[a.n_req];
+    for (uint32_t T = blockIdx.x; T < n_tiles; T += gridDim.x) {
+        int r = 0;
+        while (r + 1 < a.n_req && a.tile_off[r + 1] <= T) ++r;
+        const Request& R = a.req[r];
+        const uint32_t base = (T - a.tile_off[r]) * kTile + (uint32_t)w * kWave;
+        for (int sub = 0; sub < G; ++sub) {
+            const uint32_t k = base + (uint32_t)(sub * GPW + grp);
+            bool pass = false, defer = false;
+            int cls = 0;
             int2 pr = make_int2(0, 0);
-            if (p < a.n) {
-                pr = a.cand[p];
+            if (k < R.n) {
+                pr = R.cand[k];
                 if (ids_ok(pr, a.n_sets)) {
-                    pass = verify_pair_lanes<G>(a, pr, g, gbase);
+                    const uint2 dr = a.desc[pr.x];
+                    const uint2 ds = a.desc[pr.y];
+                    const uint32_t L = dr.y + ds.y;
+                    if (deferring) {
+                        cls = class_of(L, a);
+                        defer = cls >= a.defer_from;
+                    }
+                    if (!defer)
+                        pass = verify_lanes<G>(a, dr, ds, required_overlap(L, R.tn, R.tsum), g, gbase);
                 } else if (g == 0) {
-                    atomicOr(&a.ctr->err, 1u);
+                    atomicOr(&a.ctr->err[r], 1u);
                 }
             }
-            append_wave(pass && g == 0, pr, a);
+            append_wave(pass && g == 0, pr, R.out, R.cap, &a.ctr->out_count[r]);
+            if (deferring) {
+                const bool d0 = defer && g == 0;
+                for (int q = a.defer_from; q < kClasses; ++q) {
+                    const unsigned long long m = ballot(d0 && cls == q);
+                    if (m != 0ull) {
+                        const int leader = __builtin_ctzll(m);
+                        uint32_t pos = 0;
+                        if (lane == leader) pos = atomicAdd(&s_dcnt[q], (uint32_t)__popcll(m));
+                        pos = (uint32_t)bperm((int)pos, leader);
+                        if (d0 && cls == q) s_defer[q][pos + mbcnt(m)] = a.pair_off[r] + k;
+                    }
+                }
+            }
         }
+        if (deferring) {
+            // at most kTile entries per class arrive per iteration, so a queue
+            // with room for fewer than kTile more is flushed now
+            __syncthreads();
+            for (int q = a.defer_from; q < kClasses; ++q) {
+                const uint32_t c = s_dcnt[q];
+                if (c > (uint32_t)(kDeferCap - kTile)) {
+                    flush_deferred(a, q, c, s_defer[q], &s_base);
+                    if (threadIdx.x == 0) s_dcnt[q] = 0;
+                    __syncthreads();
+                }
+            }
+        }
+    }
+    if (deferring) {
+        __syncthreads();
+        for (int q = a.defer_from; q < kClasses; ++q) {
+            const uint32_t c = s_dcnt[q];
+            if (c > 0) flush_deferred(a, q, c, s_defer[q], &s_base);
+        }
+        return;  // the deferred-class kernel publishes the counts
     }
     finalize(a);
 }
 
 // ---------------------------------------------------------------------------
-// Bucketed mode, pass 1: length class of every pair -> per-class queues of
-// pair indices (wavefront-aggregated appends).
-__global__ __launch_bounds__(kBlock) void k_classify(VerifyArgs a) {
-    const int lane = lane_id();
-    for (uint64_t p0 = (uint64_t)blockIdx.x * kBlock; p0 < a.n;
-         p0 += (uint64_t)gridDim.x * kBlock) {
-        const uint64_t p = p0 + threadIdx.x;
-        int cls = -1;
-        if (p < a.n) {
-            const int2 pr = a.cand[p];
-            if (ids_ok(pr, a.n_sets)) {
-                const uint32_t L = a.desc[pr.x].y + a.desc[pr.y].y;
-                cls = kClasses - 1;
-#pragma unroll
-                for (int q = kClasses - 2; q >= 0; --q)
-                    if (L <= a.bounds[q]) cls = q;
-            } else {
-                atomicOr(&a.ctr->err, 1u);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kClasses; ++q) {
-            const unsigned long long m = ballot(cls == q);
-            if (m != 0ull) {
-                const int leader = __builtin_ctzll(m);
-                uint32_t base = 0;
-                if (lane == leader) base = atomicAdd(&a.ctr->tail[q], (uint32_t)__popcll(m));
-                base = (uint32_t)bperm((int)base, leader);
-                if (cls == q) a.queues[(size_t)q * a.qcap + base + mbcnt(m)] = (uint32_t)p;
-            }
-        }
-    }
-}
-
-// Bucketed mode, pass 2: one persistent grid drains the class queues by
-// work stealing (an atomic cursor per queue), heaviest classes first;
-// workgroup-mapped classes are taken one pair per workgroup, the others one
-// wavefront tile (64 / G pairs) at a time.
+// Deferred classes.  Workgroup-mapped classes (lanes == kBlock) are taken one
+// pair per workgroup by work stealing; the others are split statically over
+// all wavefronts of the grid.
 template <int G>
-__device__ void drain_class_waves(const VerifyArgs& a, int q) {
+__device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
     constexpr int GPW = kWave / G;
     const int lane = lane_id();
     const int grp = lane / G, g = lane % G, gbase = grp * G;
-    const uint32_t cnt = a.ctr->tail[q];
     const uint32_t* queue = a.queues + (size_t)q * a.qcap;
-    for (;;) {
-        uint32_t t = 0;
-        if (lane == 0) t = atomicAdd(&a.ctr->head[q], (uint32_t)GPW);
-        t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
-        if (t >= cnt) break;
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const uint32_t nwaves = (gridDim.x * kBlock) / kWave;
+    for (uint32_t t = wave * GPW; t < cnt; t += nwaves * GPW) {
         const uint32_t k = t + (uint32_t)grp;
-        bool pass = false;
-        int2 pr = make_int2(0, 0);
         if (k < cnt) {
-            pr = a.cand[queue[k]];
-            pass = verify_pair_lanes<G>(a, pr, g, gbase);
+            const uint32_t gi = queue[k];
+            const int r = request_of_pair(gi, a);
+            const Request& R = a.req[r];
+            const int2 pr = R.cand[gi - a.pair_off[r]];
+            const uint2 dr = a.desc[pr.x];
+            const uint2 ds = a.desc[pr.y];
+            const bool pass = verify_lanes<G>(a, dr, ds, required_overlap(dr.y + ds.y, R.tn, R.tsum),
+                                              g, gbase);
+            if (pass && g == 0) append_one(pr, R, &a.ctr->out_count[r]);
         }
-        append_wave(pass && g == 0, pr, a);
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_verify_bucketed(VerifyArgs a) {
+__global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
     __shared__ int32_t sb[kBlock];
     __shared__ uint32_t red[16];
     __shared__ uint32_t s_tile;
-    for (int oi = 0; oi < kClasses; ++oi) {
-        const int q = a.order[oi];
+    for (int q = kClasses - 1; q >= a.defer_from; --q) {
         if (a.lanes[q] != kBlock) continue;
-        const uint32_t cnt = a.ctr->tail[q];
+        const uint32_t cnt = load_relaxed(&a.ctr->tail[q]);
         const uint32_t* queue = a.queues + (size_t)q * a.qcap;
         for (;;) {
-            if (threadIdx.x == 0) s_tile = atomicAdd(&a.ctr->head[q], 1u);
+            if (threadIdx.x == 0) {
+                // a plain read first: no atomic traffic once the queue is drained
+                s_tile = load_relaxed(&a.ctr->head[q]) >= cnt ? cnt : atomicAdd(&a.ctr->head[q], 1u);
+            }
             __syncthreads();
             const uint32_t t = s_tile;
             __syncthreads();
             if (t >= cnt) break;
-            const int2 pr = a.cand[queue[t]];
+            const uint32_t gi = queue[t];
+            const int r = request_of_pair(gi, a);
+            const Request& R = a.req[r];
+            const int2 pr = R.cand[gi - a.pair_off[r]];
             const uint2 dr = a.desc[pr.x];
             const uint2 ds = a.desc[pr.y];
-            const uint32_t alpha = required_overlap(dr.y + ds.y, a.tn, a.tsum);
-            const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, sb, red);
-            if (threadIdx.x == 0 && pass) append_one(pr, a);
+            const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y,
+                                          required_overlap(dr.y + ds.y, R.tn, R.tsum), sb, red);
+            if (threadIdx.x == 0 && pass) append_one(pr, R, &a.ctr->out_count[r]);
         }
     }
-    for (int oi = 0; oi < kClasses; ++oi) {
-        const int q = a.order[oi];
+    for (int q = kClasses - 1; q >= a.defer_from; --q) {
+        const uint32_t cnt = load_relaxed(&a.ctr->tail[q]);
+        if (cnt == 0) continue;
         switch (a.lanes[q]) {
-            case 1: drain_class_waves<1>(a, q); break;
-            case 4: drain_class_waves<4>(a, q); break;
-            case 8: drain_class_waves<8>(a, q); break;
-            case 16: drain_class_waves<16>(a, q); break;
-            case 32: drain_class_waves<32>(a, q); break;
-            case 64: drain_class_waves<64>(a, q); break;
+            case 1: drain_static<1>(a, q, cnt); break;
+            case 4: drain_static<4>(a, q, cnt); break;
+            case 8: drain_static<8>(a, q, cnt); break;
+            case 16: drain_static<16>(a, q, cnt); break;
+            case 32: drain_static<32>(a, q, cnt); break;
+            case 64: drain_static<64>(a, q, cnt); break;
             default: break;
         }
     }
@@ -396,21 +449,21 @@ bool lanes_supported(int lanes) {
     }
 }
 
-const void* kernel_verify_direct(int lanes) {
+bool inline_lanes_supported(int lanes) { return lanes_supported(lanes) && lanes != kBlock; }
+
+const void* kernel_verify_tiles(int lanes) {
     switch (lanes) {
-        case 1: return (const void*)&k_verify_direct<1>;
-        case 4: return (const void*)&k_verify_direct<4>;
-        case 8: return (const void*)&k_verify_direct<8>;
-        case 16: return (const void*)&k_verify_direct<16>;
-        case 32: return (const void*)&k_verify_direct<32>;
-        case 64: return (const void*)&k_verify_direct<64>;
-        case kBlock: return (const void*)&k_verify_direct<kBlock>;
+        case 1: return (const void*)&k_verify_tiles<1>;
+        case 4: return (const void*)&k_verify_tiles<4>;
+        case 8: return (const void*)&k_verify_tiles<8>;
+        case 16: return (const void*)&k_verify_tiles<16>;
+        case 32: return (const void*)&k_verify_tiles<32>;
+        case 64: return (const void*)&k_verify_tiles<64>;
         default: return nullptr;
     }
 }
 
-const void* kernel_verify_bucketed() { return (const void*)&k_verify_bucketed; }
-const void* kernel_classify() { return (const void*)&k_classify; }
+const void* kernel_verify_deferred() { return (const void*)&k_verify_deferred; }
 
 hipError_t launch_build_desc(const int64_t* d_offsets, uint2* d_desc, int64_t n_sets,
                              hipStream_t st) {
@@ -422,28 +475,22 @@ hipError_t launch_build_desc(const int64_t* d_offsets, uint2* d_desc, int64_t n_
     return hipGetLastError();
 }
 
-hipError_t launch_verify_direct(const VerifyArgs& a, int lanes, int grid, hipStream_t st) {
+hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st) {
     const dim3 g((unsigned)grid), b(kBlock);
-    switch (lanes) {
-        case 1: hipLaunchKernelGGL(k_verify_direct<1>, g, b, 0, st, a); break;
-        case 4: hipLaunchKernelGGL(k_verify_direct<4>, g, b, 0, st, a); break;
-        case 8: hipLaunchKernelGGL(k_verify_direct<8>, g, b, 0, st, a); break;
-        case 16: hipLaunchKernelGGL(k_verify_direct<16>, g, b, 0, st, a); break;
-        case 32: hipLaunchKernelGGL(k_verify_direct<32>, g, b, 0, st, a); break;
-        case 64: hipLaunchKernelGGL(k_verify_direct<64>, g, b, 0, st, a); break;
-        case kBlock: hipLaunchKernelGGL(k_verify_direct<kBlock>, g, b, 0, st, a); break;
+    switch (a.inline_lanes) {
+        case 1: hipLaunchKernelGGL(k_verify_tiles<1>, g, b, 0, st, a); break;
+        case 4: hipLaunchKernelGGL(k_verify_tiles<4>, g, b, 0, st, a); break;
+        case 8: hipLaunchKernelGGL(k_verify_tiles<8>, g, b, 0, st, a); break;
+        case 16: hipLaunchKernelGGL(k_verify_tiles<16>, g, b, 0, st, a); break;
+        case 32: hipLaunchKernelGGL(k_verify_tiles<32>, g, b, 0, st, a); break;
+        case 64: hipLaunchKernelGGL(k_verify_tiles<64>, g, b, 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_classify(const VerifyArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_classify, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_verify_bucketed(const VerifyArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_verify_bucketed, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
+hipError_t launch_verify_deferred(const LaunchArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_verify_deferred, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 

@@ -1,17 +1,23 @@
-// Host runtime of libssj: the C ABI, the HBM collection store, scratch and
-// launch management, and the streaming request loop.
+// Host runtime of libssj: the C ABI, the HBM collection store, device scratch
+// and launch management (plans, batching, graph replay, autotuning) and the
+// streaming request loop.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <ctime>
 #include <deque>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -28,33 +34,20 @@ int set_error(int code, const std::string& msg) {
 }
 
 uint64_t now_ns() {
-    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
-               std::chrono::steady_clock::now().time_since_epoch())
-        .count();
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
 }
 
 constexpr uint64_t kDefaultBudget = 4ull << 30;
-constexpr int64_t kMaxChunk = (int64_t)1 << 30;  // pairs per launch (< 2^31)
-constexpr size_t kBytesPerPairBucketed = 8 + 8 + 4 * ssj::kClasses;
+constexpr int64_t kMaxLaunchPairs = ((int64_t)1 << 31) - 1;  // pairs per launch
+// device bytes per candidate pair of a request: the pair, a worst-case output
+// pair, and its deferred-class queue entries
+constexpr size_t kBytesPerPair = 8 + 8 + 4 * ssj::kClasses;
 
 bool valid_threshold(int64_t t_num, int64_t t_den) {
     return t_den > 0 && t_den <= INT32_MAX && t_num >= 0 && t_num <= t_den;
 }
-
-// Device scratch of one in-flight request.
-struct Slot {
-    hipStream_t stream = nullptr;
-    ssj::Counters* d_ctr = nullptr;
-    long long* d_count = nullptr;
-    long long* h_count = nullptr;  // pinned
-    uint32_t* d_queues = nullptr;
-    size_t q_cap = 0;
-    int2* d_cand = nullptr;
-    size_t cand_cap = 0;
-    int2* d_out = nullptr;
-    size_t out_cap = 0;
-    hipEvent_t ev_done = nullptr;
-};
 
 template <class T>
 hipError_t grow(T*& p, size_t& cap, size_t need) {
@@ -79,6 +72,28 @@ hipError_t grow(T*& p, size_t& cap, size_t need) {
     return hipSuccess;
 }
 
+// Device scratch of one launch in flight: counters and deferred queues.
+struct Scratch {
+    ssj::Counters* d_ctr = nullptr;
+    uint32_t* d_queues = nullptr;
+    size_t q_cap = 0;  // entries (kClasses x per-class capacity)
+};
+
+struct GraphKey {
+    int inline_lanes, defer_from, grid1, grid2;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(inline_lanes, defer_from, grid1, grid2) <
+               std::tie(o.inline_lanes, o.defer_from, o.grid1, o.grid2);
+    }
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t nodes[2] = {nullptr, nullptr};
+    int n_nodes = 0;
+};
+
 }  // namespace
 
 struct ssj_coll {
@@ -88,8 +103,10 @@ struct ssj_coll {
     int64_t n_sets = 0;
     int64_t n_tokens = 0;
     int64_t max_len = 0;
-    std::atomic<int> inflight{0};
+    mutable std::atomic<int> inflight{0};  // stream requests not yet finished
 };
+
+struct StreamEngine;
 
 struct ssj_ctx {
     int device = 0;
@@ -97,14 +114,31 @@ struct ssj_ctx {
     int n_slots = 4;
     int queue_depth = 64;
     int n_cu = 0;
-    int grid_bucketed = 0;
-    int grid_classify = 0;
-    int occ_direct[9] = {0};
+    int occ_tiles[6] = {0};
+    int occ_deferred = 0;
     ssj_plan plan{};
-    std::mutex mu;  // default slot, collections, plan
-    Slot def;
+    std::mutex mu;  // default scratch, host staging, collections, plan, graphs
+    hipStream_t stream = nullptr;  // the context's own stream (host-buffer calls)
+    Scratch def;
+    // host-buffer verify staging
+    int2* d_cand = nullptr;
+    size_t cand_cap = 0;
+    int2* d_out = nullptr;
+    size_t out_cap = 0;
+    long long* d_count = nullptr;
+    long long* h_count = nullptr;  // pinned
     std::atomic<bool> failed{false};
     std::vector<ssj_coll*> colls;
+    std::map<GraphKey, GraphEntry> graphs;
+    hipStream_t capture_stream = nullptr;
+    // kernel timing (ssj_timing_*)
+    bool timing = false;
+    std::mutex tmu;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::array<hipEvent_t, 3>> ev_pending;
+    double t_inorder_ms = 0.0, t_deferred_ms = 0.0;
+    int64_t t_launches = 0;
+    std::unique_ptr<StreamEngine> engine;
 };
 
 namespace {
@@ -128,88 +162,185 @@ int lanes_index(int lanes) {
         case 16: return 3;
         case 32: return 4;
         case 64: return 5;
-        case ssj::kBlock: return 6;
         default: return -1;
     }
 }
 
-int slot_init(ssj_ctx* ctx, Slot& s, bool own_stream) {
-    if (own_stream) HIP_OR_FAIL(ctx, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+int scratch_init(ssj_ctx* ctx, Scratch& s) {
     HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_ctr, sizeof(ssj::Counters)));
     HIP_OR_FAIL(ctx, hipMemset(s.d_ctr, 0, sizeof(ssj::Counters)));
-    HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_count, sizeof(long long)));
-    HIP_OR_FAIL(ctx, hipHostMalloc((void**)&s.h_count, sizeof(long long), hipHostMallocDefault));
-    HIP_OR_FAIL(ctx, hipEventCreateWithFlags(&s.ev_done, hipEventDisableTiming));
+    HIP_OR_FAIL(ctx, hipDeviceSynchronize());
     return SSJ_OK;
 }
 
-void slot_free(Slot& s) {
-    if (s.stream) (void)hipStreamSynchronize(s.stream);
+void scratch_free(Scratch& s) {
     if (s.d_ctr) (void)hipFree(s.d_ctr);
-    if (s.d_count) (void)hipFree(s.d_count);
-    if (s.h_count) (void)hipHostFree(s.h_count);
     if (s.d_queues) (void)hipFree(s.d_queues);
-    if (s.d_cand) (void)hipFree(s.d_cand);
-    if (s.d_out) (void)hipFree(s.d_out);
-    if (s.ev_done) (void)hipEventDestroy(s.ev_done);
-    if (s.stream) (void)hipStreamDestroy(s.stream);
-    s = Slot{};
+    s = Scratch{};
 }
 
 void default_plan(ssj_plan& p) {
-    p.mode = SSJ_MODE_BUCKETED;
-    const int lanes[ssj::kClasses] = {1, 16, 64, ssj::kBlock, ssj::kBlock};
+    p.inline_lanes = 4;
+    p.defer_from = 3;
+    const int lanes[ssj::kClasses] = {4, 16, 64, ssj::kBlock, ssj::kBlock};
     for (int q = 0; q < ssj::kClasses; ++q) p.lanes[q] = lanes[q];
     p.use_graph = 0;
 }
 
-int grid_direct(const ssj_ctx* ctx, int lanes, int64_t n) {
-    const int idx = lanes_index(lanes);
-    const int64_t cap = (int64_t)ctx->n_cu * std::max(1, ctx->occ_direct[idx]);
-    int64_t want;
-    if (lanes == ssj::kBlock) {
-        want = n;
-    } else {
-        const int64_t pairs_per_block = (int64_t)ssj::kBlock / lanes;
-        want = (n + pairs_per_block - 1) / pairs_per_block;
-    }
-    return (int)std::max<int64_t>(1, std::min(want, cap));
+bool plan_valid(const ssj_plan& p) {
+    if (!ssj::inline_lanes_supported(p.inline_lanes)) return false;
+    if (p.defer_from < 0 || p.defer_from > ssj::kClasses) return false;
+    for (int q = 0; q < ssj::kClasses; ++q)
+        if (!ssj::lanes_supported(p.lanes[q])) return false;
+    return true;
 }
 
-// Enqueues one verification of n pairs already on the device.
-int enqueue_verify(ssj_ctx* ctx, const ssj_coll* coll, Slot& slot, const int2* d_cand, int64_t n,
-                   int64_t t_num, int64_t t_den, int2* d_out, int64_t out_cap,
-                   long long* d_count, hipStream_t st, const ssj_plan& plan) {
-    ssj::VerifyArgs a{};
+hipEvent_t timing_event(ssj_ctx* ctx) {
+    std::lock_guard<std::mutex> g(ctx->tmu);
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// One request of a launch, host side.
+struct Req {
+    const int2* d_cand;
+    int64_t n;
+    int64_t t_num, t_den;
+    int2* d_out;
+    int64_t out_cap;
+    long long* d_count;
+};
+
+int check_req(const Req& r) {
+    if (!valid_threshold(r.t_num, r.t_den))
+        return set_error(SSJ_EINVAL, "threshold must satisfy 0 <= t_num <= t_den, 0 < t_den < 2^31");
+    if (r.n < 0) return set_error(SSJ_EINVAL, "negative candidate count");
+    if (r.out_cap < 0) return set_error(SSJ_EINVAL, "negative output capacity");
+    if (!r.d_count || (r.n > 0 && !r.d_cand)) return set_error(SSJ_EINVAL, "null device buffer");
+    return SSJ_OK;
+}
+
+int grid_tiles(const ssj_ctx* ctx, int lanes, int64_t n_tiles) {
+    const int64_t cap = (int64_t)ctx->n_cu * std::max(1, ctx->occ_tiles[lanes_index(lanes)]);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, cap));
+}
+
+int grid_deferred(const ssj_ctx* ctx) { return ctx->n_cu * std::max(1, ctx->occ_deferred); }
+
+int launch_graph(ssj_ctx* ctx, const ssj::LaunchArgs& a, int g1, int g2, bool two,
+                 hipStream_t st) {
+    GraphKey key{a.inline_lanes, a.defer_from, g1, two ? g2 : 0};
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        GraphEntry ge;
+        if (!ctx->capture_stream)
+            HIP_OR_FAIL(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        HIP_OR_FAIL(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = ssj::launch_verify_tiles(a, g1, ctx->capture_stream);
+        hipError_t e2 = two ? ssj::launch_verify_deferred(a, g2, ctx->capture_stream) : hipSuccess;
+        hipError_t e3 = hipStreamEndCapture(ctx->capture_stream, &ge.graph);
+        if (e1 != hipSuccess) return hip_fail(ctx, "capture in-order kernel", e1);
+        if (e2 != hipSuccess) return hip_fail(ctx, "capture deferred kernel", e2);
+        if (e3 != hipSuccess) return hip_fail(ctx, "hipStreamEndCapture", e3);
+        size_t n = 0;
+        HIP_OR_FAIL(ctx, hipGraphGetNodes(ge.graph, nullptr, &n));
+        if (n != (size_t)(two ? 2 : 1)) return hip_fail(ctx, "captured graph shape", hipErrorUnknown);
+        HIP_OR_FAIL(ctx, hipGraphGetNodes(ge.graph, ge.nodes, &n));
+        ge.n_nodes = (int)n;
+        if (two) {
+            // order the nodes: the root is the in-order kernel
+            size_t deps = 0;
+            HIP_OR_FAIL(ctx, hipGraphNodeGetDependencies(ge.nodes[0], nullptr, &deps));
+            if (deps != 0) std::swap(ge.nodes[0], ge.nodes[1]);
+        }
+        HIP_OR_FAIL(ctx, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
+        it = ctx->graphs.emplace(key, ge).first;
+    }
+    GraphEntry& ge = it->second;
+    ssj::LaunchArgs args = a;
+    void* params[] = {&args};
+    for (int k = 0; k < ge.n_nodes; ++k) {
+        hipKernelNodeParams p{};
+        HIP_OR_FAIL(ctx, hipGraphKernelNodeGetParams(ge.nodes[k], &p));
+        p.kernelParams = params;
+        p.extra = nullptr;
+        HIP_OR_FAIL(ctx, hipGraphExecKernelNodeSetParams(ge.exec, ge.nodes[k], &p));
+    }
+    HIP_OR_FAIL(ctx, hipGraphLaunch(ge.exec, st));
+    return SSJ_OK;
+}
+
+// Enqueues one launch verifying up to kMaxReq requests already on the device.
+int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* reqs, int n_req,
+                   hipStream_t st, const ssj_plan& plan, bool allow_graph = true) {
+    ssj::LaunchArgs a{};
     a.tok = coll->d_tok;
     a.desc = coll->d_desc;
+    a.ctr = sc.d_ctr;
     a.n_sets = (uint32_t)coll->n_sets;
-    a.n = (uint32_t)n;
-    a.cand = d_cand;
-    a.tn = (unsigned long long)t_num;
-    a.tsum = (unsigned long long)(t_num + t_den);
-    a.out = d_out;
-    a.cap = (unsigned long long)std::max<int64_t>(0, out_cap);
-    a.ctr = slot.d_ctr;
-    a.d_count = d_count;
+    a.n_req = n_req;
+    a.defer_from = plan.defer_from;
+    a.inline_lanes = plan.inline_lanes;
     const uint32_t bounds[ssj::kClasses] = SSJ_CLASS_BOUNDS;
     for (int q = 0; q < ssj::kClasses; ++q) {
         a.bounds[q] = bounds[q];
         a.lanes[q] = plan.lanes[q];
-        a.order[q] = ssj::kClasses - 1 - q;  // longest class first
     }
-    if (plan.mode == SSJ_MODE_DIRECT) {
-        HIP_OR_FAIL(ctx, ssj::launch_verify_direct(a, plan.lanes[0],
-                                                   grid_direct(ctx, plan.lanes[0], n), st));
-        return SSJ_OK;
+    uint64_t tiles = 0, pairs = 0;
+    for (int r = 0; r < n_req; ++r) {
+        const Req& q = reqs[r];
+        a.tile_off[r] = (uint32_t)tiles;
+        a.pair_off[r] = (uint32_t)pairs;
+        ssj::Request& R = a.req[r];
+        R.cand = q.d_cand;
+        R.out = q.d_out;
+        R.d_count = q.d_count;
+        R.cap = (unsigned long long)q.out_cap;
+        R.tn = (unsigned long long)q.t_num;
+        R.tsum = (unsigned long long)(q.t_num + q.t_den);
+        R.n = (uint32_t)q.n;
+        tiles += ((uint64_t)q.n + ssj::kTile - 1) / ssj::kTile;
+        pairs += (uint64_t)q.n;
     }
-    HIP_OR_FAIL(ctx, grow(slot.d_queues, slot.q_cap, (size_t)ssj::kClasses * (size_t)std::max<int64_t>(n, 1)));
-    a.queues = slot.d_queues;
-    a.qcap = (uint32_t)(slot.q_cap / ssj::kClasses);
-    const int64_t want_c = (n + ssj::kBlock - 1) / ssj::kBlock;
-    const int gc = (int)std::max<int64_t>(1, std::min<int64_t>(want_c, ctx->grid_classify));
-    HIP_OR_FAIL(ctx, ssj::launch_classify(a, gc, st));
-    HIP_OR_FAIL(ctx, ssj::launch_verify_bucketed(a, ctx->grid_bucketed, st));
+    a.tile_off[n_req] = (uint32_t)tiles;
+    a.pair_off[n_req] = (uint32_t)pairs;
+    const bool two = plan.defer_from < ssj::kClasses;
+    if (two) {
+        HIP_OR_FAIL(ctx, grow(sc.d_queues, sc.q_cap, (size_t)ssj::kClasses * std::max<uint64_t>(pairs, 1)));
+    }
+    a.queues = sc.d_queues;
+    a.qcap = (uint32_t)(sc.q_cap / ssj::kClasses);
+    const int g1 = grid_tiles(ctx, plan.inline_lanes, (int64_t)tiles);
+    const int g2 = grid_deferred(ctx);
+
+    std::array<hipEvent_t, 3> ev{nullptr, nullptr, nullptr};
+    const bool timing = ctx->timing;
+    if (timing) {
+        for (auto& e : ev) {
+            e = timing_event(ctx);
+            if (!e) return hip_fail(ctx, "hipEventCreate", hipErrorOutOfMemory);
+        }
+        HIP_OR_FAIL(ctx, hipEventRecord(ev[0], st));
+    }
+    if (plan.use_graph && allow_graph && !timing) {
+        int rc = launch_graph(ctx, a, g1, g2, two, st);
+        if (rc != SSJ_OK) return rc;
+    } else {
+        HIP_OR_FAIL(ctx, ssj::launch_verify_tiles(a, g1, st));
+        if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ev[1], st));
+        if (two) HIP_OR_FAIL(ctx, ssj::launch_verify_deferred(a, g2, st));
+    }
+    if (timing) {
+        HIP_OR_FAIL(ctx, hipEventRecord(ev[2], st));
+        std::lock_guard<std::mutex> g(ctx->tmu);
+        ctx->ev_pending.push_back(ev);
+    }
     return SSJ_OK;
 }
 
@@ -219,14 +350,312 @@ int check_ctx(ssj_ctx* ctx) {
     return SSJ_OK;
 }
 
-int check_verify_args(const ssj_coll* coll, int64_t n_cand, int64_t t_num, int64_t t_den,
-                      int64_t out_cap) {
+int check_coll(ssj_ctx* ctx, const ssj_coll* coll) {
     if (!coll) return set_error(SSJ_EINVAL, "null collection");
-    if (!valid_threshold(t_num, t_den))
-        return set_error(SSJ_EINVAL, "threshold must satisfy 0 <= t_num <= t_den, 0 < t_den < 2^31");
-    if (n_cand < 0) return set_error(SSJ_EINVAL, "negative candidate count");
-    if (out_cap < 0) return set_error(SSJ_EINVAL, "negative output capacity");
+    if (coll->ctx != ctx) return set_error(SSJ_EINVAL, "collection does not belong to this context");
     return SSJ_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Streaming: requests are copied to pinned staging at submit; an engine
+// thread admits batches of them into free slots (each slot owns device
+// buffers sized from the HBM budget and its own stream), one launch per
+// batch, and collects the results.
+struct StreamReq {
+    uint64_t ticket = 0;
+    const ssj_coll* coll = nullptr;
+    int64_t t_num = 0, t_den = 1;
+    int64_t n = 0;
+    int2* h_cand = nullptr;       // pinned copy of the candidates
+    size_t h_cand_bytes = 0;
+    // a request is verified in parts (it may be split across slots and launches);
+    // it is finished when every candidate was admitted and every admitted part
+    // has completed
+    int64_t parts_admitted = 0, parts_done = 0, next_part_off = 0;
+    bool finished = false;
+    std::vector<int2> result;
+    int status = SSJ_PENDING;    // SSJ_PENDING until every part is done
+    bool bad_id = false;         // a part reported an id out of range
+    bool failed = false;         // a part hit a device failure
+    uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+struct SlotPart {
+    StreamReq* req;
+    int64_t off, n;         // range of the request's candidates
+    int64_t dev_off;        // offset in the slot's device buffers
+};
+
+struct StreamSlot {
+    hipStream_t stream = nullptr;
+    Scratch sc;
+    int2* d_cand = nullptr;
+    int2* d_out = nullptr;
+    long long* d_count = nullptr;
+    long long* h_count = nullptr;    // pinned, kMaxReq entries
+    int2* h_out = nullptr;           // pinned, cap pairs
+    int64_t cap = 0;                 // pairs
+    hipEvent_t ev = nullptr;
+    int state = 0;                   // 0 idle, 1 running, 2 reading results, 3 results on host
+    std::vector<SlotPart> parts;
+    const ssj_coll* coll = nullptr;
+};
+
+struct StreamEngine {
+    ssj_ctx* ctx = nullptr;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_space, cv_done;
+    std::deque<StreamReq*> pending;     // not fully admitted
+    std::unordered_map<uint64_t, StreamReq*> table;
+    std::vector<StreamSlot> slots;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+    // pinned staging pool by size class (powers of two)
+    std::map<size_t, std::vector<void*>> pool;
+};
+
+namespace {
+
+void* pinned_get(StreamEngine* E, size_t bytes, size_t* got) {
+    size_t cls = 4096;
+    while (cls < bytes) cls <<= 1;
+    auto& v = E->pool[cls];
+    *got = cls;
+    if (!v.empty()) {
+        void* p = v.back();
+        v.pop_back();
+        return p;
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
+    return p;
+}
+
+void pinned_put(StreamEngine* E, void* p, size_t cls) {
+    if (p) E->pool[cls].push_back(p);
+}
+
+// Called with E->mu held after a part of r completed (or r was abandoned).
+void maybe_finish(StreamEngine* E, StreamReq* r) {
+    if (r->finished || r->next_part_off < r->n || r->parts_done < r->parts_admitted) return;
+    r->finished = true;
+    r->status = r->failed ? SSJ_EDEVICE : (r->bad_id ? SSJ_EINVAL : SSJ_OK);
+    r->t_done = now_ns();
+    pinned_put(E, r->h_cand, r->h_cand_bytes);
+    r->h_cand = nullptr;
+    r->coll->inflight.fetch_sub(1);
+}
+
+void fail_slot(StreamEngine* E, StreamSlot& s) {
+    E->ctx->failed = true;
+    for (auto& p : s.parts) {
+        p.req->failed = true;
+        ++p.req->parts_done;
+        maybe_finish(E, p.req);
+    }
+    s.parts.clear();
+    s.state = 0;
+    E->cv_done.notify_all();
+}
+
+// Called with E->mu held.  Fills idle slot s with parts of pending requests
+// and enqueues their copies, one launch, and the count read-back.
+bool admit(StreamEngine* E, StreamSlot& s) {
+    ssj_ctx* ctx = E->ctx;
+    s.parts.clear();
+    if (E->pending.empty()) return true;
+    s.coll = E->pending.front()->coll;
+    int64_t used = 0;
+    while (!E->pending.empty() && (int)s.parts.size() < ssj::kMaxReq) {
+        StreamReq* r = E->pending.front();
+        if (r->coll != s.coll) break;  // one collection per launch
+        const int64_t left = r->n - r->next_part_off;
+        const int64_t take = std::min(left, s.cap - used);
+        if (take <= 0 && left > 0) break;
+        if (r->t_admit == 0) r->t_admit = now_ns();
+        s.parts.push_back(SlotPart{r, r->next_part_off, take, used});
+        r->parts_admitted += 1;
+        r->next_part_off += take;
+        used += take;
+        if (r->next_part_off >= r->n) E->pending.pop_front();
+        if (used >= s.cap) break;
+    }
+    E->cv_space.notify_all();
+    std::vector<Req> reqs;
+    for (auto& p : s.parts) {
+        if (p.n > 0 &&
+            hipMemcpyAsync(s.d_cand + p.dev_off, p.req->h_cand + p.off, (size_t)p.n * 8,
+                           hipMemcpyHostToDevice, s.stream) != hipSuccess)
+            return false;
+        reqs.push_back(Req{s.d_cand + p.dev_off, p.n, p.req->t_num, p.req->t_den,
+                           s.d_out + p.dev_off, p.n, s.d_count + reqs.size()});
+    }
+    ssj_plan plan;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        plan = ctx->plan;
+    }
+    if (enqueue_launch(ctx, s.coll, s.sc, reqs.data(), (int)reqs.size(), s.stream, plan, false) != SSJ_OK)
+        return false;
+    if (hipMemcpyAsync(s.h_count, s.d_count, sizeof(long long) * reqs.size(), hipMemcpyDeviceToHost,
+                       s.stream) != hipSuccess)
+        return false;
+    if (hipEventRecord(s.ev, s.stream) != hipSuccess) return false;
+    s.state = 1;
+    return true;
+}
+
+// Called with E->mu held; slot state 1 and its event complete: copy back the
+// passing pairs (their number is now known).
+bool read_counts(StreamSlot& s) {
+    bool any = false;
+    for (size_t k = 0; k < s.parts.size(); ++k) {
+        const long long c = s.h_count[k];
+        if (c > 0) {
+            if (hipMemcpyAsync(s.h_out + s.parts[k].dev_off, s.d_out + s.parts[k].dev_off,
+                               (size_t)c * 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
+                return false;
+            any = true;
+        }
+    }
+    if (any) {
+        if (hipEventRecord(s.ev, s.stream) != hipSuccess) return false;
+        s.state = 2;
+    } else {
+        s.state = 3;
+    }
+    return true;
+}
+
+// Called with E->mu held; results of the slot are on the host.
+void complete_slot(StreamEngine* E, StreamSlot& s) {
+    for (size_t k = 0; k < s.parts.size(); ++k) {
+        SlotPart& p = s.parts[k];
+        StreamReq* r = p.req;
+        const long long c = s.h_count[k];
+        if (c < 0) {
+            r->bad_id = true;
+        } else if (c > 0) {
+            r->result.insert(r->result.end(), s.h_out + p.dev_off, s.h_out + p.dev_off + c);
+        }
+        ++r->parts_done;
+        maybe_finish(E, r);
+    }
+    s.parts.clear();
+    s.state = 0;
+    E->cv_done.notify_all();
+}
+
+void engine_loop(StreamEngine* E) {
+    (void)hipSetDevice(E->ctx->device);
+    std::unique_lock<std::mutex> lk(E->mu);
+    for (;;) {
+        bool busy = false;
+        for (auto& s : E->slots) {
+            if (s.state == 1 || s.state == 2) {
+                busy = true;
+                const hipError_t q = hipEventQuery(s.ev);
+                if (q == hipSuccess) {
+                    if (s.state == 1) {
+                        if (!read_counts(s)) fail_slot(E, s);
+                    } else {
+                        s.state = 3;
+                    }
+                } else if (q != hipErrorNotReady) {
+                    fail_slot(E, s);
+                }
+            }
+            if (s.state == 3) complete_slot(E, s);
+            if (s.state == 0 && !E->pending.empty() && !E->ctx->failed) {
+                if (!admit(E, s)) {
+                    fail_slot(E, s);
+                } else if (s.state == 1) {
+                    busy = true;
+                }
+            }
+        }
+        if (E->ctx->failed) {
+            // nothing more can run: fail whatever waits
+            while (!E->pending.empty()) {
+                StreamReq* r = E->pending.front();
+                E->pending.pop_front();
+                r->failed = true;
+                // the rest is never admitted; parts in flight finish in their slot
+                r->next_part_off = r->n;
+                maybe_finish(E, r);
+            }
+            E->cv_done.notify_all();
+            E->cv_space.notify_all();
+        }
+        if (E->stop && !busy && E->pending.empty()) break;
+        if (busy) {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        } else {
+            E->cv_work.wait_for(lk, std::chrono::milliseconds(50));
+        }
+    }
+}
+
+int engine_start(ssj_ctx* ctx) {
+    auto E = std::make_unique<StreamEngine>();
+    E->ctx = ctx;
+    E->slots.resize((size_t)ctx->n_slots);
+    const int64_t cap = std::max<int64_t>(
+        1024, (int64_t)(ctx->budget / ((uint64_t)ctx->n_slots * kBytesPerPair)));
+    for (auto& s : E->slots) {
+        s.cap = std::min<int64_t>(cap, kMaxLaunchPairs);
+        HIP_OR_FAIL(ctx, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+        int rc = scratch_init(ctx, s.sc);
+        if (rc != SSJ_OK) return rc;
+        HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_cand, (size_t)s.cap * 8));
+        HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_out, (size_t)s.cap * 8));
+        HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_count, sizeof(long long) * ssj::kMaxReq));
+        HIP_OR_FAIL(ctx, hipHostMalloc((void**)&s.h_count, sizeof(long long) * ssj::kMaxReq, hipHostMallocDefault));
+        HIP_OR_FAIL(ctx, hipHostMalloc((void**)&s.h_out, (size_t)s.cap * 8, hipHostMallocDefault));
+        HIP_OR_FAIL(ctx, hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+        size_t qc = 0;
+        HIP_OR_FAIL(ctx, grow(s.sc.d_queues, qc, (size_t)ssj::kClasses * (size_t)s.cap));
+        s.sc.q_cap = qc;
+    }
+    StreamEngine* raw = E.get();
+    ctx->engine = std::move(E);
+    raw->worker = std::thread(engine_loop, raw);
+    return SSJ_OK;
+}
+
+void engine_stop(ssj_ctx* ctx) {
+    StreamEngine* E = ctx->engine.get();
+    if (!E) return;
+    {
+        std::lock_guard<std::mutex> g(E->mu);
+        E->stop = true;
+    }
+    E->cv_work.notify_all();
+    E->cv_space.notify_all();
+    if (E->worker.joinable()) E->worker.join();
+    for (auto& s : E->slots) {
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
+        scratch_free(s.sc);
+        if (s.d_cand) (void)hipFree(s.d_cand);
+        if (s.d_out) (void)hipFree(s.d_out);
+        if (s.d_count) (void)hipFree(s.d_count);
+        if (s.h_count) (void)hipHostFree(s.h_count);
+        if (s.h_out) (void)hipHostFree(s.h_out);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
+    }
+    for (auto& kv : E->table) {
+        if (kv.second->h_cand) (void)hipHostFree(kv.second->h_cand);
+        delete kv.second;
+    }
+    for (auto& kv : E->pool)
+        for (void* p : kv.second) (void)hipHostFree(p);
+    ctx->engine.reset();
 }
 
 }  // namespace
@@ -259,26 +688,30 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
         hipDeviceProp_t prop;
         if ((e = hipGetDeviceProperties(&prop, ctx->device)) != hipSuccess) { rc = hip_fail(ctx, "hipGetDeviceProperties", e); break; }
         ctx->n_cu = prop.multiProcessorCount;
+        const int lanes_list[6] = {1, 4, 8, 16, 32, 64};
+        for (int k = 0; k < 6 && rc == SSJ_OK; ++k) {
+            int occ = 0;
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_tiles(lanes_list[k]), ssj::kBlock, 0)) != hipSuccess)
+                rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
+            ctx->occ_tiles[k] = occ;
+        }
+        if (rc != SSJ_OK) break;
         int occ = 0;
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_bucketed(), ssj::kBlock, 0)) != hipSuccess) {
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_deferred(), ssj::kBlock, 0)) != hipSuccess) {
             rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
             break;
         }
-        ctx->grid_bucketed = ctx->n_cu * std::max(1, occ);
-        ctx->grid_classify = ctx->n_cu * 8;
-        const int lanes_list[7] = {1, 4, 8, 16, 32, 64, ssj::kBlock};
-        for (int k = 0; k < 7 && rc == SSJ_OK; ++k) {
-            occ = 0;
-            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_direct(lanes_list[k]), ssj::kBlock, 0)) != hipSuccess)
-                rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
-            ctx->occ_direct[k] = occ;
-        }
-        if (rc != SSJ_OK) break;
-        rc = slot_init(ctx, ctx->def, true);
+        ctx->occ_deferred = occ;
+        if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) { rc = hip_fail(ctx, "hipStreamCreate", e); break; }
+        if ((rc = scratch_init(ctx, ctx->def)) != SSJ_OK) break;
+        if ((e = hipMalloc((void**)&ctx->d_count, sizeof(long long))) != hipSuccess) { rc = hip_fail(ctx, "hipMalloc", e); break; }
+        if ((e = hipHostMalloc((void**)&ctx->h_count, sizeof(long long), hipHostMallocDefault)) != hipSuccess) { rc = hip_fail(ctx, "hipHostMalloc", e); break; }
+        rc = engine_start(ctx);
     } while (0);
     if (rc != SSJ_OK) {
-        slot_free(ctx->def);
-        delete ctx;
+        const std::string msg = tl_error;
+        ssj_shutdown(ctx);
+        tl_error = msg;
         return rc;
     }
     *out = ctx;
@@ -288,16 +721,32 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
 int ssj_shutdown(ssj_ctx* ctx) {
     if (!ctx) return SSJ_OK;
     (void)hipSetDevice(ctx->device);
+    engine_stop(ctx);
     {
         std::lock_guard<std::mutex> g(ctx->mu);
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
         for (ssj_coll* c : ctx->colls) {
             if (c->d_tok) (void)hipFree(c->d_tok);
             if (c->d_desc) (void)hipFree(c->d_desc);
             delete c;
         }
         ctx->colls.clear();
-        slot_free(ctx->def);
+        scratch_free(ctx->def);
+        if (ctx->d_cand) (void)hipFree(ctx->d_cand);
+        if (ctx->d_out) (void)hipFree(ctx->d_out);
+        if (ctx->d_count) (void)hipFree(ctx->d_count);
+        if (ctx->h_count) (void)hipHostFree(ctx->h_count);
+        for (auto& kv : ctx->graphs) {
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+            if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+        }
+        ctx->graphs.clear();
+        if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+        if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     }
+    for (auto& ev : ctx->ev_pending)
+        for (auto e : ev) (void)hipEventDestroy(e);
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
     return SSJ_OK;
 }
@@ -344,10 +793,10 @@ int ssj_upload_collection(ssj_ctx* ctx, const int64_t* offsets, int64_t n_sets,
         if ((e = hipMalloc((void**)&c->d_tok, (size_t)std::max<int64_t>(n_tokens, 1) * 4)) != hipSuccess) break;
         if ((e = hipMalloc((void**)&c->d_desc, (size_t)std::max<int64_t>(n_sets, 1) * 8)) != hipSuccess) break;
         if ((e = hipMalloc((void**)&d_off, (size_t)(n_sets + 1) * 8)) != hipSuccess) break;
-        if (n_tokens > 0 && (e = hipMemcpyAsync(c->d_tok, tokens, (size_t)n_tokens * 4, hipMemcpyHostToDevice, ctx->def.stream)) != hipSuccess) break;
-        if ((e = hipMemcpyAsync(d_off, offsets, (size_t)(n_sets + 1) * 8, hipMemcpyHostToDevice, ctx->def.stream)) != hipSuccess) break;
-        if ((e = ssj::launch_build_desc(d_off, c->d_desc, n_sets, ctx->def.stream)) != hipSuccess) break;
-        if ((e = hipStreamSynchronize(ctx->def.stream)) != hipSuccess) break;
+        if (n_tokens > 0 && (e = hipMemcpyAsync(c->d_tok, tokens, (size_t)n_tokens * 4, hipMemcpyHostToDevice, ctx->stream)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(d_off, offsets, (size_t)(n_sets + 1) * 8, hipMemcpyHostToDevice, ctx->stream)) != hipSuccess) break;
+        if ((e = ssj::launch_build_desc(d_off, c->d_desc, n_sets, ctx->stream)) != hipSuccess) break;
+        if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) break;
     } while (0);
     if (d_off) (void)hipFree(d_off);
     if (e != hipSuccess) {
@@ -365,14 +814,14 @@ int ssj_upload_collection(ssj_ctx* ctx, const int64_t* offsets, int64_t n_sets,
 int ssj_free_collection(ssj_ctx* ctx, ssj_coll* coll) {
     int rc = check_ctx(ctx);
     if (rc != SSJ_OK) return rc;
-    if (!coll || coll->ctx != ctx) return set_error(SSJ_EINVAL, "collection does not belong to this context");
+    if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
     if (coll->inflight.load() != 0) return set_error(SSJ_EAGAIN, "collection has requests in flight");
     std::lock_guard<std::mutex> g(ctx->mu);
     auto it = std::find(ctx->colls.begin(), ctx->colls.end(), coll);
     if (it == ctx->colls.end()) return set_error(SSJ_EINVAL, "unknown collection");
     ctx->colls.erase(it);
     (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->def.stream);
+    (void)hipDeviceSynchronize();
     if (coll->d_tok) (void)hipFree(coll->d_tok);
     if (coll->d_desc) (void)hipFree(coll->d_desc);
     delete coll;
@@ -396,14 +845,67 @@ int ssj_get_plan(ssj_ctx* ctx, ssj_plan* plan) {
 
 int ssj_set_plan(ssj_ctx* ctx, const ssj_plan* plan) {
     if (!ctx || !plan) return set_error(SSJ_EINVAL, "null argument");
-    if (plan->mode != SSJ_MODE_BUCKETED && plan->mode != SSJ_MODE_DIRECT)
-        return set_error(SSJ_EINVAL, "unknown plan mode");
-    for (int q = 0; q < ssj::kClasses; ++q)
-        if (!ssj::lanes_supported(plan->lanes[q]))
-            return set_error(SSJ_EINVAL, "lanes must be one of 1, 4, 8, 16, 32, 64, 256");
+    if (!plan_valid(*plan))
+        return set_error(SSJ_EINVAL, "inline_lanes must be 1, 4, 8, 16, 32 or 64; defer_from in "
+                                     "[0, 5]; lanes 1, 4, 8, 16, 32, 64 or 256");
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->plan = *plan;
     return SSJ_OK;
+}
+
+int ssj_timing_enable(ssj_ctx* ctx, int enable) {
+    if (!ctx) return set_error(SSJ_EINVAL, "null context");
+    ctx->timing = enable != 0;
+    return SSJ_OK;
+}
+
+int ssj_timing_read(ssj_ctx* ctx, int reset, double* inorder_ms, double* deferred_ms,
+                    int64_t* launches) {
+    int rc = check_ctx(ctx);
+    if (rc != SSJ_OK) return rc;
+    std::lock_guard<std::mutex> g(ctx->tmu);
+    for (auto& ev : ctx->ev_pending) {
+        HIP_OR_FAIL(ctx, hipEventSynchronize(ev[2]));
+        float a = 0.f, b = 0.f;
+        HIP_OR_FAIL(ctx, hipEventElapsedTime(&a, ev[0], ev[1]));
+        HIP_OR_FAIL(ctx, hipEventElapsedTime(&b, ev[1], ev[2]));
+        ctx->t_inorder_ms += a;
+        ctx->t_deferred_ms += b;
+        ctx->t_launches += 1;
+        for (auto e : ev) ctx->ev_pool.push_back(e);
+    }
+    ctx->ev_pending.clear();
+    if (inorder_ms) *inorder_ms = ctx->t_inorder_ms;
+    if (deferred_ms) *deferred_ms = ctx->t_deferred_ms;
+    if (launches) *launches = ctx->t_launches;
+    if (reset) {
+        ctx->t_inorder_ms = ctx->t_deferred_ms = 0.0;
+        ctx->t_launches = 0;
+    }
+    return SSJ_OK;
+}
+
+int ssj_verify_batch_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_request* reqs,
+                            int n_reqs, void* hip_stream) {
+    int rc = check_ctx(ctx);
+    if (rc != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
+    if (n_reqs < 0 || n_reqs > ssj::kMaxReq || (n_reqs > 0 && !reqs))
+        return set_error(SSJ_EINVAL, "n_reqs must be in [0, SSJ_MAX_BATCH]");
+    std::vector<Req> v((size_t)n_reqs);
+    int64_t total = 0;
+    for (int i = 0; i < n_reqs; ++i) {
+        v[i] = Req{reinterpret_cast<const int2*>(reqs[i].d_cand), reqs[i].n_cand, reqs[i].t_num,
+                   reqs[i].t_den, reinterpret_cast<int2*>(reqs[i].d_out), reqs[i].out_cap,
+                   reinterpret_cast<long long*>(reqs[i].d_count)};
+        if ((rc = check_req(v[i])) != SSJ_OK) return rc;
+        total += v[i].n;
+        if (total > kMaxLaunchPairs) return set_error(SSJ_EINVAL, "a batch must hold fewer than 2^31 pairs");
+    }
+    if (n_reqs == 0) return SSJ_OK;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    return enqueue_launch(ctx, coll, ctx->def, v.data(), n_reqs, (hipStream_t)hip_stream, ctx->plan);
 }
 
 int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
@@ -411,53 +913,56 @@ int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand
                       int64_t* d_count, void* hip_stream) {
     int rc = check_ctx(ctx);
     if (rc != SSJ_OK) return rc;
-    if ((rc = check_verify_args(coll, n_cand, t_num, t_den, out_cap)) != SSJ_OK) return rc;
-    if (coll->ctx != ctx) return set_error(SSJ_EINVAL, "collection does not belong to this context");
-    if (n_cand >= INT32_MAX) return set_error(SSJ_EINVAL, "n_cand must be below 2^31 per device call");
-    if (!d_count || (n_cand > 0 && !d_cand)) return set_error(SSJ_EINVAL, "null device buffer");
+    if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
+    Req r{reinterpret_cast<const int2*>(d_cand), n_cand, t_num, t_den, reinterpret_cast<int2*>(d_out),
+          out_cap, reinterpret_cast<long long*>(d_count)};
+    if ((rc = check_req(r)) != SSJ_OK) return rc;
+    if (n_cand > kMaxLaunchPairs) return set_error(SSJ_EINVAL, "n_cand must be below 2^31 per device call");
     std::lock_guard<std::mutex> g(ctx->mu);
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
-    return enqueue_verify(ctx, coll, ctx->def, reinterpret_cast<const int2*>(d_cand), n_cand, t_num,
-                          t_den, reinterpret_cast<int2*>(d_out), out_cap,
-                          reinterpret_cast<long long*>(d_count), (hipStream_t)hip_stream, ctx->plan);
+    return enqueue_launch(ctx, coll, ctx->def, &r, 1, (hipStream_t)hip_stream, ctx->plan);
 }
 
 int ssj_verify(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
                int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap, int64_t* out_n) {
     int rc = check_ctx(ctx);
     if (rc != SSJ_OK) return rc;
-    if ((rc = check_verify_args(coll, n_cand, t_num, t_den, out_cap)) != SSJ_OK) return rc;
-    if (coll->ctx != ctx) return set_error(SSJ_EINVAL, "collection does not belong to this context");
+    if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
+    if (!valid_threshold(t_num, t_den))
+        return set_error(SSJ_EINVAL, "threshold must satisfy 0 <= t_num <= t_den, 0 < t_den < 2^31");
+    if (n_cand < 0 || out_cap < 0) return set_error(SSJ_EINVAL, "negative size");
     if (!out_n || (n_cand > 0 && !cand) || (out_cap > 0 && !out))
         return set_error(SSJ_EINVAL, "null host buffer");
     *out_n = 0;
     std::lock_guard<std::mutex> g(ctx->mu);
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
-    Slot& s = ctx->def;
-    int64_t chunk = (int64_t)std::max<uint64_t>(1, ctx->budget / kBytesPerPairBucketed);
-    chunk = std::min<int64_t>(chunk, kMaxChunk);
-    int64_t total = 0;
+    hipStream_t st = ctx->stream;
+    int64_t chunk = (int64_t)std::max<uint64_t>(1, ctx->budget / kBytesPerPair);
+    chunk = std::min<int64_t>(chunk, kMaxLaunchPairs);
+    int64_t total = 0, done = 0;
     bool bad_id = false;
-    int64_t done = 0;
     do {
         const int64_t n = std::min<int64_t>(chunk, n_cand - done);
-        HIP_OR_FAIL(ctx, grow(s.d_cand, s.cand_cap, (size_t)std::max<int64_t>(n, 1)));
-        HIP_OR_FAIL(ctx, grow(s.d_out, s.out_cap, (size_t)std::max<int64_t>(n, 1)));
+        HIP_OR_FAIL(ctx, grow(ctx->d_cand, ctx->cand_cap, (size_t)std::max<int64_t>(n, 1)));
+        HIP_OR_FAIL(ctx, grow(ctx->d_out, ctx->out_cap, (size_t)std::max<int64_t>(n, 1)));
         if (n > 0)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(s.d_cand, cand + done, (size_t)n * 8, hipMemcpyHostToDevice, s.stream));
-        rc = enqueue_verify(ctx, coll, s, s.d_cand, n, t_num, t_den, s.d_out, n, s.d_count, s.stream, ctx->plan);
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->d_cand, cand + done, (size_t)n * 8, hipMemcpyHostToDevice, st));
+        Req r{ctx->d_cand, n, t_num, t_den, ctx->d_out, n, ctx->d_count};
+        rc = enqueue_launch(ctx, coll, ctx->def, &r, 1, st, ctx->plan);
         if (rc != SSJ_OK) return rc;
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(s.h_count, s.d_count, sizeof(long long), hipMemcpyDeviceToHost, s.stream));
-        HIP_OR_FAIL(ctx, hipStreamSynchronize(s.stream));
-        const long long k = *s.h_count;
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, ctx->d_count, sizeof(long long), hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+        const long long k = *ctx->h_count;
         if (k < 0) {
             bad_id = true;
             break;
         }
         const int64_t room = std::max<int64_t>(0, out_cap - total);
         const int64_t take = std::min<int64_t>(room, k);
-        if (take > 0)
-            HIP_OR_FAIL(ctx, hipMemcpy(out + total, s.d_out, (size_t)take * 8, hipMemcpyDeviceToHost));
+        if (take > 0) {
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(out + total, ctx->d_out, (size_t)take * 8, hipMemcpyDeviceToHost, st));
+            HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+        }
         total += k;
         done += n;
     } while (done < n_cand);
@@ -470,20 +975,180 @@ int ssj_verify(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t
     return SSJ_OK;
 }
 
-int ssj_stream_submit(ssj_ctx* ctx, const ssj_coll*, const ssj_pair*, int64_t, int64_t, int64_t,
-                      int, uint64_t* ticket) {
-    if (ticket) *ticket = 0;
-    (void)ctx;
-    return set_error(SSJ_EINVAL, "streaming is not available in this build");
+int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
+                 int64_t t_num, int64_t t_den, int apply, ssj_plan* best, double* best_ms) {
+    int rc = check_ctx(ctx);
+    if (rc != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
+    if (!valid_threshold(t_num, t_den)) return set_error(SSJ_EINVAL, "bad threshold");
+    if (n_cand <= 0 || n_cand > kMaxLaunchPairs || !d_cand)
+        return set_error(SSJ_EINVAL, "autotuning needs 1 .. 2^31-1 device candidates");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    HIP_OR_FAIL(ctx, grow(ctx->d_out, ctx->out_cap, (size_t)n_cand));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OR_FAIL(ctx, hipEventCreate(&e0));
+    HIP_OR_FAIL(ctx, hipEventCreate(&e1));
+    const bool timing_was = ctx->timing;
+    ctx->timing = false;
+    auto measure = [&](const ssj_plan& p, double* ms) -> int {
+        Req r{reinterpret_cast<const int2*>(d_cand), n_cand, t_num, t_den, ctx->d_out, n_cand,
+              ctx->d_count};
+        int rc2 = enqueue_launch(ctx, coll, ctx->def, &r, 1, st, p, false);  // warm-up
+        if (rc2 != SSJ_OK) return rc2;
+        double bestt = 1e30;
+        for (int it = 0; it < 3; ++it) {
+            HIP_OR_FAIL(ctx, hipEventRecord(e0, st));
+            rc2 = enqueue_launch(ctx, coll, ctx->def, &r, 1, st, p, false);
+            if (rc2 != SSJ_OK) return rc2;
+            HIP_OR_FAIL(ctx, hipEventRecord(e1, st));
+            HIP_OR_FAIL(ctx, hipEventSynchronize(e1));
+            float t = 0.f;
+            HIP_OR_FAIL(ctx, hipEventElapsedTime(&t, e0, e1));
+            bestt = std::min(bestt, (double)t);
+        }
+        *ms = bestt;
+        return SSJ_OK;
+    };
+    ssj_plan cur = ctx->plan;
+    cur.defer_from = ssj::kClasses;
+    double cur_ms = 1e30;
+    // 1) the in-order mapping, nothing deferred
+    for (int L : {1, 4, 8, 16, 32}) {
+        ssj_plan p = cur;
+        p.inline_lanes = L;
+        double ms = 0;
+        if ((rc = measure(p, &ms)) != SSJ_OK) break;
+        if (ms < cur_ms) {
+            cur_ms = ms;
+            cur = p;
+        }
+    }
+    // 2) defer the longer classes, one more class at a time (longest first),
+    //    each with the mappings suited to its lengths
+    static const int options[ssj::kClasses][3] = {
+        {4, 8, 16}, {8, 16, 32}, {16, 32, 64}, {64, 256, 32}, {256, 64, 32}};
+    for (int q = ssj::kClasses - 1; q >= 1 && rc == SSJ_OK; --q) {
+        const ssj_plan base = cur;
+        bool improved = false;
+        for (int k = 0; k < 3 && rc == SSJ_OK; ++k) {
+            ssj_plan p = base;
+            p.defer_from = q;
+            p.lanes[q] = options[q][k];
+            double ms = 0;
+            if ((rc = measure(p, &ms)) != SSJ_OK) break;
+            if (ms < cur_ms * 0.98) {
+                cur_ms = ms;
+                cur = p;
+                improved = true;
+            }
+        }
+        if (!improved) break;
+    }
+    ctx->timing = timing_was;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SSJ_OK) return rc;
+    if (best) *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    if (apply) ctx->plan = cur;
+    return SSJ_OK;
 }
 
-int ssj_stream_poll(ssj_ctx*, uint64_t, int, ssj_pair*, int64_t, int64_t* out_n) {
+int ssj_stream_submit(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
+                      int64_t t_num, int64_t t_den, int nonblocking, uint64_t* ticket) {
+    int rc = check_ctx(ctx);
+    if (rc != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
+    if (!ticket) return set_error(SSJ_EINVAL, "null ticket pointer");
+    *ticket = 0;
+    if (!valid_threshold(t_num, t_den))
+        return set_error(SSJ_EINVAL, "threshold must satisfy 0 <= t_num <= t_den, 0 < t_den < 2^31");
+    if (n_cand < 0 || (n_cand > 0 && !cand)) return set_error(SSJ_EINVAL, "bad candidate buffer");
+    StreamEngine* E = ctx->engine.get();
+    if (!E) return set_error(SSJ_EINVAL, "streaming engine not running");
+    std::unique_lock<std::mutex> lk(E->mu);
+    auto room = [&]() { return (int)E->pending.size() < ctx->queue_depth; };
+    if (!room()) {
+        if (nonblocking) return set_error(SSJ_EAGAIN, "stream queue full");
+        E->cv_space.wait(lk, [&]() { return room() || E->stop || ctx->failed.load(); });
+        if (E->stop) return set_error(SSJ_EINVAL, "context is shutting down");
+        if (ctx->failed) return set_error(SSJ_EDEVICE, "context failed after a HIP error");
+    }
+    StreamReq* r = new (std::nothrow) StreamReq();
+    if (!r) return set_error(SSJ_ENOMEM, "host allocation failed");
+    r->ticket = E->next_ticket++;
+    r->coll = coll;
+    r->t_num = t_num;
+    r->t_den = t_den;
+    r->n = n_cand;
+    r->t_submit = now_ns();
+    r->h_cand = (int2*)pinned_get(E, (size_t)std::max<int64_t>(n_cand, 1) * 8, &r->h_cand_bytes);
+    if (!r->h_cand) {
+        delete r;
+        return set_error(SSJ_ENOMEM, "pinned staging allocation failed");
+    }
+    // the copy into staging runs outside the lock; the request is not yet
+    // visible to the engine
+    lk.unlock();
+    if (n_cand > 0) std::memcpy(r->h_cand, cand, (size_t)n_cand * 8);
+    lk.lock();
+    coll->inflight.fetch_add(1);
+    E->table.emplace(r->ticket, r);
+    E->pending.push_back(r);
+    *ticket = r->ticket;
+    lk.unlock();
+    E->cv_work.notify_all();
+    return SSJ_OK;
+}
+
+int ssj_stream_poll(ssj_ctx* ctx, uint64_t ticket, int wait, ssj_pair* out, int64_t out_cap,
+                    int64_t* out_n) {
+    if (!ctx) return set_error(SSJ_EINVAL, "null context");
     if (out_n) *out_n = 0;
-    return set_error(SSJ_ENOTFOUND, "streaming is not available in this build");
+    StreamEngine* E = ctx->engine.get();
+    if (!E) return set_error(SSJ_EINVAL, "streaming engine not running");
+    std::unique_lock<std::mutex> lk(E->mu);
+    auto it = E->table.find(ticket);
+    if (it == E->table.end()) return set_error(SSJ_ENOTFOUND, "unknown or retired ticket");
+    StreamReq* r = it->second;
+    if (r->status == SSJ_PENDING) {
+        if (!wait) return SSJ_PENDING;
+        E->cv_done.wait(lk, [&]() { return r->status != SSJ_PENDING; });
+    }
+    if (r->status == SSJ_EINVAL || r->status == SSJ_EDEVICE) {
+        const int st = r->status;
+        E->table.erase(it);
+        delete r;
+        return set_error(st, st == SSJ_EINVAL ? "candidate id out of range" : "device failure");
+    }
+    const int64_t k = (int64_t)r->result.size();
+    if (out_n) *out_n = k;
+    if (k > out_cap) return set_error(SSJ_ETRUNC, "result larger than out_cap");
+    if (k > 0) {
+        if (!out) return set_error(SSJ_EINVAL, "null output buffer");
+        std::memcpy(out, r->result.data(), (size_t)k * 8);
+    }
+    E->table.erase(it);
+    delete r;
+    return SSJ_OK;
 }
 
-int ssj_stream_times(ssj_ctx*, uint64_t, uint64_t*, uint64_t*, uint64_t*) {
-    return set_error(SSJ_ENOTFOUND, "streaming is not available in this build");
+int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, uint64_t* t_submit, uint64_t* t_admit,
+                     uint64_t* t_done) {
+    if (!ctx) return set_error(SSJ_EINVAL, "null context");
+    StreamEngine* E = ctx->engine.get();
+    if (!E) return set_error(SSJ_EINVAL, "streaming engine not running");
+    std::lock_guard<std::mutex> lk(E->mu);
+    auto it = E->table.find(ticket);
+    if (it == E->table.end()) return set_error(SSJ_ENOTFOUND, "unknown or retired ticket");
+    StreamReq* r = it->second;
+    if (r->status == SSJ_PENDING) return SSJ_PENDING;
+    if (t_submit) *t_submit = r->t_submit;
+    if (t_admit) *t_admit = r->t_admit;
+    if (t_done) *t_done = r->t_done;
+    return SSJ_OK;
 }
 
 }  // extern "C"

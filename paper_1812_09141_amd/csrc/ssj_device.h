@@ -9,52 +9,66 @@ namespace ssj {
 constexpr int kClasses = 5;      // length classes of |r| + |s|
 constexpr int kBlock = 256;      // threads per workgroup of every verify kernel
 constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kTile = kBlock;    // pairs per workgroup iteration of the in-order kernel
+constexpr int kMaxReq = 16;      // requests per launch
+constexpr int kDeferCap = 512;   // LDS entries per deferred class and workgroup
 
-// Per-request device counters.  Every verify launch leaves them zeroed again
-// (the last workgroup to finish resets them), so a request never needs a
-// memset before it runs, also not inside a captured graph.
-struct alignas(256) Counters {
-    unsigned long long out_count;   // passing pairs appended so far
-    unsigned int err;               // != 0: an id was out of range
-    unsigned int done;              // workgroups finished (last-block detection)
-    unsigned int head[kClasses];    // work-stealing cursors per class queue
-    unsigned int tail[kClasses];    // entries per class queue (written by classify)
-    unsigned int pad[64 - 4 - 2 * kClasses];
-};
-
-// Everything one verification launch needs.
-struct VerifyArgs {
-    const int32_t* tok;        // collection tokens
-    const uint2* desc;         // {start, len} per set
-    uint32_t n_sets;
-    uint32_t n;                // candidate pairs
+// One verification request inside a launch.
+struct Request {
     const int2* cand;          // (r, s) pairs
+    int2* out;                 // passing pairs
+    long long* d_count;        // result count, -1 on an id error
+    unsigned long long cap;    // capacity of out in pairs
     unsigned long long tn;     // t_num
     unsigned long long tsum;   // t_num + t_den
-    int2* out;                 // passing pairs
-    unsigned long long cap;    // capacity of out in pairs
-    Counters* ctr;             // zeroed counters (left zeroed on exit)
-    long long* d_count;        // result count, -1 on an id error
-    uint32_t* queues;          // kClasses queues of qcap entries (bucketed mode)
-    uint32_t qcap;
-    uint32_t bounds[kClasses]; // inclusive upper bound of |r|+|s| per class
-    int lanes[kClasses];       // lanes per pair, per class
-    int order[kClasses];       // class processing order (heaviest first)
+    uint32_t n;                // pairs
+    uint32_t pad;
 };
 
-// Launch helpers (defined in kernels.hip).  All return hipSuccess or the
-// launch error.
+// Per-launch device counters.  Every launch leaves them zeroed again (the
+// last workgroup of the final kernel resets them), so no memset is needed
+// before a launch, also not inside a captured graph.
+struct alignas(256) Counters {
+    unsigned long long out_count[kMaxReq];  // passing pairs appended so far
+    unsigned int err[kMaxReq];              // != 0: an id was out of range
+    unsigned int head[kClasses];            // work-stealing cursors of deferred classes
+    unsigned int tail[kClasses];            // entries in each deferred-class queue
+    unsigned int done;                      // workgroups finished (last-block detection)
+    unsigned int pad[64 - kMaxReq - 2 * kClasses - 1];
+};
+
+// Everything one launch needs (passed by value as the kernel argument).
+struct LaunchArgs {
+    const int32_t* tok;                  // collection tokens
+    const uint2* desc;                   // {start, len} per set
+    Counters* ctr;
+    uint32_t* queues;                    // deferred-class queues, kClasses x qcap
+    uint32_t qcap;
+    uint32_t n_sets;
+    int n_req;
+    int defer_from;                      // first deferred class (kClasses: none)
+    int inline_lanes;                    // lanes per pair in the in-order kernel
+    uint32_t tile_off[kMaxReq + 1];      // prefix sums of per-request tiles
+    uint32_t pair_off[kMaxReq + 1];      // prefix sums of per-request pairs
+    uint32_t bounds[kClasses];           // inclusive upper bound of |r|+|s| per class
+    int lanes[kClasses];                 // lanes per pair of each deferred class
+    Request req[kMaxReq];
+};
+
+// Launch helpers (defined in kernels.hip).  Return hipSuccess or the launch
+// error.
 hipError_t launch_build_desc(const int64_t* d_offsets, uint2* d_desc, int64_t n_sets,
                              hipStream_t st);
-hipError_t launch_verify_direct(const VerifyArgs& a, int lanes, int grid, hipStream_t st);
-hipError_t launch_classify(const VerifyArgs& a, int grid, hipStream_t st);
-hipError_t launch_verify_bucketed(const VerifyArgs& a, int grid, hipStream_t st);
+// The in-order kernel: every pair of a class below defer_from is verified
+// with inline_lanes lanes; the others are queued for launch_verify_deferred.
+hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st);
+// Drains the deferred-class queues (needed only when defer_from < kClasses).
+hipError_t launch_verify_deferred(const LaunchArgs& a, int grid, hipStream_t st);
 
-// Kernel entry points, for occupancy queries and graph capture.
-const void* kernel_verify_bucketed();
-const void* kernel_verify_direct(int lanes);
-const void* kernel_classify();
+const void* kernel_verify_tiles(int lanes);
+const void* kernel_verify_deferred();
 
-bool lanes_supported(int lanes);
+bool lanes_supported(int lanes);         // deferred classes: 1..64 or kBlock
+bool inline_lanes_supported(int lanes);  // in-order kernel: 1..64
 
 }  // namespace ssj

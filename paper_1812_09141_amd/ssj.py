@@ -30,14 +30,14 @@ SSJ_ENOTFOUND = -6
 
 SSJ_N_CLASSES = 5
 SSJ_CLASS_BOUNDS = (32, 128, 512, 2048, 0x7FFFFFFF)
-SSJ_MODE_BUCKETED = 0
-SSJ_MODE_DIRECT = 1
+SSJ_MAX_BATCH = 16
 
 EXPORTED = (
     "ssj_init", "ssj_shutdown", "ssj_last_error", "ssj_upload_collection",
     "ssj_free_collection", "ssj_verify", "ssj_verify_device", "ssj_stream_submit",
     "ssj_stream_poll", "ssj_stream_times", "ssj_get_plan", "ssj_set_plan",
-    "ssj_collection_info",
+    "ssj_collection_info", "ssj_timing_enable", "ssj_timing_read", "ssj_verify_batch_device",
+    "ssj_autotune",
 )
 
 _NAMES = {
@@ -64,8 +64,19 @@ class ssj_opts(ctypes.Structure):
 
 
 class ssj_plan(ctypes.Structure):
-    _fields_ = [("mode", ctypes.c_int), ("lanes", ctypes.c_int * SSJ_N_CLASSES),
-                ("use_graph", ctypes.c_int)]
+    _fields_ = [("inline_lanes", ctypes.c_int), ("defer_from", ctypes.c_int),
+                ("lanes", ctypes.c_int * SSJ_N_CLASSES), ("use_graph", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"inline_lanes": self.inline_lanes, "defer_from": self.defer_from,
+                "lanes": list(self.lanes), "use_graph": self.use_graph}
+
+
+class ssj_request(ctypes.Structure):
+    _fields_ = [("d_cand", ctypes.c_void_p), ("n_cand", ctypes.c_int64),
+                ("t_num", ctypes.c_int64), ("t_den", ctypes.c_int64),
+                ("d_out", ctypes.c_void_p), ("out_cap", ctypes.c_int64),
+                ("d_count", ctypes.c_void_p)]
 
 
 _lib = None
@@ -95,6 +106,10 @@ def load_library(path: str = LIB_PATH):
         "ssj_get_plan": ([p, P(ssj_plan)], c_int),
         "ssj_set_plan": ([p, P(ssj_plan)], c_int),
         "ssj_collection_info": ([p, P(i64), P(i64), P(i64)], c_int),
+        "ssj_timing_enable": ([p, c_int], c_int),
+        "ssj_timing_read": ([p, c_int, P(ctypes.c_double), P(ctypes.c_double), P(i64)], c_int),
+        "ssj_verify_batch_device": ([p, p, P(ssj_request), c_int, p], c_int),
+        "ssj_autotune": ([p, p, p, i64, i64, i64, c_int, P(ssj_plan), P(ctypes.c_double)], c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -231,15 +246,69 @@ def ssj_get_plan(ctx) -> ssj_plan:
     return p
 
 
-def ssj_set_plan(ctx, mode: int, lanes, use_graph: int = 0) -> None:
+def make_plan(inline_lanes: int = 4, defer_from: int = SSJ_N_CLASSES, lanes=(4, 16, 64, 256, 256),
+              use_graph: int = 0) -> ssj_plan:
     p = ssj_plan()
-    p.mode = int(mode)
+    p.inline_lanes = int(inline_lanes)
+    p.defer_from = int(defer_from)
     for q in range(SSJ_N_CLASSES):
-        p.lanes[q] = int(lanes[q] if not isinstance(lanes, int) else lanes)
+        p.lanes[q] = int(lanes[q])
     p.use_graph = int(use_graph)
-    rc = load_library().ssj_set_plan(ctx, ctypes.byref(p))
+    return p
+
+
+def ssj_set_plan(ctx, plan: ssj_plan) -> None:
+    rc = load_library().ssj_set_plan(ctx, ctypes.byref(plan))
     if rc != SSJ_OK:
         _err(ctx, rc)
+
+
+def ssj_verify_batch_device(ctx, coll, requests, stream=None) -> None:
+    """requests: list of (d_cand, t_num, t_den, d_out, d_count) torch tensors/ints."""
+    n = len(requests)
+    arr = (ssj_request * max(n, 1))()
+    dev = None
+    for i, (d_cand, tn, td, d_out, d_count) in enumerate(requests):
+        assert d_cand.is_cuda and d_cand.dtype == torch.int32 and d_cand.is_contiguous()
+        assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
+        assert d_count.is_cuda and d_count.dtype == torch.int64
+        nc = d_cand.numel() // 2
+        arr[i] = ssj_request(d_cand.data_ptr() if nc else None, nc, int(tn), int(td),
+                             d_out.data_ptr() if d_out.numel() else None, d_out.numel() // 2,
+                             d_count.data_ptr())
+        dev = d_cand.device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    rc = load_library().ssj_verify_batch_device(ctx, coll, arr, n, ctypes.c_void_p(st.cuda_stream))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def ssj_autotune(ctx, coll, d_cand: "torch.Tensor", t_num: int, t_den: int, apply: bool = True):
+    """Best plan for the given device candidates and its kernel time (ms)."""
+    p = ssj_plan()
+    ms = ctypes.c_double()
+    n = d_cand.numel() // 2
+    rc = load_library().ssj_autotune(ctx, coll, d_cand.data_ptr(), n, int(t_num), int(t_den),
+                                     int(bool(apply)), ctypes.byref(p), ctypes.byref(ms))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+    return p, ms.value
+
+
+def ssj_timing_enable(ctx, enable: bool = True) -> None:
+    rc = load_library().ssj_timing_enable(ctx, int(bool(enable)))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def ssj_timing_read(ctx, reset: bool = False):
+    """(classify_ms, verify_ms, verify launches) summed since the last reset."""
+    a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    rc = load_library().ssj_timing_read(ctx, int(bool(reset)), ctypes.byref(a), ctypes.byref(b),
+                                        ctypes.byref(n))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+    return a.value, b.value, n.value
 
 
 def ssj_stream_collect(ctx, ticket: int):

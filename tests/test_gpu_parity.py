@@ -45,19 +45,24 @@ def ctx(S):
 
 
 def plans():
-    out = [("bucketed-default", None)]
+    """(name, plan kwargs) covering every mapping in both kernels."""
+    out = [("default", None)]
+    for L in [1, 4, 8, 16, 32, 64]:
+        out.append((f"inline-{L}", dict(inline_lanes=L, defer_from=5)))
     for L in ALL_LANES:
-        out.append((f"direct-{L}", (1, [L] * 5)))
-    for L in ALL_LANES:
-        out.append((f"bucketed-all-{L}", (0, [L] * 5)))
+        out.append((f"deferred-all-{L}", dict(inline_lanes=4, defer_from=0, lanes=[L] * 5)))
+    out.append(("mixed-1", dict(inline_lanes=1, defer_from=1, lanes=[4, 8, 32, 256, 256])))
+    out.append(("mixed-graph", dict(inline_lanes=8, defer_from=2, lanes=[4, 16, 16, 64, 256],
+                                    use_graph=1)))
+    out.append(("inline-graph", dict(inline_lanes=4, defer_from=5, use_graph=1)))
     return out
 
 
 def set_plan(S, ctx, plan):
     if plan is None:
-        S.ssj_set_plan(ctx, 0, [1, 16, 64, 256, 256])
+        S.ssj_set_plan(ctx, S.make_plan(inline_lanes=4, defer_from=3, lanes=[4, 16, 64, 256, 256]))
     else:
-        S.ssj_set_plan(ctx, plan[0], plan[1])
+        S.ssj_set_plan(ctx, S.make_plan(**plan))
 
 
 def run_host(S, ctx, h, cand, tn, td):
@@ -180,7 +185,7 @@ def test_config2_default_plan_matches_manifest(S, ctx, golden_dir):
         assert got.shape[0] == m["n_result"]
         assert oracle.result_digest(got) == m["result_sha256"]
         for L in [1, 16]:
-            S.ssj_set_plan(ctx, 1, [L] * 5)
+            S.ssj_set_plan(ctx, S.make_plan(inline_lanes=L, defer_from=5))
             assert oracle.result_digest(run_host(S, ctx, h, cand, tn, td)) == m["result_sha256"]
         set_plan(S, ctx, None)
     S.ssj_free_collection(ctx, h)
@@ -194,8 +199,10 @@ def test_config3_long_sets(S, ctx, golden_dir):
     (tn, td), = synth.WORKLOADS[3].thresholds
     cand = cfilter.workload_candidates(3, tn, td)
     m = man["thresholds"][f"{tn}/{td}"]
-    for name, plan in [("bucketed-default", None), ("direct-16", (1, [16] * 5)),
-                       ("direct-64", (1, [64] * 5)), ("bucketed-all-256", (0, [256] * 5))]:
+    for name, plan in [("default", None), ("inline-16", dict(inline_lanes=16, defer_from=5)),
+                       ("inline-64", dict(inline_lanes=64, defer_from=5)),
+                       ("deferred-all-256", dict(inline_lanes=4, defer_from=0, lanes=[256] * 5)),
+                       ("deferred-long", dict(inline_lanes=1, defer_from=2, lanes=[4, 8, 16, 64, 256]))]:
         _log(f"config3 {name}")
         set_plan(S, ctx, plan)
         got = run_host(S, ctx, h, cand, tn, td)
