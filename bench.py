@@ -41,19 +41,25 @@ def parse():
                     help="also time plain one-launch-per-batch verification")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work budget of the oracle baseline (0 disables it)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (5 times), "
+                         "the reference for HBM byte counters, and exit")
     return ap.parse_args()
 
 
 def plan_of(S, spec):
-    """auto | inline:L | defer:L,F,l0,l1,l2,l3,l4"""
+    """auto | inline:L[xU] | defer:L[xU],F,l0,l1,l2,l3,l4"""
     if spec == "auto":
         return None
     kind, _, rest = spec.partition(":")
-    vals = [int(v) for v in rest.split(",")] if rest else []
+    parts = rest.split(",") if rest else []
+    lanes, _, unroll = parts[0].partition("x")
+    L, U = int(lanes), int(unroll or 1)
+    vals = [int(v) for v in parts[1:]]
     if kind == "inline":
-        return S.make_plan(inline_lanes=vals[0], defer_from=5)
+        return S.make_plan(inline_lanes=L, inline_unroll=U, defer_from=5)
     if kind == "defer":
-        return S.make_plan(inline_lanes=vals[0], defer_from=vals[1], lanes=vals[2:7])
+        return S.make_plan(inline_lanes=L, inline_unroll=U, defer_from=vals[0], lanes=vals[1:6])
     raise SystemExit(f"unknown plan {spec!r}")
 
 
@@ -115,6 +121,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_mb:
+        n = args.copy_mb << 20
+        src = torch.ones(n // 4, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "repeats": 5}), flush=True)
+        return
 
     import paper_1812_09141_amd.ssj as S
     from ssj_inputs import filter as cfilter
@@ -208,6 +225,8 @@ def main():
     avg_in_ms = in_ms / launches
     avg_def_ms = def_ms / launches
     deferred = plan.defer_from < 5
+    # in-order kernel alone, or with the deferred-class kernel when one runs
+    # (avg_def_ms also holds the one-workgroup finalize kernel)
     avg_kernel_ms = avg_in_ms + (avg_def_ms if deferred else 0.0)
     achieved = per_launch_bytes / (avg_kernel_ms * 1e-3) / 1e9 if avg_kernel_ms > 0 else 0.0
     src_hash = kernel_source_hash()
@@ -269,7 +288,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": (f"k_verify_tiles<{plan.inline_lanes}>" +
+            "kernel": (f"k_verify_tiles<{plan.inline_lanes},{plan.inline_unroll}>" +
                        (" + k_verify_deferred" if deferred else "")),
             "achieved": round(achieved, 2),
             "peak": PEAK_HBM_GBS,

@@ -153,8 +153,9 @@ int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, uint64_t* t_submit, uint64_t
  * Execution plan.  Verification runs as one or two kernels per launch:
  *  1. an in-order kernel walks the candidates in tiles of consecutive pairs
  *     and verifies each pair with inline_lanes lanes (1 = one thread per
- *     pair, a sequential early-exit merge; 4..64 = a group of lanes of one
- *     wavefront per pair, intersecting tile by tile);
+ *     pair, a sequential early-exit merge, inline_unroll pairs per thread
+ *     advanced in lockstep; 4..64 = a group of lanes of one wavefront per
+ *     pair, intersecting tile by tile);
  *  2. pairs whose length class (by |r| + |s|, inclusive upper bounds
  *     SSJ_CLASS_BOUNDS) is defer_from or higher are not verified by (1) but
  *     queued per class; a persistent kernel then drains each class with
@@ -170,6 +171,7 @@ int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, uint64_t* t_submit, uint64_t
 
 typedef struct {
     int inline_lanes;            /* 1, 4, 8, 16, 32 or 64 */
+    int inline_unroll;           /* 1, 2 or 4 with inline_lanes == 1, else 1 */
     int defer_from;              /* 0 .. SSJ_N_CLASSES */
     int lanes[SSJ_N_CLASSES];    /* per deferred class: 1, 4, 8, 16, 32, 64 or 256 */
     int use_graph;

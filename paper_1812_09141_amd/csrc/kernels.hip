@@ -227,33 +227,6 @@ __device__ __forceinline__ int request_of_pair(uint32_t gi, const LaunchArgs& a)
     return r;
 }
 
-// The last workgroup to finish publishes each request's count (or -1 on an
-// id error) and returns the counters to zero for the next launch.
-__device__ void finalize(const LaunchArgs& a) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&a.ctr->done, 1u);
-        if (prev == gridDim.x - 1) {
-            __threadfence();
-            for (int r = 0; r < a.n_req; ++r) {
-                const unsigned long long cnt = atomicAdd(&a.ctr->out_count[r], 0ull);
-                const unsigned err = atomicOr(&a.ctr->err[r], 0u);
-                *a.req[r].d_count = err ? -1ll : (long long)cnt;
-                atomicExch(&a.ctr->out_count[r], 0ull);
-                atomicExch(&a.ctr->err[r], 0u);
-            }
-#pragma unroll
-            for (int q = 0; q < kClasses; ++q) {
-                atomicExch(&a.ctr->head[q], 0u);
-                atomicExch(&a.ctr->tail[q], 0u);
-            }
-            atomicExch(&a.ctr->done, 0u);
-            __threadfence();
-        }
-    }
-}
-
 template <int G>
 __device__ __forceinline__ bool verify_lanes(const LaunchArgs& a, uint2 dr, uint2 ds,
                                              uint32_t alpha, int g, int gbase) {
@@ -276,14 +249,120 @@ __device__ void flush_deferred(const LaunchArgs& a, int q, uint32_t c, const uin
     __syncthreads();
 }
 
+// Queues the pairs of the lanes with defer set into the workgroup's LDS
+// queue of their class (wavefront-aggregated LDS atomics).
+__device__ __forceinline__ void defer_wave(const LaunchArgs& a, bool defer, int cls, uint32_t gi,
+                                           uint32_t* s_defer, uint32_t* s_dcnt) {
+    const int lane = lane_id();
+    for (int q = a.defer_from; q < kClasses; ++q) {
+        const unsigned long long m = ballot(defer && cls == q);
+        if (m != 0ull) {
+            const int leader = __builtin_ctzll(m);
+            uint32_t pos = 0;
+            if (lane == leader) pos = atomicAdd(&s_dcnt[q], (uint32_t)__popcll(m));
+            pos = (uint32_t)bperm((int)pos, leader);
+            if (defer && cls == q)
+                s_defer[(uint32_t)(q - a.defer_from) * a.defer_cap + pos + mbcnt(m)] = gi;
+        }
+    }
+}
+
+// Thread-per-pair step of the in-order kernel for U pairs per lane: the
+// lane's pairs are wbase + u*64 + lane.  Their loads are issued together and
+// their merges advance in lockstep, so U independent chains of memory
+// accesses are in flight per lane.
+template <int U>
+__device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Request& R, int r,
+                                                  uint32_t wbase, bool deferring,
+                                                  uint32_t* s_defer, uint32_t* s_dcnt) {
+    const int lane = lane_id();
+    const int32_t* __restrict__ tok = a.tok;
+    int2 pr[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t k = wbase + (uint32_t)(u * kWave + lane);
+        const bool valid = k < R.n;
+        pr[u] = R.cand[valid ? k : R.n - 1];
+        ok[u] = valid && ids_ok(pr[u], a.n_sets);
+        if (valid && !ok[u]) atomicOr(&a.ctr->err[r], 1u);
+    }
+    uint2 dr[U], ds[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        dr[u] = a.desc[ok[u] ? pr[u].x : 0];
+        ds[u] = a.desc[ok[u] ? pr[u].y : 0];
+    }
+    uint32_t ia[U], ib[U], na[U], nb[U], alpha[U], i[U], j[U], o[U];
+    bool act[U], pass[U], defer[U];
+    int cls[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t L = dr[u].y + ds[u].y;
+        cls[u] = deferring ? class_of(L, a) : 0;
+        defer[u] = ok[u] && deferring && cls[u] >= a.defer_from;
+        act[u] = ok[u] && !defer[u];
+        pass[u] = false;
+        // inactive pairs keep a valid one-token range so that the lockstep
+        // loads below stay in bounds
+        ia[u] = act[u] ? dr[u].x : 0u;
+        ib[u] = act[u] ? ds[u].x : 0u;
+        na[u] = act[u] ? dr[u].y : 1u;
+        nb[u] = act[u] ? ds[u].y : 1u;
+        alpha[u] = act[u] ? required_overlap(L, R.tn, R.tsum) : 0u;
+        i[u] = j[u] = o[u] = 0;
+    }
+    for (;;) {
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (act[u]) {
+                if (o[u] >= alpha[u]) {
+                    pass[u] = true;
+                    act[u] = false;
+                } else if (o[u] + min(na[u] - i[u], nb[u] - j[u]) < alpha[u]) {
+                    act[u] = false;
+                }
+            }
+            any |= act[u];
+        }
+        if (!any) break;
+        int32_t x[U], y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            x[u] = tok[ia[u] + min(i[u], na[u] - 1)];
+            y[u] = tok[ib[u] + min(j[u], nb[u] - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (act[u]) {
+                i[u] += (x[u] <= y[u]);
+                j[u] += (y[u] <= x[u]);
+                o[u] += (x[u] == y[u]);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        append_wave(pass[u], pr[u], R.out, R.cap, &a.ctr->out_count[r]);
+        if (deferring)
+            defer_wave(a, defer[u], cls[u], a.pair_off[r] + wbase + (uint32_t)(u * kWave + lane),
+                       s_defer, s_dcnt);
+    }
+}
+
 // ---------------------------------------------------------------------------
-// In-order kernel.  Workgroup iteration = one tile of kTile consecutive pairs
-// of one request; wavefront w takes the tile's pairs w*64 .. w*64+63, as
-// 64/G pairs at a time when G lanes share a pair.
-template <int G>
+// In-order kernel.  Workgroup iteration = one tile of consecutive pairs of one
+// request.  G == 1: tile = kBlock * U pairs, wavefront w takes U runs of 64
+// pairs.  G > 1 (U == 1): tile = kBlock pairs, wavefront w takes the pairs
+// w*64 .. w*64+63, 64/G at a time.
+template <int G, int U>
 __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     constexpr int GPW = kWave / G;
-    __shared__ uint32_t s_defer[kClasses][kDeferCap];
+    constexpr uint32_t kTilePairs = (uint32_t)kBlock * U;
+    // per deferred class q >= defer_from: defer_cap LDS entries (dynamic LDS;
+    // none when nothing is deferred); defer_cap >= 2 * kTilePairs
+    extern __shared__ uint32_t s_defer[];
     __shared__ uint32_t s_dcnt[kClasses];
     __shared__ uint32_t s_base;
     const bool deferring = a.defer_from < kClasses;
@@ -297,51 +376,46 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
         int r = 0;
         while (r + 1 < a.n_req && a.tile_off[r + 1] <= T) ++r;
         const Request& R = a.req[r];
-        const uint32_t base = (T - a.tile_off[r]) * kTile + (uint32_t)w * kWave;
-        for (int sub = 0; sub < G; ++sub) {
-            const uint32_t k = base + (uint32_t)(sub * GPW + grp);
-            bool pass = false, defer = false;
-            int cls = 0;
-            int2 pr = make_int2(0, 0);
-            if (k < R.n) {
-                pr = R.cand[k];
-                if (ids_ok(pr, a.n_sets)) {
-                    const uint2 dr = a.desc[pr.x];
-                    const uint2 ds = a.desc[pr.y];
-                    const uint32_t L = dr.y + ds.y;
-                    if (deferring) {
-                        cls = class_of(L, a);
-                        defer = cls >= a.defer_from;
-                    }
-                    if (!defer)
-                        pass = verify_lanes<G>(a, dr, ds, required_overlap(L, R.tn, R.tsum), g, gbase);
-                } else if (g == 0) {
-                    atomicOr(&a.ctr->err[r], 1u);
-                }
-            }
-            append_wave(pass && g == 0, pr, R.out, R.cap, &a.ctr->out_count[r]);
-            if (deferring) {
-                const bool d0 = defer && g == 0;
-                for (int q = a.defer_from; q < kClasses; ++q) {
-                    const unsigned long long m = ballot(d0 && cls == q);
-                    if (m != 0ull) {
-                        const int leader = __builtin_ctzll(m);
-                        uint32_t pos = 0;
-                        if (lane == leader) pos = atomicAdd(&s_dcnt[q], (uint32_t)__popcll(m));
-                        pos = (uint32_t)bperm((int)pos, leader);
-                        if (d0 && cls == q) s_defer[q][pos + mbcnt(m)] = a.pair_off[r] + k;
+        const uint32_t wbase = (T - a.tile_off[r]) * kTilePairs + (uint32_t)w * kWave * U;
+        if constexpr (G == 1) {
+            tile_thread_pairs<U>(a, R, r, wbase, deferring, s_defer, s_dcnt);
+        } else {
+            for (int sub = 0; sub < G; ++sub) {
+                const uint32_t k = wbase + (uint32_t)(sub * GPW + grp);
+                bool pass = false, defer = false;
+                int cls = 0;
+                int2 pr = make_int2(0, 0);
+                if (k < R.n) {
+                    pr = R.cand[k];
+                    if (ids_ok(pr, a.n_sets)) {
+                        const uint2 dr = a.desc[pr.x];
+                        const uint2 ds = a.desc[pr.y];
+                        const uint32_t L = dr.y + ds.y;
+                        if (deferring) {
+                            cls = class_of(L, a);
+                            defer = cls >= a.defer_from;
+                        }
+                        if (!defer)
+                            pass = verify_lanes<G>(a, dr, ds, required_overlap(L, R.tn, R.tsum), g,
+                                                   gbase);
+                    } else if (g == 0) {
+                        atomicOr(&a.ctr->err[r], 1u);
                     }
                 }
+                append_wave(pass && g == 0, pr, R.out, R.cap, &a.ctr->out_count[r]);
+                if (deferring)
+                    defer_wave(a, defer && g == 0, cls, a.pair_off[r] + k, s_defer, s_dcnt);
             }
         }
         if (deferring) {
-            // at most kTile entries per class arrive per iteration, so a queue
-            // with room for fewer than kTile more is flushed now
+            // at most kTilePairs entries per class arrive per iteration, so a
+            // queue with room for fewer than that is flushed now
             __syncthreads();
             for (int q = a.defer_from; q < kClasses; ++q) {
                 const uint32_t c = s_dcnt[q];
-                if (c > (uint32_t)(kDeferCap - kTile)) {
-                    flush_deferred(a, q, c, s_defer[q], &s_base);
+                if (c > a.defer_cap - kTilePairs) {
+                    flush_deferred(a, q, c, s_defer + (uint32_t)(q - a.defer_from) * a.defer_cap,
+                                   &s_base);
                     if (threadIdx.x == 0) s_dcnt[q] = 0;
                     __syncthreads();
                 }
@@ -352,11 +426,28 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
         __syncthreads();
         for (int q = a.defer_from; q < kClasses; ++q) {
             const uint32_t c = s_dcnt[q];
-            if (c > 0) flush_deferred(a, q, c, s_defer[q], &s_base);
+            if (c > 0)
+                flush_deferred(a, q, c, s_defer + (uint32_t)(q - a.defer_from) * a.defer_cap, &s_base);
         }
-        return;  // the deferred-class kernel publishes the counts
     }
-    finalize(a);
+}
+
+// Publishes each request's count (-1 after an id error) and returns the
+// counters to zero for the next launch.  One workgroup, after the verify
+// kernels of the launch (the kernel boundary makes their atomics visible).
+__global__ void k_finalize(LaunchArgs a) {
+    const int t = (int)threadIdx.x;
+    if (t < a.n_req) {
+        const unsigned long long cnt = a.ctr->out_count[t];
+        const unsigned err = a.ctr->err[t];
+        *a.req[t].d_count = err ? -1ll : (long long)cnt;
+        a.ctr->out_count[t] = 0ull;
+        a.ctr->err[t] = 0u;
+    }
+    if (t < kClasses) {
+        a.ctr->head[t] = 0u;
+        a.ctr->tail[t] = 0u;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -428,7 +519,6 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
             default: break;
         }
     }
-    finalize(a);
 }
 
 __global__ void k_build_desc(const int64_t* __restrict__ off, uint2* __restrict__ desc,
@@ -449,16 +539,24 @@ bool lanes_supported(int lanes) {
     }
 }
 
-bool inline_lanes_supported(int lanes) { return lanes_supported(lanes) && lanes != kBlock; }
+bool inline_supported(int lanes, int unroll) { return kernel_verify_tiles(lanes, unroll) != nullptr; }
 
-const void* kernel_verify_tiles(int lanes) {
+const void* kernel_verify_tiles(int lanes, int unroll) {
+    if (lanes == 1) {
+        switch (unroll) {
+            case 1: return (const void*)&k_verify_tiles<1, 1>;
+            case 2: return (const void*)&k_verify_tiles<1, 2>;
+            case 4: return (const void*)&k_verify_tiles<1, 4>;
+            default: return nullptr;
+        }
+    }
+    if (unroll != 1) return nullptr;
     switch (lanes) {
-        case 1: return (const void*)&k_verify_tiles<1>;
-        case 4: return (const void*)&k_verify_tiles<4>;
-        case 8: return (const void*)&k_verify_tiles<8>;
-        case 16: return (const void*)&k_verify_tiles<16>;
-        case 32: return (const void*)&k_verify_tiles<32>;
-        case 64: return (const void*)&k_verify_tiles<64>;
+        case 4: return (const void*)&k_verify_tiles<4, 1>;
+        case 8: return (const void*)&k_verify_tiles<8, 1>;
+        case 16: return (const void*)&k_verify_tiles<16, 1>;
+        case 32: return (const void*)&k_verify_tiles<32, 1>;
+        case 64: return (const void*)&k_verify_tiles<64, 1>;
         default: return nullptr;
     }
 }
@@ -475,19 +573,24 @@ hipError_t launch_build_desc(const int64_t* d_offsets, uint2* d_desc, int64_t n_
     return hipGetLastError();
 }
 
+size_t tiles_lds_bytes(const LaunchArgs& a) {
+    return a.defer_from < kClasses ? (size_t)(kClasses - a.defer_from) * a.defer_cap * 4u : 0u;
+}
+
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st) {
-    const dim3 g((unsigned)grid), b(kBlock);
-    switch (a.inline_lanes) {
-        case 1: hipLaunchKernelGGL(k_verify_tiles<1>, g, b, 0, st, a); break;
-        case 4: hipLaunchKernelGGL(k_verify_tiles<4>, g, b, 0, st, a); break;
-        case 8: hipLaunchKernelGGL(k_verify_tiles<8>, g, b, 0, st, a); break;
-        case 16: hipLaunchKernelGGL(k_verify_tiles<16>, g, b, 0, st, a); break;
-        case 32: hipLaunchKernelGGL(k_verify_tiles<32>, g, b, 0, st, a); break;
-        case 64: hipLaunchKernelGGL(k_verify_tiles<64>, g, b, 0, st, a); break;
-        default: return hipErrorInvalidValue;
-    }
+    const void* f = kernel_verify_tiles(a.inline_lanes, a.inline_unroll);
+    if (!f) return hipErrorInvalidValue;
+    LaunchArgs args = a;
+    void* params[] = {&args};
+    return hipLaunchKernel(f, dim3((unsigned)grid), dim3(kBlock), params, tiles_lds_bytes(a), st);
+}
+
+hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kWave), 0, st, a);
     return hipGetLastError();
 }
+
+const void* kernel_finalize() { return (const void*)&k_finalize; }
 
 hipError_t launch_verify_deferred(const LaunchArgs& a, int grid, hipStream_t st) {
     hipLaunchKernelGGL(k_verify_deferred, dim3((unsigned)grid), dim3(kBlock), 0, st, a);

@@ -80,17 +80,20 @@ struct Scratch {
 };
 
 struct GraphKey {
-    int inline_lanes, defer_from, grid1, grid2;
+    int inline_lanes, inline_unroll, defer_from, grid1, grid2;
     bool operator<(const GraphKey& o) const {
-        return std::tie(inline_lanes, defer_from, grid1, grid2) <
-               std::tie(o.inline_lanes, o.defer_from, o.grid1, o.grid2);
+        return std::tie(inline_lanes, inline_unroll, defer_from, grid1, grid2) <
+               std::tie(o.inline_lanes, o.inline_unroll, o.defer_from, o.grid1, o.grid2);
     }
 };
 
+// A launch as a graph of kernel nodes (in-order, [deferred], finalize) whose
+// arguments are replaced before every replay.
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t nodes[2] = {nullptr, nullptr};
+    hipGraphNode_t nodes[3] = {nullptr, nullptr, nullptr};
+    hipKernelNodeParams params[3] = {};
     int n_nodes = 0;
 };
 
@@ -114,7 +117,7 @@ struct ssj_ctx {
     int n_slots = 4;
     int queue_depth = 64;
     int n_cu = 0;
-    int occ_tiles[6] = {0};
+    int occ_tiles[8] = {0};
     int occ_deferred = 0;
     ssj_plan plan{};
     std::mutex mu;  // default scratch, host staging, collections, plan, graphs
@@ -154,17 +157,21 @@ int hip_fail(ssj_ctx* ctx, const char* what, hipError_t e) {
         if (_e != hipSuccess) return hip_fail((ctx), #expr, _e); \
     } while (0)
 
-int lanes_index(int lanes) {
+// index of an in-order mapping in occ_tiles
+int inline_index(int lanes, int unroll) {
+    if (lanes == 1) return unroll == 1 ? 0 : (unroll == 2 ? 6 : 7);
     switch (lanes) {
-        case 1: return 0;
         case 4: return 1;
         case 8: return 2;
         case 16: return 3;
         case 32: return 4;
         case 64: return 5;
-        default: return -1;
+        default: return 0;
     }
 }
+
+const int kInlineLanes[8] = {1, 4, 8, 16, 32, 64, 1, 1};
+const int kInlineUnroll[8] = {1, 1, 1, 1, 1, 1, 2, 4};
 
 int scratch_init(ssj_ctx* ctx, Scratch& s) {
     HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_ctr, sizeof(ssj::Counters)));
@@ -180,7 +187,8 @@ void scratch_free(Scratch& s) {
 }
 
 void default_plan(ssj_plan& p) {
-    p.inline_lanes = 4;
+    p.inline_lanes = 1;
+    p.inline_unroll = 2;
     p.defer_from = 3;
     const int lanes[ssj::kClasses] = {4, 16, 64, ssj::kBlock, ssj::kBlock};
     for (int q = 0; q < ssj::kClasses; ++q) p.lanes[q] = lanes[q];
@@ -188,7 +196,7 @@ void default_plan(ssj_plan& p) {
 }
 
 bool plan_valid(const ssj_plan& p) {
-    if (!ssj::inline_lanes_supported(p.inline_lanes)) return false;
+    if (!ssj::inline_supported(p.inline_lanes, p.inline_unroll)) return false;
     if (p.defer_from < 0 || p.defer_from > ssj::kClasses) return false;
     for (int q = 0; q < ssj::kClasses; ++q)
         if (!ssj::lanes_supported(p.lanes[q])) return false;
@@ -226,8 +234,8 @@ int check_req(const Req& r) {
     return SSJ_OK;
 }
 
-int grid_tiles(const ssj_ctx* ctx, int lanes, int64_t n_tiles) {
-    const int64_t cap = (int64_t)ctx->n_cu * std::max(1, ctx->occ_tiles[lanes_index(lanes)]);
+int grid_tiles(const ssj_ctx* ctx, int lanes, int unroll, int64_t n_tiles) {
+    const int64_t cap = (int64_t)ctx->n_cu * std::max(1, ctx->occ_tiles[inline_index(lanes, unroll)]);
     return (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, cap));
 }
 
@@ -235,44 +243,43 @@ int grid_deferred(const ssj_ctx* ctx) { return ctx->n_cu * std::max(1, ctx->occ_
 
 int launch_graph(ssj_ctx* ctx, const ssj::LaunchArgs& a, int g1, int g2, bool two,
                  hipStream_t st) {
-    GraphKey key{a.inline_lanes, a.defer_from, g1, two ? g2 : 0};
+    GraphKey key{a.inline_lanes, a.inline_unroll, a.defer_from, g1, two ? g2 : 0};
+    ssj::LaunchArgs args = a;
+    void* kparams[] = {&args};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         GraphEntry ge;
-        if (!ctx->capture_stream)
-            HIP_OR_FAIL(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
-        HIP_OR_FAIL(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = ssj::launch_verify_tiles(a, g1, ctx->capture_stream);
-        hipError_t e2 = two ? ssj::launch_verify_deferred(a, g2, ctx->capture_stream) : hipSuccess;
-        hipError_t e3 = hipStreamEndCapture(ctx->capture_stream, &ge.graph);
-        if (e1 != hipSuccess) return hip_fail(ctx, "capture in-order kernel", e1);
-        if (e2 != hipSuccess) return hip_fail(ctx, "capture deferred kernel", e2);
-        if (e3 != hipSuccess) return hip_fail(ctx, "hipStreamEndCapture", e3);
-        size_t n = 0;
-        HIP_OR_FAIL(ctx, hipGraphGetNodes(ge.graph, nullptr, &n));
-        if (n != (size_t)(two ? 2 : 1)) return hip_fail(ctx, "captured graph shape", hipErrorUnknown);
-        HIP_OR_FAIL(ctx, hipGraphGetNodes(ge.graph, ge.nodes, &n));
-        ge.n_nodes = (int)n;
-        if (two) {
-            // order the nodes: the root is the in-order kernel
-            size_t deps = 0;
-            HIP_OR_FAIL(ctx, hipGraphNodeGetDependencies(ge.nodes[0], nullptr, &deps));
-            if (deps != 0) std::swap(ge.nodes[0], ge.nodes[1]);
+        HIP_OR_FAIL(ctx, hipGraphCreate(&ge.graph, 0));
+        const void* funcs[3] = {ssj::kernel_verify_tiles(a.inline_lanes, a.inline_unroll),
+                                ssj::kernel_verify_deferred(), ssj::kernel_finalize()};
+        const int grids[3] = {g1, g2, 1};
+        const int blocks[3] = {ssj::kBlock, ssj::kBlock, ssj::kWave};
+        for (int k = 0; k < 3; ++k) {
+            if (k == 1 && !two) continue;
+            hipKernelNodeParams p{};
+            p.func = const_cast<void*>(funcs[k]);
+            p.gridDim = dim3((unsigned)grids[k]);
+            p.blockDim = dim3((unsigned)blocks[k]);
+            p.sharedMemBytes = k == 0 ? (unsigned)ssj::tiles_lds_bytes(a) : 0u;
+            p.kernelParams = kparams;
+            p.extra = nullptr;
+            hipGraphNode_t dep = ge.n_nodes ? ge.nodes[ge.n_nodes - 1] : nullptr;
+            HIP_OR_FAIL(ctx, hipGraphAddKernelNode(&ge.nodes[ge.n_nodes], ge.graph, dep ? &dep : nullptr,
+                                                   dep ? 1 : 0, &p));
+            ge.params[ge.n_nodes] = p;
+            ++ge.n_nodes;
         }
         HIP_OR_FAIL(ctx, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
         it = ctx->graphs.emplace(key, ge).first;
+    } else {
+        GraphEntry& ge = it->second;
+        for (int k = 0; k < ge.n_nodes; ++k) {
+            hipKernelNodeParams p = ge.params[k];
+            p.kernelParams = kparams;
+            HIP_OR_FAIL(ctx, hipGraphExecKernelNodeSetParams(ge.exec, ge.nodes[k], &p));
+        }
     }
-    GraphEntry& ge = it->second;
-    ssj::LaunchArgs args = a;
-    void* params[] = {&args};
-    for (int k = 0; k < ge.n_nodes; ++k) {
-        hipKernelNodeParams p{};
-        HIP_OR_FAIL(ctx, hipGraphKernelNodeGetParams(ge.nodes[k], &p));
-        p.kernelParams = params;
-        p.extra = nullptr;
-        HIP_OR_FAIL(ctx, hipGraphExecKernelNodeSetParams(ge.exec, ge.nodes[k], &p));
-    }
-    HIP_OR_FAIL(ctx, hipGraphLaunch(ge.exec, st));
+    HIP_OR_FAIL(ctx, hipGraphLaunch(it->second.exec, st));
     return SSJ_OK;
 }
 
@@ -287,6 +294,9 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     a.n_req = n_req;
     a.defer_from = plan.defer_from;
     a.inline_lanes = plan.inline_lanes;
+    a.inline_unroll = plan.inline_unroll;
+    const uint64_t tile_pairs = (uint64_t)ssj::kBlock * (plan.inline_lanes == 1 ? plan.inline_unroll : 1);
+    a.defer_cap = (uint32_t)(2 * tile_pairs);
     const uint32_t bounds[ssj::kClasses] = SSJ_CLASS_BOUNDS;
     for (int q = 0; q < ssj::kClasses; ++q) {
         a.bounds[q] = bounds[q];
@@ -305,7 +315,7 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
         R.tn = (unsigned long long)q.t_num;
         R.tsum = (unsigned long long)(q.t_num + q.t_den);
         R.n = (uint32_t)q.n;
-        tiles += ((uint64_t)q.n + ssj::kTile - 1) / ssj::kTile;
+        tiles += ((uint64_t)q.n + tile_pairs - 1) / tile_pairs;
         pairs += (uint64_t)q.n;
     }
     a.tile_off[n_req] = (uint32_t)tiles;
@@ -316,7 +326,7 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     }
     a.queues = sc.d_queues;
     a.qcap = (uint32_t)(sc.q_cap / ssj::kClasses);
-    const int g1 = grid_tiles(ctx, plan.inline_lanes, (int64_t)tiles);
+    const int g1 = grid_tiles(ctx, plan.inline_lanes, plan.inline_unroll, (int64_t)tiles);
     const int g2 = grid_deferred(ctx);
 
     std::array<hipEvent_t, 3> ev{nullptr, nullptr, nullptr};
@@ -335,6 +345,7 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
         HIP_OR_FAIL(ctx, ssj::launch_verify_tiles(a, g1, st));
         if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ev[1], st));
         if (two) HIP_OR_FAIL(ctx, ssj::launch_verify_deferred(a, g2, st));
+        HIP_OR_FAIL(ctx, ssj::launch_finalize(a, st));
     }
     if (timing) {
         HIP_OR_FAIL(ctx, hipEventRecord(ev[2], st));
@@ -688,10 +699,9 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
         hipDeviceProp_t prop;
         if ((e = hipGetDeviceProperties(&prop, ctx->device)) != hipSuccess) { rc = hip_fail(ctx, "hipGetDeviceProperties", e); break; }
         ctx->n_cu = prop.multiProcessorCount;
-        const int lanes_list[6] = {1, 4, 8, 16, 32, 64};
-        for (int k = 0; k < 6 && rc == SSJ_OK; ++k) {
+        for (int k = 0; k < 8 && rc == SSJ_OK; ++k) {
             int occ = 0;
-            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_tiles(lanes_list[k]), ssj::kBlock, 0)) != hipSuccess)
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_tiles(kInlineLanes[k], kInlineUnroll[k]), ssj::kBlock, 0)) != hipSuccess)
                 rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
             ctx->occ_tiles[k] = occ;
         }
@@ -846,8 +856,9 @@ int ssj_get_plan(ssj_ctx* ctx, ssj_plan* plan) {
 int ssj_set_plan(ssj_ctx* ctx, const ssj_plan* plan) {
     if (!ctx || !plan) return set_error(SSJ_EINVAL, "null argument");
     if (!plan_valid(*plan))
-        return set_error(SSJ_EINVAL, "inline_lanes must be 1, 4, 8, 16, 32 or 64; defer_from in "
-                                     "[0, 5]; lanes 1, 4, 8, 16, 32, 64 or 256");
+        return set_error(SSJ_EINVAL, "inline_lanes must be 1, 4, 8, 16, 32 or 64 (inline_unroll "
+                                     "1, 2 or 4 with 1 lane, else 1); defer_from in [0, 5]; "
+                                     "lanes 1, 4, 8, 16, 32, 64 or 256");
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->plan = *plan;
     return SSJ_OK;
@@ -1015,9 +1026,10 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
     cur.defer_from = ssj::kClasses;
     double cur_ms = 1e30;
     // 1) the in-order mapping, nothing deferred
-    for (int L : {1, 4, 8, 16, 32}) {
+    for (int k : {0, 6, 7, 1, 2, 3, 4}) {
         ssj_plan p = cur;
-        p.inline_lanes = L;
+        p.inline_lanes = kInlineLanes[k];
+        p.inline_unroll = kInlineUnroll[k];
         double ms = 0;
         if ((rc = measure(p, &ms)) != SSJ_OK) break;
         if (ms < cur_ms) {

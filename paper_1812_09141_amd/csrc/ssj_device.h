@@ -9,9 +9,7 @@ namespace ssj {
 constexpr int kClasses = 5;      // length classes of |r| + |s|
 constexpr int kBlock = 256;      // threads per workgroup of every verify kernel
 constexpr int kWave = 64;        // CDNA wavefront width
-constexpr int kTile = kBlock;    // pairs per workgroup iteration of the in-order kernel
 constexpr int kMaxReq = 16;      // requests per launch
-constexpr int kDeferCap = 512;   // LDS entries per deferred class and workgroup
 
 // One verification request inside a launch.
 struct Request {
@@ -25,16 +23,15 @@ struct Request {
     uint32_t pad;
 };
 
-// Per-launch device counters.  Every launch leaves them zeroed again (the
-// last workgroup of the final kernel resets them), so no memset is needed
-// before a launch, also not inside a captured graph.
+// Per-launch device counters.  Every launch leaves them zeroed again (its
+// final one-workgroup kernel resets them), so no memset is needed before a
+// launch, also not inside a captured graph.
 struct alignas(256) Counters {
     unsigned long long out_count[kMaxReq];  // passing pairs appended so far
     unsigned int err[kMaxReq];              // != 0: an id was out of range
     unsigned int head[kClasses];            // work-stealing cursors of deferred classes
     unsigned int tail[kClasses];            // entries in each deferred-class queue
-    unsigned int done;                      // workgroups finished (last-block detection)
-    unsigned int pad[64 - kMaxReq - 2 * kClasses - 1];
+    unsigned int pad[64 - kMaxReq - 2 * kClasses];
 };
 
 // Everything one launch needs (passed by value as the kernel argument).
@@ -48,7 +45,9 @@ struct LaunchArgs {
     int n_req;
     int defer_from;                      // first deferred class (kClasses: none)
     int inline_lanes;                    // lanes per pair in the in-order kernel
-    uint32_t tile_off[kMaxReq + 1];      // prefix sums of per-request tiles
+    int inline_unroll;                   // pairs per lane at a time (inline_lanes == 1)
+    uint32_t defer_cap;                  // LDS queue entries per deferred class (>= 2 tiles)
+    uint32_t tile_off[kMaxReq + 1];      // prefix sums of per-request tiles (of tile_pairs)
     uint32_t pair_off[kMaxReq + 1];      // prefix sums of per-request pairs
     uint32_t bounds[kClasses];           // inclusive upper bound of |r|+|s| per class
     int lanes[kClasses];                 // lanes per pair of each deferred class
@@ -64,11 +63,16 @@ hipError_t launch_build_desc(const int64_t* d_offsets, uint2* d_desc, int64_t n_
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st);
 // Drains the deferred-class queues (needed only when defer_from < kClasses).
 hipError_t launch_verify_deferred(const LaunchArgs& a, int grid, hipStream_t st);
+// Dynamic LDS of the in-order kernel for a.defer_from / a.defer_cap.
+size_t tiles_lds_bytes(const LaunchArgs& a);
+// Publishes the request counts and resets the counters (always last).
+hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st);
 
-const void* kernel_verify_tiles(int lanes);
+const void* kernel_verify_tiles(int lanes, int unroll);
 const void* kernel_verify_deferred();
+const void* kernel_finalize();
 
-bool lanes_supported(int lanes);         // deferred classes: 1..64 or kBlock
-bool inline_lanes_supported(int lanes);  // in-order kernel: 1..64
+bool lanes_supported(int lanes);              // deferred classes: 1..64 or kBlock
+bool inline_supported(int lanes, int unroll);  // in-order kernel: 1..64; unroll 1,2,4 for 1 lane
 
 }  // namespace ssj
