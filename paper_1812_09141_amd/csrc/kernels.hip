@@ -62,6 +62,23 @@ __device__ __forceinline__ uint32_t mbcnt(unsigned long long m) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Set record: {start, len, first kHeadTokens tokens} in two 16-byte words.
+__device__ __forceinline__ uint2 set_desc(const LaunchArgs& a, int id) {
+    const uint4 v = a.heads[2 * id];
+    return make_uint2(v.x, v.y);
+}
+
+// Token i of a set whose record words are w0, w1 (i < kHeadTokens).
+__device__ __forceinline__ int32_t head_token(uint4 w0, uint4 w1, uint32_t i) {
+    int32_t v = (int32_t)w0.z;
+    v = (i == 1) ? (int32_t)w0.w : v;
+    v = (i == 2) ? (int32_t)w1.x : v;
+    v = (i == 3) ? (int32_t)w1.y : v;
+    v = (i == 4) ? (int32_t)w1.z : v;
+    v = (i == 5) ? (int32_t)w1.w : v;
+    return v;
+}
+
 __device__ __forceinline__ uint32_t load_relaxed(const unsigned int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -287,28 +304,29 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
         ok[u] = valid && ids_ok(pr[u], a.n_sets);
         if (valid && !ok[u]) atomicOr(&a.ctr->err[r], 1u);
     }
-    uint2 dr[U], ds[U];
+    // set records of both sides: {start, len, first tokens}; most pairs are
+    // decided from these alone
+    uint4 ra0[U], ra1[U], rb0[U], rb1[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        dr[u] = a.desc[ok[u] ? pr[u].x : 0];
-        ds[u] = a.desc[ok[u] ? pr[u].y : 0];
+        const int ir = ok[u] ? pr[u].x : 0, is = ok[u] ? pr[u].y : 0;
+        ra0[u] = a.heads[2 * ir];
+        ra1[u] = a.heads[2 * ir + 1];
+        rb0[u] = a.heads[2 * is];
+        rb1[u] = a.heads[2 * is + 1];
     }
-    uint32_t ia[U], ib[U], na[U], nb[U], alpha[U], i[U], j[U], o[U];
+    uint32_t na[U], nb[U], alpha[U], i[U], j[U], o[U];
     bool act[U], pass[U], defer[U];
     int cls[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const uint32_t L = dr[u].y + ds[u].y;
+        const uint32_t L = ra0[u].y + rb0[u].y;
         cls[u] = deferring ? class_of(L, a) : 0;
         defer[u] = ok[u] && deferring && cls[u] >= a.defer_from;
         act[u] = ok[u] && !defer[u];
         pass[u] = false;
-        // inactive pairs keep a valid one-token range so that the lockstep
-        // loads below stay in bounds
-        ia[u] = act[u] ? dr[u].x : 0u;
-        ib[u] = act[u] ? ds[u].x : 0u;
-        na[u] = act[u] ? dr[u].y : 1u;
-        nb[u] = act[u] ? ds[u].y : 1u;
+        na[u] = ra0[u].y;
+        nb[u] = rb0[u].y;
         alpha[u] = act[u] ? required_overlap(L, R.tn, R.tsum) : 0u;
         i[u] = j[u] = o[u] = 0;
     }
@@ -327,18 +345,16 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
             any |= act[u];
         }
         if (!any) break;
-        int32_t x[U], y[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            x[u] = tok[ia[u] + min(i[u], na[u] - 1)];
-            y[u] = tok[ib[u] + min(j[u], nb[u] - 1)];
-        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (act[u]) {
-                i[u] += (x[u] <= y[u]);
-                j[u] += (y[u] <= x[u]);
-                o[u] += (x[u] == y[u]);
+                const int32_t x = i[u] < kHeadTokens ? head_token(ra0[u], ra1[u], i[u])
+                                                     : tok[ra0[u].x + i[u]];
+                const int32_t y = j[u] < kHeadTokens ? head_token(rb0[u], rb1[u], j[u])
+                                                     : tok[rb0[u].x + j[u]];
+                i[u] += (x <= y);
+                j[u] += (y <= x);
+                o[u] += (x == y);
             }
         }
     }
@@ -388,8 +404,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                 if (k < R.n) {
                     pr = R.cand[k];
                     if (ids_ok(pr, a.n_sets)) {
-                        const uint2 dr = a.desc[pr.x];
-                        const uint2 ds = a.desc[pr.y];
+                        const uint2 dr = set_desc(a, pr.x);
+                        const uint2 ds = set_desc(a, pr.y);
                         const uint32_t L = dr.y + ds.y;
                         if (deferring) {
                             cls = class_of(L, a);
@@ -469,8 +485,8 @@ __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
             const int r = request_of_pair(gi, a);
             const Request& R = a.req[r];
             const int2 pr = R.cand[gi - a.pair_off[r]];
-            const uint2 dr = a.desc[pr.x];
-            const uint2 ds = a.desc[pr.y];
+            const uint2 dr = set_desc(a, pr.x);
+            const uint2 ds = set_desc(a, pr.y);
             const bool pass = verify_lanes<G>(a, dr, ds, required_overlap(dr.y + ds.y, R.tn, R.tsum),
                                               g, gbase);
             if (pass && g == 0) append_one(pr, R, &a.ctr->out_count[r]);
@@ -499,8 +515,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
             const int r = request_of_pair(gi, a);
             const Request& R = a.req[r];
             const int2 pr = R.cand[gi - a.pair_off[r]];
-            const uint2 dr = a.desc[pr.x];
-            const uint2 ds = a.desc[pr.y];
+            const uint2 dr = set_desc(a, pr.x);
+            const uint2 ds = set_desc(a, pr.y);
             const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y,
                                           required_overlap(dr.y + ds.y, R.tn, R.tsum), sb, red);
             if (threadIdx.x == 0 && pass) append_one(pr, R, &a.ctr->out_count[r]);
@@ -521,12 +537,16 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
     }
 }
 
-__global__ void k_build_desc(const int64_t* __restrict__ off, uint2* __restrict__ desc,
-                             int64_t n) {
+__global__ void k_build_heads(const int64_t* __restrict__ off, const int32_t* __restrict__ tok,
+                              uint4* __restrict__ heads, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = off[i], e = off[i + 1];
-        desc[i] = make_uint2((uint32_t)b, (uint32_t)(e - b));
+        int32_t h[kHeadTokens];
+#pragma unroll
+        for (int k = 0; k < kHeadTokens; ++k) h[k] = (b + k < e) ? tok[b + k] : 0;
+        heads[2 * i] = make_uint4((uint32_t)b, (uint32_t)(e - b), (uint32_t)h[0], (uint32_t)h[1]);
+        heads[2 * i + 1] = make_uint4((uint32_t)h[2], (uint32_t)h[3], (uint32_t)h[4], (uint32_t)h[5]);
     }
 }
 
@@ -563,13 +583,13 @@ const void* kernel_verify_tiles(int lanes, int unroll) {
 
 const void* kernel_verify_deferred() { return (const void*)&k_verify_deferred; }
 
-hipError_t launch_build_desc(const int64_t* d_offsets, uint2* d_desc, int64_t n_sets,
-                             hipStream_t st) {
+hipError_t launch_build_heads(const int64_t* d_offsets, const int32_t* d_tok, uint4* d_heads,
+                              int64_t n_sets, hipStream_t st) {
     if (n_sets <= 0) return hipSuccess;
     int64_t blocks = (n_sets + kBlock - 1) / kBlock;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_build_desc, dim3((unsigned)blocks), dim3(kBlock), 0, st, d_offsets,
-                       d_desc, n_sets);
+    hipLaunchKernelGGL(k_build_heads, dim3((unsigned)blocks), dim3(kBlock), 0, st, d_offsets, d_tok,
+                       d_heads, n_sets);
     return hipGetLastError();
 }
 

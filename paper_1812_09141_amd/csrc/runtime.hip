@@ -102,7 +102,7 @@ struct GraphEntry {
 struct ssj_coll {
     ssj_ctx* ctx = nullptr;
     int32_t* d_tok = nullptr;
-    uint2* d_desc = nullptr;
+    uint4* d_heads = nullptr;  // 32-byte record per set: start, len, first tokens
     int64_t n_sets = 0;
     int64_t n_tokens = 0;
     int64_t max_len = 0;
@@ -288,7 +288,7 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
                    hipStream_t st, const ssj_plan& plan, bool allow_graph = true) {
     ssj::LaunchArgs a{};
     a.tok = coll->d_tok;
-    a.desc = coll->d_desc;
+    a.heads = coll->d_heads;
     a.ctr = sc.d_ctr;
     a.n_sets = (uint32_t)coll->n_sets;
     a.n_req = n_req;
@@ -737,7 +737,7 @@ int ssj_shutdown(ssj_ctx* ctx) {
         if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
         for (ssj_coll* c : ctx->colls) {
             if (c->d_tok) (void)hipFree(c->d_tok);
-            if (c->d_desc) (void)hipFree(c->d_desc);
+            if (c->d_heads) (void)hipFree(c->d_heads);
             delete c;
         }
         ctx->colls.clear();
@@ -801,17 +801,17 @@ int ssj_upload_collection(ssj_ctx* ctx, const int64_t* offsets, int64_t n_sets,
     hipError_t e = hipSuccess;
     do {
         if ((e = hipMalloc((void**)&c->d_tok, (size_t)std::max<int64_t>(n_tokens, 1) * 4)) != hipSuccess) break;
-        if ((e = hipMalloc((void**)&c->d_desc, (size_t)std::max<int64_t>(n_sets, 1) * 8)) != hipSuccess) break;
+        if ((e = hipMalloc((void**)&c->d_heads, (size_t)std::max<int64_t>(n_sets, 1) * 32)) != hipSuccess) break;
         if ((e = hipMalloc((void**)&d_off, (size_t)(n_sets + 1) * 8)) != hipSuccess) break;
         if (n_tokens > 0 && (e = hipMemcpyAsync(c->d_tok, tokens, (size_t)n_tokens * 4, hipMemcpyHostToDevice, ctx->stream)) != hipSuccess) break;
         if ((e = hipMemcpyAsync(d_off, offsets, (size_t)(n_sets + 1) * 8, hipMemcpyHostToDevice, ctx->stream)) != hipSuccess) break;
-        if ((e = ssj::launch_build_desc(d_off, c->d_desc, n_sets, ctx->stream)) != hipSuccess) break;
+        if ((e = ssj::launch_build_heads(d_off, c->d_tok, c->d_heads, n_sets, ctx->stream)) != hipSuccess) break;
         if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) break;
     } while (0);
     if (d_off) (void)hipFree(d_off);
     if (e != hipSuccess) {
         if (c->d_tok) (void)hipFree(c->d_tok);
-        if (c->d_desc) (void)hipFree(c->d_desc);
+        if (c->d_heads) (void)hipFree(c->d_heads);
         delete c;
         if (e == hipErrorOutOfMemory) return set_error(SSJ_ENOMEM, "device allocation failed");
         return hip_fail(ctx, "upload", e);
@@ -833,7 +833,7 @@ int ssj_free_collection(ssj_ctx* ctx, ssj_coll* coll) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (coll->d_tok) (void)hipFree(coll->d_tok);
-    if (coll->d_desc) (void)hipFree(coll->d_desc);
+    if (coll->d_heads) (void)hipFree(coll->d_heads);
     delete coll;
     return SSJ_OK;
 }

@@ -10,6 +10,7 @@ constexpr int kClasses = 5;      // length classes of |r| + |s|
 constexpr int kBlock = 256;      // threads per workgroup of every verify kernel
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kMaxReq = 16;      // requests per launch
+constexpr int kHeadTokens = 6;   // leading tokens kept in each 32-byte set record
 
 // One verification request inside a launch.
 struct Request {
@@ -37,7 +38,7 @@ struct alignas(256) Counters {
 // Everything one launch needs (passed by value as the kernel argument).
 struct LaunchArgs {
     const int32_t* tok;                  // collection tokens
-    const uint2* desc;                   // {start, len} per set
+    const uint4* heads;                  // per set: {start, len, tok0, tok1}, {tok2..tok5}
     Counters* ctr;
     uint32_t* queues;                    // deferred-class queues, kClasses x qcap
     uint32_t qcap;
@@ -56,8 +57,9 @@ struct LaunchArgs {
 
 // Launch helpers (defined in kernels.hip).  Return hipSuccess or the launch
 // error.
-hipError_t launch_build_desc(const int64_t* d_offsets, uint2* d_desc, int64_t n_sets,
-                             hipStream_t st);
+// Set records (2 x uint4 per set) from the CSR offsets and tokens on the device.
+hipError_t launch_build_heads(const int64_t* d_offsets, const int32_t* d_tok, uint4* d_heads,
+                              int64_t n_sets, hipStream_t st);
 // The in-order kernel: every pair of a class below defer_from is verified
 // with inline_lanes lanes; the others are queued for launch_verify_deferred.
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st);
