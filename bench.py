@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "verified candidate pairs/sec + achieved HBM GB/s; p50/p99 batch latency (stream)"
 PEAK_HBM_GBS = 8000.0
+TIMING_PERIOD = 5
 WORKLOAD_CFG = {"offline": 2, "tiny": 1, "longsets": 3}
 
 
@@ -41,6 +42,8 @@ def parse():
                     help="also time plain one-launch-per-batch verification")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work budget of the oracle baseline (0 disables it)")
+    ap.add_argument("--sweep", default="",
+                    help="semicolon-separated plan specs to time as well (reported under 'sweep')")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (5 times), "
                          "the reference for HBM byte counters, and exit")
@@ -190,8 +193,9 @@ def main():
         log(f"autotuned plan: {tuned}")
     S.ssj_set_plan(ctx, plan)
 
-    # main timed region, kernel timing on (HIP events on the launch stream)
-    S.ssj_timing_enable(ctx, True)
+    # main timed region; every TIMING_PERIOD-th launch is bracketed by HIP
+    # events on the launch stream (sampled: event records perturb a launch)
+    S.ssj_timing_enable(ctx, TIMING_PERIOD)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -202,7 +206,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     in_ms, def_ms, launches = S.ssj_timing_read(ctx, reset=True)
-    S.ssj_timing_enable(ctx, False)
+    S.ssj_timing_enable(ctx, 0)
     parity = check()
     if not parity:
         log("RESULT MISMATCH against the oracle manifest")
@@ -221,7 +225,7 @@ def main():
         c = cands[i]
         b_full += 24 * c.shape[0] + 4 * int(sizes[c[:, 0]].sum() + sizes[c[:, 1]].sum()) + 8 * m["n_result"]
     launches = max(launches, 1)
-    per_launch_bytes = b_alg / (launches / args.steps)
+    per_launch_bytes = b_alg  # one launch per step
     avg_in_ms = in_ms / launches
     avg_def_ms = def_ms / launches
     deferred = plan.defer_from < 5
@@ -242,6 +246,16 @@ def main():
         extra["plain_ms_per_step"] = round(dt * 1e3 / n_plain, 4)
         extra["plain_parity"] = bool(check())
         extra["batched_over_plain"] = round(value / (n_pairs * n_plain / dt), 3)
+
+    if args.sweep:
+        sweep = {}
+        for spec in args.sweep.split(";"):
+            S.ssj_set_plan(ctx, plan_of(S, spec))
+            n_sw = max(5, args.steps // 2)
+            dt = timed_steps(torch, step, n_sw, 2)
+            sweep[spec] = {"pairs_per_s": round(n_pairs * n_sw / dt, 1), "parity": bool(check())}
+        extra["sweep"] = sweep
+        S.ssj_set_plan(ctx, plan)
 
     # CPU baseline: the oracle (full merge, plain C) on the host cores
     cpu = None
@@ -299,6 +313,7 @@ def main():
             "avg_kernel_ms": round(avg_kernel_ms, 5),
             "avg_inorder_ms": round(avg_in_ms, 5),
             "avg_deferred_ms": round(avg_def_ms, 5),
+            "timed_launches": launches,
         },
         "cpu_baseline": cpu,
         "parity": bool(parity),

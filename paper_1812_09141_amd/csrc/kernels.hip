@@ -284,36 +284,63 @@ __device__ __forceinline__ void defer_wave(const LaunchArgs& a, bool defer, int 
     }
 }
 
-// Thread-per-pair step of the in-order kernel for U pairs per lane: the
-// lane's pairs are wbase + u*64 + lane.  Their loads are issued together and
-// their merges advance in lockstep, so U independent chains of memory
-// accesses are in flight per lane.
+// Request and first pair index of wavefront w in in-order tile T.
+template <int U>
+__device__ __forceinline__ void tile_origin(const LaunchArgs& a, uint32_t T, int w, int* r,
+                                            uint32_t* wbase) {
+    int q = 0;
+    while (q + 1 < a.n_req && a.tile_off[q + 1] <= T) ++q;
+    *r = q;
+    *wbase = (T - a.tile_off[q]) * ((uint32_t)kBlock * U) + (uint32_t)w * kWave * U;
+}
+
+// The lane's U pairs of a tile (clamped to the request; validity is
+// re-derived from the index when they are used).
+template <int U>
+__device__ __forceinline__ void load_lane_pairs(const Request& R, uint32_t wbase, int lane,
+                                                int2* pr) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t k = wbase + (uint32_t)(u * kWave + lane);
+        pr[u] = R.cand[k < R.n ? k : R.n - 1];
+    }
+}
+
+// Token t of a set given its record words (the first kHeadTokens come from
+// the record, later ones from the token array).
+__device__ __forceinline__ int32_t record_token(const LaunchArgs& a, uint4 w0, uint4 w1, uint32_t t) {
+    return t < kHeadTokens ? head_token(w0, w1, t) : a.tok[w0.x + t];
+}
+
+// Thread-per-pair step of the in-order kernel for U pairs per lane (pairs
+// wbase + u*64 + lane, already loaded into pr).  Their record loads are
+// issued together and their merges advance in lockstep, so U independent
+// chains of memory accesses are in flight per lane.
 template <int U>
 __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Request& R, int r,
-                                                  uint32_t wbase, bool deferring,
+                                                  uint32_t wbase, const int2* pr, bool deferring,
                                                   uint32_t* s_defer, uint32_t* s_dcnt) {
     const int lane = lane_id();
-    const int32_t* __restrict__ tok = a.tok;
-    int2 pr[U];
     bool ok[U];
+    int ir[U], is[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const uint32_t k = wbase + (uint32_t)(u * kWave + lane);
         const bool valid = k < R.n;
-        pr[u] = R.cand[valid ? k : R.n - 1];
         ok[u] = valid && ids_ok(pr[u], a.n_sets);
         if (valid && !ok[u]) atomicOr(&a.ctr->err[r], 1u);
+        ir[u] = ok[u] ? pr[u].x : 0;
+        is[u] = ok[u] ? pr[u].y : 0;
     }
-    // set records of both sides: {start, len, first tokens}; most pairs are
-    // decided from these alone
+    // records of both sides: {start, len, tok0..tok5}; most pairs are decided
+    // from these alone
     uint4 ra0[U], ra1[U], rb0[U], rb1[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int ir = ok[u] ? pr[u].x : 0, is = ok[u] ? pr[u].y : 0;
-        ra0[u] = a.heads[2 * ir];
-        ra1[u] = a.heads[2 * ir + 1];
-        rb0[u] = a.heads[2 * is];
-        rb1[u] = a.heads[2 * is + 1];
+        ra0[u] = a.heads[2 * ir[u]];
+        ra1[u] = a.heads[2 * ir[u] + 1];
+        rb0[u] = a.heads[2 * is[u]];
+        rb1[u] = a.heads[2 * is[u] + 1];
     }
     uint32_t na[U], nb[U], alpha[U], i[U], j[U], o[U];
     bool act[U], pass[U], defer[U];
@@ -348,10 +375,8 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (act[u]) {
-                const int32_t x = i[u] < kHeadTokens ? head_token(ra0[u], ra1[u], i[u])
-                                                     : tok[ra0[u].x + i[u]];
-                const int32_t y = j[u] < kHeadTokens ? head_token(rb0[u], rb1[u], j[u])
-                                                     : tok[rb0[u].x + j[u]];
+                const int32_t x = record_token(a, ra0[u], ra1[u], i[u]);
+                const int32_t y = record_token(a, rb0[u], rb1[u], j[u]);
                 i[u] += (x <= y);
                 j[u] += (y <= x);
                 o[u] += (x == y);
@@ -388,24 +413,44 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     const int lane = lane_id();
     const int grp = lane / G, g = lane % G, gbase = grp * G;
     const uint32_t n_tiles = a.tile_off[a.n_req];
+    // G == 1: the pairs of the next tile are loaded while this one is verified
+    int2 pr[U];
+    int r_cur = 0;
+    uint32_t wb_cur = 0;
+    if constexpr (G == 1) {
+        if (blockIdx.x < n_tiles) {
+            tile_origin<U>(a, blockIdx.x, w, &r_cur, &wb_cur);
+            load_lane_pairs<U>(a.req[r_cur], wb_cur, lane, pr);
+        }
+    }
     for (uint32_t T = blockIdx.x; T < n_tiles; T += gridDim.x) {
-        int r = 0;
-        while (r + 1 < a.n_req && a.tile_off[r + 1] <= T) ++r;
-        const Request& R = a.req[r];
-        const uint32_t wbase = (T - a.tile_off[r]) * kTilePairs + (uint32_t)w * kWave * U;
         if constexpr (G == 1) {
-            tile_thread_pairs<U>(a, R, r, wbase, deferring, s_defer, s_dcnt);
+            const int r = r_cur;
+            const uint32_t wbase = wb_cur;
+            int2 cur[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) cur[u] = pr[u];
+            const uint32_t Tn = T + gridDim.x;
+            if (Tn < n_tiles) {
+                tile_origin<U>(a, Tn, w, &r_cur, &wb_cur);
+                load_lane_pairs<U>(a.req[r_cur], wb_cur, lane, pr);
+            }
+            tile_thread_pairs<U>(a, a.req[r], r, wbase, cur, deferring, s_defer, s_dcnt);
         } else {
+            int r = 0;
+            uint32_t wbase = 0;
+            tile_origin<1>(a, T, w, &r, &wbase);
+            const Request& R = a.req[r];
             for (int sub = 0; sub < G; ++sub) {
                 const uint32_t k = wbase + (uint32_t)(sub * GPW + grp);
                 bool pass = false, defer = false;
                 int cls = 0;
-                int2 pr = make_int2(0, 0);
+                int2 pq = make_int2(0, 0);
                 if (k < R.n) {
-                    pr = R.cand[k];
-                    if (ids_ok(pr, a.n_sets)) {
-                        const uint2 dr = set_desc(a, pr.x);
-                        const uint2 ds = set_desc(a, pr.y);
+                    pq = R.cand[k];
+                    if (ids_ok(pq, a.n_sets)) {
+                        const uint2 dr = set_desc(a, pq.x);
+                        const uint2 ds = set_desc(a, pq.y);
                         const uint32_t L = dr.y + ds.y;
                         if (deferring) {
                             cls = class_of(L, a);
@@ -418,7 +463,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                         atomicOr(&a.ctr->err[r], 1u);
                     }
                 }
-                append_wave(pass && g == 0, pr, R.out, R.cap, &a.ctr->out_count[r]);
+                append_wave(pass && g == 0, pq, R.out, R.cap, &a.ctr->out_count[r]);
                 if (deferring)
                     defer_wave(a, defer && g == 0, cls, a.pair_off[r] + k, s_defer, s_dcnt);
             }

@@ -134,8 +134,9 @@ struct ssj_ctx {
     std::vector<ssj_coll*> colls;
     std::map<GraphKey, GraphEntry> graphs;
     hipStream_t capture_stream = nullptr;
-    // kernel timing (ssj_timing_*)
-    bool timing = false;
+    // kernel timing (ssj_timing_*): every timing_period-th launch is timed
+    std::atomic<int> timing_period{0};
+    std::atomic<uint64_t> timing_tick{0};
     std::mutex tmu;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::array<hipEvent_t, 3>> ev_pending;
@@ -211,7 +212,8 @@ hipEvent_t timing_event(ssj_ctx* ctx) {
         return e;
     }
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    // no system-scope fence on completion: the events only time kernels
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -330,7 +332,8 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     const int g2 = grid_deferred(ctx);
 
     std::array<hipEvent_t, 3> ev{nullptr, nullptr, nullptr};
-    const bool timing = ctx->timing;
+    const int period = ctx->timing_period.load();
+    const bool timing = period > 0 && (ctx->timing_tick.fetch_add(1) % (uint64_t)period) == 0;
     if (timing) {
         for (auto& e : ev) {
             e = timing_event(ctx);
@@ -864,9 +867,11 @@ int ssj_set_plan(ssj_ctx* ctx, const ssj_plan* plan) {
     return SSJ_OK;
 }
 
-int ssj_timing_enable(ssj_ctx* ctx, int enable) {
+int ssj_timing_enable(ssj_ctx* ctx, int period) {
     if (!ctx) return set_error(SSJ_EINVAL, "null context");
-    ctx->timing = enable != 0;
+    if (period < 0) return set_error(SSJ_EINVAL, "negative timing period");
+    ctx->timing_period = period;
+    ctx->timing_tick = 0;
     return SSJ_OK;
 }
 
@@ -1001,8 +1006,7 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OR_FAIL(ctx, hipEventCreate(&e0));
     HIP_OR_FAIL(ctx, hipEventCreate(&e1));
-    const bool timing_was = ctx->timing;
-    ctx->timing = false;
+    const int timing_was = ctx->timing_period.exchange(0);
     auto measure = [&](const ssj_plan& p, double* ms) -> int {
         Req r{reinterpret_cast<const int2*>(d_cand), n_cand, t_num, t_den, ctx->d_out, n_cand,
               ctx->d_count};
@@ -1058,7 +1062,7 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
         }
         if (!improved) break;
     }
-    ctx->timing = timing_was;
+    ctx->timing_period = timing_was;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SSJ_OK) return rc;

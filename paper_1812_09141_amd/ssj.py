@@ -17,7 +17,8 @@ import numpy as np
 import torch  # noqa: F401  (shared HIP runtime, device memory, streams)
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libssj.so")
+# SSJ_LIB may name another build of the same library (e.g. for comparisons)
+LIB_PATH = os.environ.get("SSJ_LIB") or os.path.join(_PKG, "libssj.so")
 
 SSJ_OK = 0
 SSJ_PENDING = 1
@@ -298,14 +299,15 @@ def ssj_autotune(ctx, coll, d_cand: "torch.Tensor", t_num: int, t_den: int, appl
     return p, ms.value
 
 
-def ssj_timing_enable(ctx, enable: bool = True) -> None:
-    rc = load_library().ssj_timing_enable(ctx, int(bool(enable)))
+def ssj_timing_enable(ctx, period: int = 1) -> None:
+    """Time every period-th launch (0 = off)."""
+    rc = load_library().ssj_timing_enable(ctx, int(period))
     if rc != SSJ_OK:
         _err(ctx, rc)
 
 
 def ssj_timing_read(ctx, reset: bool = False):
-    """(classify_ms, verify_ms, verify launches) summed since the last reset."""
+    """(in-order ms, rest-of-launch ms, timed launches) summed since the last reset."""
     a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
     rc = load_library().ssj_timing_read(ctx, int(bool(reset)), ctypes.byref(a), ctypes.byref(b),
                                         ctypes.byref(n))

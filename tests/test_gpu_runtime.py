@@ -149,13 +149,21 @@ def test_timing_counts_launches(S, ctx, data):
     d_out = torch.empty((cand.shape[0], 2), dtype=torch.int32, device="cuda:0")
     d_cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
     S.ssj_timing_read(ctx, reset=True)
-    S.ssj_timing_enable(ctx, True)
+    S.ssj_timing_enable(ctx, 1)
     for _ in range(5):
         S.ssj_verify_device(ctx, h, d_cand, tn, td, d_out, d_cnt)
     torch.cuda.synchronize()
     a, b, n = S.ssj_timing_read(ctx, reset=True)
-    S.ssj_timing_enable(ctx, False)
     assert n == 5 and a > 0 and b > 0
+    S.ssj_timing_enable(ctx, 3)
+    for _ in range(7):
+        S.ssj_verify_device(ctx, h, d_cand, tn, td, d_out, d_cnt)
+    torch.cuda.synchronize()
+    a, b, n = S.ssj_timing_read(ctx, reset=True)
+    assert n == 3 and a > 0
+    S.ssj_timing_enable(ctx, 0)
+    k = int(d_cnt.item())
+    assert np.array_equal(oracle.sort_pairs(d_out[:k].cpu().numpy()), want)
     S.ssj_free_collection(ctx, h)
 
 
