@@ -42,6 +42,9 @@ def parse():
                     help="also time plain one-launch-per-batch verification")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work budget of the oracle baseline (0 disables it)")
+    ap.add_argument("--stream-batches", type=int, default=200,
+                    help="streamed-serving phase: batches drawn from the 1,000,000-set "
+                         "collection (0 disables it)")
     ap.add_argument("--sweep", default="",
                     help="semicolon-separated plan specs to time as well (reported under 'sweep')")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -257,6 +260,35 @@ def main():
         extra["sweep"] = sweep
         S.ssj_set_plan(ctx, plan)
 
+    stream = None
+    if args.stream_batches > 0:
+        from paper_1812_09141_amd import serving
+        w5 = synth.WORKLOADS[5]
+        t0 = time.time()
+        c5 = synth.workload_collection(5)
+        sizes5, ts5, _ = synth.stream_schedule(args.stream_batches, seed=0, thresholds=w5.thresholds)
+        nthr = max(1, min(os.cpu_count() or 1, 16))
+        t1 = time.time()
+        batches = serving.build_batches(c5.offsets, c5.tokens, sizes5, ts5, n_threads=nthr)
+        t_filter = time.time() - t1
+        log(f"stream inputs ready in {time.time() - t0:.1f}s ({len(batches)} batches)")
+        h5 = S.ssj_upload_collection(ctx, c5.offsets, c5.tokens)
+        serving.run_stream(S, ctx, h5, batches[:8], None)  # warm-up
+        sat = serving.run_stream(S, ctx, h5, batches, None)
+        offered = 0.8 * sat["pairs_per_s"]
+        loaded = serving.run_stream(S, ctx, h5, batches, offered, seed=1)
+        n5 = sum(b[0].shape[0] for b in batches)
+        stream = {
+            "workload": (f"{w5.name}: {w5.n_sets} sets, lognormal(mean 12, sigma 0.5) sizes, "
+                         f"Zipf(1.0) over {w5.universe} tokens; batches of 1e3-1e6 pairs "
+                         f"(log-uniform), t in {{0.6,0.8,0.9}}"),
+            "filter_threads": nthr,
+            "filter_pairs_per_s": round(n5 / t_filter, 1) if t_filter > 0 else None,
+            "saturated": sat,
+            "offered_load_0.8": loaded,
+        }
+        S.ssj_free_collection(ctx, h5)
+
     # CPU baseline: the oracle (full merge, plain C) on the host cores
     cpu = None
     if args.cpu_seconds > 0:
@@ -316,6 +348,7 @@ def main():
             "timed_launches": launches,
         },
         "cpu_baseline": cpu,
+        "stream": stream,
         "parity": bool(parity),
         "alg_gbs_whole_step": round(b_alg * args.steps / elapsed / 1e9, 2),
         "full_read_bytes_per_step": int(b_full),

@@ -144,10 +144,12 @@ int ssj_stream_poll(ssj_ctx* ctx, uint64_t ticket, int wait, ssj_pair* out, int6
                     int64_t* out_n);
 
 /* Timing of a finished stream request, in nanoseconds of CLOCK_MONOTONIC:
- * submit, admission (copy start), device completion observed.  Valid until
- * the ticket is retired.  SSJ_PENDING if not done. */
-int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, uint64_t* t_submit, uint64_t* t_admit,
-                     uint64_t* t_done);
+ * submit (entry of ssj_stream_submit), admission (its first copy to the
+ * device was enqueued), completion (its results were on the host).  wait != 0
+ * blocks until the request is done; otherwise SSJ_PENDING while it runs.
+ * Does not retire the ticket.  SSJ_ENOTFOUND for an unknown ticket. */
+int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, int wait, uint64_t* t_submit,
+                     uint64_t* t_admit, uint64_t* t_done);
 
 /*
  * Execution plan.  Verification runs as one or two kernels per launch:

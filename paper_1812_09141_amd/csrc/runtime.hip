@@ -1151,16 +1151,19 @@ int ssj_stream_poll(ssj_ctx* ctx, uint64_t ticket, int wait, ssj_pair* out, int6
     return SSJ_OK;
 }
 
-int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, uint64_t* t_submit, uint64_t* t_admit,
-                     uint64_t* t_done) {
+int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, int wait, uint64_t* t_submit,
+                     uint64_t* t_admit, uint64_t* t_done) {
     if (!ctx) return set_error(SSJ_EINVAL, "null context");
     StreamEngine* E = ctx->engine.get();
     if (!E) return set_error(SSJ_EINVAL, "streaming engine not running");
-    std::lock_guard<std::mutex> lk(E->mu);
+    std::unique_lock<std::mutex> lk(E->mu);
     auto it = E->table.find(ticket);
     if (it == E->table.end()) return set_error(SSJ_ENOTFOUND, "unknown or retired ticket");
     StreamReq* r = it->second;
-    if (r->status == SSJ_PENDING) return SSJ_PENDING;
+    if (r->status == SSJ_PENDING) {
+        if (!wait) return SSJ_PENDING;
+        E->cv_done.wait(lk, [&]() { return r->status != SSJ_PENDING; });
+    }
     if (t_submit) *t_submit = r->t_submit;
     if (t_admit) *t_admit = r->t_admit;
     if (t_done) *t_done = r->t_done;

@@ -105,7 +105,7 @@ def load_library(path: str = LIB_PATH):
         "ssj_verify_device": ([p, p, p, i64, i64, i64, p, i64, p, p], c_int),
         "ssj_stream_submit": ([p, p, p, i64, i64, i64, c_int, P(u64)], c_int),
         "ssj_stream_poll": ([p, u64, c_int, p, i64, P(i64)], c_int),
-        "ssj_stream_times": ([p, u64, P(u64), P(u64), P(u64)], c_int),
+        "ssj_stream_times": ([p, u64, c_int, P(u64), P(u64), P(u64)], c_int),
         "ssj_get_plan": ([p, P(ssj_plan)], c_int),
         "ssj_set_plan": ([p, P(ssj_plan)], c_int),
         "ssj_collection_info": ([p, P(i64), P(i64), P(i64)], c_int),
@@ -231,9 +231,11 @@ def ssj_stream_poll(ctx, ticket: int, wait: bool = True, out_cap: int = 0):
     return out[:out_n.value].copy()
 
 
-def ssj_stream_times(ctx, ticket: int):
+def ssj_stream_times(ctx, ticket: int, wait: bool = False):
+    """(t_submit, t_admit, t_done) in ns of CLOCK_MONOTONIC, or None while pending."""
     a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
-    rc = load_library().ssj_stream_times(ctx, ticket, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    rc = load_library().ssj_stream_times(ctx, ticket, int(bool(wait)), ctypes.byref(a),
+                                         ctypes.byref(b), ctypes.byref(c))
     if rc == SSJ_PENDING:
         return None
     if rc != SSJ_OK:

@@ -248,8 +248,7 @@ def test_stream_poll_states(S, data):
         with pytest.raises(S.SsjError) as e:
             S.ssj_stream_poll(ctx, t, wait=True, out_cap=1)
         assert e.value.code == S.SSJ_ETRUNC and e.value.n == want.shape[0]
-        assert S.ssj_stream_times(ctx, t) is not None
-        ts, ta, td_ = S.ssj_stream_times(ctx, t)
+        ts, ta, td_ = S.ssj_stream_times(ctx, t, wait=True)
         assert ts <= ta <= td_
         assert np.array_equal(oracle.sort_pairs(S.ssj_stream_poll(ctx, t, True, want.shape[0])), want)
         # an id out of range fails only its own request
