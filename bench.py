@@ -76,7 +76,7 @@ def load_manifest(cfg):
 
 def traffic_from_profiles(kernel_src_hash):
     """HBM bytes per verify launch from committed PMC summaries, if current."""
-    p = os.path.join(ROOT, "profiles", "verify_bucketed_offline_traffic.json")
+    p = os.path.join(ROOT, "profiles", "verify_tiles_offline_traffic.json")
     if not os.path.exists(p):
         return None
     try:
@@ -259,6 +259,19 @@ def main():
             sweep[spec] = {"pairs_per_s": round(n_pairs * n_sw / dt, 1), "parity": bool(check())}
         extra["sweep"] = sweep
         S.ssj_set_plan(ctx, plan)
+
+    # PCIe-inclusive rate of the host-buffer entry point (candidates copied in,
+    # results copied out, synchronous per call); context only, never `value`
+    n_host = 3
+    t_h = time.perf_counter()
+    host_ok = True
+    for _ in range(n_host):
+        for i, (tn, td) in enumerate(w.thresholds):
+            res = S.ssj_verify(ctx, h, cands[i], tn, td)
+            host_ok &= res.shape[0] == man["thresholds"][f"{tn}/{td}"]["n_result"]
+    dt_h = time.perf_counter() - t_h
+    extra["host_api_pairs_per_s_pcie_inclusive"] = round(n_pairs * n_host / dt_h, 1)
+    extra["host_api_counts_ok"] = bool(host_ok)
 
     stream = None
     if args.stream_batches > 0:
