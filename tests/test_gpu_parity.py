@@ -287,3 +287,52 @@ def test_chunked_budget(S):
         assert np.array_equal(run_host(S, ctx, h, cand, 1, 2), want)
     finally:
         S.ssj_shutdown(ctx)
+
+
+def test_config4_full_size(S, ctx, golden_dir):
+    """Heavy-tail collection at full size (168M candidates) through the device
+    entry point, as bench.py launches it; compared with the oracle's digest."""
+    import json
+    import torch
+    man = json.load(open(os.path.join(golden_dir, "manifest.json")))["4"]
+    c = synth.workload_collection(4)
+    assert c.digest() == man["collection_sha256"]
+    (tn, td), = synth.WORKLOADS[4].thresholds
+    m = man["thresholds"][f"{tn}/{td}"]
+    cand = cfilter.workload_candidates(4, tn, td)
+    assert cand.shape[0] == m["n_candidates"]
+    h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+    d_cand = torch.from_numpy(cand).to("cuda:0")
+    d_out = torch.empty((m["n_result"] + 1024, 2), dtype=torch.int32, device="cuda:0")
+    d_cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    for name, plan in [("inline-1", dict(inline_lanes=1, defer_from=5)),
+                       ("defer-3", dict(inline_lanes=1, defer_from=3, lanes=[4, 16, 64, 256, 256])),
+                       ("defer-1", dict(inline_lanes=1, defer_from=1, lanes=[4, 16, 32, 64, 256]))]:
+        _log(f"config4 {name}")
+        set_plan(S, ctx, plan)
+        S.ssj_verify_device(ctx, h, d_cand, tn, td, d_out, d_cnt)
+        torch.cuda.synchronize()
+        k = int(d_cnt.item())
+        assert k == m["n_result"], name
+        got = d_out[:k].cpu().numpy()
+        assert oracle.result_digest(got) == m["result_sha256"], name
+    del d_cand, d_out
+    S.ssj_free_collection(ctx, h)
+
+
+def test_config5_stream_batches(S, golden_dir):
+    """Streamed batches of the 1,000,000-set collection, each against the oracle."""
+    from paper_1812_09141_amd import serving
+    c = synth.workload_collection(5)
+    sizes, ts, _ = synth.stream_schedule(24, seed=3, thresholds=synth.WORKLOADS[5].thresholds)
+    batches = serving.build_batches(c.offsets, c.tokens, sizes, ts, n_threads=8)
+    ctx = S.ssj_init(0, n_slots=3, queue_depth=8)
+    try:
+        h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+        tickets = [S.ssj_stream_submit(ctx, h, b, tn, td) for (b, tn, td) in batches]
+        for t, (b, tn, td) in zip(tickets, batches):
+            got = oracle.sort_pairs(S.ssj_stream_collect(ctx, t))
+            want = want_of(c, b, tn, td)
+            assert np.array_equal(got, want), (tn, td, b.shape[0])
+    finally:
+        S.ssj_shutdown(ctx)
