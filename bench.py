@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 METRIC = "verified candidate pairs/sec + achieved HBM GB/s; p50/p99 batch latency (stream)"
 PEAK_HBM_GBS = 8000.0
 TIMING_PERIOD = 5
-WORKLOAD_CFG = {"offline": 2, "tiny": 1, "longsets": 3}
+WORKLOAD_CFG = {"offline": 2, "tiny": 1, "longsets": 3, "heavytail": 4}
 
 
 def log(msg):
@@ -74,8 +74,9 @@ def load_manifest(cfg):
         return json.load(f)[str(cfg)]
 
 
-def traffic_from_profiles(kernel_src_hash):
-    """HBM bytes per verify launch from committed PMC summaries, if current."""
+def traffic_from_profiles(kernel_src_hash, workload, kernel):
+    """HBM bytes per verify launch from committed PMC summaries, if they were
+    taken for this kernel source, workload and kernel instance."""
     p = os.path.join(ROOT, "profiles", "verify_tiles_offline_traffic.json")
     if not os.path.exists(p):
         return None
@@ -84,7 +85,8 @@ def traffic_from_profiles(kernel_src_hash):
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha256") != kernel_src_hash:
+    if (d.get("kernel_source_sha256") != kernel_src_hash or d.get("workload_key") != workload
+            or d.get("kernel") != kernel):
         return None
     return d.get("bytes_per_launch")
 
@@ -237,7 +239,9 @@ def main():
     avg_kernel_ms = avg_in_ms + (avg_def_ms if deferred else 0.0)
     achieved = per_launch_bytes / (avg_kernel_ms * 1e-3) / 1e9 if avg_kernel_ms > 0 else 0.0
     src_hash = kernel_source_hash()
-    traffic = traffic_from_profiles(src_hash)
+    kernel_name = (f"k_verify_tiles<{plan.inline_lanes},{plan.inline_unroll}>" +
+                   (" + k_verify_deferred" if deferred else ""))
+    traffic = traffic_from_profiles(src_hash, args.workload, kernel_name)
 
     extra = {"plan": plan.as_dict()}
     if tuned:
@@ -347,8 +351,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": (f"k_verify_tiles<{plan.inline_lanes},{plan.inline_unroll}>" +
-                       (" + k_verify_deferred" if deferred else "")),
+            "kernel": kernel_name,
             "achieved": round(achieved, 2),
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
