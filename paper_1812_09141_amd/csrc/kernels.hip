@@ -225,6 +225,20 @@ __device__ __forceinline__ void append_one(int2 pr, const Request& R, unsigned l
     if (k < R.cap) R.out[k] = pr;
 }
 
+// Stages the pairs of the lanes with pass set in the workgroup's LDS output
+// buffer (wavefront-aggregated LDS atomic); flush_out moves them to the
+// request's output with one global atomic per flush.
+__device__ __forceinline__ void stage_wave(bool pass, int2 pr, int2* s_out, uint32_t* s_ocnt) {
+    const unsigned long long m = ballot(pass);
+    if (m == 0ull) return;
+    const int lane = lane_id();
+    const int leader = __builtin_ctzll(m);
+    uint32_t pos = 0;
+    if (lane == leader) pos = atomicAdd(s_ocnt, (uint32_t)__popcll(m));
+    pos = (uint32_t)bperm((int)pos, leader);
+    if (pass) s_out[pos + mbcnt(m)] = pr;
+}
+
 __device__ __forceinline__ bool ids_ok(int2 pr, uint32_t n_sets) {
     return (uint32_t)pr.x < n_sets && (uint32_t)pr.y < n_sets;
 }
@@ -252,6 +266,21 @@ __device__ __forceinline__ bool verify_lanes(const LaunchArgs& a, uint2 dr, uint
     } else {
         return merge_group<G>(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, g, gbase);
     }
+}
+
+// Moves the workgroup's c staged output pairs (request r) to the request's
+// output.  Called by the whole workgroup with the same r and c.
+__device__ void flush_out(const LaunchArgs& a, int r, uint32_t c, const int2* s_out,
+                          unsigned long long* s_obase) {
+    if (threadIdx.x == 0) *s_obase = atomicAdd(&a.ctr->out_count[r], (unsigned long long)c);
+    __syncthreads();
+    const unsigned long long base = *s_obase;
+    const Request& R = a.req[r];
+    for (uint32_t i = threadIdx.x; i < c; i += kBlock) {
+        const unsigned long long k = base + i;
+        if (k < R.cap) R.out[k] = s_out[i];
+    }
+    __syncthreads();
 }
 
 // Moves the workgroup's LDS queue of class q to the global queue.  Called by
@@ -319,7 +348,8 @@ __device__ __forceinline__ int32_t record_token(const LaunchArgs& a, uint4 w0, u
 template <int U>
 __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Request& R, int r,
                                                   uint32_t wbase, const int2* pr, bool deferring,
-                                                  uint32_t* s_defer, uint32_t* s_dcnt) {
+                                                  uint32_t* s_defer, uint32_t* s_dcnt, int2* s_out,
+                                                  uint32_t* s_ocnt) {
     const int lane = lane_id();
     bool ok[U];
     int ir[U], is[U];
@@ -385,7 +415,7 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        append_wave(pass[u], pr[u], R.out, R.cap, &a.ctr->out_count[r]);
+        stage_wave(pass[u], pr[u], s_out, s_ocnt);
         if (deferring)
             defer_wave(a, defer[u], cls[u], a.pair_off[r] + wbase + (uint32_t)(u * kWave + lane),
                        s_defer, s_dcnt);
@@ -401,13 +431,19 @@ template <int G, int U>
 __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     constexpr int GPW = kWave / G;
     constexpr uint32_t kTilePairs = (uint32_t)kBlock * U;
-    // per deferred class q >= defer_from: defer_cap LDS entries (dynamic LDS;
-    // none when nothing is deferred); defer_cap >= 2 * kTilePairs
-    extern __shared__ uint32_t s_defer[];
+    constexpr uint32_t kStage = 2 * kTilePairs;  // staged output pairs per workgroup
+    // dynamic LDS: kStage staged output pairs, then defer_cap entries per
+    // deferred class q >= defer_from (defer_cap >= 2 * kTilePairs)
+    extern __shared__ uint4 s_dyn[];
+    int2* s_out = reinterpret_cast<int2*>(s_dyn);
+    uint32_t* s_defer = reinterpret_cast<uint32_t*>(s_out + kStage);
     __shared__ uint32_t s_dcnt[kClasses];
+    __shared__ uint32_t s_ocnt;
     __shared__ uint32_t s_base;
+    __shared__ unsigned long long s_obase;
     const bool deferring = a.defer_from < kClasses;
     if (threadIdx.x < kClasses) s_dcnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_ocnt = 0;
     __syncthreads();
     const int w = (int)(threadIdx.x >> 6);
     const int lane = lane_id();
@@ -417,29 +453,24 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     int2 pr[U];
     int r_cur = 0;
     uint32_t wb_cur = 0;
+    if (blockIdx.x < n_tiles) tile_origin<U>(a, blockIdx.x, w, &r_cur, &wb_cur);
     if constexpr (G == 1) {
-        if (blockIdx.x < n_tiles) {
-            tile_origin<U>(a, blockIdx.x, w, &r_cur, &wb_cur);
-            load_lane_pairs<U>(a.req[r_cur], wb_cur, lane, pr);
-        }
+        if (blockIdx.x < n_tiles) load_lane_pairs<U>(a.req[r_cur], wb_cur, lane, pr);
     }
+    int r_last = 0;
     for (uint32_t T = blockIdx.x; T < n_tiles; T += gridDim.x) {
+        const int r = r_cur;
+        const uint32_t wbase = wb_cur;
+        const uint32_t Tn = T + gridDim.x;
+        if (Tn < n_tiles) tile_origin<U>(a, Tn, w, &r_cur, &wb_cur);
         if constexpr (G == 1) {
-            const int r = r_cur;
-            const uint32_t wbase = wb_cur;
             int2 cur[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) cur[u] = pr[u];
-            const uint32_t Tn = T + gridDim.x;
-            if (Tn < n_tiles) {
-                tile_origin<U>(a, Tn, w, &r_cur, &wb_cur);
-                load_lane_pairs<U>(a.req[r_cur], wb_cur, lane, pr);
-            }
-            tile_thread_pairs<U>(a, a.req[r], r, wbase, cur, deferring, s_defer, s_dcnt);
+            if (Tn < n_tiles) load_lane_pairs<U>(a.req[r_cur], wb_cur, lane, pr);
+            tile_thread_pairs<U>(a, a.req[r], r, wbase, cur, deferring, s_defer, s_dcnt, s_out,
+                                 &s_ocnt);
         } else {
-            int r = 0;
-            uint32_t wbase = 0;
-            tile_origin<1>(a, T, w, &r, &wbase);
             const Request& R = a.req[r];
             for (int sub = 0; sub < G; ++sub) {
                 const uint32_t k = wbase + (uint32_t)(sub * GPW + grp);
@@ -463,15 +494,25 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                         atomicOr(&a.ctr->err[r], 1u);
                     }
                 }
-                append_wave(pass && g == 0, pq, R.out, R.cap, &a.ctr->out_count[r]);
+                stage_wave(pass && g == 0, pq, s_out, &s_ocnt);
                 if (deferring)
                     defer_wave(a, defer && g == 0, cls, a.pair_off[r] + k, s_defer, s_dcnt);
             }
         }
+        __syncthreads();
+        // at most kTilePairs pairs are staged per iteration: flush when fewer
+        // than that fit, or when the next tile belongs to another request
+        {
+            const uint32_t c = s_ocnt;
+            const bool same_next = Tn < n_tiles && r_cur == r;
+            if (c > 0 && (c > kStage - kTilePairs || !same_next)) {
+                flush_out(a, r, c, s_out, &s_obase);
+                if (threadIdx.x == 0) s_ocnt = 0;
+                __syncthreads();
+            }
+        }
         if (deferring) {
-            // at most kTilePairs entries per class arrive per iteration, so a
-            // queue with room for fewer than that is flushed now
-            __syncthreads();
+            // the same bound holds for each deferred class
             for (int q = a.defer_from; q < kClasses; ++q) {
                 const uint32_t c = s_dcnt[q];
                 if (c > a.defer_cap - kTilePairs) {
@@ -482,7 +523,9 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                 }
             }
         }
+        r_last = r;
     }
+    (void)r_last;
     if (deferring) {
         __syncthreads();
         for (int q = a.defer_from; q < kClasses; ++q) {
@@ -639,7 +682,10 @@ hipError_t launch_build_heads(const int64_t* d_offsets, const int32_t* d_tok, ui
 }
 
 size_t tiles_lds_bytes(const LaunchArgs& a) {
-    return a.defer_from < kClasses ? (size_t)(kClasses - a.defer_from) * a.defer_cap * 4u : 0u;
+    const size_t tile = (size_t)kBlock * (a.inline_lanes == 1 ? (size_t)a.inline_unroll : 1u);
+    const size_t stage = 2 * tile * sizeof(int2);
+    const size_t defer = a.defer_from < kClasses ? (size_t)(kClasses - a.defer_from) * a.defer_cap * 4u : 0u;
+    return stage + defer;
 }
 
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st) {

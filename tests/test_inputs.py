@@ -118,3 +118,20 @@ def test_stream_schedule():
     lg = np.log10(sizes)
     assert abs(lg.mean() - 4.5) < 0.1
     assert set(ts) == {(3, 5), (4, 5), (9, 10)}
+
+
+def test_serving_batches_cover_the_candidate_stream():
+    """Batches cut by the serving driver are the filter's candidates, in order."""
+    from paper_1812_09141_amd import serving
+    rng = np.random.default_rng(77)
+    c = synth.random_collection(rng, n_sets=400, max_size=12, universe=120)
+    full = cfilter.candidates(c.offsets, c.tokens, 1, 2)
+    sizes = [50, 120, 7, 300, 10_000]
+    batches = serving.build_batches(c.offsets, c.tokens, sizes, [(1, 2)] * len(sizes), n_threads=3)
+    got = np.concatenate([b[0] for b in batches])
+    # the stream wraps around at the end of the collection
+    k = min(got.shape[0], full.shape[0])
+    assert np.array_equal(got[:k], full[:k])
+    if got.shape[0] > full.shape[0]:
+        assert np.array_equal(got[full.shape[0]:], full[:got.shape[0] - full.shape[0]])
+    assert all(b[1:] == (1, 2) for b in batches)
