@@ -107,6 +107,9 @@ int ssj_verify(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t
 /*
  * Device-pointer variant: no host copies, no synchronisation.  d_cand and
  * d_out are device buffers owned by the caller; d_count is a device int64.
+ * Output-count mode (the paper's aggregation on top of the join, Sec. 3.3.2
+ * and Sec. 5.1): d_out = NULL and out_cap = 0 produce only the count, with no
+ * pair writes.
  * The work is enqueued on hip_stream (a hipStream_t; NULL = the legacy
  * default stream).  When the stream reaches the end of the call, *d_count
  * holds the number of passing candidates (which may exceed out_cap: then

@@ -228,13 +228,17 @@ __device__ __forceinline__ void append_one(int2 pr, const Request& R, unsigned l
 // Stages the pairs of the lanes with pass set in the workgroup's LDS output
 // buffer (wavefront-aggregated LDS atomic); flush_out moves them to the
 // request's output with one global atomic per flush.
-__device__ __forceinline__ void stage_wave(bool pass, int2 pr, int2* s_out, uint32_t* s_ocnt) {
+// With count_only (a request without an output buffer) only the number of
+// passing pairs is accumulated.
+__device__ __forceinline__ void stage_wave(bool pass, int2 pr, int2* s_out, uint32_t* s_ocnt,
+                                           bool count_only) {
     const unsigned long long m = ballot(pass);
     if (m == 0ull) return;
     const int lane = lane_id();
     const int leader = __builtin_ctzll(m);
     uint32_t pos = 0;
     if (lane == leader) pos = atomicAdd(s_ocnt, (uint32_t)__popcll(m));
+    if (count_only) return;
     pos = (uint32_t)bperm((int)pos, leader);
     if (pass) s_out[pos + mbcnt(m)] = pr;
 }
@@ -276,7 +280,8 @@ __device__ void flush_out(const LaunchArgs& a, int r, uint32_t c, const int2* s_
     __syncthreads();
     const unsigned long long base = *s_obase;
     const Request& R = a.req[r];
-    for (uint32_t i = threadIdx.x; i < c; i += kBlock) {
+    const uint32_t n_copy = R.cap == 0 ? 0u : c;  // nothing staged in count-only mode
+    for (uint32_t i = threadIdx.x; i < n_copy; i += kBlock) {
         const unsigned long long k = base + i;
         if (k < R.cap) R.out[k] = s_out[i];
     }
@@ -341,49 +346,57 @@ __device__ __forceinline__ int32_t record_token(const LaunchArgs& a, uint4 w0, u
     return t < kHeadTokens ? head_token(w0, w1, t) : a.tok[w0.x + t];
 }
 
-// Thread-per-pair step of the in-order kernel for U pairs per lane (pairs
-// wbase + u*64 + lane, already loaded into pr).  Their record loads are
-// issued together and their merges advance in lockstep, so U independent
-// chains of memory accesses are in flight per lane.
+// Set records of the lane's U pairs: four 16-byte loads per pair (first and
+// second word of both sides), issued back to back.  Pairs with an invalid id
+// read record 0 and are ignored later.
+template <int U>
+struct LaneRecords {
+    uint4 ra0[U], ra1[U], rb0[U], rb1[U];
+};
+
+template <int U>
+__device__ __forceinline__ void issue_records(const LaunchArgs& a, const int2* pr,
+                                              LaneRecords<U>& rec) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool ok = ids_ok(pr[u], a.n_sets);
+        const int ir = ok ? pr[u].x : 0, is = ok ? pr[u].y : 0;
+        rec.ra0[u] = a.heads[2 * ir];
+        rec.ra1[u] = a.heads[2 * ir + 1];
+        rec.rb0[u] = a.heads[2 * is];
+        rec.rb1[u] = a.heads[2 * is + 1];
+    }
+}
+
+// Thread-per-pair verification of the lane's U pairs (wbase + u*64 + lane)
+// from their records; the merges advance in lockstep.
 template <int U>
 __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Request& R, int r,
-                                                  uint32_t wbase, const int2* pr, bool deferring,
+                                                  uint32_t wbase, const int2* pr,
+                                                  const LaneRecords<U>& rec, bool deferring,
                                                   uint32_t* s_defer, uint32_t* s_dcnt, int2* s_out,
                                                   uint32_t* s_ocnt) {
     const int lane = lane_id();
-    bool ok[U];
-    int ir[U], is[U];
+    bool ok[U], bad = false;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const uint32_t k = wbase + (uint32_t)(u * kWave + lane);
         const bool valid = k < R.n;
         ok[u] = valid && ids_ok(pr[u], a.n_sets);
-        if (valid && !ok[u]) atomicOr(&a.ctr->err[r], 1u);
-        ir[u] = ok[u] ? pr[u].x : 0;
-        is[u] = ok[u] ? pr[u].y : 0;
-    }
-    // records of both sides: {start, len, tok0..tok5}; most pairs are decided
-    // from these alone
-    uint4 ra0[U], ra1[U], rb0[U], rb1[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        ra0[u] = a.heads[2 * ir[u]];
-        ra1[u] = a.heads[2 * ir[u] + 1];
-        rb0[u] = a.heads[2 * is[u]];
-        rb1[u] = a.heads[2 * is[u] + 1];
+        bad |= valid && !ok[u];
     }
     uint32_t na[U], nb[U], alpha[U], i[U], j[U], o[U];
     bool act[U], pass[U], defer[U];
     int cls[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const uint32_t L = ra0[u].y + rb0[u].y;
+        const uint32_t L = rec.ra0[u].y + rec.rb0[u].y;
         cls[u] = deferring ? class_of(L, a) : 0;
         defer[u] = ok[u] && deferring && cls[u] >= a.defer_from;
         act[u] = ok[u] && !defer[u];
         pass[u] = false;
-        na[u] = ra0[u].y;
-        nb[u] = rb0[u].y;
+        na[u] = rec.ra0[u].y;
+        nb[u] = rec.rb0[u].y;
         alpha[u] = act[u] ? required_overlap(L, R.tn, R.tsum) : 0u;
         i[u] = j[u] = o[u] = 0;
     }
@@ -405,17 +418,20 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (act[u]) {
-                const int32_t x = record_token(a, ra0[u], ra1[u], i[u]);
-                const int32_t y = record_token(a, rb0[u], rb1[u], j[u]);
+                const int32_t x = record_token(a, rec.ra0[u], rec.ra1[u], i[u]);
+                const int32_t y = record_token(a, rec.rb0[u], rec.rb1[u], j[u]);
                 i[u] += (x <= y);
                 j[u] += (y <= x);
                 o[u] += (x == y);
             }
         }
     }
+    // (after the merges: atomics count with loads, so none sits between the
+    // record loads in flight and their use)
+    if (bad) atomicOr(&a.ctr->err[r], 1u);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        stage_wave(pass[u], pr[u], s_out, s_ocnt);
+        stage_wave(pass[u], pr[u], s_out, s_ocnt, R.cap == 0);
         if (deferring)
             defer_wave(a, defer[u], cls[u], a.pair_off[r] + wbase + (uint32_t)(u * kWave + lane),
                        s_defer, s_dcnt);
@@ -449,55 +465,100 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     const int lane = lane_id();
     const int grp = lane / G, g = lane % G, gbase = grp * G;
     const uint32_t n_tiles = a.tile_off[a.n_req];
-    // G == 1: the pairs of the next tile are loaded while this one is verified
-    int2 pr[U];
-    int r_cur = 0;
-    uint32_t wb_cur = 0;
+    // G == 1: a two-stage pipeline.  While tile T is verified, the records of
+    // tile T + grid and the pairs of tile T + 2 grid are in flight (memory
+    // operations complete in issue order, so the records of T, issued one
+    // iteration earlier, are waited for without draining the newer loads).
+    int2 p0[U], p1[U];
+    LaneRecords<U> rec0, rec1;
+    int r_cur = 0, r1 = 0;
+    uint32_t wb_cur = 0, wb1 = 0;
     if (blockIdx.x < n_tiles) tile_origin<U>(a, blockIdx.x, w, &r_cur, &wb_cur);
     if constexpr (G == 1) {
-        if (blockIdx.x < n_tiles) load_lane_pairs<U>(a.req[r_cur], wb_cur, lane, pr);
+        // loads beyond the last tile are clamped to it (results unused), so
+        // every iteration issues the same loads in the same order
+        if (blockIdx.x < n_tiles) {
+            load_lane_pairs<U>(a.req[r_cur], wb_cur, lane, p0);
+            issue_records<U>(a, p0, rec0);
+            tile_origin<U>(a, min(blockIdx.x + gridDim.x, n_tiles - 1), w, &r1, &wb1);
+            load_lane_pairs<U>(a.req[r1], wb1, lane, p1);
+        }
     }
     int r_last = 0;
     for (uint32_t T = blockIdx.x; T < n_tiles; T += gridDim.x) {
         const int r = r_cur;
         const uint32_t wbase = wb_cur;
         const uint32_t Tn = T + gridDim.x;
-        if (Tn < n_tiles) tile_origin<U>(a, Tn, w, &r_cur, &wb_cur);
         if constexpr (G == 1) {
-            int2 cur[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) cur[u] = pr[u];
-            if (Tn < n_tiles) load_lane_pairs<U>(a.req[r_cur], wb_cur, lane, pr);
-            tile_thread_pairs<U>(a, a.req[r], r, wbase, cur, deferring, s_defer, s_dcnt, s_out,
+            int2 p2[U];
+            int r2 = 0;
+            uint32_t wb2 = 0;
+            issue_records<U>(a, p1, rec1);
+            tile_origin<U>(a, min(Tn + gridDim.x, n_tiles - 1), w, &r2, &wb2);
+            load_lane_pairs<U>(a.req[r2], wb2, lane, p2);
+            tile_thread_pairs<U>(a, a.req[r], r, wbase, p0, rec0, deferring, s_defer, s_dcnt, s_out,
                                  &s_ocnt);
+            // rotate the pipeline
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                p0[u] = p1[u];
+                p1[u] = p2[u];
+            }
+            rec0 = rec1;
+            r_cur = r1;
+            wb_cur = wb1;
+            r1 = r2;
+            wb1 = wb2;
         } else {
+            if (Tn < n_tiles) tile_origin<U>(a, Tn, w, &r_cur, &wb_cur);
             const Request& R = a.req[r];
+            // sub-rounds of 64/G pairs: the pair of sub-round s + 2 and the
+            // set descriptors of s + 1 are loaded while s is merged (clamped,
+            // unconditional loads keep the issue order fixed)
+            auto pair_at = [&](int sub) -> int2 {
+                const uint32_t k = wbase + (uint32_t)(min(sub, G - 1) * GPW + grp);
+                return R.cand[k < R.n ? k : R.n - 1];
+            };
+            auto desc_of = [&](int2 pq, uint2* dr, uint2* ds) {
+                const bool ok = ids_ok(pq, a.n_sets);
+                *dr = set_desc(a, ok ? pq.x : 0);
+                *ds = set_desc(a, ok ? pq.y : 0);
+            };
+            int2 pq0 = pair_at(0), pq1 = pair_at(1);
+            uint2 dr0, ds0;
+            desc_of(pq0, &dr0, &ds0);
+            bool bad = false;
             for (int sub = 0; sub < G; ++sub) {
+                const int2 pq2 = pair_at(sub + 2);
+                uint2 dr1, ds1;
+                desc_of(pq1, &dr1, &ds1);
                 const uint32_t k = wbase + (uint32_t)(sub * GPW + grp);
                 bool pass = false, defer = false;
                 int cls = 0;
-                int2 pq = make_int2(0, 0);
+                const int2 pq = pq0;
                 if (k < R.n) {
-                    pq = R.cand[k];
                     if (ids_ok(pq, a.n_sets)) {
-                        const uint2 dr = set_desc(a, pq.x);
-                        const uint2 ds = set_desc(a, pq.y);
-                        const uint32_t L = dr.y + ds.y;
+                        const uint32_t L = dr0.y + ds0.y;
                         if (deferring) {
                             cls = class_of(L, a);
                             defer = cls >= a.defer_from;
                         }
                         if (!defer)
-                            pass = verify_lanes<G>(a, dr, ds, required_overlap(L, R.tn, R.tsum), g,
+                            pass = verify_lanes<G>(a, dr0, ds0, required_overlap(L, R.tn, R.tsum), g,
                                                    gbase);
-                    } else if (g == 0) {
-                        atomicOr(&a.ctr->err[r], 1u);
+                    } else {
+                        bad = true;
                     }
                 }
-                stage_wave(pass && g == 0, pq, s_out, &s_ocnt);
+                stage_wave(pass && g == 0, pq, s_out, &s_ocnt, R.cap == 0);
                 if (deferring)
                     defer_wave(a, defer && g == 0, cls, a.pair_off[r] + k, s_defer, s_dcnt);
+                pq0 = pq1;
+                pq1 = pq2;
+                dr0 = dr1;
+                ds0 = ds1;
             }
+            if (bad && g == 0) atomicOr(&a.ctr->err[r], 1u);
         }
         __syncthreads();
         // at most kTilePairs pairs are staged per iteration: flush when fewer
@@ -505,7 +566,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
         {
             const uint32_t c = s_ocnt;
             const bool same_next = Tn < n_tiles && r_cur == r;
-            if (c > 0 && (c > kStage - kTilePairs || !same_next)) {
+            const bool full = a.req[r].cap != 0 && c > kStage - kTilePairs;
+            if (c > 0 && (full || !same_next)) {
                 flush_out(a, r, c, s_out, &s_obase);
                 if (threadIdx.x == 0) s_ocnt = 0;
                 __syncthreads();

@@ -193,12 +193,15 @@ def ssj_verify(ctx, coll, cand, t_num: int, t_den: int, out_cap: Optional[int] =
 
 def ssj_verify_device(ctx, coll, d_cand: "torch.Tensor", t_num: int, t_den: int,
                       d_out: "torch.Tensor", d_count: "torch.Tensor", stream=None) -> None:
-    """Enqueues verification of device pairs on a torch stream (no sync)."""
+    """Enqueues verification of device pairs on a torch stream (no sync).
+
+    d_out=None selects the output-count mode: only *d_count is produced."""
     assert d_cand.is_cuda and d_cand.dtype == torch.int32 and d_cand.is_contiguous()
-    assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
+    if d_out is not None:
+        assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
     assert d_count.is_cuda and d_count.dtype == torch.int64 and d_count.numel() >= 1
     n = d_cand.numel() // 2
-    cap = d_out.numel() // 2
+    cap = d_out.numel() // 2 if d_out is not None else 0
     st = stream if stream is not None else torch.cuda.current_stream(d_cand.device)
     rc = load_library().ssj_verify_device(ctx, coll, d_cand.data_ptr() if n else None, n,
                                           int(t_num), int(t_den), d_out.data_ptr() if cap else None,
@@ -276,12 +279,13 @@ def ssj_verify_batch_device(ctx, coll, requests, stream=None) -> None:
     dev = None
     for i, (d_cand, tn, td, d_out, d_count) in enumerate(requests):
         assert d_cand.is_cuda and d_cand.dtype == torch.int32 and d_cand.is_contiguous()
-        assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
+        if d_out is not None:
+            assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
         assert d_count.is_cuda and d_count.dtype == torch.int64
         nc = d_cand.numel() // 2
+        cap = d_out.numel() // 2 if d_out is not None else 0
         arr[i] = ssj_request(d_cand.data_ptr() if nc else None, nc, int(tn), int(td),
-                             d_out.data_ptr() if d_out.numel() else None, d_out.numel() // 2,
-                             d_count.data_ptr())
+                             d_out.data_ptr() if cap else None, cap, d_count.data_ptr())
         dev = d_cand.device
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     rc = load_library().ssj_verify_batch_device(ctx, coll, arr, n, ctypes.c_void_p(st.cuda_stream))

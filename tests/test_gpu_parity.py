@@ -316,6 +316,9 @@ def test_config4_full_size(S, ctx, golden_dir):
         assert k == m["n_result"], name
         got = d_out[:k].cpu().numpy()
         assert oracle.result_digest(got) == m["result_sha256"], name
+        S.ssj_verify_device(ctx, h, d_cand, tn, td, None, d_cnt)  # output-count mode
+        torch.cuda.synchronize()
+        assert int(d_cnt.item()) == m["n_result"], name
     del d_cand, d_out
     S.ssj_free_collection(ctx, h)
 

@@ -319,3 +319,26 @@ def test_stream_64_tickets_8_threads(S, data):
             assert np.array_equal(got, reqs[i][3])
     finally:
         S.ssj_shutdown(ctx)
+
+
+def test_count_mode_equals_result_size(S, ctx, data):
+    """Output-count mode (no pair writes) reports the result size."""
+    import torch
+    c, reqs = data
+    h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+    for plan in [dict(inline_lanes=1, defer_from=5), dict(inline_lanes=16, defer_from=5),
+                 dict(inline_lanes=1, defer_from=1, lanes=[4, 8, 32, 256, 256])]:
+        S.ssj_set_plan(ctx, S.make_plan(**plan))
+        d = [(_dev(torch, cand), tn, td, None, torch.full((1,), -7, dtype=torch.int64, device="cuda:0"))
+             for (cand, tn, td, want) in reqs]
+        S.ssj_verify_batch_device(ctx, h, d)
+        torch.cuda.synchronize()
+        for (cand, tn, td, want), (_, _, _, _, cnt) in zip(reqs, d):
+            assert int(cnt.item()) == want.shape[0], (plan, tn, td)
+        # and a single request through ssj_verify_device
+        cand, tn, td, want = reqs[0]
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+        S.ssj_verify_device(ctx, h, _dev(torch, cand), tn, td, None, cnt)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == want.shape[0]
+    S.ssj_free_collection(ctx, h)
