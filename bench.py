@@ -54,18 +54,18 @@ def parse():
 
 
 def plan_of(S, spec):
-    """auto | inline:L[xU] | defer:L[xU],F,l0,l1,l2,l3,l4"""
+    """auto | inline:L[hF] | defer:L[hF],D,l0,l1,l2,l3,l4 (F hard lanes, D first deferred class)"""
     if spec == "auto":
         return None
     kind, _, rest = spec.partition(":")
     parts = rest.split(",") if rest else []
-    lanes, _, unroll = parts[0].partition("x")
-    L, U = int(lanes), int(unroll or 1)
+    lanes, _, hard = parts[0].partition("h")
+    L, F = int(lanes), int(hard or 0)
     vals = [int(v) for v in parts[1:]]
     if kind == "inline":
-        return S.make_plan(inline_lanes=L, inline_unroll=U, defer_from=5)
+        return S.make_plan(inline_lanes=L, hard_lanes=F, defer_from=5)
     if kind == "defer":
-        return S.make_plan(inline_lanes=L, inline_unroll=U, defer_from=vals[0], lanes=vals[1:6])
+        return S.make_plan(inline_lanes=L, hard_lanes=F, defer_from=vals[0], lanes=vals[1:6])
     raise SystemExit(f"unknown plan {spec!r}")
 
 
@@ -239,7 +239,7 @@ def main():
     avg_kernel_ms = avg_in_ms + (avg_def_ms if deferred else 0.0)
     achieved = per_launch_bytes / (avg_kernel_ms * 1e-3) / 1e9 if avg_kernel_ms > 0 else 0.0
     src_hash = kernel_source_hash()
-    kernel_name = (f"k_verify_tiles<{plan.inline_lanes},{plan.inline_unroll}>" +
+    kernel_name = (f"k_verify_tiles<{plan.inline_lanes},{plan.hard_lanes}>" +
                    (" + k_verify_deferred" if deferred else ""))
     traffic = traffic_from_profiles(src_hash, args.workload, kernel_name)
 

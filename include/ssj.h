@@ -158,9 +158,11 @@ int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, int wait, uint64_t* t_submit
  * Execution plan.  Verification runs as one or two kernels per launch:
  *  1. an in-order kernel walks the candidates in tiles of consecutive pairs
  *     and verifies each pair with inline_lanes lanes (1 = one thread per
- *     pair, a sequential early-exit merge, inline_unroll pairs per thread
- *     advanced in lockstep; 4..64 = a group of lanes of one wavefront per
- *     pair, intersecting tile by tile);
+ *     pair, a sequential early-exit merge; 4..64 = a group of lanes of one
+ *     wavefront per pair, intersecting tile by tile).  With one thread per
+ *     pair and hard_lanes > 0, a merge that outruns the six tokens kept in a
+ *     set's record is handed, with its state, to groups of hard_lanes lanes
+ *     of the same workgroup (0: the thread continues on the token array);
  *  2. pairs whose length class (by |r| + |s|, inclusive upper bounds
  *     SSJ_CLASS_BOUNDS) is defer_from or higher are not verified by (1) but
  *     queued per class; a persistent kernel then drains each class with
@@ -176,7 +178,7 @@ int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, int wait, uint64_t* t_submit
 
 typedef struct {
     int inline_lanes;            /* 1, 4, 8, 16, 32 or 64 */
-    int inline_unroll;           /* 1, 2 or 4 with inline_lanes == 1, else 1 */
+    int hard_lanes;              /* 0, 8 or 16 with inline_lanes == 1, else 0 */
     int defer_from;              /* 0 .. SSJ_N_CLASSES */
     int lanes[SSJ_N_CLASSES];    /* per deferred class: 1, 4, 8, 16, 32, 64 or 256 */
     int use_graph;
@@ -213,9 +215,10 @@ int ssj_verify_batch_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_reques
  * Autotuner: times candidate plans on the given device candidates (which
  * should be representative of the workload; a few million pairs suffice) and
  * returns the fastest in *best (its kernel time per launch in *best_ms).
- * apply != 0 also makes it the context's plan.  The search first picks the
- * in-order mapping, then tries deferring the longer length classes, one
- * class at a time, with the mappings suited to each length.  Synchronous.
+ * apply != 0 also makes it the context's plan.  The search times every
+ * in-order mapping with every deferral point (deferred classes starting from
+ * mappings suited to their lengths), then refines the mapping of each
+ * deferred class of the best plan, one class at a time.  Synchronous.
  */
 int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
                  int64_t t_num, int64_t t_den, int apply, ssj_plan* best, double* best_ms);

@@ -105,10 +105,10 @@ __device__ __forceinline__ bool merge_thread(const int32_t* __restrict__ A, uint
 template <int G>
 __device__ __forceinline__ bool merge_group(const int32_t* __restrict__ A, uint32_t na,
                                             const int32_t* __restrict__ B, uint32_t nb,
-                                            uint32_t alpha, int g, int gbase) {
+                                            uint32_t alpha, int g, int gbase, uint32_t i = 0,
+                                            uint32_t j = 0, uint32_t o = 0) {
     const unsigned long long gmask =
         (G == kWave) ? ~0ull : (((1ull << (G % kWave)) - 1ull) << gbase);
-    uint32_t i = 0, j = 0, o = 0;
     for (;;) {
         if (o >= alpha) return true;
         const uint32_t ra = na - i, rb = nb - j;
@@ -369,13 +369,19 @@ __device__ __forceinline__ void issue_records(const LaunchArgs& a, const int2* p
 }
 
 // Thread-per-pair verification of the lane's U pairs (wbase + u*64 + lane)
-// from their records; the merges advance in lockstep.
-template <int U>
+// from their records; the merges advance in lockstep.  F == 0: a merge that
+// outruns the tokens held in a record continues on the token array.  F > 0: a
+// pair still undecided at that point is appended, with its merge state, to
+// the workgroup's list of hard pairs, finished by groups of F lanes
+// (finish_hard), so that no lane walks the token array alone while the rest
+// of its wavefront waits.
+template <int U, int F>
 __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Request& R, int r,
                                                   uint32_t wbase, const int2* pr,
                                                   const LaneRecords<U>& rec, bool deferring,
                                                   uint32_t* s_defer, uint32_t* s_dcnt, int2* s_out,
-                                                  uint32_t* s_ocnt) {
+                                                  uint32_t* s_ocnt, int2* s_hpr, uint32_t* s_hst,
+                                                  uint32_t* s_hcnt) {
     const int lane = lane_id();
     bool ok[U], bad = false;
 #pragma unroll
@@ -386,7 +392,7 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
         bad |= valid && !ok[u];
     }
     uint32_t na[U], nb[U], alpha[U], i[U], j[U], o[U];
-    bool act[U], pass[U], defer[U];
+    bool act[U], pass[U], defer[U], hard[U];
     int cls[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -394,7 +400,7 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
         cls[u] = deferring ? class_of(L, a) : 0;
         defer[u] = ok[u] && deferring && cls[u] >= a.defer_from;
         act[u] = ok[u] && !defer[u];
-        pass[u] = false;
+        pass[u] = hard[u] = false;
         na[u] = rec.ra0[u].y;
         nb[u] = rec.rb0[u].y;
         alpha[u] = act[u] ? required_overlap(L, R.tn, R.tsum) : 0u;
@@ -410,6 +416,9 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
                     act[u] = false;
                 } else if (o[u] + min(na[u] - i[u], nb[u] - j[u]) < alpha[u]) {
                     act[u] = false;
+                } else if (F > 0 && (i[u] >= kHeadTokens || j[u] >= kHeadTokens)) {
+                    hard[u] = true;
+                    act[u] = false;
                 }
             }
             any |= act[u];
@@ -418,8 +427,14 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (act[u]) {
-                const int32_t x = record_token(a, rec.ra0[u], rec.ra1[u], i[u]);
-                const int32_t y = record_token(a, rec.rb0[u], rec.rb1[u], j[u]);
+                int32_t x, y;
+                if constexpr (F > 0) {
+                    x = head_token(rec.ra0[u], rec.ra1[u], i[u]);
+                    y = head_token(rec.rb0[u], rec.rb1[u], j[u]);
+                } else {
+                    x = record_token(a, rec.ra0[u], rec.ra1[u], i[u]);
+                    y = record_token(a, rec.rb0[u], rec.rb1[u], j[u]);
+                }
                 i[u] += (x <= y);
                 j[u] += (y <= x);
                 o[u] += (x == y);
@@ -431,10 +446,45 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
     if (bad) atomicOr(&a.ctr->err[r], 1u);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+        if constexpr (F > 0) {
+            const unsigned long long m = ballot(hard[u]);
+            if (m != 0ull) {
+                const int leader = __builtin_ctzll(m);
+                uint32_t pos = 0;
+                if (lane == leader) pos = atomicAdd(s_hcnt, (uint32_t)__popcll(m));
+                pos = (uint32_t)bperm((int)pos, leader) + mbcnt(m);
+                if (hard[u]) {
+                    s_hpr[pos] = pr[u];
+                    s_hst[pos] = i[u] | (j[u] << 8) | (o[u] << 16);  // each <= kHeadTokens
+                }
+            }
+        }
         stage_wave(pass[u], pr[u], s_out, s_ocnt, R.cap == 0);
         if (deferring)
             defer_wave(a, defer[u], cls[u], a.pair_off[r] + wbase + (uint32_t)(u * kWave + lane),
                        s_defer, s_dcnt);
+    }
+}
+
+// Finishes the workgroup's hard pairs of this tile: groups of G lanes resume
+// their merges from the saved state with the tile merge.
+template <int G>
+__device__ __forceinline__ void finish_hard(const LaunchArgs& a, const Request& R, uint32_t h,
+                                            const int2* s_hpr, const uint32_t* s_hst, int2* s_out,
+                                            uint32_t* s_ocnt) {
+    const int lane = lane_id();
+    const int g = lane % G, gbase = (lane / G) * G;
+    const uint32_t gid = threadIdx.x / G;
+    constexpr uint32_t kGroups = kBlock / G;
+    for (uint32_t e = gid; e < h; e += kGroups) {
+        const int2 pq = s_hpr[e];
+        const uint32_t st = s_hst[e];
+        const uint2 dr = set_desc(a, pq.x);
+        const uint2 ds = set_desc(a, pq.y);
+        const uint32_t alpha = required_overlap(dr.y + ds.y, R.tn, R.tsum);
+        const bool pass = merge_group<G>(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, g, gbase,
+                                         st & 0xffu, (st >> 8) & 0xffu, st >> 16);
+        stage_wave(pass && g == 0, pq, s_out, s_ocnt, R.cap == 0);
     }
 }
 
@@ -443,8 +493,9 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
 // request.  G == 1: tile = kBlock * U pairs, wavefront w takes U runs of 64
 // pairs.  G > 1 (U == 1): tile = kBlock pairs, wavefront w takes the pairs
 // w*64 .. w*64+63, 64/G at a time.
-template <int G, int U>
+template <int G, int F>
 __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
+    constexpr int U = 1;
     constexpr int GPW = kWave / G;
     constexpr uint32_t kTilePairs = (uint32_t)kBlock * U;
     constexpr uint32_t kStage = 2 * kTilePairs;  // staged output pairs per workgroup
@@ -457,9 +508,16 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     __shared__ uint32_t s_ocnt;
     __shared__ uint32_t s_base;
     __shared__ unsigned long long s_obase;
+    // hard pairs of the current tile (thread-per-pair mapping with F > 0)
+    __shared__ int2 s_hpr[F > 0 ? kTilePairs : 1];
+    __shared__ uint32_t s_hst[F > 0 ? kTilePairs : 1];
+    __shared__ uint32_t s_hcnt;
     const bool deferring = a.defer_from < kClasses;
     if (threadIdx.x < kClasses) s_dcnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) s_ocnt = 0;
+    if (threadIdx.x == 0) {
+        s_ocnt = 0;
+        s_hcnt = 0;
+    }
     __syncthreads();
     const int w = (int)(threadIdx.x >> 6);
     const int lane = lane_id();
@@ -496,8 +554,17 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
             issue_records<U>(a, p1, rec1);
             tile_origin<U>(a, min(Tn + gridDim.x, n_tiles - 1), w, &r2, &wb2);
             load_lane_pairs<U>(a.req[r2], wb2, lane, p2);
-            tile_thread_pairs<U>(a, a.req[r], r, wbase, p0, rec0, deferring, s_defer, s_dcnt, s_out,
-                                 &s_ocnt);
+            tile_thread_pairs<U, F>(a, a.req[r], r, wbase, p0, rec0, deferring, s_defer, s_dcnt,
+                                    s_out, &s_ocnt, s_hpr, s_hst, &s_hcnt);
+            if constexpr (F > 0) {
+                __syncthreads();
+                const uint32_t h = s_hcnt;
+                if (h > 0) {
+                    finish_hard<F>(a, a.req[r], h, s_hpr, s_hst, s_out, &s_ocnt);
+                    __syncthreads();
+                    if (threadIdx.x == 0) s_hcnt = 0;
+                }
+            }
             // rotate the pipeline
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -709,24 +776,26 @@ bool lanes_supported(int lanes) {
     }
 }
 
-bool inline_supported(int lanes, int unroll) { return kernel_verify_tiles(lanes, unroll) != nullptr; }
+bool inline_supported(int lanes, int hard_lanes) {
+    return kernel_verify_tiles(lanes, hard_lanes) != nullptr;
+}
 
-const void* kernel_verify_tiles(int lanes, int unroll) {
+const void* kernel_verify_tiles(int lanes, int hard_lanes) {
     if (lanes == 1) {
-        switch (unroll) {
-            case 1: return (const void*)&k_verify_tiles<1, 1>;
-            case 2: return (const void*)&k_verify_tiles<1, 2>;
-            case 4: return (const void*)&k_verify_tiles<1, 4>;
+        switch (hard_lanes) {
+            case 0: return (const void*)&k_verify_tiles<1, 0>;
+            case 8: return (const void*)&k_verify_tiles<1, 8>;
+            case 16: return (const void*)&k_verify_tiles<1, 16>;
             default: return nullptr;
         }
     }
-    if (unroll != 1) return nullptr;
+    if (hard_lanes != 0) return nullptr;
     switch (lanes) {
-        case 4: return (const void*)&k_verify_tiles<4, 1>;
-        case 8: return (const void*)&k_verify_tiles<8, 1>;
-        case 16: return (const void*)&k_verify_tiles<16, 1>;
-        case 32: return (const void*)&k_verify_tiles<32, 1>;
-        case 64: return (const void*)&k_verify_tiles<64, 1>;
+        case 4: return (const void*)&k_verify_tiles<4, 0>;
+        case 8: return (const void*)&k_verify_tiles<8, 0>;
+        case 16: return (const void*)&k_verify_tiles<16, 0>;
+        case 32: return (const void*)&k_verify_tiles<32, 0>;
+        case 64: return (const void*)&k_verify_tiles<64, 0>;
         default: return nullptr;
     }
 }
@@ -744,14 +813,14 @@ hipError_t launch_build_heads(const int64_t* d_offsets, const int32_t* d_tok, ui
 }
 
 size_t tiles_lds_bytes(const LaunchArgs& a) {
-    const size_t tile = (size_t)kBlock * (a.inline_lanes == 1 ? (size_t)a.inline_unroll : 1u);
+    const size_t tile = (size_t)kBlock;
     const size_t stage = 2 * tile * sizeof(int2);
     const size_t defer = a.defer_from < kClasses ? (size_t)(kClasses - a.defer_from) * a.defer_cap * 4u : 0u;
     return stage + defer;
 }
 
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st) {
-    const void* f = kernel_verify_tiles(a.inline_lanes, a.inline_unroll);
+    const void* f = kernel_verify_tiles(a.inline_lanes, a.hard_lanes);
     if (!f) return hipErrorInvalidValue;
     LaunchArgs args = a;
     void* params[] = {&args};

@@ -80,10 +80,10 @@ struct Scratch {
 };
 
 struct GraphKey {
-    int inline_lanes, inline_unroll, defer_from, grid1, grid2;
+    int inline_lanes, hard_lanes, defer_from, grid1, grid2;
     bool operator<(const GraphKey& o) const {
-        return std::tie(inline_lanes, inline_unroll, defer_from, grid1, grid2) <
-               std::tie(o.inline_lanes, o.inline_unroll, o.defer_from, o.grid1, o.grid2);
+        return std::tie(inline_lanes, hard_lanes, defer_from, grid1, grid2) <
+               std::tie(o.inline_lanes, o.hard_lanes, o.defer_from, o.grid1, o.grid2);
     }
 };
 
@@ -159,8 +159,8 @@ int hip_fail(ssj_ctx* ctx, const char* what, hipError_t e) {
     } while (0)
 
 // index of an in-order mapping in occ_tiles
-int inline_index(int lanes, int unroll) {
-    if (lanes == 1) return unroll == 1 ? 0 : (unroll == 2 ? 6 : 7);
+int inline_index(int lanes, int hard_lanes) {
+    if (lanes == 1) return hard_lanes == 0 ? 0 : (hard_lanes == 8 ? 6 : 7);
     switch (lanes) {
         case 4: return 1;
         case 8: return 2;
@@ -172,7 +172,7 @@ int inline_index(int lanes, int unroll) {
 }
 
 const int kInlineLanes[8] = {1, 4, 8, 16, 32, 64, 1, 1};
-const int kInlineUnroll[8] = {1, 1, 1, 1, 1, 1, 2, 4};
+const int kInlineHard[8] = {0, 0, 0, 0, 0, 0, 8, 16};
 
 int scratch_init(ssj_ctx* ctx, Scratch& s) {
     HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_ctr, sizeof(ssj::Counters)));
@@ -189,7 +189,7 @@ void scratch_free(Scratch& s) {
 
 void default_plan(ssj_plan& p) {
     p.inline_lanes = 1;
-    p.inline_unroll = 2;
+    p.hard_lanes = 0;
     p.defer_from = 3;
     const int lanes[ssj::kClasses] = {4, 16, 64, ssj::kBlock, ssj::kBlock};
     for (int q = 0; q < ssj::kClasses; ++q) p.lanes[q] = lanes[q];
@@ -197,7 +197,7 @@ void default_plan(ssj_plan& p) {
 }
 
 bool plan_valid(const ssj_plan& p) {
-    if (!ssj::inline_supported(p.inline_lanes, p.inline_unroll)) return false;
+    if (!ssj::inline_supported(p.inline_lanes, p.hard_lanes)) return false;
     if (p.defer_from < 0 || p.defer_from > ssj::kClasses) return false;
     for (int q = 0; q < ssj::kClasses; ++q)
         if (!ssj::lanes_supported(p.lanes[q])) return false;
@@ -236,8 +236,8 @@ int check_req(const Req& r) {
     return SSJ_OK;
 }
 
-int grid_tiles(const ssj_ctx* ctx, int lanes, int unroll, int64_t n_tiles) {
-    const int64_t cap = (int64_t)ctx->n_cu * std::max(1, ctx->occ_tiles[inline_index(lanes, unroll)]);
+int grid_tiles(const ssj_ctx* ctx, int lanes, int hard_lanes, int64_t n_tiles) {
+    const int64_t cap = (int64_t)ctx->n_cu * std::max(1, ctx->occ_tiles[inline_index(lanes, hard_lanes)]);
     return (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, cap));
 }
 
@@ -245,14 +245,14 @@ int grid_deferred(const ssj_ctx* ctx) { return ctx->n_cu * std::max(1, ctx->occ_
 
 int launch_graph(ssj_ctx* ctx, const ssj::LaunchArgs& a, int g1, int g2, bool two,
                  hipStream_t st) {
-    GraphKey key{a.inline_lanes, a.inline_unroll, a.defer_from, g1, two ? g2 : 0};
+    GraphKey key{a.inline_lanes, a.hard_lanes, a.defer_from, g1, two ? g2 : 0};
     ssj::LaunchArgs args = a;
     void* kparams[] = {&args};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         GraphEntry ge;
         HIP_OR_FAIL(ctx, hipGraphCreate(&ge.graph, 0));
-        const void* funcs[3] = {ssj::kernel_verify_tiles(a.inline_lanes, a.inline_unroll),
+        const void* funcs[3] = {ssj::kernel_verify_tiles(a.inline_lanes, a.hard_lanes),
                                 ssj::kernel_verify_deferred(), ssj::kernel_finalize()};
         const int grids[3] = {g1, g2, 1};
         const int blocks[3] = {ssj::kBlock, ssj::kBlock, ssj::kWave};
@@ -296,8 +296,8 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     a.n_req = n_req;
     a.defer_from = plan.defer_from;
     a.inline_lanes = plan.inline_lanes;
-    a.inline_unroll = plan.inline_unroll;
-    const uint64_t tile_pairs = (uint64_t)ssj::kBlock * (plan.inline_lanes == 1 ? plan.inline_unroll : 1);
+    a.hard_lanes = plan.hard_lanes;
+    const uint64_t tile_pairs = (uint64_t)ssj::kBlock;
     a.defer_cap = (uint32_t)(2 * tile_pairs);
     const uint32_t bounds[ssj::kClasses] = SSJ_CLASS_BOUNDS;
     for (int q = 0; q < ssj::kClasses; ++q) {
@@ -328,7 +328,7 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     }
     a.queues = sc.d_queues;
     a.qcap = (uint32_t)(sc.q_cap / ssj::kClasses);
-    const int g1 = grid_tiles(ctx, plan.inline_lanes, plan.inline_unroll, (int64_t)tiles);
+    const int g1 = grid_tiles(ctx, plan.inline_lanes, plan.hard_lanes, (int64_t)tiles);
     const int g2 = grid_deferred(ctx);
 
     std::array<hipEvent_t, 3> ev{nullptr, nullptr, nullptr};
@@ -704,7 +704,7 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
         ctx->n_cu = prop.multiProcessorCount;
         for (int k = 0; k < 8 && rc == SSJ_OK; ++k) {
             int occ = 0;
-            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_tiles(kInlineLanes[k], kInlineUnroll[k]), ssj::kBlock, 0)) != hipSuccess)
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_tiles(kInlineLanes[k], kInlineHard[k]), ssj::kBlock, 0)) != hipSuccess)
                 rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
             ctx->occ_tiles[k] = occ;
         }
@@ -859,8 +859,8 @@ int ssj_get_plan(ssj_ctx* ctx, ssj_plan* plan) {
 int ssj_set_plan(ssj_ctx* ctx, const ssj_plan* plan) {
     if (!ctx || !plan) return set_error(SSJ_EINVAL, "null argument");
     if (!plan_valid(*plan))
-        return set_error(SSJ_EINVAL, "inline_lanes must be 1, 4, 8, 16, 32 or 64 (inline_unroll "
-                                     "1, 2 or 4 with 1 lane, else 1); defer_from in [0, 5]; "
+        return set_error(SSJ_EINVAL, "inline_lanes must be 1, 4, 8, 16, 32 or 64 (hard_lanes 0, 8 "
+                                     "or 16 with 1 lane, else 0); defer_from in [0, 5]; "
                                      "lanes 1, 4, 8, 16, 32, 64 or 256");
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->plan = *plan;
@@ -1026,41 +1026,41 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
         *ms = bestt;
         return SSJ_OK;
     };
+    // 1) every in-order mapping with every deferral point (deferred classes
+    //    start from mappings suited to their lengths)
+    static const int kDeferredDefault[ssj::kClasses] = {4, 8, 16, 32, 64};
     ssj_plan cur = ctx->plan;
-    cur.defer_from = ssj::kClasses;
     double cur_ms = 1e30;
-    // 1) the in-order mapping, nothing deferred
-    for (int k : {0, 6, 7, 1, 2, 3, 4}) {
-        ssj_plan p = cur;
-        p.inline_lanes = kInlineLanes[k];
-        p.inline_unroll = kInlineUnroll[k];
-        double ms = 0;
-        if ((rc = measure(p, &ms)) != SSJ_OK) break;
-        if (ms < cur_ms) {
-            cur_ms = ms;
-            cur = p;
-        }
-    }
-    // 2) defer the longer classes, one more class at a time (longest first),
-    //    each with the mappings suited to its lengths
-    static const int options[ssj::kClasses][3] = {
-        {4, 8, 16}, {8, 16, 32}, {16, 32, 64}, {64, 256, 32}, {256, 64, 32}};
-    for (int q = ssj::kClasses - 1; q >= 1 && rc == SSJ_OK; --q) {
-        const ssj_plan base = cur;
-        bool improved = false;
-        for (int k = 0; k < 3 && rc == SSJ_OK; ++k) {
-            ssj_plan p = base;
-            p.defer_from = q;
-            p.lanes[q] = options[q][k];
+    for (int k = 0; k < 8 && rc == SSJ_OK; ++k) {
+        for (int d = ssj::kClasses; d >= 1 && rc == SSJ_OK; --d) {
+            ssj_plan p = ctx->plan;
+            p.inline_lanes = kInlineLanes[k];
+            p.hard_lanes = kInlineHard[k];
+            p.defer_from = d;
+            for (int q = 0; q < ssj::kClasses; ++q) p.lanes[q] = kDeferredDefault[q];
             double ms = 0;
             if ((rc = measure(p, &ms)) != SSJ_OK) break;
-            if (ms < cur_ms * 0.98) {
+            if (ms < cur_ms) {
                 cur_ms = ms;
                 cur = p;
-                improved = true;
             }
         }
-        if (!improved) break;
+    }
+    // 2) refine the mapping of each deferred class, one class at a time
+    static const int kDeferredOptions[6] = {4, 8, 16, 32, 64, ssj::kBlock};
+    for (int q = cur.defer_from; q < ssj::kClasses && rc == SSJ_OK; ++q) {
+        const ssj_plan base = cur;
+        for (int o : kDeferredOptions) {
+            if (o == base.lanes[q]) continue;
+            ssj_plan p = base;
+            p.lanes[q] = o;
+            double ms = 0;
+            if ((rc = measure(p, &ms)) != SSJ_OK) break;
+            if (ms < cur_ms * 0.99) {
+                cur_ms = ms;
+                cur = p;
+            }
+        }
     }
     ctx->timing_period = timing_was;
     (void)hipEventDestroy(e0);

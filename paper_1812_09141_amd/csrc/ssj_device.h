@@ -46,7 +46,7 @@ struct LaunchArgs {
     int n_req;
     int defer_from;                      // first deferred class (kClasses: none)
     int inline_lanes;                    // lanes per pair in the in-order kernel
-    int inline_unroll;                   // pairs per lane at a time (inline_lanes == 1)
+    int hard_lanes;                      // lanes finishing long merges (inline_lanes == 1)
     uint32_t defer_cap;                  // LDS queue entries per deferred class (>= 2 tiles)
     uint32_t tile_off[kMaxReq + 1];      // prefix sums of per-request tiles (of tile_pairs)
     uint32_t pair_off[kMaxReq + 1];      // prefix sums of per-request pairs
@@ -70,11 +70,11 @@ size_t tiles_lds_bytes(const LaunchArgs& a);
 // Publishes the request counts and resets the counters (always last).
 hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st);
 
-const void* kernel_verify_tiles(int lanes, int unroll);
+const void* kernel_verify_tiles(int lanes, int hard_lanes);
 const void* kernel_verify_deferred();
 const void* kernel_finalize();
 
 bool lanes_supported(int lanes);              // deferred classes: 1..64 or kBlock
-bool inline_supported(int lanes, int unroll);  // in-order kernel: 1..64; unroll 1,2,4 for 1 lane
+bool inline_supported(int lanes, int hard_lanes);  // in-order kernel: 1..64; 0/8/16 hard lanes with 1
 
 }  // namespace ssj

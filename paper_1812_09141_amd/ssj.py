@@ -65,12 +65,12 @@ class ssj_opts(ctypes.Structure):
 
 
 class ssj_plan(ctypes.Structure):
-    _fields_ = [("inline_lanes", ctypes.c_int), ("inline_unroll", ctypes.c_int),
+    _fields_ = [("inline_lanes", ctypes.c_int), ("hard_lanes", ctypes.c_int),
                 ("defer_from", ctypes.c_int), ("lanes", ctypes.c_int * SSJ_N_CLASSES),
                 ("use_graph", ctypes.c_int)]
 
     def as_dict(self):
-        return {"inline_lanes": self.inline_lanes, "inline_unroll": self.inline_unroll,
+        return {"inline_lanes": self.inline_lanes, "hard_lanes": self.hard_lanes,
                 "defer_from": self.defer_from, "lanes": list(self.lanes),
                 "use_graph": self.use_graph}
 
@@ -255,10 +255,10 @@ def ssj_get_plan(ctx) -> ssj_plan:
 
 
 def make_plan(inline_lanes: int = 1, defer_from: int = SSJ_N_CLASSES, lanes=(4, 16, 64, 256, 256),
-              use_graph: int = 0, inline_unroll: int = 1) -> ssj_plan:
+              use_graph: int = 0, hard_lanes: int = 0) -> ssj_plan:
     p = ssj_plan()
     p.inline_lanes = int(inline_lanes)
-    p.inline_unroll = int(inline_unroll)
+    p.hard_lanes = int(hard_lanes)
     p.defer_from = int(defer_from)
     for q in range(SSJ_N_CLASSES):
         p.lanes[q] = int(lanes[q])

@@ -49,9 +49,9 @@ def plans():
     out = [("default", None)]
     for L in [1, 4, 8, 16, 32, 64]:
         out.append((f"inline-{L}", dict(inline_lanes=L, defer_from=5)))
-    for U in [2, 4]:
-        out.append((f"inline-1x{U}", dict(inline_lanes=1, inline_unroll=U, defer_from=5)))
-        out.append((f"inline-1x{U}-defer", dict(inline_lanes=1, inline_unroll=U, defer_from=1,
+    for F in [8, 16]:
+        out.append((f"inline-1h{F}", dict(inline_lanes=1, hard_lanes=F, defer_from=5)))
+        out.append((f"inline-1h{F}-defer", dict(inline_lanes=1, hard_lanes=F, defer_from=1,
                                                  lanes=[4, 16, 32, 64, 256])))
     for L in ALL_LANES:
         out.append((f"deferred-all-{L}", dict(inline_lanes=4, defer_from=0, lanes=[L] * 5)))
@@ -64,7 +64,7 @@ def plans():
 
 def set_plan(S, ctx, plan):
     if plan is None:
-        S.ssj_set_plan(ctx, S.make_plan(inline_lanes=1, inline_unroll=2, defer_from=3,
+        S.ssj_set_plan(ctx, S.make_plan(inline_lanes=1, hard_lanes=16, defer_from=3,
                                          lanes=[4, 16, 64, 256, 256]))
     else:
         S.ssj_set_plan(ctx, S.make_plan(**plan))
