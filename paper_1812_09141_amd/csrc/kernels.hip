@@ -62,7 +62,8 @@ __device__ __forceinline__ uint32_t mbcnt(unsigned long long m) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Set record: {start, len, first kHeadTokens tokens} in two 16-byte words.
+// Set record: {start, len, first kHeadTokens tokens} in two 16-byte words
+// (slots past the end of a shorter set hold -1).
 __device__ __forceinline__ uint2 set_desc(const LaunchArgs& a, int id) {
     const uint4 v = a.heads[2 * id];
     return make_uint2(v.x, v.y);
@@ -77,6 +78,11 @@ __device__ __forceinline__ int32_t head_token(uint4 w0, uint4 w1, uint32_t i) {
     v = (i == 4) ? (int32_t)w1.z : v;
     v = (i == 5) ? (int32_t)w1.w : v;
     return v;
+}
+
+// Candidate pair k of a request.
+__device__ __forceinline__ int2 load_pair(const int2* __restrict__ cand, uint32_t k) {
+    return cand[k];
 }
 
 __device__ __forceinline__ uint32_t load_relaxed(const unsigned int* p) {
@@ -99,49 +105,80 @@ __device__ __forceinline__ bool merge_thread(const int32_t* __restrict__ A, uint
     }
 }
 
-// G lanes of one wavefront (lanes gbase .. gbase+G-1, g = lane - gbase):
-// tile merge.  Control flow is uniform inside the group, so the cross-lane
-// permutes only read lanes that are active.
+// One round of the tile merge of G lanes of one wavefront (lanes gbase ..
+// gbase+G-1, g = lane - gbase) at merge position (i, j): lane g holds a = A[i+g]
+// if g < ka and b = B[j+g] if g < kb.  Each lane finds its a-token in the
+// s tile by binary search over the lanes; the side whose tile ends lower is
+// consumed whole, the other up to that end, so an equal pair on the seam is
+// counted exactly once.  Control flow is uniform inside the group, so the
+// cross-lane permutes only read lanes that are active.
+template <int G>
+__device__ __forceinline__ void group_round(int32_t a, int32_t b, int ka, int kb, int g, int gbase,
+                                            uint32_t& i, uint32_t& j, uint32_t& o) {
+    const unsigned long long gmask =
+        (G == kWave) ? ~0ull : (((1ull << (G % kWave)) - 1ull) << gbase);
+    const bool va = g < ka, vb = g < kb;
+    const int32_t amax = bperm(a, gbase + ka - 1);
+    const int32_t bmax = bperm(b, gbase + kb - 1);
+    // pos = number of s-tile tokens below a (capped at G-1)
+    int pos = 0;
+#pragma unroll
+    for (int step = G / 2; step >= 1; step >>= 1) {
+        const int k = pos + step - 1;
+        const int32_t v = bperm(b, gbase + k);
+        if (k < kb && v < a) pos += step;
+    }
+    const int32_t at = bperm(b, gbase + pos);
+    const bool hit = va && pos < kb && at == a;
+    const uint32_t nh = (uint32_t)__popcll(ballot(hit) & gmask);
+    const uint32_t na_le = (uint32_t)__popcll(ballot(va && a <= bmax) & gmask);
+    const uint32_t nb_le = (uint32_t)__popcll(ballot(vb && b <= amax) & gmask);
+    // value selects (branches that update i or j by reference end up as a
+    // select of addresses, which puts i and j in scratch memory)
+    const bool a_low = amax < bmax, b_low = bmax < amax;
+    i += b_low ? na_le : (uint32_t)ka;
+    j += a_low ? nb_le : (uint32_t)kb;
+    o += nh;
+}
+
+// Tile merge of G lanes from merge state (i, j, o), loading each tile.
 template <int G>
 __device__ __forceinline__ bool merge_group(const int32_t* __restrict__ A, uint32_t na,
                                             const int32_t* __restrict__ B, uint32_t nb,
                                             uint32_t alpha, int g, int gbase, uint32_t i = 0,
                                             uint32_t j = 0, uint32_t o = 0) {
-    const unsigned long long gmask =
-        (G == kWave) ? ~0ull : (((1ull << (G % kWave)) - 1ull) << gbase);
     for (;;) {
         if (o >= alpha) return true;
         const uint32_t ra = na - i, rb = nb - j;
         if (o + min(ra, rb) < alpha) return false;
         const int ka = (int)min(ra, (uint32_t)G), kb = (int)min(rb, (uint32_t)G);
-        const bool va = g < ka, vb = g < kb;
-        const int32_t a = va ? A[i + g] : 0;
-        const int32_t b = vb ? B[j + g] : 0;
-        const int32_t amax = bperm(a, gbase + ka - 1);
-        const int32_t bmax = bperm(b, gbase + kb - 1);
-        // pos = number of s-tile tokens below a (capped at G-1)
-        int pos = 0;
-#pragma unroll
-        for (int step = G / 2; step >= 1; step >>= 1) {
-            const int k = pos + step - 1;
-            const int32_t v = bperm(b, gbase + k);
-            if (k < kb && v < a) pos += step;
-        }
-        const int32_t at = bperm(b, gbase + pos);
-        const bool hit = va && pos < kb && at == a;
-        const uint32_t nh = (uint32_t)__popcll(ballot(hit) & gmask);
-        if (amax < bmax) {
-            i += (uint32_t)ka;
-            j += (uint32_t)__popcll(ballot(vb && b <= amax) & gmask);
-        } else if (bmax < amax) {
-            j += (uint32_t)kb;
-            i += (uint32_t)__popcll(ballot(va && a <= bmax) & gmask);
-        } else {
-            i += (uint32_t)ka;
-            j += (uint32_t)kb;
-        }
-        o += nh;
+        const int32_t a = g < ka ? A[i + g] : 0;
+        const int32_t b = g < kb ? B[j + g] : 0;
+        group_round<G>(a, b, ka, kb, g, gbase, i, j, o);
     }
+}
+
+// The same merge from the start, with the first tiles already loaded by the
+// caller: a0 = A[min(g, na-1)], b0 = B[min(g, nb-1)] (a software pipeline
+// issues them one pair ahead, so a pair decided within its first tiles waits
+// for no load).
+template <int G>
+__device__ __forceinline__ bool merge_group_first(const int32_t* __restrict__ A, uint32_t na,
+                                                  const int32_t* __restrict__ B, uint32_t nb,
+                                                  uint32_t alpha, int g, int gbase, int32_t a0,
+                                                  int32_t b0) {
+    if (alpha == 0u) return true;
+    if (min(na, nb) < alpha) return false;
+    const int ka = (int)min(na, (uint32_t)G), kb = (int)min(nb, (uint32_t)G);
+    uint32_t i = 0, j = 0, o = 0;
+    group_round<G>(g < ka ? a0 : 0, g < kb ? b0 : 0, ka, kb, g, gbase, i, j, o);
+    return merge_group<G>(A, na, B, nb, alpha, g, gbase, i, j, o);
+}
+
+// Token min(g, n-1) of a set with descriptor d = (start, n), n >= 1: the
+// lane's token of the set's first tile (clamped, so the load is unconditional).
+__device__ __forceinline__ int32_t first_tile_token(const int32_t* __restrict__ tok, uint2 d, int g) {
+    return tok[d.x + min((uint32_t)g, d.y - 1u)];
 }
 
 // Whole workgroup: the tile merge with kBlock-token tiles, the s tile in LDS.
@@ -187,36 +224,9 @@ __device__ bool merge_block(const int32_t* __restrict__ A, uint32_t na,
             nb_le += red[q * 3 + 2];
         }
         __syncthreads();  // sb and red are rewritten by the next round
-        if (amax < bmax) {
-            i += (uint32_t)ka;
-            j += nb_le;
-        } else if (bmax < amax) {
-            j += (uint32_t)kb;
-            i += na_le;
-        } else {
-            i += (uint32_t)ka;
-            j += (uint32_t)kb;
-        }
+        i += bmax < amax ? na_le : (uint32_t)ka;
+        j += amax < bmax ? nb_le : (uint32_t)kb;
         o += nh;
-    }
-}
-
-// Appends the pairs of the lanes with pass set (one request); wavefront
-// compaction with a single atomic add.
-__device__ __forceinline__ void append_wave(bool pass, int2 pr, int2* out, unsigned long long cap,
-                                            unsigned long long* counter) {
-    const unsigned long long m = ballot(pass);
-    if (m == 0ull) return;
-    const int lane = lane_id();
-    const int leader = __builtin_ctzll(m);
-    unsigned long long base = 0ull;
-    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
-    const uint32_t lo = (uint32_t)bperm((int)(uint32_t)base, leader);
-    const uint32_t hi = (uint32_t)bperm((int)(uint32_t)(base >> 32), leader);
-    base = ((unsigned long long)hi << 32) | lo;
-    if (pass) {
-        const unsigned long long k = base + mbcnt(m);
-        if (k < cap) out[k] = pr;
     }
 }
 
@@ -260,16 +270,6 @@ __device__ __forceinline__ int request_of_pair(uint32_t gi, const LaunchArgs& a)
     int r = 0;
     for (int q = 1; q < a.n_req; ++q) r += (gi >= a.pair_off[q]) ? 1 : 0;
     return r;
-}
-
-template <int G>
-__device__ __forceinline__ bool verify_lanes(const LaunchArgs& a, uint2 dr, uint2 ds,
-                                             uint32_t alpha, int g, int gbase) {
-    if constexpr (G == 1) {
-        return merge_thread(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha);
-    } else {
-        return merge_group<G>(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, g, gbase);
-    }
 }
 
 // Moves the workgroup's c staged output pairs (request r) to the request's
@@ -336,7 +336,7 @@ __device__ __forceinline__ void load_lane_pairs(const Request& R, uint32_t wbase
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const uint32_t k = wbase + (uint32_t)(u * kWave + lane);
-        pr[u] = R.cand[k < R.n ? k : R.n - 1];
+        pr[u] = load_pair(R.cand, k < R.n ? k : R.n - 1);
     }
 }
 
@@ -368,13 +368,48 @@ __device__ __forceinline__ void issue_records(const LaunchArgs& a, const int2* p
     }
 }
 
+// Merge state after the first tile of one side is consumed, with the six
+// record tokens of each side as the tiles (the tile merge of merge_group,
+// done by one lane in straight-line code): with m the smaller of the two
+// tile ends, the merge has consumed every token <= m of both tiles, and the
+// overlap so far is the number of equal tokens in the two tiles (all of them
+// are <= m).  Record slots past the end of a set hold -1; tokens are >= 0, so
+// unsigned comparisons with m >= 0 leave those slots out of both counts.
+__device__ __forceinline__ void head_tiles(uint4 a0, uint4 a1, uint4 b0, uint4 b1, uint32_t* i,
+                                           uint32_t* j, uint32_t* o) {
+    const int32_t A[kHeadTokens] = {(int32_t)a0.z, (int32_t)a0.w, (int32_t)a1.x,
+                                    (int32_t)a1.y, (int32_t)a1.z, (int32_t)a1.w};
+    const int32_t B[kHeadTokens] = {(int32_t)b0.z, (int32_t)b0.w, (int32_t)b1.x,
+                                    (int32_t)b1.y, (int32_t)b1.z, (int32_t)b1.w};
+    int32_t am = A[0], bm = B[0];
+#pragma unroll
+    for (int x = 1; x < kHeadTokens; ++x) {
+        am = max(am, A[x]);
+        bm = max(bm, B[x]);
+    }
+    const uint32_t m = (uint32_t)min(am, bm);
+    uint32_t ci = 0, cj = 0, co = 0;
+#pragma unroll
+    for (int x = 0; x < kHeadTokens; ++x) {
+        ci += ((uint32_t)A[x] <= m) ? 1u : 0u;
+        cj += ((uint32_t)B[x] <= m) ? 1u : 0u;
+        bool hit = false;
+#pragma unroll
+        for (int y = 0; y < kHeadTokens; ++y) hit |= A[x] == B[y];
+        co += (hit && A[x] >= 0) ? 1u : 0u;
+    }
+    *i = ci;
+    *j = cj;
+    *o = co;
+}
+
 // Thread-per-pair verification of the lane's U pairs (wbase + u*64 + lane)
-// from their records; the merges advance in lockstep.  F == 0: a merge that
-// outruns the tokens held in a record continues on the token array.  F > 0: a
-// pair still undecided at that point is appended, with its merge state, to
-// the workgroup's list of hard pairs, finished by groups of F lanes
-// (finish_hard), so that no lane walks the token array alone while the rest
-// of its wavefront waits.
+// from their records: first the head tiles (head_tiles), which decide most
+// pairs; a pair still undecided continues from that merge state.  F == 0: it
+// continues on the token array in the same lane.  F > 0: it is appended, with
+// its merge state, to the workgroup's list of hard pairs, finished by groups
+// of F lanes (finish_hard), so that no lane walks the token array alone while
+// the rest of its wavefront waits.
 template <int U, int F>
 __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Request& R, int r,
                                                   uint32_t wbase, const int2* pr,
@@ -392,52 +427,42 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
         bad |= valid && !ok[u];
     }
     uint32_t na[U], nb[U], alpha[U], i[U], j[U], o[U];
-    bool act[U], pass[U], defer[U], hard[U];
+    bool act[U], pass[U], defer[U];
     int cls[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const uint32_t L = rec.ra0[u].y + rec.rb0[u].y;
-        cls[u] = deferring ? class_of(L, a) : 0;
-        defer[u] = ok[u] && deferring && cls[u] >= a.defer_from;
-        act[u] = ok[u] && !defer[u];
-        pass[u] = hard[u] = false;
         na[u] = rec.ra0[u].y;
         nb[u] = rec.rb0[u].y;
-        alpha[u] = act[u] ? required_overlap(L, R.tn, R.tsum) : 0u;
-        i[u] = j[u] = o[u] = 0;
+        const uint32_t L = na[u] + nb[u];
+        cls[u] = deferring ? class_of(L, a) : 0;
+        defer[u] = ok[u] && deferring && cls[u] >= a.defer_from;
+        const bool run = ok[u] && !defer[u];
+        alpha[u] = run ? required_overlap(L, R.tn, R.tsum) : 0u;
+        head_tiles(rec.ra0[u], rec.ra1[u], rec.rb0[u], rec.rb1[u], &i[u], &j[u], &o[u]);
+        pass[u] = run && o[u] >= alpha[u];
+        act[u] = run && !pass[u] && o[u] + min(na[u] - i[u], nb[u] - j[u]) >= alpha[u];
     }
-    for (;;) {
-        bool any = false;
+    if constexpr (F == 0) {
+        for (;;) {
+            bool any = false;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (act[u]) {
-                if (o[u] >= alpha[u]) {
-                    pass[u] = true;
-                    act[u] = false;
-                } else if (o[u] + min(na[u] - i[u], nb[u] - j[u]) < alpha[u]) {
-                    act[u] = false;
-                } else if (F > 0 && (i[u] >= kHeadTokens || j[u] >= kHeadTokens)) {
-                    hard[u] = true;
-                    act[u] = false;
-                }
-            }
-            any |= act[u];
-        }
-        if (!any) break;
+            for (int u = 0; u < U; ++u) any |= act[u];
+            if (!any) break;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (act[u]) {
-                int32_t x, y;
-                if constexpr (F > 0) {
-                    x = head_token(rec.ra0[u], rec.ra1[u], i[u]);
-                    y = head_token(rec.rb0[u], rec.rb1[u], j[u]);
-                } else {
-                    x = record_token(a, rec.ra0[u], rec.ra1[u], i[u]);
-                    y = record_token(a, rec.rb0[u], rec.rb1[u], j[u]);
+            for (int u = 0; u < U; ++u) {
+                if (act[u]) {
+                    const int32_t x = record_token(a, rec.ra0[u], rec.ra1[u], i[u]);
+                    const int32_t y = record_token(a, rec.rb0[u], rec.rb1[u], j[u]);
+                    i[u] += (x <= y);
+                    j[u] += (y <= x);
+                    o[u] += (x == y);
+                    if (o[u] >= alpha[u]) {
+                        pass[u] = true;
+                        act[u] = false;
+                    } else if (o[u] + min(na[u] - i[u], nb[u] - j[u]) < alpha[u]) {
+                        act[u] = false;
+                    }
                 }
-                i[u] += (x <= y);
-                j[u] += (y <= x);
-                o[u] += (x == y);
             }
         }
     }
@@ -447,13 +472,13 @@ __device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Req
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         if constexpr (F > 0) {
-            const unsigned long long m = ballot(hard[u]);
+            const unsigned long long m = ballot(act[u]);
             if (m != 0ull) {
                 const int leader = __builtin_ctzll(m);
                 uint32_t pos = 0;
                 if (lane == leader) pos = atomicAdd(s_hcnt, (uint32_t)__popcll(m));
                 pos = (uint32_t)bperm((int)pos, leader) + mbcnt(m);
-                if (hard[u]) {
+                if (act[u]) {
                     s_hpr[pos] = pr[u];
                     s_hst[pos] = i[u] | (j[u] << 8) | (o[u] << 16);  // each <= kHeadTokens
                 }
@@ -542,7 +567,6 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
             load_lane_pairs<U>(a.req[r1], wb1, lane, p1);
         }
     }
-    int r_last = 0;
     for (uint32_t T = blockIdx.x; T < n_tiles; T += gridDim.x) {
         const int r = r_cur;
         const uint32_t wbase = wb_cur;
@@ -579,26 +603,32 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
         } else {
             if (Tn < n_tiles) tile_origin<U>(a, Tn, w, &r_cur, &wb_cur);
             const Request& R = a.req[r];
-            // sub-rounds of 64/G pairs: the pair of sub-round s + 2 and the
-            // set descriptors of s + 1 are loaded while s is merged (clamped,
-            // unconditional loads keep the issue order fixed)
+            // sub-rounds of 64/G pairs, software-pipelined: while sub-round s
+            // is merged, the first tiles of s + 1, the set descriptors of s + 2
+            // and the pair of s + 3 are in flight (clamped, unconditional loads
+            // keep the issue order fixed, so each wait covers only loads issued
+            // one sub-round earlier)
             auto pair_at = [&](int sub) -> int2 {
                 const uint32_t k = wbase + (uint32_t)(min(sub, G - 1) * GPW + grp);
-                return R.cand[k < R.n ? k : R.n - 1];
+                return load_pair(R.cand, k < R.n ? k : R.n - 1);
             };
             auto desc_of = [&](int2 pq, uint2* dr, uint2* ds) {
                 const bool ok = ids_ok(pq, a.n_sets);
                 *dr = set_desc(a, ok ? pq.x : 0);
                 *ds = set_desc(a, ok ? pq.y : 0);
             };
-            int2 pq0 = pair_at(0), pq1 = pair_at(1);
-            uint2 dr0, ds0;
+            int2 pq0 = pair_at(0), pq1 = pair_at(1), pq2 = pair_at(2);
+            uint2 dr0, ds0, dr1, ds1;
             desc_of(pq0, &dr0, &ds0);
+            desc_of(pq1, &dr1, &ds1);
+            int32_t wa0 = first_tile_token(a.tok, dr0, g), wb0 = first_tile_token(a.tok, ds0, g);
             bool bad = false;
             for (int sub = 0; sub < G; ++sub) {
-                const int2 pq2 = pair_at(sub + 2);
-                uint2 dr1, ds1;
-                desc_of(pq1, &dr1, &ds1);
+                const int2 pq3 = pair_at(sub + 3);
+                uint2 dr2, ds2;
+                desc_of(pq2, &dr2, &ds2);
+                const int32_t wa1 = first_tile_token(a.tok, dr1, g);
+                const int32_t wb1 = first_tile_token(a.tok, ds1, g);
                 const uint32_t k = wbase + (uint32_t)(sub * GPW + grp);
                 bool pass = false, defer = false;
                 int cls = 0;
@@ -611,8 +641,9 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                             defer = cls >= a.defer_from;
                         }
                         if (!defer)
-                            pass = verify_lanes<G>(a, dr0, ds0, required_overlap(L, R.tn, R.tsum), g,
-                                                   gbase);
+                            pass = merge_group_first<G>(a.tok + dr0.x, dr0.y, a.tok + ds0.x, ds0.y,
+                                                        required_overlap(L, R.tn, R.tsum), g, gbase,
+                                                        wa0, wb0);
                     } else {
                         bad = true;
                     }
@@ -622,8 +653,13 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                     defer_wave(a, defer && g == 0, cls, a.pair_off[r] + k, s_defer, s_dcnt);
                 pq0 = pq1;
                 pq1 = pq2;
+                pq2 = pq3;
                 dr0 = dr1;
                 ds0 = ds1;
+                dr1 = dr2;
+                ds1 = ds2;
+                wa0 = wa1;
+                wb0 = wb1;
             }
             if (bad && g == 0) atomicOr(&a.ctr->err[r], 1u);
         }
@@ -652,9 +688,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                 }
             }
         }
-        r_last = r;
     }
-    (void)r_last;
     if (deferring) {
         __syncthreads();
         for (int q = a.defer_from; q < kClasses; ++q) {
@@ -694,20 +728,71 @@ __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
     const int grp = lane / G, g = lane % G, gbase = grp * G;
     const uint32_t* queue = a.queues + (size_t)q * a.qcap;
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-    const uint32_t nwaves = (gridDim.x * kBlock) / kWave;
-    for (uint32_t t = wave * GPW; t < cnt; t += nwaves * GPW) {
-        const uint32_t k = t + (uint32_t)grp;
-        if (k < cnt) {
-            const uint32_t gi = queue[k];
-            const int r = request_of_pair(gi, a);
-            const Request& R = a.req[r];
-            const int2 pr = R.cand[gi - a.pair_off[r]];
-            const uint2 dr = set_desc(a, pr.x);
-            const uint2 ds = set_desc(a, pr.y);
-            const bool pass = verify_lanes<G>(a, dr, ds, required_overlap(dr.y + ds.y, R.tn, R.tsum),
-                                              g, gbase);
-            if (pass && g == 0) append_one(pr, R, &a.ctr->out_count[r]);
+    const uint32_t stride = (gridDim.x * kBlock) / kWave * GPW;
+    const uint32_t t0 = wave * GPW;
+    // Item s of the group is queue entry t0 + s * stride + grp.  Software
+    // pipeline: while item s is merged, the first tiles of s + 1, the set
+    // descriptors of s + 2, the pair of s + 3 and the queue entry of s + 4
+    // are in flight (loads clamped to the last entry, so every iteration
+    // issues the same loads in the same order).
+    auto entry_at = [&](uint32_t s) -> uint32_t {
+        const uint32_t k = t0 + s * stride + (uint32_t)grp;
+        return queue[min(k, cnt - 1u)];
+    };
+    auto pair_of = [&](uint32_t gi, int* r) -> int2 {
+        *r = request_of_pair(gi, a);
+        return load_pair(a.req[*r].cand, gi - a.pair_off[*r]);
+    };
+    uint32_t e3;
+    int2 p0, p1, p2;
+    int r0, r1, r2;
+    uint2 dr0, ds0, dr1, ds1;
+    int32_t wa0, wb0;
+    {
+        const uint32_t e0 = entry_at(0), e1 = entry_at(1), e2 = entry_at(2);
+        e3 = entry_at(3);
+        p0 = pair_of(e0, &r0);
+        p1 = pair_of(e1, &r1);
+        p2 = pair_of(e2, &r2);
+        dr0 = set_desc(a, p0.x);
+        ds0 = set_desc(a, p0.y);
+        dr1 = set_desc(a, p1.x);
+        ds1 = set_desc(a, p1.y);
+        wa0 = first_tile_token(a.tok, dr0, g);
+        wb0 = first_tile_token(a.tok, ds0, g);
+    }
+    for (uint32_t t = t0, s = 0; t < cnt; t += stride, ++s) {
+        const uint32_t e4 = entry_at(s + 4);
+        int r3;
+        const int2 p3 = pair_of(e3, &r3);
+        const uint2 dr2 = set_desc(a, p2.x);
+        const uint2 ds2 = set_desc(a, p2.y);
+        const int32_t wa1 = first_tile_token(a.tok, dr1, g);
+        const int32_t wb1 = first_tile_token(a.tok, ds1, g);
+        if (t + (uint32_t)grp < cnt) {
+            const Request& R = a.req[r0];
+            const uint32_t alpha = required_overlap(dr0.y + ds0.y, R.tn, R.tsum);
+            bool pass;
+            if constexpr (G == 1)
+                pass = merge_thread(a.tok + dr0.x, dr0.y, a.tok + ds0.x, ds0.y, alpha);
+            else
+                pass = merge_group_first<G>(a.tok + dr0.x, dr0.y, a.tok + ds0.x, ds0.y, alpha, g,
+                                            gbase, wa0, wb0);
+            if (pass && g == 0) append_one(p0, R, &a.ctr->out_count[r0]);
         }
+        e3 = e4;
+        p0 = p1;
+        r0 = r1;
+        p1 = p2;
+        r1 = r2;
+        p2 = p3;
+        r2 = r3;
+        dr0 = dr1;
+        ds0 = ds1;
+        dr1 = dr2;
+        ds1 = ds2;
+        wa0 = wa1;
+        wb0 = wb1;
     }
 }
 
@@ -731,7 +816,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
             const uint32_t gi = queue[t];
             const int r = request_of_pair(gi, a);
             const Request& R = a.req[r];
-            const int2 pr = R.cand[gi - a.pair_off[r]];
+            const int2 pr = load_pair(R.cand, gi - a.pair_off[r]);
             const uint2 dr = set_desc(a, pr.x);
             const uint2 ds = set_desc(a, pr.y);
             const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y,
@@ -761,7 +846,7 @@ __global__ void k_build_heads(const int64_t* __restrict__ off, const int32_t* __
         const int64_t b = off[i], e = off[i + 1];
         int32_t h[kHeadTokens];
 #pragma unroll
-        for (int k = 0; k < kHeadTokens; ++k) h[k] = (b + k < e) ? tok[b + k] : 0;
+        for (int k = 0; k < kHeadTokens; ++k) h[k] = (b + k < e) ? tok[b + k] : -1;
         heads[2 * i] = make_uint4((uint32_t)b, (uint32_t)(e - b), (uint32_t)h[0], (uint32_t)h[1]);
         heads[2 * i + 1] = make_uint4((uint32_t)h[2], (uint32_t)h[3], (uint32_t)h[4], (uint32_t)h[5]);
     }
