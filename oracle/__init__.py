@@ -1,13 +1,14 @@
 """Verification oracle -- TEST INFRASTRUCTURE ONLY.
 
 Plain CPU references for the verification phase of an exact set-similarity
-join (paper Sec. 3, Definition 1; Jaccard row of Table 1).  Only the tests,
+join (paper Sec. 3, Definition 1; the similarity functions of Table 1).  Only the tests,
 the smoke check and the benchmark's CPU-baseline leg may import this package.
 It shares no code with the GPU library and imports nothing from it.
 
   * ``verify`` / ``select`` / ``merge_trace``: ctypes wrappers of the plain C
-    oracle (``verify_ref.c``): full-merge overlap + exact integer Jaccard test,
-    and the early-terminating merge replayed for token accounting.
+    oracle (``verify_ref.c``): full-merge overlap + the exact integer test of
+    Jaccard, Cosine, Dice or Overlap (``sim``), and the early-terminating
+    Jaccard merge replayed for token accounting.
   * ``brute``: pure-Python all-pairs join and per-pair verification with
     ``frozenset`` and ``fractions.Fraction`` (tiny inputs only).
 """
@@ -25,9 +26,12 @@ SRC_PATH = os.path.join(_HERE, "verify_ref.c")
 
 _lib = None
 
+# similarity functions of Table 1 (the threshold of "overlap" is a count)
+SIMS = {"jaccard": 0, "cosine": 1, "dice": 2, "overlap": 3}
+
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-shared", "-fPIC", "-o", LIB_PATH + ".tmp",
+    cmd = ["gcc", "-O2", "-std=gnu99", "-fopenmp", "-shared", "-fPIC", "-o", LIB_PATH + ".tmp",
            SRC_PATH]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -45,10 +49,11 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     p = ctypes.c_void_p
     i64 = ctypes.c_int64
-    lib.ssjref_verify.argtypes = [p, i64, p, p, i64, i64, i64, p, p, ctypes.c_int]
-    lib.ssjref_verify.restype = ctypes.c_int
-    lib.ssjref_select.argtypes = [p, i64, p, p, i64, i64, i64, p, p, ctypes.c_int]
-    lib.ssjref_select.restype = i64
+    ci = ctypes.c_int
+    lib.ssjref_verify_sim.argtypes = [p, i64, p, p, i64, ci, i64, i64, p, p, ci]
+    lib.ssjref_verify_sim.restype = ctypes.c_int
+    lib.ssjref_select_sim.argtypes = [p, i64, p, p, i64, ci, i64, i64, p, p, ci]
+    lib.ssjref_select_sim.restype = i64
     lib.ssjref_merge_trace.argtypes = [p, i64, p, p, i64, i64, i64, p, p, p, ctypes.c_int]
     lib.ssjref_merge_trace.restype = ctypes.c_int
     lib.ssjref_max_threads.argtypes = []
@@ -74,16 +79,23 @@ def _prep(offsets, tokens, pairs):
     return off, tok, pr
 
 
+def _sim_code(sim: str) -> int:
+    if sim not in SIMS:
+        raise OracleError(f"unknown similarity function {sim!r}")
+    return SIMS[sim]
+
+
 def verify(offsets, tokens, pairs, t_num: int, t_den: int, n_threads: int = 1,
-           with_overlap: bool = False):
+           with_overlap: bool = False, sim: str = "jaccard"):
     """pass flags (uint8 per pair) and optionally the exact overlaps."""
     off, tok, pr = _prep(offsets, tokens, pairs)
     n = pr.shape[0]
     passed = np.zeros(max(n, 1), dtype=np.uint8)
     ov = np.zeros(max(n, 1), dtype=np.int32) if with_overlap else None
-    rc = _load().ssjref_verify(off.ctypes.data, off.shape[0] - 1, tok.ctypes.data, pr.ctypes.data,
-                               n, int(t_num), int(t_den), passed.ctypes.data,
-                               ov.ctypes.data if ov is not None else None, int(n_threads))
+    rc = _load().ssjref_verify_sim(off.ctypes.data, off.shape[0] - 1, tok.ctypes.data,
+                                   pr.ctypes.data, n, _sim_code(sim), int(t_num), int(t_den),
+                                   passed.ctypes.data, ov.ctypes.data if ov is not None else None,
+                                   int(n_threads))
     if rc != 0:
         raise OracleError("invalid threshold, id out of range or empty set")
     if with_overlap:
@@ -91,15 +103,16 @@ def verify(offsets, tokens, pairs, t_num: int, t_den: int, n_threads: int = 1,
     return passed[:n]
 
 
-def select(offsets, tokens, pairs, t_num: int, t_den: int, n_threads: int = 1) -> np.ndarray:
+def select(offsets, tokens, pairs, t_num: int, t_den: int, n_threads: int = 1,
+           sim: str = "jaccard") -> np.ndarray:
     """The passing pairs (int32 [k, 2]) in input order."""
     off, tok, pr = _prep(offsets, tokens, pairs)
     n = pr.shape[0]
     scratch = np.zeros(max(n, 1), dtype=np.uint8)
     out = np.zeros((max(n, 1), 2), dtype=np.int32)
-    k = _load().ssjref_select(off.ctypes.data, off.shape[0] - 1, tok.ctypes.data, pr.ctypes.data,
-                              n, int(t_num), int(t_den), scratch.ctypes.data, out.ctypes.data,
-                              int(n_threads))
+    k = _load().ssjref_select_sim(off.ctypes.data, off.shape[0] - 1, tok.ctypes.data,
+                                  pr.ctypes.data, n, _sim_code(sim), int(t_num), int(t_den),
+                                  scratch.ctypes.data, out.ctypes.data, int(n_threads))
     if k < 0:
         raise OracleError("invalid threshold, id out of range or empty set")
     return out[:k].copy()

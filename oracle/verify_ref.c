@@ -6,13 +6,18 @@
  * benchmark's CPU-baseline leg may load it.  It shares no code, header or
  * constant with the GPU library and includes nothing from it.
  *
- * What it computes (paper Sec. 3, Definition 1, with the Jaccard row of
- * Table 1): a candidate pair (r, s) is in the result iff
- *     J(r, s) = |r & s| / |r | s|  >=  t = t_num / t_den,
- * evaluated exactly in integers:  |r & s| * t_den >= t_num * |r | s|,
- * where |r | s| = |r| + |s| - |r & s|.  The overlap is a full two-pointer
- * merge of the two sorted token lists (no early exit), so the result is the
- * plain definition, not the paper's early-terminating procedure.
+ * What it computes (paper Sec. 3, Definition 1, with the similarity
+ * functions of Table 1): a candidate pair (r, s) is in the result iff
+ * sim(r, s) >= t = t_num / t_den, evaluated exactly in integers with
+ * o = |r & s|:
+ *     Jaccard  o / |r | s| >= t        o * t_den >= t_num * (|r| + |s| - o)
+ *     Cosine   o / sqrt(|r||s|) >= t   o^2 * t_den^2 >= t_num^2 * |r| * |s|
+ *     Dice     2o / (|r| + |s|) >= t   2 * o * t_den >= t_num * (|r| + |s|)
+ *     Overlap  o >= t                  o * t_den >= t_num
+ * (the Cosine form squares both non-negative sides; its right side needs 128
+ * bits).  The overlap is a full two-pointer merge of the two sorted token
+ * lists (no early exit), so the result is the plain definition, not the
+ * paper's early-terminating procedure.
  *
  * A second routine replays the paper's early-terminating merge (Sec. 3.1:
  * the merge-like loop stops once the required overlap is met or can no
@@ -48,16 +53,45 @@ static int64_t overlap_full(const int32_t *a, int64_t na, const int32_t *b, int6
     return o;
 }
 
-/* Jaccard(r, s) >= t_num / t_den, given the overlap o and the two sizes. */
-static int jaccard_at_least(int64_t o, int64_t nr, int64_t ns, int64_t t_num, int64_t t_den)
+/* Similarity functions of Table 1. */
+#define REF_JACCARD 0
+#define REF_COSINE 1
+#define REF_DICE 2
+#define REF_OVERLAP 3
+
+/* sim(r, s) >= t_num / t_den, given the overlap o and the two sizes. */
+static int sim_at_least(int sim, int64_t o, int64_t nr, int64_t ns, int64_t t_num, int64_t t_den)
 {
-    int64_t uni = nr + ns - o;
-    return o * t_den >= t_num * uni;
+    switch (sim) {
+    case REF_JACCARD:
+        return o * t_den >= t_num * (nr + ns - o);
+    case REF_COSINE: {
+        unsigned __int128 lhs = (unsigned __int128)(uint64_t)(o * t_den) * (uint64_t)(o * t_den);
+        unsigned __int128 rhs = (unsigned __int128)(uint64_t)(t_num * t_num) *
+                                (unsigned __int128)((uint64_t)nr * (uint64_t)ns);
+        return lhs >= rhs;
+    }
+    case REF_DICE:
+        return 2 * o * t_den >= t_num * (nr + ns);
+    case REF_OVERLAP:
+        return o * t_den >= t_num;
+    }
+    return 0;
+}
+
+/* 0 < t_den < 2^31 and 0 <= t_num; t <= 1 for the normalised functions. */
+static int valid_sim_threshold(int sim, int64_t t_num, int64_t t_den)
+{
+    if (sim < REF_JACCARD || sim > REF_OVERLAP)
+        return 0;
+    if (t_den <= 0 || t_den > INT32_MAX || t_num < 0 || t_num > INT32_MAX)
+        return 0;
+    return sim == REF_OVERLAP || t_num <= t_den;
 }
 
 static int valid_threshold(int64_t t_num, int64_t t_den)
 {
-    return t_den > 0 && t_num >= 0 && t_num <= t_den && t_den <= INT32_MAX;
+    return valid_sim_threshold(REF_JACCARD, t_num, t_den);
 }
 
 static int pair_ok(const int64_t *offsets, int64_t n_sets, int32_t r, int32_t s)
@@ -71,17 +105,18 @@ static int pair_ok(const int64_t *offsets, int64_t n_sets, int32_t r, int32_t s)
 
 /*
  * For each pair k (pairs[2k] = r, pairs[2k+1] = s): pass[k] = 1 iff
- * J(r, s) >= t_num / t_den; overlap[k] = |r & s| (overlap may be NULL).
- * Returns REF_EINVAL (and writes nothing useful) for an invalid threshold or
- * any id out of range / empty set.
+ * sim(r, s) >= t_num / t_den for the similarity function sim (REF_*);
+ * overlap[k] = |r & s| (overlap may be NULL).  Returns REF_EINVAL (and writes
+ * nothing useful) for an invalid function or threshold or any id out of
+ * range / empty set.
  */
-int ssjref_verify(const int64_t *offsets, int64_t n_sets, const int32_t *tokens,
-                  const int32_t *pairs, int64_t n_pairs, int64_t t_num, int64_t t_den,
-                  uint8_t *pass, int32_t *overlap, int n_threads)
+int ssjref_verify_sim(const int64_t *offsets, int64_t n_sets, const int32_t *tokens,
+                      const int32_t *pairs, int64_t n_pairs, int sim, int64_t t_num,
+                      int64_t t_den, uint8_t *pass, int32_t *overlap, int n_threads)
 {
     int64_t k;
     int bad = 0;
-    if (!valid_threshold(t_num, t_den) || n_pairs < 0)
+    if (!valid_sim_threshold(sim, t_num, t_den) || n_pairs < 0)
         return REF_EINVAL;
     for (k = 0; k < n_pairs; k++)
         if (!pair_ok(offsets, n_sets, pairs[2 * k], pairs[2 * k + 1]))
@@ -98,7 +133,7 @@ int ssjref_verify(const int64_t *offsets, int64_t n_sets, const int32_t *tokens,
         int64_t nr = offsets[r + 1] - offsets[r];
         int64_t ns = offsets[s + 1] - offsets[s];
         int64_t o = overlap_full(tokens + offsets[r], nr, tokens + offsets[s], ns);
-        pass[k] = (uint8_t)jaccard_at_least(o, nr, ns, t_num, t_den);
+        pass[k] = (uint8_t)sim_at_least(sim, o, nr, ns, t_num, t_den);
         if (overlap)
             overlap[k] = (int32_t)o;
     }
@@ -106,17 +141,26 @@ int ssjref_verify(const int64_t *offsets, int64_t n_sets, const int32_t *tokens,
     return REF_OK;
 }
 
+/* ssjref_verify_sim with the Jaccard similarity. */
+int ssjref_verify(const int64_t *offsets, int64_t n_sets, const int32_t *tokens,
+                  const int32_t *pairs, int64_t n_pairs, int64_t t_num, int64_t t_den,
+                  uint8_t *pass, int32_t *overlap, int n_threads)
+{
+    return ssjref_verify_sim(offsets, n_sets, tokens, pairs, n_pairs, REF_JACCARD, t_num, t_den,
+                             pass, overlap, n_threads);
+}
+
 /*
  * Copies the passing pairs, in input order, to out (2 ints per pair) and
  * returns their number (or REF_EINVAL).  out must hold n_pairs pairs.
  */
-int64_t ssjref_select(const int64_t *offsets, int64_t n_sets, const int32_t *tokens,
-                      const int32_t *pairs, int64_t n_pairs, int64_t t_num, int64_t t_den,
-                      uint8_t *scratch_pass, int32_t *out, int n_threads)
+int64_t ssjref_select_sim(const int64_t *offsets, int64_t n_sets, const int32_t *tokens,
+                          const int32_t *pairs, int64_t n_pairs, int sim, int64_t t_num,
+                          int64_t t_den, uint8_t *scratch_pass, int32_t *out, int n_threads)
 {
     int64_t k, n = 0;
-    int rc = ssjref_verify(offsets, n_sets, tokens, pairs, n_pairs, t_num, t_den, scratch_pass,
-                           NULL, n_threads);
+    int rc = ssjref_verify_sim(offsets, n_sets, tokens, pairs, n_pairs, sim, t_num, t_den,
+                               scratch_pass, NULL, n_threads);
     if (rc != REF_OK)
         return rc;
     for (k = 0; k < n_pairs; k++) {
@@ -127,6 +171,15 @@ int64_t ssjref_select(const int64_t *offsets, int64_t n_sets, const int32_t *tok
         }
     }
     return n;
+}
+
+/* ssjref_select_sim with the Jaccard similarity. */
+int64_t ssjref_select(const int64_t *offsets, int64_t n_sets, const int32_t *tokens,
+                      const int32_t *pairs, int64_t n_pairs, int64_t t_num, int64_t t_den,
+                      uint8_t *scratch_pass, int32_t *out, int n_threads)
+{
+    return ssjref_select_sim(offsets, n_sets, tokens, pairs, n_pairs, REF_JACCARD, t_num, t_den,
+                             scratch_pass, out, n_threads);
 }
 
 /*

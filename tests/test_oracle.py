@@ -216,3 +216,143 @@ def test_select_keeps_order_and_multiplicity():
     pairs = np.array([[1, 0], [2, 0], [0, 1], [1, 0]], dtype=np.int32)
     out = oracle.select(c.offsets, c.tokens, pairs, 1, 2)
     assert out.tolist() == [[1, 0], [0, 1], [1, 0]]
+
+
+# ---------------------------------------------------------------------------
+# The other similarity functions of Table 1 (Cosine, Dice, Overlap).
+
+SIMS = ("jaccard", "cosine", "dice", "overlap")
+
+
+def table1_equivalent_overlap(sim, t_num, t_den, nr, ns):
+    """The "Equivalent Overlap" column of Table 1, in exact rationals."""
+    t = Fraction(t_num, t_den)
+    if sim == "jaccard":
+        return math.ceil(t / (1 + t) * (nr + ns))
+    if sim == "dice":
+        return math.ceil(t * (nr + ns) / 2)
+    if sim == "overlap":
+        return math.ceil(t)
+    # cosine: ceil(t sqrt(nr ns)), i.e. the least o >= 0 with o >= t sqrt(nr ns)
+    x = t * t * nr * ns  # = (t sqrt(nr ns))^2
+    o = math.isqrt(x.numerator // x.denominator)
+    while Fraction(o * o) < x:
+        o += 1
+    return o
+
+
+def test_sim_required_overlap_examples(examples):
+    for ex in examples["sim_required_overlap"]:
+        got = table1_equivalent_overlap(ex["sim"], ex["t_num"], ex["t_den"], ex["size_r"], ex["size_s"])
+        assert got == ex["alpha"], ex["cite"]
+
+
+def test_sim_float_traps_documented():
+    # Table 1 in binary floating point rounds 55 up to 56 for t = 0.55 at these
+    # sizes (Dice |r|+|s| = 200, Cosine |r| = |s| = 100); exact value 55.
+    assert math.ceil(0.55 * 200 / 2) == 56
+    assert math.ceil(0.55 * math.sqrt(100 * 100)) == 56
+    assert table1_equivalent_overlap("dice", 11, 20, 100, 100) == 55
+    assert table1_equivalent_overlap("cosine", 11, 20, 100, 100) == 55
+
+
+def test_sim_pair_examples(examples):
+    for ex in examples["sim_pairs"]:
+        r, s = _expand(ex["r"]), _expand(ex["s"])
+        c = _coll(r, s)
+        pairs = np.array([[0, 1], [1, 0]], dtype=np.int32)
+        passed, ov = oracle.verify(c.offsets, c.tokens, pairs, ex["t_num"], ex["t_den"],
+                                   with_overlap=True, sim=ex["sim"])
+        assert list(ov) == [ex["overlap"]] * 2, ex["cite"]
+        assert [bool(x) for x in passed] == [ex["similar"]] * 2, ex["cite"]
+        dec, bov = brute.brute_verify(c.offsets, c.tokens, pairs, ex["t_num"], ex["t_den"], sim=ex["sim"])
+        assert dec == [ex["similar"]] * 2 and bov == [ex["overlap"]] * 2, ex["cite"]
+
+
+SIM_THRESHOLDS = {
+    "jaccard": [(0, 1), (1, 2), (3, 5), (4, 5), (11, 20), (1, 1)],
+    "cosine": [(0, 1), (1, 2), (3, 5), (4, 5), (11, 20), (9, 10), (1, 1)],
+    "dice": [(0, 1), (1, 2), (3, 5), (4, 5), (11, 20), (9, 10), (1, 1)],
+    "overlap": [(0, 1), (1, 1), (2, 1), (5, 1), (7, 2), (12, 1)],
+}
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("sim", SIMS)
+def test_sim_oracle_equals_brute_and_table1(seed, sim):
+    """Oracle decision = brute force (definition with Fractions) = o >= the
+    Table 1 equivalent overlap, on random pairs (many near the threshold)."""
+    rng = np.random.default_rng(5000 + seed)
+    c = synth.near_duplicate_collection(rng, n_base=25, copies=4, max_size=14, universe=60,
+                                        change_frac=0.25)
+    pairs = _random_pairs(rng, c.n_sets, 400)
+    sizes = np.diff(c.offsets)
+    for tn, td in SIM_THRESHOLDS[sim]:
+        passed, ov = oracle.verify(c.offsets, c.tokens, pairs, tn, td, with_overlap=True, sim=sim)
+        dec, bov = brute.brute_verify(c.offsets, c.tokens, pairs, tn, td, sim=sim)
+        assert list(ov) == bov
+        assert [bool(x) for x in passed] == dec, (sim, tn, td)
+        for (r, s), o, p in zip(pairs, ov, passed):
+            alpha = table1_equivalent_overlap(sim, tn, td, int(sizes[r]), int(sizes[s]))
+            assert bool(p) == (int(o) >= alpha), (sim, tn, td, r, s)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dice_is_jaccard_at_transformed_threshold(seed):
+    """D = 2J / (1 + J), so D >= a/b  <=>  J >= a / (2b - a)."""
+    rng = np.random.default_rng(6000 + seed)
+    c = synth.near_duplicate_collection(rng, n_base=30, copies=4, max_size=16, universe=70,
+                                        change_frac=0.3)
+    pairs = _random_pairs(rng, c.n_sets, 500)
+    for a, b in [(0, 1), (1, 2), (3, 5), (2, 3), (4, 5), (9, 10), (1, 1)]:
+        d = oracle.verify(c.offsets, c.tokens, pairs, a, b, sim="dice")
+        j = oracle.verify(c.offsets, c.tokens, pairs, a, 2 * b - a, sim="jaccard")
+        assert np.array_equal(d, j), (a, b)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_similarity_orderings(seed):
+    """Jaccard <= Dice <= Cosine for every pair (|r|+|s|-o >= (|r|+|s|)/2 and
+    the arithmetic-geometric mean inequality), with Cosine = Dice when
+    |r| = |s|: so at one threshold the passing sets are nested."""
+    rng = np.random.default_rng(7000 + seed)
+    c = synth.near_duplicate_collection(rng, n_base=30, copies=4, max_size=16, universe=70,
+                                        change_frac=0.3)
+    pairs = _random_pairs(rng, c.n_sets, 500)
+    sizes = np.diff(c.offsets)
+    eq = sizes[pairs[:, 0]] == sizes[pairs[:, 1]]
+    for tn, td in [(1, 2), (3, 5), (7, 10), (4, 5), (9, 10)]:
+        j = oracle.verify(c.offsets, c.tokens, pairs, tn, td, sim="jaccard").astype(bool)
+        d = oracle.verify(c.offsets, c.tokens, pairs, tn, td, sim="dice").astype(bool)
+        k = oracle.verify(c.offsets, c.tokens, pairs, tn, td, sim="cosine").astype(bool)
+        assert not np.any(j & ~d) and not np.any(d & ~k)
+        assert np.array_equal(d[eq], k[eq])
+
+
+def test_overlap_closed_forms():
+    rng = np.random.default_rng(8000)
+    c = synth.near_duplicate_collection(rng, n_base=20, copies=3, max_size=12, universe=40,
+                                        change_frac=0.3)
+    pairs = _random_pairs(rng, c.n_sets, 300)
+    sizes = np.diff(c.offsets)
+    _, ov = oracle.verify(c.offsets, c.tokens, pairs, 0, 1, with_overlap=True, sim="overlap")
+    assert oracle.verify(c.offsets, c.tokens, pairs, 0, 1, sim="overlap").all()
+    big = int(sizes.max()) + 1
+    assert not oracle.verify(c.offsets, c.tokens, pairs, big, 1, sim="overlap").any()
+    for k in range(0, 8):
+        assert np.array_equal(oracle.verify(c.offsets, c.tokens, pairs, k, 1, sim="overlap"),
+                              (ov >= k).astype(np.uint8))
+
+
+def test_sim_rejects_bad_input():
+    c = _coll([1, 2, 3], [2, 3, 4])
+    pairs = np.array([[0, 1]], dtype=np.int32)
+    for sim in ("jaccard", "cosine", "dice"):
+        with pytest.raises(oracle.OracleError):
+            oracle.verify(c.offsets, c.tokens, pairs, 3, 2, sim=sim)  # t > 1
+    assert oracle.verify(c.offsets, c.tokens, pairs, 3, 2, sim="overlap")[0] == 1  # 2 >= 1.5
+    assert oracle.verify(c.offsets, c.tokens, pairs, 5, 2, sim="overlap")[0] == 0  # 2 < 2.5
+    with pytest.raises(oracle.OracleError):
+        oracle.verify(c.offsets, c.tokens, pairs, 1, 0, sim="overlap")
+    with pytest.raises(oracle.OracleError):
+        oracle.verify(c.offsets, c.tokens, pairs, 1, 2, sim="hamming")
