@@ -239,7 +239,8 @@ def main():
     avg_kernel_ms = avg_in_ms + (avg_def_ms if deferred else 0.0)
     achieved = per_launch_bytes / (avg_kernel_ms * 1e-3) / 1e9 if avg_kernel_ms > 0 else 0.0
     src_hash = kernel_source_hash()
-    kernel_name = (f"k_verify_tiles<{plan.inline_lanes},{plan.hard_lanes}>" +
+    kernel_name = (f"k_verify_tiles<{plan.inline_lanes},{plan.hard_lanes},"
+                   f"{'true' if deferred else 'false'}>" +
                    (" + k_verify_deferred" if deferred else ""))
     traffic = traffic_from_profiles(src_hash, args.workload, kernel_name)
 

@@ -2,13 +2,15 @@
  * libssj -- verification phase of exact set-similarity joins on MI355X (gfx950).
  *
  * The library verifies candidate pairs (r, s) of token sets held in an HBM
- * resident collection: a pair is in the result iff its Jaccard similarity
- * |r & s| / |r | s| is at least t = t_num / t_den (paper Sec. 3,
- * Definition 1, with the Jaccard row of Table 1).  The decision is taken in
- * integers as  |r & s| * (t_den + t_num) >= t_num * (|r| + |s|);  no floating
- * point enters the path.  The overlap comes from an intersection that stops
- * as soon as the required overlap is met or can no longer be reached (paper
- * Sec. 3.1), so only candidates whose outcome is undecided cost more work.
+ * resident collection: a pair is in the result iff its similarity is at
+ * least t = t_num / t_den (paper Sec. 3, Definition 1).  The similarity is
+ * Jaccard |r & s| / |r | s| unless a call names another function of Table 1
+ * (SSJ_SIM_*).  Each function is turned into the equivalent overlap of
+ * Table 1, the least |r & s| that reaches t, computed exactly in integers;  no
+ * floating point decides a pair.  The overlap comes from an intersection that
+ * stops as soon as the required overlap is met or can no longer be reached
+ * (paper Sec. 3.1), so only candidates whose outcome is undecided cost more
+ * work.
  *
  * Collections follow the paper's preprocessing contract (Sec. 2.2, "Data
  * layout"): every set is non-empty, its tokens are unique non-negative int32
@@ -89,6 +91,21 @@ int ssj_upload_collection(ssj_ctx* ctx, const int64_t* offsets, int64_t n_sets,
 int ssj_free_collection(ssj_ctx* ctx, ssj_coll* coll);
 
 /*
+ * Similarity functions (paper Table 1) and the decision each one takes, with
+ * o = |r & s|:
+ *   SSJ_SIM_JACCARD  o / |r | s| >= t        o * (t_num + t_den) >= t_num * (|r| + |s|)
+ *   SSJ_SIM_COSINE   o / sqrt(|r||s|) >= t   o^2 * t_den^2 >= t_num^2 * |r| * |s|
+ *   SSJ_SIM_DICE     2o / (|r| + |s|) >= t   2 * o * t_den >= t_num * (|r| + |s|)
+ *   SSJ_SIM_OVERLAP  o >= t                  o * t_den >= t_num
+ * Thresholds: 0 < t_den < 2^31 and 0 <= t_num < 2^31; t_num <= t_den except
+ * for SSJ_SIM_OVERLAP, whose threshold is a count.
+ */
+#define SSJ_SIM_JACCARD 0
+#define SSJ_SIM_COSINE 1
+#define SSJ_SIM_DICE 2
+#define SSJ_SIM_OVERLAP 3
+
+/*
  * Synchronous verification of host-resident candidates.
  * cand:   host, n_cand pairs (ids must lie in [0, n_sets)).
  * t:      0 <= t_num <= t_den, 0 < t_den < 2^31.
@@ -103,6 +120,12 @@ int ssj_free_collection(ssj_ctx* ctx, ssj_coll* coll);
  */
 int ssj_verify(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
                int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap, int64_t* out_n);
+
+/* ssj_verify with the similarity function sim (SSJ_SIM_*, paper Table 1);
+ * SSJ_EINVAL for an unknown function or a threshold outside its range. */
+int ssj_verify_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
+                   int sim, int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap,
+                   int64_t* out_n);
 
 /*
  * Device-pointer variant: no host copies, no synchronisation.  d_cand and
@@ -123,6 +146,12 @@ int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand
                       int64_t n_cand, int64_t t_num, int64_t t_den, ssj_pair* d_out,
                       int64_t out_cap, int64_t* d_count, void* hip_stream);
 
+/* ssj_verify_device with the similarity function sim (SSJ_SIM_*, paper
+ * Table 1). */
+int ssj_verify_device_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand,
+                          int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* d_out,
+                          int64_t out_cap, int64_t* d_count, void* hip_stream);
+
 /*
  * Streaming (continuous batching) -- the paper's host/device pipeline
  * (Sec. 3.2, threads H0/H1/H2; Sec. 4.1.2) as a request loop.
@@ -134,6 +163,12 @@ int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand
  */
 int ssj_stream_submit(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
                       int64_t t_num, int64_t t_den, int nonblocking, uint64_t* ticket);
+
+/* ssj_stream_submit with the similarity function sim (SSJ_SIM_*, paper
+ * Table 1). */
+int ssj_stream_submit_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand,
+                          int64_t n_cand, int sim, int64_t t_num, int64_t t_den, int nonblocking,
+                          uint64_t* ticket);
 
 /*
  * Collects a request.  wait != 0 blocks until it is done.  SSJ_PENDING if
@@ -156,13 +191,14 @@ int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, int wait, uint64_t* t_submit
 
 /*
  * Execution plan.  Verification runs as one or two kernels per launch:
- *  1. an in-order kernel walks the candidates in tiles of consecutive pairs
- *     and verifies each pair with inline_lanes lanes (1 = one thread per
- *     pair, a sequential early-exit merge; 4..64 = a group of lanes of one
+ *  1. an in-order kernel in which every wavefront walks chunks of 64
+ *     consecutive pairs and verifies each pair with inline_lanes lanes (1 =
+ *     one thread per pair, an early-exit merge that starts from the six
+ *     tokens kept in each set's record; 4..64 = a group of lanes of one
  *     wavefront per pair, intersecting tile by tile).  With one thread per
- *     pair and hard_lanes > 0, a merge that outruns the six tokens kept in a
- *     set's record is handed, with its state, to groups of hard_lanes lanes
- *     of the same workgroup (0: the thread continues on the token array);
+ *     pair and hard_lanes > 0, a merge that outruns the six record tokens is
+ *     handed, with its state, to groups of hard_lanes lanes of the same
+ *     wavefront (0: the thread continues on the token array);
  *  2. pairs whose length class (by |r| + |s|, inclusive upper bounds
  *     SSJ_CLASS_BOUNDS) is defer_from or higher are not verified by (1) but
  *     queued per class; a persistent kernel then drains each class with
@@ -190,7 +226,8 @@ int ssj_get_plan(ssj_ctx* ctx, ssj_plan* plan);
 int ssj_set_plan(ssj_ctx* ctx, const ssj_plan* plan);
 
 /* One request of a batched launch: device buffers owned by the caller, with
- * the meaning of the ssj_verify_device arguments of the same names. */
+ * the meaning of the ssj_verify_device_sim arguments of the same names
+ * (sim = 0 is SSJ_SIM_JACCARD, so a zero-filled field keeps Jaccard). */
 typedef struct {
     const ssj_pair* d_cand;
     int64_t n_cand;
@@ -199,6 +236,7 @@ typedef struct {
     ssj_pair* d_out;
     int64_t out_cap;
     int64_t* d_count;
+    int32_t sim;
 } ssj_request;
 
 /*

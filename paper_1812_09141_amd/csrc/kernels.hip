@@ -26,25 +26,45 @@
 // exactly once; the stopping rule is checked before every round.
 //
 // Scheduling.  One launch carries up to kMaxReq requests (candidate arrays
-// with their own threshold and output).  The in-order kernel walks tiles of
-// kTile consecutive pairs of one request (a static grid-stride split: with
-// early termination the cost of a pair depends on its first few tokens, not
-// on its length, so in-order tiles are balanced).  Optionally, pairs whose
-// length class |r| + |s| is at or above defer_from are not verified there but
-// queued per class (collected in LDS, one global atomic per workgroup flush);
-// a second, persistent kernel drains those queues with the class's own
-// mapping -- workgroup-per-pair classes by work stealing, the others by a
-// static split.  Passing pairs are appended by wavefront compaction: a ballot
-// of the pass flags, one atomic add per wavefront that has passes, and a
-// per-lane offset from the lane's rank among the passing lanes.
+// with their own threshold and output).  In the in-order kernel every
+// wavefront walks chunks of kWave consecutive pairs of one request (a static
+// grid-stride split: with early termination the cost of a pair depends on its
+// first few tokens, not on its length, so in-order chunks are balanced), with
+// the loads of the next chunks in flight.  Optionally, pairs whose length
+// class |r| + |s| is at or above defer_from are not verified there but queued
+// per class (collected in LDS, one global atomic per flush); a second,
+// persistent kernel drains those queues with the class's own mapping --
+// workgroup-per-pair classes by work stealing, the others by a static split.
+// Passing pairs are compacted in LDS (a ballot of the pass flags and each
+// lane's rank among the passing lanes) and moved to the request's output
+// with one global atomic per flush.  The in-order kernel keeps all of this
+// per wavefront, so it has no workgroup barrier.
 #include "ssj_device.h"
 
 namespace ssj {
 namespace {
 
-__device__ __forceinline__ uint32_t required_overlap(uint32_t L, unsigned long long tn,
-                                                     unsigned long long tsum) {
-    return (uint32_t)((tn * (unsigned long long)L + tsum - 1ull) / tsum);
+// Required overlap of a pair with sizes na, nb under the request's rule
+// (paper Table 1, in integers).
+__device__ __forceinline__ uint32_t cosine_overlap(uint32_t na, uint32_t nb, unsigned long long tn,
+                                                   unsigned long long td) {
+    // least o with (o td)^2 >= tn^2 na nb; both sides stay below 2^124.  A
+    // double estimate lands within one of it and exact steps finish the job.
+    const unsigned __int128 x = (unsigned __int128)(tn * tn) * ((unsigned long long)na * nb);
+    unsigned long long o = (unsigned long long)ceil((double)tn * sqrt((double)na * (double)nb) / (double)td);
+    auto sq = [&](unsigned long long v) { return (unsigned __int128)(v * td) * (v * td); };
+    while (o > 0 && sq(o - 1) >= x) --o;
+    while (sq(o) < x) ++o;
+    return (uint32_t)o;
+}
+
+__device__ __forceinline__ uint32_t required_overlap(uint32_t na, uint32_t nb, const Request& R) {
+    if (R.rule == kLinear) {
+        const unsigned long long L = (unsigned long long)na + nb;
+        return (uint32_t)((R.num * L + R.den - 1ull) / R.den);
+    }
+    if (R.rule == kConstant) return (uint32_t)R.num;
+    return cosine_overlap(na, nb, R.num, R.den);
 }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
@@ -235,24 +255,6 @@ __device__ __forceinline__ void append_one(int2 pr, const Request& R, unsigned l
     if (k < R.cap) R.out[k] = pr;
 }
 
-// Stages the pairs of the lanes with pass set in the workgroup's LDS output
-// buffer (wavefront-aggregated LDS atomic); flush_out moves them to the
-// request's output with one global atomic per flush.
-// With count_only (a request without an output buffer) only the number of
-// passing pairs is accumulated.
-__device__ __forceinline__ void stage_wave(bool pass, int2 pr, int2* s_out, uint32_t* s_ocnt,
-                                           bool count_only) {
-    const unsigned long long m = ballot(pass);
-    if (m == 0ull) return;
-    const int lane = lane_id();
-    const int leader = __builtin_ctzll(m);
-    uint32_t pos = 0;
-    if (lane == leader) pos = atomicAdd(s_ocnt, (uint32_t)__popcll(m));
-    if (count_only) return;
-    pos = (uint32_t)bperm((int)pos, leader);
-    if (pass) s_out[pos + mbcnt(m)] = pr;
-}
-
 __device__ __forceinline__ bool ids_ok(int2 pr, uint32_t n_sets) {
     return (uint32_t)pr.x < n_sets && (uint32_t)pr.y < n_sets;
 }
@@ -272,72 +274,102 @@ __device__ __forceinline__ int request_of_pair(uint32_t gi, const LaunchArgs& a)
     return r;
 }
 
-// Moves the workgroup's c staged output pairs (request r) to the request's
-// output.  Called by the whole workgroup with the same r and c.
-__device__ void flush_out(const LaunchArgs& a, int r, uint32_t c, const int2* s_out,
-                          unsigned long long* s_obase) {
-    if (threadIdx.x == 0) *s_obase = atomicAdd(&a.ctr->out_count[r], (unsigned long long)c);
-    __syncthreads();
-    const unsigned long long base = *s_obase;
-    const Request& R = a.req[r];
-    const uint32_t n_copy = R.cap == 0 ? 0u : c;  // nothing staged in count-only mode
-    for (uint32_t i = threadIdx.x; i < n_copy; i += kBlock) {
-        const unsigned long long k = base + i;
-        if (k < R.cap) R.out[k] = s_out[i];
-    }
-    __syncthreads();
+// ---------------------------------------------------------------------------
+// Wavefront-private buffers of the in-order kernel.  Every wavefront works on
+// its own chunks of kWave consecutive pairs and keeps its own LDS buffers
+// (staged output pairs, deferred pairs, hard pairs).  Their fill counts are
+// wave-uniform values held in registers, so the kernel needs no workgroup
+// barrier: a wavefront slowed by a long merge holds up no other.
+
+// Orders one wavefront's LDS accesses: writes by some lanes before reads by
+// others (the LDS serves a wavefront's operations in issue order; the fences
+// keep the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Moves the workgroup's LDS queue of class q to the global queue.  Called by
-// the whole workgroup with the same c (= entries in the LDS queue).
-__device__ void flush_deferred(const LaunchArgs& a, int q, uint32_t c, const uint32_t* buf,
-                               uint32_t* s_base) {
-    if (threadIdx.x == 0) *s_base = atomicAdd(&a.ctr->tail[q], c);
-    __syncthreads();
-    const uint32_t base = *s_base;
-    uint32_t* dst = a.queues + (size_t)q * a.qcap + base;
-    for (uint32_t i = threadIdx.x; i < c; i += kBlock) dst[i] = buf[i];
-    __syncthreads();
+// Lane 0's value of v (all lanes active).
+__device__ __forceinline__ unsigned long long lane0_u64(unsigned long long v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
 }
 
-// Queues the pairs of the lanes with defer set into the workgroup's LDS
-// queue of their class (wavefront-aggregated LDS atomics).
-__device__ __forceinline__ void defer_wave(const LaunchArgs& a, bool defer, int cls, uint32_t gi,
-                                           uint32_t* s_defer, uint32_t* s_dcnt) {
+// Appends the pairs of the lanes with pass set to the wavefront's staged
+// output (ocnt entries so far, wave-uniform).  A request without an output
+// buffer only counts.
+__device__ __forceinline__ void stage_pass(bool pass, int2 pr, int2* w_out, uint32_t& ocnt,
+                                           bool count_only) {
+    const unsigned long long m = ballot(pass);
+    if (!count_only && pass) w_out[ocnt + mbcnt(m)] = pr;
+    ocnt += (uint32_t)__popcll(m);
+}
+
+// Moves the wavefront's c staged pairs of request r to the request's output
+// with one global atomic.  Called by the whole wavefront.
+__device__ void wave_flush_out(const LaunchArgs& a, int r, uint32_t c, const int2* w_out) {
+    wave_sync();
     const int lane = lane_id();
-    for (int q = a.defer_from; q < kClasses; ++q) {
-        const unsigned long long m = ballot(defer && cls == q);
-        if (m != 0ull) {
-            const int leader = __builtin_ctzll(m);
-            uint32_t pos = 0;
-            if (lane == leader) pos = atomicAdd(&s_dcnt[q], (uint32_t)__popcll(m));
-            pos = (uint32_t)bperm((int)pos, leader);
-            if (defer && cls == q)
-                s_defer[(uint32_t)(q - a.defer_from) * a.defer_cap + pos + mbcnt(m)] = gi;
+    unsigned long long base = 0ull;
+    if (lane == 0) base = atomicAdd(&a.ctr->out_count[r], (unsigned long long)c);
+    base = lane0_u64(base);
+    const Request& R = a.req[r];
+    if (R.cap != 0) {
+        for (uint32_t i = (uint32_t)lane; i < c; i += kWave) {
+            const unsigned long long k = base + i;
+            if (k < R.cap) R.out[k] = w_out[i];
         }
     }
+    wave_sync();
 }
 
-// Request and first pair index of wavefront w in in-order tile T.
-template <int U>
-__device__ __forceinline__ void tile_origin(const LaunchArgs& a, uint32_t T, int w, int* r,
-                                            uint32_t* wbase) {
+// Entries of class q in the wavefront's deferred queues: 8 bits per class
+// in one wave-uniform word (a queue never holds more than defer_cap <= 255).
+__device__ __forceinline__ uint32_t dcount(unsigned long long dc, int q) {
+    return (uint32_t)(dc >> (8 * q)) & 0xffu;
+}
+
+// Queues deferred pairs (global pair index gi) in the wavefront's LDS queue
+// of their class.
+__device__ __forceinline__ void defer_pass(const LaunchArgs& a, bool defer, int cls, uint32_t gi,
+                                           uint32_t* w_defer, unsigned long long& dc) {
+    for (int q = a.defer_from; q < kClasses; ++q) {
+        const bool mine = defer && cls == q;
+        const unsigned long long m = ballot(mine);
+        if (mine) w_defer[(uint32_t)(q - a.defer_from) * a.defer_cap + dcount(dc, q) + mbcnt(m)] = gi;
+        dc += (unsigned long long)__popcll(m) << (8 * q);
+    }
+}
+
+// Moves the wavefront's c queued pairs of class q to the global queue.
+__device__ void wave_flush_deferred(const LaunchArgs& a, int q, uint32_t c, const uint32_t* w_defer) {
+    wave_sync();
+    const int lane = lane_id();
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&a.ctr->tail[q], c);
+    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+    const uint32_t* src = w_defer + (uint32_t)(q - a.defer_from) * a.defer_cap;
+    uint32_t* dst = a.queues + (size_t)q * a.qcap + base;
+    for (uint32_t i = (uint32_t)lane; i < c; i += kWave) dst[i] = src[i];
+    wave_sync();
+}
+
+// Request and first pair index of chunk T (prefix sums in tile_off, in
+// chunks of kWave pairs).
+__device__ __forceinline__ void chunk_origin(const LaunchArgs& a, uint32_t T, int* r, uint32_t* kb) {
     int q = 0;
     while (q + 1 < a.n_req && a.tile_off[q + 1] <= T) ++q;
     *r = q;
-    *wbase = (T - a.tile_off[q]) * ((uint32_t)kBlock * U) + (uint32_t)w * kWave * U;
+    *kb = (T - a.tile_off[q]) * (uint32_t)kWave;
 }
 
-// The lane's U pairs of a tile (clamped to the request; validity is
-// re-derived from the index when they are used).
-template <int U>
-__device__ __forceinline__ void load_lane_pairs(const Request& R, uint32_t wbase, int lane,
-                                                int2* pr) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint32_t k = wbase + (uint32_t)(u * kWave + lane);
-        pr[u] = load_pair(R.cand, k < R.n ? k : R.n - 1);
-    }
+// The lane's pair of a chunk (clamped to the request; validity is re-derived
+// from the index when it is used).
+__device__ __forceinline__ int2 lane_pair(const Request& R, uint32_t kb, int lane) {
+    const uint32_t k = kb + (uint32_t)lane;
+    return load_pair(R.cand, k < R.n ? k : R.n - 1);
 }
 
 // Token t of a set given its record words (the first kHeadTokens come from
@@ -346,26 +378,20 @@ __device__ __forceinline__ int32_t record_token(const LaunchArgs& a, uint4 w0, u
     return t < kHeadTokens ? head_token(w0, w1, t) : a.tok[w0.x + t];
 }
 
-// Set records of the lane's U pairs: four 16-byte loads per pair (first and
-// second word of both sides), issued back to back.  Pairs with an invalid id
-// read record 0 and are ignored later.
-template <int U>
+// Set records of a lane's pair: four 16-byte loads (first and second word of
+// both sides), issued back to back.  A pair with an invalid id reads record 0
+// and is ignored later.
 struct LaneRecords {
-    uint4 ra0[U], ra1[U], rb0[U], rb1[U];
+    uint4 ra0, ra1, rb0, rb1;
 };
 
-template <int U>
-__device__ __forceinline__ void issue_records(const LaunchArgs& a, const int2* pr,
-                                              LaneRecords<U>& rec) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const bool ok = ids_ok(pr[u], a.n_sets);
-        const int ir = ok ? pr[u].x : 0, is = ok ? pr[u].y : 0;
-        rec.ra0[u] = a.heads[2 * ir];
-        rec.ra1[u] = a.heads[2 * ir + 1];
-        rec.rb0[u] = a.heads[2 * is];
-        rec.rb1[u] = a.heads[2 * is + 1];
-    }
+__device__ __forceinline__ void issue_records(const LaunchArgs& a, int2 pr, LaneRecords& rec) {
+    const bool ok = ids_ok(pr, a.n_sets);
+    const int ir = ok ? pr.x : 0, is = ok ? pr.y : 0;
+    rec.ra0 = a.heads[2 * ir];
+    rec.ra1 = a.heads[2 * ir + 1];
+    rec.rb0 = a.heads[2 * is];
+    rec.rb1 = a.heads[2 * is + 1];
 }
 
 // Merge state after the first tile of one side is consumed, with the six
@@ -403,213 +429,184 @@ __device__ __forceinline__ void head_tiles(uint4 a0, uint4 a1, uint4 b0, uint4 b
     *o = co;
 }
 
-// Thread-per-pair verification of the lane's U pairs (wbase + u*64 + lane)
-// from their records: first the head tiles (head_tiles), which decide most
+// Thread-per-pair verification of the lane's pair (chunk index kb + lane)
+// from its records: first the head tiles (head_tiles), which decide most
 // pairs; a pair still undecided continues from that merge state.  F == 0: it
 // continues on the token array in the same lane.  F > 0: it is appended, with
-// its merge state, to the workgroup's list of hard pairs, finished by groups
-// of F lanes (finish_hard), so that no lane walks the token array alone while
-// the rest of its wavefront waits.
-template <int U, int F>
-__device__ __forceinline__ void tile_thread_pairs(const LaunchArgs& a, const Request& R, int r,
-                                                  uint32_t wbase, const int2* pr,
-                                                  const LaneRecords<U>& rec, bool deferring,
-                                                  uint32_t* s_defer, uint32_t* s_dcnt, int2* s_out,
-                                                  uint32_t* s_ocnt, int2* s_hpr, uint32_t* s_hst,
-                                                  uint32_t* s_hcnt) {
+// its merge state, to the wavefront's list of hard pairs (hcnt entries), which
+// groups of F lanes finish (finish_hard), so that no lane walks the token
+// array alone while the rest of its wavefront waits.
+template <int F>
+__device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Request& R, int r,
+                                                   uint32_t kb, int2 pr, const LaneRecords& rec,
+                                                   bool deferring, uint32_t* w_defer,
+                                                   unsigned long long& dc, int2* w_out, uint32_t& ocnt,
+                                                   int2* w_hpr, uint32_t* w_hst, uint32_t& hcnt) {
     const int lane = lane_id();
-    bool ok[U], bad = false;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint32_t k = wbase + (uint32_t)(u * kWave + lane);
-        const bool valid = k < R.n;
-        ok[u] = valid && ids_ok(pr[u], a.n_sets);
-        bad |= valid && !ok[u];
-    }
-    uint32_t na[U], nb[U], alpha[U], i[U], j[U], o[U];
-    bool act[U], pass[U], defer[U];
-    int cls[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        na[u] = rec.ra0[u].y;
-        nb[u] = rec.rb0[u].y;
-        const uint32_t L = na[u] + nb[u];
-        cls[u] = deferring ? class_of(L, a) : 0;
-        defer[u] = ok[u] && deferring && cls[u] >= a.defer_from;
-        const bool run = ok[u] && !defer[u];
-        alpha[u] = run ? required_overlap(L, R.tn, R.tsum) : 0u;
-        head_tiles(rec.ra0[u], rec.ra1[u], rec.rb0[u], rec.rb1[u], &i[u], &j[u], &o[u]);
-        pass[u] = run && o[u] >= alpha[u];
-        act[u] = run && !pass[u] && o[u] + min(na[u] - i[u], nb[u] - j[u]) >= alpha[u];
-    }
+    const uint32_t k = kb + (uint32_t)lane;
+    const bool valid = k < R.n;
+    const bool ok = valid && ids_ok(pr, a.n_sets);
+    const uint32_t na = rec.ra0.y, nb = rec.rb0.y;
+    const uint32_t L = na + nb;
+    const int cls = deferring ? class_of(L, a) : 0;
+    const bool defer = ok && deferring && cls >= a.defer_from;
+    const bool run = ok && !defer;
+    const uint32_t alpha = run ? required_overlap(na, nb, R) : 0u;
+    uint32_t i, j, o;
+    head_tiles(rec.ra0, rec.ra1, rec.rb0, rec.rb1, &i, &j, &o);
+    bool pass = run && o >= alpha;
+    bool act = run && !pass && o + min(na - i, nb - j) >= alpha;
     if constexpr (F == 0) {
-        for (;;) {
-            bool any = false;
-#pragma unroll
-            for (int u = 0; u < U; ++u) any |= act[u];
-            if (!any) break;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (act[u]) {
-                    const int32_t x = record_token(a, rec.ra0[u], rec.ra1[u], i[u]);
-                    const int32_t y = record_token(a, rec.rb0[u], rec.rb1[u], j[u]);
-                    i[u] += (x <= y);
-                    j[u] += (y <= x);
-                    o[u] += (x == y);
-                    if (o[u] >= alpha[u]) {
-                        pass[u] = true;
-                        act[u] = false;
-                    } else if (o[u] + min(na[u] - i[u], nb[u] - j[u]) < alpha[u]) {
-                        act[u] = false;
-                    }
-                }
+        while (act) {
+            const int32_t x = record_token(a, rec.ra0, rec.ra1, i);
+            const int32_t y = record_token(a, rec.rb0, rec.rb1, j);
+            i += (x <= y);
+            j += (y <= x);
+            o += (x == y);
+            if (o >= alpha) {
+                pass = true;
+                act = false;
+            } else if (o + min(na - i, nb - j) < alpha) {
+                act = false;
             }
         }
     }
     // (after the merges: atomics count with loads, so none sits between the
     // record loads in flight and their use)
-    if (bad) atomicOr(&a.ctr->err[r], 1u);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        if constexpr (F > 0) {
-            const unsigned long long m = ballot(act[u]);
-            if (m != 0ull) {
-                const int leader = __builtin_ctzll(m);
-                uint32_t pos = 0;
-                if (lane == leader) pos = atomicAdd(s_hcnt, (uint32_t)__popcll(m));
-                pos = (uint32_t)bperm((int)pos, leader) + mbcnt(m);
-                if (act[u]) {
-                    s_hpr[pos] = pr[u];
-                    s_hst[pos] = i[u] | (j[u] << 8) | (o[u] << 16);  // each <= kHeadTokens
-                }
-            }
+    if (ballot(valid && !ok) != 0ull && lane == 0) atomicOr(&a.ctr->err[r], 1u);
+    if constexpr (F > 0) {
+        const unsigned long long m = ballot(act);
+        if (act) {
+            const uint32_t pos = hcnt + mbcnt(m);
+            w_hpr[pos] = pr;
+            w_hst[pos] = i | (j << 8) | (o << 16);  // each <= kHeadTokens
         }
-        stage_wave(pass[u], pr[u], s_out, s_ocnt, R.cap == 0);
-        if (deferring)
-            defer_wave(a, defer[u], cls[u], a.pair_off[r] + wbase + (uint32_t)(u * kWave + lane),
-                       s_defer, s_dcnt);
+        hcnt += (uint32_t)__popcll(m);
     }
+    stage_pass(pass, pr, w_out, ocnt, R.cap == 0);
+    if (deferring) defer_pass(a, defer, cls, a.pair_off[r] + k, w_defer, dc);
 }
 
-// Finishes the workgroup's hard pairs of this tile: groups of G lanes resume
-// their merges from the saved state with the tile merge.
+// Finishes the wavefront's h hard pairs: groups of G lanes resume their
+// merges from the saved state with the tile merge.  The loop over the list
+// is wave-uniform, so the staging after each step runs with all lanes.
 template <int G>
 __device__ __forceinline__ void finish_hard(const LaunchArgs& a, const Request& R, uint32_t h,
-                                            const int2* s_hpr, const uint32_t* s_hst, int2* s_out,
-                                            uint32_t* s_ocnt) {
+                                            const int2* w_hpr, const uint32_t* w_hst, int2* w_out,
+                                            uint32_t& ocnt) {
+    constexpr uint32_t kGroups = kWave / G;
     const int lane = lane_id();
     const int g = lane % G, gbase = (lane / G) * G;
-    const uint32_t gid = threadIdx.x / G;
-    constexpr uint32_t kGroups = kBlock / G;
-    for (uint32_t e = gid; e < h; e += kGroups) {
-        const int2 pq = s_hpr[e];
-        const uint32_t st = s_hst[e];
-        const uint2 dr = set_desc(a, pq.x);
-        const uint2 ds = set_desc(a, pq.y);
-        const uint32_t alpha = required_overlap(dr.y + ds.y, R.tn, R.tsum);
-        const bool pass = merge_group<G>(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, g, gbase,
-                                         st & 0xffu, (st >> 8) & 0xffu, st >> 16);
-        stage_wave(pass && g == 0, pq, s_out, s_ocnt, R.cap == 0);
+    const uint32_t grp = (uint32_t)(lane / G);
+    wave_sync();
+    for (uint32_t e0 = 0; e0 < h; e0 += kGroups) {
+        const uint32_t e = e0 + grp;
+        bool pass = false;
+        int2 pq = make_int2(0, 0);
+        if (e < h) {
+            pq = w_hpr[e];
+            const uint32_t st = w_hst[e];
+            const uint2 dr = set_desc(a, pq.x);
+            const uint2 ds = set_desc(a, pq.y);
+            const uint32_t alpha = required_overlap(dr.y, ds.y, R);
+            pass = merge_group<G>(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, g, gbase,
+                                  st & 0xffu, (st >> 8) & 0xffu, st >> 16);
+        }
+        stage_pass(pass && g == 0, pq, w_out, ocnt, R.cap == 0);
     }
+    wave_sync();
 }
 
 // ---------------------------------------------------------------------------
-// In-order kernel.  Workgroup iteration = one tile of consecutive pairs of one
-// request.  G == 1: tile = kBlock * U pairs, wavefront w takes U runs of 64
-// pairs.  G > 1 (U == 1): tile = kBlock pairs, wavefront w takes the pairs
-// w*64 .. w*64+63, 64/G at a time.
-template <int G, int F>
+// In-order kernel.  Every wavefront takes chunks of kWave consecutive pairs
+// of one request, grid-stride over all wavefronts of the grid.  G == 1: a
+// lane per pair.  G > 1: 64/G pairs at a time, G lanes each.  D: whether
+// the instance can defer length classes (an instance without that code needs
+// fewer registers).
+template <int G, int F, bool D>
 __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
-    constexpr int U = 1;
     constexpr int GPW = kWave / G;
-    constexpr uint32_t kTilePairs = (uint32_t)kBlock * U;
-    constexpr uint32_t kStage = 2 * kTilePairs;  // staged output pairs per workgroup
-    // dynamic LDS: kStage staged output pairs, then defer_cap entries per
-    // deferred class q >= defer_from (defer_cap >= 2 * kTilePairs)
-    extern __shared__ uint4 s_dyn[];
-    int2* s_out = reinterpret_cast<int2*>(s_dyn);
-    uint32_t* s_defer = reinterpret_cast<uint32_t*>(s_out + kStage);
-    __shared__ uint32_t s_dcnt[kClasses];
-    __shared__ uint32_t s_ocnt;
-    __shared__ uint32_t s_base;
-    __shared__ unsigned long long s_obase;
-    // hard pairs of the current tile (thread-per-pair mapping with F > 0)
-    __shared__ int2 s_hpr[F > 0 ? kTilePairs : 1];
-    __shared__ uint32_t s_hst[F > 0 ? kTilePairs : 1];
-    __shared__ uint32_t s_hcnt;
-    const bool deferring = a.defer_from < kClasses;
-    if (threadIdx.x < kClasses) s_dcnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) {
-        s_ocnt = 0;
-        s_hcnt = 0;
-    }
-    __syncthreads();
-    const int w = (int)(threadIdx.x >> 6);
+    constexpr uint32_t kWaves = (uint32_t)(kBlock / kWave);
+    constexpr uint32_t kWStage = 2 * (uint32_t)kWave;  // staged output pairs per wavefront
+    // the wavefront index is uniform in the wavefront: taken through a scalar
+    // register for the chunk walk (which then stays scalar); the LDS
+    // addresses use the per-lane copy (vector registers are the cheaper ones)
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t wl = threadIdx.x >> 6;
     const int lane = lane_id();
     const int grp = lane / G, g = lane % G, gbase = grp * G;
-    const uint32_t n_tiles = a.tile_off[a.n_req];
-    // G == 1: a two-stage pipeline.  While tile T is verified, the records of
-    // tile T + grid and the pairs of tile T + 2 grid are in flight (memory
+    // dynamic LDS, per wavefront: kWStage staged output pairs, then defer_cap
+    // entries per deferred class q >= defer_from (defer_cap >= 2 * kWave)
+    extern __shared__ uint4 s_dyn[];
+    const bool deferring = D && a.defer_from < kClasses;
+    const uint32_t wave_words =
+        (kWStage * 8u + (deferring ? (uint32_t)(kClasses - a.defer_from) * a.defer_cap * 4u : 0u)) / 16u;
+    int2* w_out = reinterpret_cast<int2*>(s_dyn + wl * wave_words);
+    uint32_t* w_defer = reinterpret_cast<uint32_t*>(w_out + kWStage);
+    // hard pairs of the current chunk (thread-per-pair mapping with F > 0)
+    __shared__ int2 s_hpr[F > 0 ? kWaves * kWave : 1];
+    __shared__ uint32_t s_hst[F > 0 ? kWaves * kWave : 1];
+    int2* w_hpr = s_hpr + (F > 0 ? wl * kWave : 0u);
+    uint32_t* w_hst = s_hst + (F > 0 ? wl * kWave : 0u);
+    uint32_t ocnt = 0, hcnt = 0;
+    unsigned long long dc = 0ull;  // deferred queue fill counts (dcount)
+    const uint32_t n_chunks = a.tile_off[a.n_req];
+    const uint32_t nw = gridDim.x * kWaves;
+    const uint32_t first = blockIdx.x * kWaves + (uint32_t)w;
+    // G == 1: a two-stage pipeline.  While chunk T is verified, the records of
+    // chunk T + nw and the pairs of chunk T + 2 nw are in flight (memory
     // operations complete in issue order, so the records of T, issued one
     // iteration earlier, are waited for without draining the newer loads).
-    int2 p0[U], p1[U];
-    LaneRecords<U> rec0, rec1;
+    int2 p0 = make_int2(0, 0), p1 = make_int2(0, 0);
+    LaneRecords rec0{}, rec1{};
     int r_cur = 0, r1 = 0;
-    uint32_t wb_cur = 0, wb1 = 0;
-    if (blockIdx.x < n_tiles) tile_origin<U>(a, blockIdx.x, w, &r_cur, &wb_cur);
-    if constexpr (G == 1) {
-        // loads beyond the last tile are clamped to it (results unused), so
-        // every iteration issues the same loads in the same order
-        if (blockIdx.x < n_tiles) {
-            load_lane_pairs<U>(a.req[r_cur], wb_cur, lane, p0);
-            issue_records<U>(a, p0, rec0);
-            tile_origin<U>(a, min(blockIdx.x + gridDim.x, n_tiles - 1), w, &r1, &wb1);
-            load_lane_pairs<U>(a.req[r1], wb1, lane, p1);
+    uint32_t kb_cur = 0, kb1 = 0;
+    if (first < n_chunks) {
+        chunk_origin(a, first, &r_cur, &kb_cur);
+        if constexpr (G == 1) {
+            // loads beyond the last chunk are clamped to it (results unused),
+            // so every iteration issues the same loads in the same order
+            p0 = lane_pair(a.req[r_cur], kb_cur, lane);
+            issue_records(a, p0, rec0);
+            chunk_origin(a, min(first + nw, n_chunks - 1), &r1, &kb1);
+            p1 = lane_pair(a.req[r1], kb1, lane);
         }
     }
-    for (uint32_t T = blockIdx.x; T < n_tiles; T += gridDim.x) {
+    for (uint32_t T = first; T < n_chunks; T += nw) {
         const int r = r_cur;
-        const uint32_t wbase = wb_cur;
-        const uint32_t Tn = T + gridDim.x;
+        const uint32_t kb = kb_cur;
+        const uint32_t Tn = T + nw;
+        const Request& R = a.req[r];
         if constexpr (G == 1) {
-            int2 p2[U];
+            issue_records(a, p1, rec1);
             int r2 = 0;
-            uint32_t wb2 = 0;
-            issue_records<U>(a, p1, rec1);
-            tile_origin<U>(a, min(Tn + gridDim.x, n_tiles - 1), w, &r2, &wb2);
-            load_lane_pairs<U>(a.req[r2], wb2, lane, p2);
-            tile_thread_pairs<U, F>(a, a.req[r], r, wbase, p0, rec0, deferring, s_defer, s_dcnt,
-                                    s_out, &s_ocnt, s_hpr, s_hst, &s_hcnt);
+            uint32_t kb2 = 0;
+            chunk_origin(a, min(Tn + nw, n_chunks - 1), &r2, &kb2);
+            const int2 p2 = lane_pair(a.req[r2], kb2, lane);
+            chunk_thread_pairs<F>(a, R, r, kb, p0, rec0, deferring, w_defer, dc, w_out, ocnt,
+                                  w_hpr, w_hst, hcnt);
             if constexpr (F > 0) {
-                __syncthreads();
-                const uint32_t h = s_hcnt;
-                if (h > 0) {
-                    finish_hard<F>(a, a.req[r], h, s_hpr, s_hst, s_out, &s_ocnt);
-                    __syncthreads();
-                    if (threadIdx.x == 0) s_hcnt = 0;
+                if (hcnt > 0) {
+                    finish_hard<F>(a, R, hcnt, w_hpr, w_hst, w_out, ocnt);
+                    hcnt = 0;
                 }
             }
             // rotate the pipeline
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                p0[u] = p1[u];
-                p1[u] = p2[u];
-            }
+            p0 = p1;
+            p1 = p2;
             rec0 = rec1;
             r_cur = r1;
-            wb_cur = wb1;
+            kb_cur = kb1;
             r1 = r2;
-            wb1 = wb2;
+            kb1 = kb2;
         } else {
-            if (Tn < n_tiles) tile_origin<U>(a, Tn, w, &r_cur, &wb_cur);
-            const Request& R = a.req[r];
+            if (Tn < n_chunks) chunk_origin(a, Tn, &r_cur, &kb_cur);
             // sub-rounds of 64/G pairs, software-pipelined: while sub-round s
             // is merged, the first tiles of s + 1, the set descriptors of s + 2
             // and the pair of s + 3 are in flight (clamped, unconditional loads
-            // keep the issue order fixed, so each wait covers only loads issued
-            // one sub-round earlier)
+            // keep the issue order fixed)
             auto pair_at = [&](int sub) -> int2 {
-                const uint32_t k = wbase + (uint32_t)(min(sub, G - 1) * GPW + grp);
+                const uint32_t k = kb + (uint32_t)(min(sub, G - 1) * GPW + grp);
                 return load_pair(R.cand, k < R.n ? k : R.n - 1);
             };
             auto desc_of = [&](int2 pq, uint2* dr, uint2* ds) {
@@ -629,7 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                 desc_of(pq2, &dr2, &ds2);
                 const int32_t wa1 = first_tile_token(a.tok, dr1, g);
                 const int32_t wb1 = first_tile_token(a.tok, ds1, g);
-                const uint32_t k = wbase + (uint32_t)(sub * GPW + grp);
+                const uint32_t k = kb + (uint32_t)(sub * GPW + grp);
                 bool pass = false, defer = false;
                 int cls = 0;
                 const int2 pq = pq0;
@@ -642,15 +639,14 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                         }
                         if (!defer)
                             pass = merge_group_first<G>(a.tok + dr0.x, dr0.y, a.tok + ds0.x, ds0.y,
-                                                        required_overlap(L, R.tn, R.tsum), g, gbase,
+                                                        required_overlap(dr0.y, ds0.y, R), g, gbase,
                                                         wa0, wb0);
                     } else {
                         bad = true;
                     }
                 }
-                stage_wave(pass && g == 0, pq, s_out, &s_ocnt, R.cap == 0);
-                if (deferring)
-                    defer_wave(a, defer && g == 0, cls, a.pair_off[r] + k, s_defer, s_dcnt);
+                stage_pass(pass && g == 0, pq, w_out, ocnt, R.cap == 0);
+                if (deferring) defer_pass(a, defer && g == 0, cls, a.pair_off[r] + k, w_defer, dc);
                 pq0 = pq1;
                 pq1 = pq2;
                 pq2 = pq3;
@@ -661,40 +657,29 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                 wa0 = wa1;
                 wb0 = wb1;
             }
-            if (bad && g == 0) atomicOr(&a.ctr->err[r], 1u);
+            if (ballot(bad) != 0ull && lane == 0) atomicOr(&a.ctr->err[r], 1u);
         }
-        __syncthreads();
-        // at most kTilePairs pairs are staged per iteration: flush when fewer
-        // than that fit, or when the next tile belongs to another request
-        {
-            const uint32_t c = s_ocnt;
-            const bool same_next = Tn < n_tiles && r_cur == r;
-            const bool full = a.req[r].cap != 0 && c > kStage - kTilePairs;
-            if (c > 0 && (full || !same_next)) {
-                flush_out(a, r, c, s_out, &s_obase);
-                if (threadIdx.x == 0) s_ocnt = 0;
-                __syncthreads();
-            }
+        // at most kWave pairs are staged per chunk: flush when fewer than that
+        // fit, or when the next chunk belongs to another request
+        const bool same_next = Tn < n_chunks && r_cur == r;
+        if (ocnt > 0 && ((R.cap != 0 && ocnt > kWStage - kWave) || !same_next)) {
+            wave_flush_out(a, r, ocnt, w_out);
+            ocnt = 0;
         }
         if (deferring) {
             // the same bound holds for each deferred class
             for (int q = a.defer_from; q < kClasses; ++q) {
-                const uint32_t c = s_dcnt[q];
-                if (c > a.defer_cap - kTilePairs) {
-                    flush_deferred(a, q, c, s_defer + (uint32_t)(q - a.defer_from) * a.defer_cap,
-                                   &s_base);
-                    if (threadIdx.x == 0) s_dcnt[q] = 0;
-                    __syncthreads();
+                const uint32_t c = dcount(dc, q);
+                if (c > a.defer_cap - kWave) {
+                    wave_flush_deferred(a, q, c, w_defer);
+                    dc &= ~(0xffull << (8 * q));
                 }
             }
         }
     }
     if (deferring) {
-        __syncthreads();
         for (int q = a.defer_from; q < kClasses; ++q) {
-            const uint32_t c = s_dcnt[q];
-            if (c > 0)
-                flush_deferred(a, q, c, s_defer + (uint32_t)(q - a.defer_from) * a.defer_cap, &s_base);
+            if (dcount(dc, q) > 0) wave_flush_deferred(a, q, dcount(dc, q), w_defer);
         }
     }
 }
@@ -771,7 +756,7 @@ __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
         const int32_t wb1 = first_tile_token(a.tok, ds1, g);
         if (t + (uint32_t)grp < cnt) {
             const Request& R = a.req[r0];
-            const uint32_t alpha = required_overlap(dr0.y + ds0.y, R.tn, R.tsum);
+            const uint32_t alpha = required_overlap(dr0.y, ds0.y, R);
             bool pass;
             if constexpr (G == 1)
                 pass = merge_thread(a.tok + dr0.x, dr0.y, a.tok + ds0.x, ds0.y, alpha);
@@ -820,7 +805,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
             const uint2 dr = set_desc(a, pr.x);
             const uint2 ds = set_desc(a, pr.y);
             const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y,
-                                          required_overlap(dr.y + ds.y, R.tn, R.tsum), sb, red);
+                                          required_overlap(dr.y, ds.y, R), sb, red);
             if (threadIdx.x == 0 && pass) append_one(pr, R, &a.ctr->out_count[r]);
         }
     }
@@ -862,27 +847,33 @@ bool lanes_supported(int lanes) {
 }
 
 bool inline_supported(int lanes, int hard_lanes) {
-    return kernel_verify_tiles(lanes, hard_lanes) != nullptr;
+    return kernel_verify_tiles(lanes, hard_lanes, false) != nullptr;
 }
 
-const void* kernel_verify_tiles(int lanes, int hard_lanes) {
+template <bool D>
+const void* verify_tiles_instance(int lanes, int hard_lanes) {
     if (lanes == 1) {
         switch (hard_lanes) {
-            case 0: return (const void*)&k_verify_tiles<1, 0>;
-            case 8: return (const void*)&k_verify_tiles<1, 8>;
-            case 16: return (const void*)&k_verify_tiles<1, 16>;
+            case 0: return (const void*)&k_verify_tiles<1, 0, D>;
+            case 8: return (const void*)&k_verify_tiles<1, 8, D>;
+            case 16: return (const void*)&k_verify_tiles<1, 16, D>;
             default: return nullptr;
         }
     }
     if (hard_lanes != 0) return nullptr;
     switch (lanes) {
-        case 4: return (const void*)&k_verify_tiles<4, 0>;
-        case 8: return (const void*)&k_verify_tiles<8, 0>;
-        case 16: return (const void*)&k_verify_tiles<16, 0>;
-        case 32: return (const void*)&k_verify_tiles<32, 0>;
-        case 64: return (const void*)&k_verify_tiles<64, 0>;
+        case 4: return (const void*)&k_verify_tiles<4, 0, D>;
+        case 8: return (const void*)&k_verify_tiles<8, 0, D>;
+        case 16: return (const void*)&k_verify_tiles<16, 0, D>;
+        case 32: return (const void*)&k_verify_tiles<32, 0, D>;
+        case 64: return (const void*)&k_verify_tiles<64, 0, D>;
         default: return nullptr;
     }
+}
+
+const void* kernel_verify_tiles(int lanes, int hard_lanes, bool deferring) {
+    return deferring ? verify_tiles_instance<true>(lanes, hard_lanes)
+                     : verify_tiles_instance<false>(lanes, hard_lanes);
 }
 
 const void* kernel_verify_deferred() { return (const void*)&k_verify_deferred; }
@@ -898,14 +889,15 @@ hipError_t launch_build_heads(const int64_t* d_offsets, const int32_t* d_tok, ui
 }
 
 size_t tiles_lds_bytes(const LaunchArgs& a) {
-    const size_t tile = (size_t)kBlock;
-    const size_t stage = 2 * tile * sizeof(int2);
+    // per wavefront: 2 * kWave staged output pairs, then defer_cap entries
+    // per deferred class (a multiple of 16 bytes)
+    const size_t stage = 2 * (size_t)kWave * sizeof(int2);
     const size_t defer = a.defer_from < kClasses ? (size_t)(kClasses - a.defer_from) * a.defer_cap * 4u : 0u;
-    return stage + defer;
+    return (size_t)(kBlock / kWave) * (stage + defer);
 }
 
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st) {
-    const void* f = kernel_verify_tiles(a.inline_lanes, a.hard_lanes);
+    const void* f = kernel_verify_tiles(a.inline_lanes, a.hard_lanes, a.defer_from < kClasses);
     if (!f) return hipErrorInvalidValue;
     LaunchArgs args = a;
     void* params[] = {&args};

@@ -45,8 +45,46 @@ constexpr int64_t kMaxLaunchPairs = ((int64_t)1 << 31) - 1;  // pairs per launch
 // pair, and its deferred-class queue entries
 constexpr size_t kBytesPerPair = 8 + 8 + 4 * ssj::kClasses;
 
-bool valid_threshold(int64_t t_num, int64_t t_den) {
-    return t_den > 0 && t_den <= INT32_MAX && t_num >= 0 && t_num <= t_den;
+// Threshold range of a similarity function (SSJ_SIM_*): 0 < t_den < 2^31,
+// 0 <= t_num < 2^31, and t <= 1 for the normalised functions.
+bool valid_threshold(int sim, int64_t t_num, int64_t t_den) {
+    if (sim < SSJ_SIM_JACCARD || sim > SSJ_SIM_OVERLAP) return false;
+    if (t_den <= 0 || t_den > INT32_MAX || t_num < 0 || t_num > INT32_MAX) return false;
+    return sim == SSJ_SIM_OVERLAP || t_num <= t_den;
+}
+
+const char* kThresholdError =
+    "bad similarity function or threshold: need 0 < t_den < 2^31, 0 <= t_num < 2^31, "
+    "and t_num <= t_den except for SSJ_SIM_OVERLAP";
+
+// The request's required-overlap rule (paper Table 1 in integers):
+//   Jaccard  ceil(t_num (|r|+|s|) / (t_num + t_den))
+//   Dice     ceil(t_num (|r|+|s|) / (2 t_den))
+//   Cosine   least o with o^2 t_den^2 >= t_num^2 |r| |s|
+//   Overlap  ceil(t_num / t_den)
+void overlap_rule(int sim, int64_t t_num, int64_t t_den, ssj::Request& R) {
+    switch (sim) {
+        case SSJ_SIM_DICE:
+            R.rule = ssj::kLinear;
+            R.num = (unsigned long long)t_num;
+            R.den = 2ull * (unsigned long long)t_den;
+            break;
+        case SSJ_SIM_COSINE:
+            R.rule = ssj::kCosine;
+            R.num = (unsigned long long)t_num;
+            R.den = (unsigned long long)t_den;
+            break;
+        case SSJ_SIM_OVERLAP:
+            R.rule = ssj::kConstant;
+            R.num = (unsigned long long)((t_num + t_den - 1) / t_den);
+            R.den = 1ull;
+            break;
+        default:
+            R.rule = ssj::kLinear;
+            R.num = (unsigned long long)t_num;
+            R.den = (unsigned long long)(t_num + t_den);
+            break;
+    }
 }
 
 template <class T>
@@ -117,7 +155,7 @@ struct ssj_ctx {
     int n_slots = 4;
     int queue_depth = 64;
     int n_cu = 0;
-    int occ_tiles[8] = {0};
+    int occ_tiles[16] = {0};  // [2 * mapping index + deferring]
     int occ_deferred = 0;
     ssj_plan plan{};
     std::mutex mu;  // default scratch, host staging, collections, plan, graphs
@@ -225,20 +263,24 @@ struct Req {
     int2* d_out;
     int64_t out_cap;
     long long* d_count;
+    int sim = SSJ_SIM_JACCARD;
 };
 
 int check_req(const Req& r) {
-    if (!valid_threshold(r.t_num, r.t_den))
-        return set_error(SSJ_EINVAL, "threshold must satisfy 0 <= t_num <= t_den, 0 < t_den < 2^31");
+    if (!valid_threshold(r.sim, r.t_num, r.t_den)) return set_error(SSJ_EINVAL, kThresholdError);
     if (r.n < 0) return set_error(SSJ_EINVAL, "negative candidate count");
     if (r.out_cap < 0) return set_error(SSJ_EINVAL, "negative output capacity");
     if (!r.d_count || (r.n > 0 && !r.d_cand)) return set_error(SSJ_EINVAL, "null device buffer");
     return SSJ_OK;
 }
 
-int grid_tiles(const ssj_ctx* ctx, int lanes, int hard_lanes, int64_t n_tiles) {
-    const int64_t cap = (int64_t)ctx->n_cu * std::max(1, ctx->occ_tiles[inline_index(lanes, hard_lanes)]);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, cap));
+// Workgroups of the in-order kernel: one per kBlock / kWave chunks, at most
+// what the device holds at once.
+int grid_tiles(const ssj_ctx* ctx, int lanes, int hard_lanes, bool deferring, int64_t n_chunks) {
+    const int occ = ctx->occ_tiles[2 * inline_index(lanes, hard_lanes) + (deferring ? 1 : 0)];
+    const int64_t cap = (int64_t)ctx->n_cu * std::max(1, occ);
+    const int64_t per_wg = ssj::kBlock / ssj::kWave;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n_chunks + per_wg - 1) / per_wg, cap));
 }
 
 int grid_deferred(const ssj_ctx* ctx) { return ctx->n_cu * std::max(1, ctx->occ_deferred); }
@@ -252,7 +294,7 @@ int launch_graph(ssj_ctx* ctx, const ssj::LaunchArgs& a, int g1, int g2, bool tw
     if (it == ctx->graphs.end()) {
         GraphEntry ge;
         HIP_OR_FAIL(ctx, hipGraphCreate(&ge.graph, 0));
-        const void* funcs[3] = {ssj::kernel_verify_tiles(a.inline_lanes, a.hard_lanes),
+        const void* funcs[3] = {ssj::kernel_verify_tiles(a.inline_lanes, a.hard_lanes, two),
                                 ssj::kernel_verify_deferred(), ssj::kernel_finalize()};
         const int grids[3] = {g1, g2, 1};
         const int blocks[3] = {ssj::kBlock, ssj::kBlock, ssj::kWave};
@@ -297,7 +339,8 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     a.defer_from = plan.defer_from;
     a.inline_lanes = plan.inline_lanes;
     a.hard_lanes = plan.hard_lanes;
-    const uint64_t tile_pairs = (uint64_t)ssj::kBlock;
+    // in-order work unit: a chunk of kWave pairs of one request per wavefront
+    const uint64_t tile_pairs = (uint64_t)ssj::kWave;
     a.defer_cap = (uint32_t)(2 * tile_pairs);
     const uint32_t bounds[ssj::kClasses] = SSJ_CLASS_BOUNDS;
     for (int q = 0; q < ssj::kClasses; ++q) {
@@ -314,8 +357,7 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
         R.out = q.d_out;
         R.d_count = q.d_count;
         R.cap = (unsigned long long)q.out_cap;
-        R.tn = (unsigned long long)q.t_num;
-        R.tsum = (unsigned long long)(q.t_num + q.t_den);
+        overlap_rule(q.sim, q.t_num, q.t_den, R);
         R.n = (uint32_t)q.n;
         tiles += ((uint64_t)q.n + tile_pairs - 1) / tile_pairs;
         pairs += (uint64_t)q.n;
@@ -328,7 +370,7 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     }
     a.queues = sc.d_queues;
     a.qcap = (uint32_t)(sc.q_cap / ssj::kClasses);
-    const int g1 = grid_tiles(ctx, plan.inline_lanes, plan.hard_lanes, (int64_t)tiles);
+    const int g1 = grid_tiles(ctx, plan.inline_lanes, plan.hard_lanes, two, (int64_t)tiles);
     const int g2 = grid_deferred(ctx);
 
     std::array<hipEvent_t, 3> ev{nullptr, nullptr, nullptr};
@@ -381,6 +423,7 @@ struct StreamReq {
     uint64_t ticket = 0;
     const ssj_coll* coll = nullptr;
     int64_t t_num = 0, t_den = 1;
+    int sim = SSJ_SIM_JACCARD;
     int64_t n = 0;
     int2* h_cand = nullptr;       // pinned copy of the candidates
     size_t h_cand_bytes = 0;
@@ -505,7 +548,7 @@ bool admit(StreamEngine* E, StreamSlot& s) {
                            hipMemcpyHostToDevice, s.stream) != hipSuccess)
             return false;
         reqs.push_back(Req{s.d_cand + p.dev_off, p.n, p.req->t_num, p.req->t_den,
-                           s.d_out + p.dev_off, p.n, s.d_count + reqs.size()});
+                           s.d_out + p.dev_off, p.n, s.d_count + reqs.size(), p.req->sim});
     }
     ssj_plan plan;
     {
@@ -702,9 +745,10 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
         hipDeviceProp_t prop;
         if ((e = hipGetDeviceProperties(&prop, ctx->device)) != hipSuccess) { rc = hip_fail(ctx, "hipGetDeviceProperties", e); break; }
         ctx->n_cu = prop.multiProcessorCount;
-        for (int k = 0; k < 8 && rc == SSJ_OK; ++k) {
+        for (int k = 0; k < 16 && rc == SSJ_OK; ++k) {
             int occ = 0;
-            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_tiles(kInlineLanes[k], kInlineHard[k]), ssj::kBlock, 0)) != hipSuccess)
+            const void* f = ssj::kernel_verify_tiles(kInlineLanes[k / 2], kInlineHard[k / 2], (k & 1) != 0);
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, ssj::kBlock, 0)) != hipSuccess)
                 rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
             ctx->occ_tiles[k] = occ;
         }
@@ -913,7 +957,7 @@ int ssj_verify_batch_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_reques
     for (int i = 0; i < n_reqs; ++i) {
         v[i] = Req{reinterpret_cast<const int2*>(reqs[i].d_cand), reqs[i].n_cand, reqs[i].t_num,
                    reqs[i].t_den, reinterpret_cast<int2*>(reqs[i].d_out), reqs[i].out_cap,
-                   reinterpret_cast<long long*>(reqs[i].d_count)};
+                   reinterpret_cast<long long*>(reqs[i].d_count), reqs[i].sim};
         if ((rc = check_req(v[i])) != SSJ_OK) return rc;
         total += v[i].n;
         if (total > kMaxLaunchPairs) return set_error(SSJ_EINVAL, "a batch must hold fewer than 2^31 pairs");
@@ -924,14 +968,14 @@ int ssj_verify_batch_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_reques
     return enqueue_launch(ctx, coll, ctx->def, v.data(), n_reqs, (hipStream_t)hip_stream, ctx->plan);
 }
 
-int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
-                      int64_t t_num, int64_t t_den, ssj_pair* d_out, int64_t out_cap,
-                      int64_t* d_count, void* hip_stream) {
+int ssj_verify_device_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand,
+                          int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* d_out,
+                          int64_t out_cap, int64_t* d_count, void* hip_stream) {
     int rc = check_ctx(ctx);
     if (rc != SSJ_OK) return rc;
     if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
     Req r{reinterpret_cast<const int2*>(d_cand), n_cand, t_num, t_den, reinterpret_cast<int2*>(d_out),
-          out_cap, reinterpret_cast<long long*>(d_count)};
+          out_cap, reinterpret_cast<long long*>(d_count), sim};
     if ((rc = check_req(r)) != SSJ_OK) return rc;
     if (n_cand > kMaxLaunchPairs) return set_error(SSJ_EINVAL, "n_cand must be below 2^31 per device call");
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -939,13 +983,20 @@ int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand
     return enqueue_launch(ctx, coll, ctx->def, &r, 1, (hipStream_t)hip_stream, ctx->plan);
 }
 
-int ssj_verify(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
-               int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap, int64_t* out_n) {
+int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
+                      int64_t t_num, int64_t t_den, ssj_pair* d_out, int64_t out_cap,
+                      int64_t* d_count, void* hip_stream) {
+    return ssj_verify_device_sim(ctx, coll, d_cand, n_cand, SSJ_SIM_JACCARD, t_num, t_den, d_out,
+                                 out_cap, d_count, hip_stream);
+}
+
+int ssj_verify_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
+                   int sim, int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap,
+                   int64_t* out_n) {
     int rc = check_ctx(ctx);
     if (rc != SSJ_OK) return rc;
     if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
-    if (!valid_threshold(t_num, t_den))
-        return set_error(SSJ_EINVAL, "threshold must satisfy 0 <= t_num <= t_den, 0 < t_den < 2^31");
+    if (!valid_threshold(sim, t_num, t_den)) return set_error(SSJ_EINVAL, kThresholdError);
     if (n_cand < 0 || out_cap < 0) return set_error(SSJ_EINVAL, "negative size");
     if (!out_n || (n_cand > 0 && !cand) || (out_cap > 0 && !out))
         return set_error(SSJ_EINVAL, "null host buffer");
@@ -963,7 +1014,7 @@ int ssj_verify(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t
         HIP_OR_FAIL(ctx, grow(ctx->d_out, ctx->out_cap, (size_t)std::max<int64_t>(n, 1)));
         if (n > 0)
             HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->d_cand, cand + done, (size_t)n * 8, hipMemcpyHostToDevice, st));
-        Req r{ctx->d_cand, n, t_num, t_den, ctx->d_out, n, ctx->d_count};
+        Req r{ctx->d_cand, n, t_num, t_den, ctx->d_out, n, ctx->d_count, sim};
         rc = enqueue_launch(ctx, coll, ctx->def, &r, 1, st, ctx->plan);
         if (rc != SSJ_OK) return rc;
         HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, ctx->d_count, sizeof(long long), hipMemcpyDeviceToHost, st));
@@ -991,12 +1042,18 @@ int ssj_verify(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t
     return SSJ_OK;
 }
 
+int ssj_verify(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
+               int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap, int64_t* out_n) {
+    return ssj_verify_sim(ctx, coll, cand, n_cand, SSJ_SIM_JACCARD, t_num, t_den, out, out_cap,
+                          out_n);
+}
+
 int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
                  int64_t t_num, int64_t t_den, int apply, ssj_plan* best, double* best_ms) {
     int rc = check_ctx(ctx);
     if (rc != SSJ_OK) return rc;
     if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
-    if (!valid_threshold(t_num, t_den)) return set_error(SSJ_EINVAL, "bad threshold");
+    if (!valid_threshold(SSJ_SIM_JACCARD, t_num, t_den)) return set_error(SSJ_EINVAL, kThresholdError);
     if (n_cand <= 0 || n_cand > kMaxLaunchPairs || !d_cand)
         return set_error(SSJ_EINVAL, "autotuning needs 1 .. 2^31-1 device candidates");
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -1074,13 +1131,19 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
 
 int ssj_stream_submit(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
                       int64_t t_num, int64_t t_den, int nonblocking, uint64_t* ticket) {
+    return ssj_stream_submit_sim(ctx, coll, cand, n_cand, SSJ_SIM_JACCARD, t_num, t_den,
+                                 nonblocking, ticket);
+}
+
+int ssj_stream_submit_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand,
+                          int64_t n_cand, int sim, int64_t t_num, int64_t t_den, int nonblocking,
+                          uint64_t* ticket) {
     int rc = check_ctx(ctx);
     if (rc != SSJ_OK) return rc;
     if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
     if (!ticket) return set_error(SSJ_EINVAL, "null ticket pointer");
     *ticket = 0;
-    if (!valid_threshold(t_num, t_den))
-        return set_error(SSJ_EINVAL, "threshold must satisfy 0 <= t_num <= t_den, 0 < t_den < 2^31");
+    if (!valid_threshold(sim, t_num, t_den)) return set_error(SSJ_EINVAL, kThresholdError);
     if (n_cand < 0 || (n_cand > 0 && !cand)) return set_error(SSJ_EINVAL, "bad candidate buffer");
     StreamEngine* E = ctx->engine.get();
     if (!E) return set_error(SSJ_EINVAL, "streaming engine not running");
@@ -1098,6 +1161,7 @@ int ssj_stream_submit(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, 
     r->coll = coll;
     r->t_num = t_num;
     r->t_den = t_den;
+    r->sim = sim;
     r->n = n_cand;
     r->t_submit = now_ns();
     r->h_cand = (int2*)pinned_get(E, (size_t)std::max<int64_t>(n_cand, 1) * 8, &r->h_cand_bytes);

@@ -12,16 +12,24 @@ constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kMaxReq = 16;      // requests per launch
 constexpr int kHeadTokens = 6;   // leading tokens kept in each 32-byte set record
 
+// How a request turns set sizes into its required overlap alpha (the
+// equivalent overlap of paper Table 1).
+enum OverlapRule : uint32_t {
+    kLinear = 0,    // alpha = ceil(num * (|r| + |s|) / den): Jaccard, Dice
+    kCosine = 1,    // alpha = least o with o^2 * den^2 >= num^2 * |r| * |s|
+    kConstant = 2,  // alpha = num: Overlap
+};
+
 // One verification request inside a launch.
 struct Request {
     const int2* cand;          // (r, s) pairs
     int2* out;                 // passing pairs
     long long* d_count;        // result count, -1 on an id error
     unsigned long long cap;    // capacity of out in pairs
-    unsigned long long tn;     // t_num
-    unsigned long long tsum;   // t_num + t_den
+    unsigned long long num;    // threshold terms of the overlap rule
+    unsigned long long den;
     uint32_t n;                // pairs
-    uint32_t pad;
+    uint32_t rule;             // OverlapRule
 };
 
 // Per-launch device counters.  Every launch leaves them zeroed again (its
@@ -47,8 +55,8 @@ struct LaunchArgs {
     int defer_from;                      // first deferred class (kClasses: none)
     int inline_lanes;                    // lanes per pair in the in-order kernel
     int hard_lanes;                      // lanes finishing long merges (inline_lanes == 1)
-    uint32_t defer_cap;                  // LDS queue entries per deferred class (>= 2 tiles)
-    uint32_t tile_off[kMaxReq + 1];      // prefix sums of per-request tiles (of tile_pairs)
+    uint32_t defer_cap;                  // LDS queue entries per deferred class and wavefront (>= 2 chunks)
+    uint32_t tile_off[kMaxReq + 1];      // prefix sums of per-request chunks (of kWave pairs)
     uint32_t pair_off[kMaxReq + 1];      // prefix sums of per-request pairs
     uint32_t bounds[kClasses];           // inclusive upper bound of |r|+|s| per class
     int lanes[kClasses];                 // lanes per pair of each deferred class
@@ -70,7 +78,7 @@ size_t tiles_lds_bytes(const LaunchArgs& a);
 // Publishes the request counts and resets the counters (always last).
 hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st);
 
-const void* kernel_verify_tiles(int lanes, int hard_lanes);
+const void* kernel_verify_tiles(int lanes, int hard_lanes, bool deferring);
 const void* kernel_verify_deferred();
 const void* kernel_finalize();
 

@@ -29,6 +29,14 @@ SSJ_EAGAIN = -4
 SSJ_EDEVICE = -5
 SSJ_ENOTFOUND = -6
 
+# similarity functions (paper Table 1); Overlap's threshold is a count
+SSJ_SIM_JACCARD = 0
+SSJ_SIM_COSINE = 1
+SSJ_SIM_DICE = 2
+SSJ_SIM_OVERLAP = 3
+SIMS = {"jaccard": SSJ_SIM_JACCARD, "cosine": SSJ_SIM_COSINE, "dice": SSJ_SIM_DICE,
+        "overlap": SSJ_SIM_OVERLAP}
+
 SSJ_N_CLASSES = 5
 SSJ_CLASS_BOUNDS = (32, 128, 512, 2048, 0x7FFFFFFF)
 SSJ_MAX_BATCH = 16
@@ -38,7 +46,7 @@ EXPORTED = (
     "ssj_free_collection", "ssj_verify", "ssj_verify_device", "ssj_stream_submit",
     "ssj_stream_poll", "ssj_stream_times", "ssj_get_plan", "ssj_set_plan",
     "ssj_collection_info", "ssj_timing_enable", "ssj_timing_read", "ssj_verify_batch_device",
-    "ssj_autotune",
+    "ssj_autotune", "ssj_verify_sim", "ssj_verify_device_sim", "ssj_stream_submit_sim",
 )
 
 _NAMES = {
@@ -79,7 +87,7 @@ class ssj_request(ctypes.Structure):
     _fields_ = [("d_cand", ctypes.c_void_p), ("n_cand", ctypes.c_int64),
                 ("t_num", ctypes.c_int64), ("t_den", ctypes.c_int64),
                 ("d_out", ctypes.c_void_p), ("out_cap", ctypes.c_int64),
-                ("d_count", ctypes.c_void_p)]
+                ("d_count", ctypes.c_void_p), ("sim", ctypes.c_int32)]
 
 
 _lib = None
@@ -113,6 +121,9 @@ def load_library(path: str = LIB_PATH):
         "ssj_timing_read": ([p, c_int, P(ctypes.c_double), P(ctypes.c_double), P(i64)], c_int),
         "ssj_verify_batch_device": ([p, p, P(ssj_request), c_int, p], c_int),
         "ssj_autotune": ([p, p, p, i64, i64, i64, c_int, P(ssj_plan), P(ctypes.c_double)], c_int),
+        "ssj_verify_sim": ([p, p, p, i64, c_int, i64, i64, p, i64, P(i64)], c_int),
+        "ssj_verify_device_sim": ([p, p, p, i64, c_int, i64, i64, p, i64, p, p], c_int),
+        "ssj_stream_submit_sim": ([p, p, p, i64, c_int, i64, i64, c_int, P(u64)], c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -189,6 +200,62 @@ def ssj_verify(ctx, coll, cand, t_num: int, t_den: int, out_cap: Optional[int] =
     if rc != SSJ_OK:
         _err(ctx, rc, out_n.value)
     return out[:out_n.value].copy()
+
+
+def sim_code(sim) -> int:
+    """SSJ_SIM_* code of a similarity function given by code or name."""
+    if isinstance(sim, str):
+        if sim not in SIMS:
+            raise ValueError(f"unknown similarity function {sim!r}")
+        return SIMS[sim]
+    return int(sim)
+
+
+def ssj_verify_sim(ctx, coll, cand, sim, t_num: int, t_den: int,
+                   out_cap: Optional[int] = None) -> np.ndarray:
+    """ssj_verify with a similarity function of Table 1 (code or name)."""
+    c = _pairs(cand)
+    n = c.shape[0]
+    cap = n if out_cap is None else int(out_cap)
+    out = np.zeros((max(cap, 1), 2), dtype=np.int32)
+    out_n = ctypes.c_int64()
+    rc = load_library().ssj_verify_sim(ctx, coll, c.ctypes.data if n else None, n, sim_code(sim),
+                                       int(t_num), int(t_den), out.ctypes.data, cap,
+                                       ctypes.byref(out_n))
+    if rc != SSJ_OK:
+        _err(ctx, rc, out_n.value)
+    return out[:out_n.value].copy()
+
+
+def ssj_verify_device_sim(ctx, coll, d_cand: "torch.Tensor", sim, t_num: int, t_den: int,
+                          d_out: "torch.Tensor", d_count: "torch.Tensor", stream=None) -> None:
+    """ssj_verify_device with a similarity function of Table 1 (code or name)."""
+    assert d_cand.is_cuda and d_cand.dtype == torch.int32 and d_cand.is_contiguous()
+    if d_out is not None:
+        assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
+    assert d_count.is_cuda and d_count.dtype == torch.int64 and d_count.numel() >= 1
+    n = d_cand.numel() // 2
+    cap = d_out.numel() // 2 if d_out is not None else 0
+    st = stream if stream is not None else torch.cuda.current_stream(d_cand.device)
+    rc = load_library().ssj_verify_device_sim(ctx, coll, d_cand.data_ptr() if n else None, n,
+                                              sim_code(sim), int(t_num), int(t_den),
+                                              d_out.data_ptr() if cap else None, cap,
+                                              d_count.data_ptr(), ctypes.c_void_p(st.cuda_stream))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def ssj_stream_submit_sim(ctx, coll, cand, sim, t_num: int, t_den: int,
+                          nonblocking: bool = False) -> int:
+    """ssj_stream_submit with a similarity function of Table 1 (code or name)."""
+    c = _pairs(cand)
+    t = ctypes.c_uint64()
+    rc = load_library().ssj_stream_submit_sim(ctx, coll, c.ctypes.data if c.shape[0] else None,
+                                              c.shape[0], sim_code(sim), int(t_num), int(t_den),
+                                              int(bool(nonblocking)), ctypes.byref(t))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+    return t.value
 
 
 def ssj_verify_device(ctx, coll, d_cand: "torch.Tensor", t_num: int, t_den: int,
@@ -273,11 +340,14 @@ def ssj_set_plan(ctx, plan: ssj_plan) -> None:
 
 
 def ssj_verify_batch_device(ctx, coll, requests, stream=None) -> None:
-    """requests: list of (d_cand, t_num, t_den, d_out, d_count) torch tensors/ints."""
+    """requests: list of (d_cand, t_num, t_den, d_out, d_count[, sim]) torch tensors/ints
+    (sim, a code or name of a Table 1 function, defaults to Jaccard)."""
     n = len(requests)
     arr = (ssj_request * max(n, 1))()
     dev = None
-    for i, (d_cand, tn, td, d_out, d_count) in enumerate(requests):
+    for i, req in enumerate(requests):
+        d_cand, tn, td, d_out, d_count = req[:5]
+        sim = sim_code(req[5]) if len(req) > 5 else SSJ_SIM_JACCARD
         assert d_cand.is_cuda and d_cand.dtype == torch.int32 and d_cand.is_contiguous()
         if d_out is not None:
             assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
@@ -285,7 +355,7 @@ def ssj_verify_batch_device(ctx, coll, requests, stream=None) -> None:
         nc = d_cand.numel() // 2
         cap = d_out.numel() // 2 if d_out is not None else 0
         arr[i] = ssj_request(d_cand.data_ptr() if nc else None, nc, int(tn), int(td),
-                             d_out.data_ptr() if cap else None, cap, d_count.data_ptr())
+                             d_out.data_ptr() if cap else None, cap, d_count.data_ptr(), sim)
         dev = d_cand.device
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     rc = load_library().ssj_verify_batch_device(ctx, coll, arr, n, ctypes.c_void_p(st.cuda_stream))

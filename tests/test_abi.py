@@ -80,3 +80,18 @@ def test_constants_match_header():
     vals = tuple(int(v.strip(), 0) for v in m.group(1).split(","))
     assert vals == ssj.SSJ_CLASS_BOUNDS
     assert int(re.search(r"SSJ_N_CLASSES\s+(\d+)", text).group(1)) == ssj.SSJ_N_CLASSES
+    for name in ["SSJ_SIM_JACCARD", "SSJ_SIM_COSINE", "SSJ_SIM_DICE", "SSJ_SIM_OVERLAP"]:
+        m = re.search(r"#define\s+" + name + r"\s+(\d+)", text)
+        assert m and int(m.group(1)) == getattr(ssj, name)
+
+
+def test_request_struct_matches_header():
+    # the batch request struct ends with the similarity function
+    import ctypes
+    import paper_1812_09141_amd.ssj as ssj
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{([^}]*)\} ssj_request;", text).group(1)
+    fields = [ln.strip().rstrip(";").split()[-1].lstrip("*") for ln in body.strip().splitlines()
+              if ln.strip() and not ln.strip().startswith("/")]
+    assert fields == [f[0] for f in ssj.ssj_request._fields_]
+    assert ctypes.sizeof(ssj.ssj_request) == 64
