@@ -58,13 +58,17 @@ __device__ __forceinline__ uint32_t cosine_overlap(uint32_t na, uint32_t nb, uns
     return (uint32_t)o;
 }
 
+// C: whether the instance handles the Cosine rule (its 128-bit arithmetic
+// costs registers in every kernel that contains it, so only launches with a
+// Cosine request use such an instance).
+template <bool C>
 __device__ __forceinline__ uint32_t required_overlap(uint32_t na, uint32_t nb, const Request& R) {
-    if (R.rule == kLinear) {
-        const unsigned long long L = (unsigned long long)na + nb;
-        return (uint32_t)((R.num * L + R.den - 1ull) / R.den);
+    if constexpr (C) {
+        if (R.rule == kCosine) return cosine_overlap(na, nb, R.num, R.den);
     }
     if (R.rule == kConstant) return (uint32_t)R.num;
-    return cosine_overlap(na, nb, R.num, R.den);
+    const unsigned long long L = (unsigned long long)na + nb;
+    return (uint32_t)((R.num * L + R.den - 1ull) / R.den);
 }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
@@ -436,7 +440,7 @@ __device__ __forceinline__ void head_tiles(uint4 a0, uint4 a1, uint4 b0, uint4 b
 // its merge state, to the wavefront's list of hard pairs (hcnt entries), which
 // groups of F lanes finish (finish_hard), so that no lane walks the token
 // array alone while the rest of its wavefront waits.
-template <int F>
+template <int F, bool C>
 __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Request& R, int r,
                                                    uint32_t kb, int2 pr, const LaneRecords& rec,
                                                    bool deferring, uint32_t* w_defer,
@@ -451,7 +455,7 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
     const int cls = deferring ? class_of(L, a) : 0;
     const bool defer = ok && deferring && cls >= a.defer_from;
     const bool run = ok && !defer;
-    const uint32_t alpha = run ? required_overlap(na, nb, R) : 0u;
+    const uint32_t alpha = run ? required_overlap<C>(na, nb, R) : 0u;
     uint32_t i, j, o;
     head_tiles(rec.ra0, rec.ra1, rec.rb0, rec.rb1, &i, &j, &o);
     bool pass = run && o >= alpha;
@@ -490,7 +494,7 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
 // Finishes the wavefront's h hard pairs: groups of G lanes resume their
 // merges from the saved state with the tile merge.  The loop over the list
 // is wave-uniform, so the staging after each step runs with all lanes.
-template <int G>
+template <int G, bool C>
 __device__ __forceinline__ void finish_hard(const LaunchArgs& a, const Request& R, uint32_t h,
                                             const int2* w_hpr, const uint32_t* w_hst, int2* w_out,
                                             uint32_t& ocnt) {
@@ -508,7 +512,7 @@ __device__ __forceinline__ void finish_hard(const LaunchArgs& a, const Request& 
             const uint32_t st = w_hst[e];
             const uint2 dr = set_desc(a, pq.x);
             const uint2 ds = set_desc(a, pq.y);
-            const uint32_t alpha = required_overlap(dr.y, ds.y, R);
+            const uint32_t alpha = required_overlap<C>(dr.y, ds.y, R);
             pass = merge_group<G>(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, g, gbase,
                                   st & 0xffu, (st >> 8) & 0xffu, st >> 16);
         }
@@ -523,11 +527,14 @@ __device__ __forceinline__ void finish_hard(const LaunchArgs& a, const Request& 
 // lane per pair.  G > 1: 64/G pairs at a time, G lanes each.  D: whether
 // the instance can defer length classes (an instance without that code needs
 // fewer registers).
-template <int G, int F, bool D>
+template <int G, int F, bool D, bool C>
 __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     constexpr int GPW = kWave / G;
     constexpr uint32_t kWaves = (uint32_t)(kBlock / kWave);
-    constexpr uint32_t kWStage = 2 * (uint32_t)kWave;  // staged output pairs per wavefront
+    // staged output pairs per wavefront: every flush is one atomic on the
+    // request's counter, and same-address atomics from all wavefronts are
+    // serialised, so flushes carry at least kWStage - kWave pairs
+    constexpr uint32_t kWStage = kWaveStage;
     // the wavefront index is uniform in the wavefront: taken through a scalar
     // register for the chunk walk (which then stays scalar); the LDS
     // addresses use the per-lane copy (vector registers are the cheaper ones)
@@ -583,11 +590,11 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
             uint32_t kb2 = 0;
             chunk_origin(a, min(Tn + nw, n_chunks - 1), &r2, &kb2);
             const int2 p2 = lane_pair(a.req[r2], kb2, lane);
-            chunk_thread_pairs<F>(a, R, r, kb, p0, rec0, deferring, w_defer, dc, w_out, ocnt,
+            chunk_thread_pairs<F, C>(a, R, r, kb, p0, rec0, deferring, w_defer, dc, w_out, ocnt,
                                   w_hpr, w_hst, hcnt);
             if constexpr (F > 0) {
                 if (hcnt > 0) {
-                    finish_hard<F>(a, R, hcnt, w_hpr, w_hst, w_out, ocnt);
+                    finish_hard<F, C>(a, R, hcnt, w_hpr, w_hst, w_out, ocnt);
                     hcnt = 0;
                 }
             }
@@ -639,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                         }
                         if (!defer)
                             pass = merge_group_first<G>(a.tok + dr0.x, dr0.y, a.tok + ds0.x, ds0.y,
-                                                        required_overlap(dr0.y, ds0.y, R), g, gbase,
+                                                        required_overlap<C>(dr0.y, ds0.y, R), g, gbase,
                                                         wa0, wb0);
                     } else {
                         bad = true;
@@ -706,7 +713,7 @@ __global__ void k_finalize(LaunchArgs a) {
 // Deferred classes.  Workgroup-mapped classes (lanes == kBlock) are taken one
 // pair per workgroup by work stealing; the others are split statically over
 // all wavefronts of the grid.
-template <int G>
+template <int G, bool C>
 __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
     constexpr int GPW = kWave / G;
     const int lane = lane_id();
@@ -756,7 +763,7 @@ __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
         const int32_t wb1 = first_tile_token(a.tok, ds1, g);
         if (t + (uint32_t)grp < cnt) {
             const Request& R = a.req[r0];
-            const uint32_t alpha = required_overlap(dr0.y, ds0.y, R);
+            const uint32_t alpha = required_overlap<C>(dr0.y, ds0.y, R);
             bool pass;
             if constexpr (G == 1)
                 pass = merge_thread(a.tok + dr0.x, dr0.y, a.tok + ds0.x, ds0.y, alpha);
@@ -781,6 +788,7 @@ __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
     }
 }
 
+template <bool C>
 __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
     __shared__ int32_t sb[kBlock];
     __shared__ uint32_t red[16];
@@ -805,7 +813,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
             const uint2 dr = set_desc(a, pr.x);
             const uint2 ds = set_desc(a, pr.y);
             const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y,
-                                          required_overlap(dr.y, ds.y, R), sb, red);
+                                          required_overlap<C>(dr.y, ds.y, R), sb, red);
             if (threadIdx.x == 0 && pass) append_one(pr, R, &a.ctr->out_count[r]);
         }
     }
@@ -813,12 +821,12 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
         const uint32_t cnt = load_relaxed(&a.ctr->tail[q]);
         if (cnt == 0) continue;
         switch (a.lanes[q]) {
-            case 1: drain_static<1>(a, q, cnt); break;
-            case 4: drain_static<4>(a, q, cnt); break;
-            case 8: drain_static<8>(a, q, cnt); break;
-            case 16: drain_static<16>(a, q, cnt); break;
-            case 32: drain_static<32>(a, q, cnt); break;
-            case 64: drain_static<64>(a, q, cnt); break;
+            case 1: drain_static<1, C>(a, q, cnt); break;
+            case 4: drain_static<4, C>(a, q, cnt); break;
+            case 8: drain_static<8, C>(a, q, cnt); break;
+            case 16: drain_static<16, C>(a, q, cnt); break;
+            case 32: drain_static<32, C>(a, q, cnt); break;
+            case 64: drain_static<64, C>(a, q, cnt); break;
             default: break;
         }
     }
@@ -847,36 +855,41 @@ bool lanes_supported(int lanes) {
 }
 
 bool inline_supported(int lanes, int hard_lanes) {
-    return kernel_verify_tiles(lanes, hard_lanes, false) != nullptr;
+    return kernel_verify_tiles(lanes, hard_lanes, false, false) != nullptr;
 }
 
-template <bool D>
+template <bool D, bool C>
 const void* verify_tiles_instance(int lanes, int hard_lanes) {
     if (lanes == 1) {
         switch (hard_lanes) {
-            case 0: return (const void*)&k_verify_tiles<1, 0, D>;
-            case 8: return (const void*)&k_verify_tiles<1, 8, D>;
-            case 16: return (const void*)&k_verify_tiles<1, 16, D>;
+            case 0: return (const void*)&k_verify_tiles<1, 0, D, C>;
+            case 8: return (const void*)&k_verify_tiles<1, 8, D, C>;
+            case 16: return (const void*)&k_verify_tiles<1, 16, D, C>;
             default: return nullptr;
         }
     }
     if (hard_lanes != 0) return nullptr;
     switch (lanes) {
-        case 4: return (const void*)&k_verify_tiles<4, 0, D>;
-        case 8: return (const void*)&k_verify_tiles<8, 0, D>;
-        case 16: return (const void*)&k_verify_tiles<16, 0, D>;
-        case 32: return (const void*)&k_verify_tiles<32, 0, D>;
-        case 64: return (const void*)&k_verify_tiles<64, 0, D>;
+        case 4: return (const void*)&k_verify_tiles<4, 0, D, C>;
+        case 8: return (const void*)&k_verify_tiles<8, 0, D, C>;
+        case 16: return (const void*)&k_verify_tiles<16, 0, D, C>;
+        case 32: return (const void*)&k_verify_tiles<32, 0, D, C>;
+        case 64: return (const void*)&k_verify_tiles<64, 0, D, C>;
         default: return nullptr;
     }
 }
 
-const void* kernel_verify_tiles(int lanes, int hard_lanes, bool deferring) {
-    return deferring ? verify_tiles_instance<true>(lanes, hard_lanes)
-                     : verify_tiles_instance<false>(lanes, hard_lanes);
+const void* kernel_verify_tiles(int lanes, int hard_lanes, bool deferring, bool cosine) {
+    if (cosine)
+        return deferring ? verify_tiles_instance<true, true>(lanes, hard_lanes)
+                         : verify_tiles_instance<false, true>(lanes, hard_lanes);
+    return deferring ? verify_tiles_instance<true, false>(lanes, hard_lanes)
+                     : verify_tiles_instance<false, false>(lanes, hard_lanes);
 }
 
-const void* kernel_verify_deferred() { return (const void*)&k_verify_deferred; }
+const void* kernel_verify_deferred(bool cosine) {
+    return cosine ? (const void*)&k_verify_deferred<true> : (const void*)&k_verify_deferred<false>;
+}
 
 hipError_t launch_build_heads(const int64_t* d_offsets, const int32_t* d_tok, uint4* d_heads,
                               int64_t n_sets, hipStream_t st) {
@@ -889,15 +902,16 @@ hipError_t launch_build_heads(const int64_t* d_offsets, const int32_t* d_tok, ui
 }
 
 size_t tiles_lds_bytes(const LaunchArgs& a) {
-    // per wavefront: 2 * kWave staged output pairs, then defer_cap entries
+    // per wavefront: kWaveStage staged output pairs, then defer_cap entries
     // per deferred class (a multiple of 16 bytes)
-    const size_t stage = 2 * (size_t)kWave * sizeof(int2);
+    const size_t stage = (size_t)kWaveStage * sizeof(int2);
     const size_t defer = a.defer_from < kClasses ? (size_t)(kClasses - a.defer_from) * a.defer_cap * 4u : 0u;
     return (size_t)(kBlock / kWave) * (stage + defer);
 }
 
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st) {
-    const void* f = kernel_verify_tiles(a.inline_lanes, a.hard_lanes, a.defer_from < kClasses);
+    const void* f = kernel_verify_tiles(a.inline_lanes, a.hard_lanes, a.defer_from < kClasses,
+                                        a.cosine != 0);
     if (!f) return hipErrorInvalidValue;
     LaunchArgs args = a;
     void* params[] = {&args};
@@ -912,7 +926,10 @@ hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st) {
 const void* kernel_finalize() { return (const void*)&k_finalize; }
 
 hipError_t launch_verify_deferred(const LaunchArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_verify_deferred, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
+    if (a.cosine)
+        hipLaunchKernelGGL(k_verify_deferred<true>, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_verify_deferred<false>, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 

@@ -118,10 +118,10 @@ struct Scratch {
 };
 
 struct GraphKey {
-    int inline_lanes, hard_lanes, defer_from, grid1, grid2;
+    int inline_lanes, hard_lanes, defer_from, cosine, grid1, grid2;
     bool operator<(const GraphKey& o) const {
-        return std::tie(inline_lanes, hard_lanes, defer_from, grid1, grid2) <
-               std::tie(o.inline_lanes, o.hard_lanes, o.defer_from, o.grid1, o.grid2);
+        return std::tie(inline_lanes, hard_lanes, defer_from, cosine, grid1, grid2) <
+               std::tie(o.inline_lanes, o.hard_lanes, o.defer_from, o.cosine, o.grid1, o.grid2);
     }
 };
 
@@ -155,8 +155,10 @@ struct ssj_ctx {
     int n_slots = 4;
     int queue_depth = 64;
     int n_cu = 0;
-    int occ_tiles[16] = {0};  // [2 * mapping index + deferring]
-    int occ_deferred = 0;
+    // in-order kernel workgroups per CU, limited by registers and by its
+    // dynamic LDS: [4 * mapping index + 2 * cosine + deferring][deferred classes]
+    int occ_tiles[32][ssj::kClasses + 1] = {};
+    int occ_deferred2[2] = {0};  // [cosine]
     ssj_plan plan{};
     std::mutex mu;  // default scratch, host staging, collections, plan, graphs
     hipStream_t stream = nullptr;  // the context's own stream (host-buffer calls)
@@ -276,26 +278,31 @@ int check_req(const Req& r) {
 
 // Workgroups of the in-order kernel: one per kBlock / kWave chunks, at most
 // what the device holds at once.
-int grid_tiles(const ssj_ctx* ctx, int lanes, int hard_lanes, bool deferring, int64_t n_chunks) {
-    const int occ = ctx->occ_tiles[2 * inline_index(lanes, hard_lanes) + (deferring ? 1 : 0)];
+int grid_tiles(const ssj_ctx* ctx, int lanes, int hard_lanes, int defer_from, bool cosine,
+               int64_t n_chunks) {
+    const bool deferring = defer_from < ssj::kClasses;
+    const int occ = ctx->occ_tiles[4 * inline_index(lanes, hard_lanes) + (cosine ? 2 : 0) +
+                                   (deferring ? 1 : 0)][ssj::kClasses - defer_from];
     const int64_t cap = (int64_t)ctx->n_cu * std::max(1, occ);
     const int64_t per_wg = ssj::kBlock / ssj::kWave;
     return (int)std::max<int64_t>(1, std::min<int64_t>((n_chunks + per_wg - 1) / per_wg, cap));
 }
 
-int grid_deferred(const ssj_ctx* ctx) { return ctx->n_cu * std::max(1, ctx->occ_deferred); }
+int grid_deferred(const ssj_ctx* ctx, bool cosine) {
+    return ctx->n_cu * std::max(1, ctx->occ_deferred2[cosine ? 1 : 0]);
+}
 
 int launch_graph(ssj_ctx* ctx, const ssj::LaunchArgs& a, int g1, int g2, bool two,
                  hipStream_t st) {
-    GraphKey key{a.inline_lanes, a.hard_lanes, a.defer_from, g1, two ? g2 : 0};
+    GraphKey key{a.inline_lanes, a.hard_lanes, a.defer_from, (int)a.cosine, g1, two ? g2 : 0};
     ssj::LaunchArgs args = a;
     void* kparams[] = {&args};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         GraphEntry ge;
         HIP_OR_FAIL(ctx, hipGraphCreate(&ge.graph, 0));
-        const void* funcs[3] = {ssj::kernel_verify_tiles(a.inline_lanes, a.hard_lanes, two),
-                                ssj::kernel_verify_deferred(), ssj::kernel_finalize()};
+        const void* funcs[3] = {ssj::kernel_verify_tiles(a.inline_lanes, a.hard_lanes, two, a.cosine != 0),
+                                ssj::kernel_verify_deferred(a.cosine != 0), ssj::kernel_finalize()};
         const int grids[3] = {g1, g2, 1};
         const int blocks[3] = {ssj::kBlock, ssj::kBlock, ssj::kWave};
         for (int k = 0; k < 3; ++k) {
@@ -358,6 +365,7 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
         R.d_count = q.d_count;
         R.cap = (unsigned long long)q.out_cap;
         overlap_rule(q.sim, q.t_num, q.t_den, R);
+        if (R.rule == ssj::kCosine) a.cosine = 1u;
         R.n = (uint32_t)q.n;
         tiles += ((uint64_t)q.n + tile_pairs - 1) / tile_pairs;
         pairs += (uint64_t)q.n;
@@ -370,8 +378,9 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     }
     a.queues = sc.d_queues;
     a.qcap = (uint32_t)(sc.q_cap / ssj::kClasses);
-    const int g1 = grid_tiles(ctx, plan.inline_lanes, plan.hard_lanes, two, (int64_t)tiles);
-    const int g2 = grid_deferred(ctx);
+    const int g1 = grid_tiles(ctx, plan.inline_lanes, plan.hard_lanes, plan.defer_from, a.cosine != 0,
+                              (int64_t)tiles);
+    const int g2 = grid_deferred(ctx, a.cosine != 0);
 
     std::array<hipEvent_t, 3> ev{nullptr, nullptr, nullptr};
     const int period = ctx->timing_period.load();
@@ -745,20 +754,28 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
         hipDeviceProp_t prop;
         if ((e = hipGetDeviceProperties(&prop, ctx->device)) != hipSuccess) { rc = hip_fail(ctx, "hipGetDeviceProperties", e); break; }
         ctx->n_cu = prop.multiProcessorCount;
-        for (int k = 0; k < 16 && rc == SSJ_OK; ++k) {
-            int occ = 0;
-            const void* f = ssj::kernel_verify_tiles(kInlineLanes[k / 2], kInlineHard[k / 2], (k & 1) != 0);
-            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, ssj::kBlock, 0)) != hipSuccess)
-                rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
-            ctx->occ_tiles[k] = occ;
+        for (int k = 0; k < 32 && rc == SSJ_OK; ++k) {
+            const bool deferring = (k & 1) != 0;
+            const void* f = ssj::kernel_verify_tiles(kInlineLanes[k / 4], kInlineHard[k / 4], deferring,
+                                                     (k & 2) != 0);
+            for (int nd = deferring ? 1 : 0; nd <= (deferring ? ssj::kClasses : 0) && rc == SSJ_OK; ++nd) {
+                ssj::LaunchArgs la{};
+                la.defer_from = ssj::kClasses - nd;
+                la.defer_cap = 2 * ssj::kWave;
+                int occ = 0;
+                if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, ssj::kBlock, ssj::tiles_lds_bytes(la))) != hipSuccess)
+                    rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
+                ctx->occ_tiles[k][nd] = occ;
+            }
         }
         if (rc != SSJ_OK) break;
-        int occ = 0;
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_deferred(), ssj::kBlock, 0)) != hipSuccess) {
-            rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
-            break;
+        for (int k = 0; k < 2 && rc == SSJ_OK; ++k) {
+            int occ = 0;
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_deferred(k != 0), ssj::kBlock, 0)) != hipSuccess)
+                rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
+            ctx->occ_deferred2[k] = occ;
         }
-        ctx->occ_deferred = occ;
+        if (rc != SSJ_OK) break;
         if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) { rc = hip_fail(ctx, "hipStreamCreate", e); break; }
         if ((rc = scratch_init(ctx, ctx->def)) != SSJ_OK) break;
         if ((e = hipMalloc((void**)&ctx->d_count, sizeof(long long))) != hipSuccess) { rc = hip_fail(ctx, "hipMalloc", e); break; }

@@ -11,6 +11,7 @@ constexpr int kBlock = 256;      // threads per workgroup of every verify kernel
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kMaxReq = 16;      // requests per launch
 constexpr int kHeadTokens = 6;   // leading tokens kept in each 32-byte set record
+constexpr unsigned kWaveStage = 8 * kWave;  // staged output pairs per wavefront (in-order kernel)
 
 // How a request turns set sizes into its required overlap alpha (the
 // equivalent overlap of paper Table 1).
@@ -56,6 +57,7 @@ struct LaunchArgs {
     int inline_lanes;                    // lanes per pair in the in-order kernel
     int hard_lanes;                      // lanes finishing long merges (inline_lanes == 1)
     uint32_t defer_cap;                  // LDS queue entries per deferred class and wavefront (>= 2 chunks)
+    uint32_t cosine;                     // != 0: some request uses the Cosine rule
     uint32_t tile_off[kMaxReq + 1];      // prefix sums of per-request chunks (of kWave pairs)
     uint32_t pair_off[kMaxReq + 1];      // prefix sums of per-request pairs
     uint32_t bounds[kClasses];           // inclusive upper bound of |r|+|s| per class
@@ -78,8 +80,8 @@ size_t tiles_lds_bytes(const LaunchArgs& a);
 // Publishes the request counts and resets the counters (always last).
 hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st);
 
-const void* kernel_verify_tiles(int lanes, int hard_lanes, bool deferring);
-const void* kernel_verify_deferred();
+const void* kernel_verify_tiles(int lanes, int hard_lanes, bool deferring, bool cosine);
+const void* kernel_verify_deferred(bool cosine);
 const void* kernel_finalize();
 
 bool lanes_supported(int lanes);              // deferred classes: 1..64 or kBlock
