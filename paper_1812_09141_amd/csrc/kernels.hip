@@ -376,12 +376,6 @@ __device__ __forceinline__ int2 lane_pair(const Request& R, uint32_t kb, int lan
     return load_pair(R.cand, k < R.n ? k : R.n - 1);
 }
 
-// Token t of a set given its record words (the first kHeadTokens come from
-// the record, later ones from the token array).
-__device__ __forceinline__ int32_t record_token(const LaunchArgs& a, uint4 w0, uint4 w1, uint32_t t) {
-    return t < kHeadTokens ? head_token(w0, w1, t) : a.tok[w0.x + t];
-}
-
 // Set records of a lane's pair: four 16-byte loads (first and second word of
 // both sides), issued back to back.  A pair with an invalid id reads record 0
 // and is ignored later.
@@ -433,10 +427,86 @@ __device__ __forceinline__ void head_tiles(uint4 a0, uint4 a1, uint4 b0, uint4 b
     *o = co;
 }
 
+// One lane's merge continued from state (i, j, o) over 16-byte windows of
+// the two token lists (every set starts on a 16-byte boundary of the token
+// array): window w of a side holds its tokens 4w .. 4w+3.  A step merges the
+// unconsumed tokens of the current windows of both sides (up to 4 x 4
+// comparisons) and consumes, as in the tile merge, every token that can have
+// no partner beyond the two windows: all of the window with the lower end,
+// and the tokens of the other window up to that end (both windows when the
+// ends are equal).  The window after the current one of each side is always
+// one step in flight: a step takes it over where the current window is used
+// up, and then requests the next one unconditionally (a side that did not
+// advance requests the window it already holds, a cache hit; a conditional
+// load ends up in a temporary register plus a copy that waits for it).  The
+// scheduling barrier keeps those loads after the selects that read the
+// registers they refill, for the same reason.  The pair must be undecided at (i, j, o), so
+// i < na and j < nb.
+__device__ __forceinline__ bool merge_windows(const int32_t* __restrict__ tok, uint32_t sa,
+                                              uint32_t na, uint32_t sb, uint32_t nb,
+                                              uint32_t alpha, uint32_t i, uint32_t j, uint32_t o) {
+    const uint4* __restrict__ t4 = reinterpret_cast<const uint4*>(tok);
+    const uint32_t qa = sa >> 2, qb = sb >> 2;              // first window of each set
+    const uint32_t la = (na - 1u) >> 2, lb = (nb - 1u) >> 2;  // last window index
+    uint32_t wa = i >> 2, wb = j >> 2;
+    // the windows as separate 32-bit values (selects on whole vectors become
+    // address selects into scratch memory)
+    int32_t a[4], b[4], an[4], bn[4];
+    auto unpack = [](uint4 v, int32_t (&d)[4]) {
+        d[0] = (int32_t)v.x;
+        d[1] = (int32_t)v.y;
+        d[2] = (int32_t)v.z;
+        d[3] = (int32_t)v.w;
+    };
+    unpack(t4[qa + wa], a);
+    unpack(t4[qb + wb], b);
+    unpack(t4[qa + min(wa + 1u, la)], an);
+    unpack(t4[qb + min(wb + 1u, lb)], bn);
+    for (;;) {
+        const uint32_t ba = wa << 2, bb = wb << 2;
+        const uint32_t ea = min(na - ba, 4u), eb = min(nb - bb, 4u);  // tokens in the windows
+        int32_t amax = a[0], bmax = b[0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            amax = ((uint32_t)k < ea) ? a[k] : amax;
+            bmax = ((uint32_t)k < eb) ? b[k] : bmax;
+        }
+        uint32_t hits = 0, na_le = 0, nb_le = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool va = ba + k >= i && (uint32_t)k < ea;
+            const bool vb = bb + k >= j && (uint32_t)k < eb;
+            bool hit = false;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) hit |= (bb + t >= j && (uint32_t)t < eb) && a[k] == b[t];
+            hits += (va && hit) ? 1u : 0u;
+            na_le += (va && a[k] <= bmax) ? 1u : 0u;
+            nb_le += (vb && b[k] <= amax) ? 1u : 0u;
+        }
+        i = bmax < amax ? i + na_le : ba + ea;
+        j = amax < bmax ? j + nb_le : bb + eb;
+        o += hits;
+        if (o >= alpha) return true;
+        if (o + min(na - i, nb - j) < alpha) return false;
+        const bool adv_a = i >= ba + 4u, adv_b = j >= bb + 4u;
+        wa += adv_a ? 1u : 0u;
+        wb += adv_b ? 1u : 0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a[k] = adv_a ? an[k] : a[k];
+            b[k] = adv_b ? bn[k] : b[k];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        unpack(t4[qa + min(wa + 1u, la)], an);
+        unpack(t4[qb + min(wb + 1u, lb)], bn);
+    }
+}
+
 // Thread-per-pair verification of the lane's pair (chunk index kb + lane)
 // from its records: first the head tiles (head_tiles), which decide most
 // pairs; a pair still undecided continues from that merge state.  F == 0: it
-// continues on the token array in the same lane.  F > 0: it is appended, with
+// continues in the same lane over 16-byte windows of the token array
+// (merge_windows).  F > 0: it is appended, with
 // its merge state, to the wavefront's list of hard pairs (hcnt entries), which
 // groups of F lanes finish (finish_hard), so that no lane walks the token
 // array alone while the rest of its wavefront waits.
@@ -461,19 +531,7 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
     bool pass = run && o >= alpha;
     bool act = run && !pass && o + min(na - i, nb - j) >= alpha;
     if constexpr (F == 0) {
-        while (act) {
-            const int32_t x = record_token(a, rec.ra0, rec.ra1, i);
-            const int32_t y = record_token(a, rec.rb0, rec.rb1, j);
-            i += (x <= y);
-            j += (y <= x);
-            o += (x == y);
-            if (o >= alpha) {
-                pass = true;
-                act = false;
-            } else if (o + min(na - i, nb - j) < alpha) {
-                act = false;
-            }
-        }
+        if (act) pass = merge_windows(a.tok, rec.ra0.x, na, rec.rb0.x, nb, alpha, i, j, o);
     }
     // (after the merges: atomics count with loads, so none sits between the
     // record loads in flight and their use)
@@ -832,15 +890,18 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
     }
 }
 
-__global__ void k_build_heads(const int64_t* __restrict__ off, const int32_t* __restrict__ tok,
-                              uint4* __restrict__ heads, int64_t n) {
+// Set records from the set lengths (CSR offsets of the caller's layout) and
+// the start of each set in the device token array (16-byte aligned).
+__global__ void k_build_heads(const int64_t* __restrict__ off, const uint32_t* __restrict__ start,
+                              const int32_t* __restrict__ tok, uint4* __restrict__ heads, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = off[i], e = off[i + 1];
+        const uint32_t b = start[i];
+        const uint32_t len = (uint32_t)(off[i + 1] - off[i]);
         int32_t h[kHeadTokens];
 #pragma unroll
-        for (int k = 0; k < kHeadTokens; ++k) h[k] = (b + k < e) ? tok[b + k] : -1;
-        heads[2 * i] = make_uint4((uint32_t)b, (uint32_t)(e - b), (uint32_t)h[0], (uint32_t)h[1]);
+        for (int k = 0; k < kHeadTokens; ++k) h[k] = ((uint32_t)k < len) ? tok[b + k] : -1;
+        heads[2 * i] = make_uint4(b, len, (uint32_t)h[0], (uint32_t)h[1]);
         heads[2 * i + 1] = make_uint4((uint32_t)h[2], (uint32_t)h[3], (uint32_t)h[4], (uint32_t)h[5]);
     }
 }
@@ -891,13 +952,13 @@ const void* kernel_verify_deferred(bool cosine) {
     return cosine ? (const void*)&k_verify_deferred<true> : (const void*)&k_verify_deferred<false>;
 }
 
-hipError_t launch_build_heads(const int64_t* d_offsets, const int32_t* d_tok, uint4* d_heads,
-                              int64_t n_sets, hipStream_t st) {
+hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start, const int32_t* d_tok,
+                              uint4* d_heads, int64_t n_sets, hipStream_t st) {
     if (n_sets <= 0) return hipSuccess;
     int64_t blocks = (n_sets + kBlock - 1) / kBlock;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_build_heads, dim3((unsigned)blocks), dim3(kBlock), 0, st, d_offsets, d_tok,
-                       d_heads, n_sets);
+    hipLaunchKernelGGL(k_build_heads, dim3((unsigned)blocks), dim3(kBlock), 0, st, d_offsets, d_start,
+                       d_tok, d_heads, n_sets);
     return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <ctime>
 #include <deque>
+#include <new>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -853,6 +854,27 @@ int ssj_upload_collection(ssj_ctx* ctx, const int64_t* offsets, int64_t n_sets,
         }
         max_len = std::max(max_len, e - b);
     }
+    // Device layout: every set starts on a 16-byte boundary (a multiple of 4
+    // tokens), so a lane can read 4 consecutive tokens of a set with one
+    // aligned 16-byte load; the slots after a set's end hold -1.
+    std::vector<uint32_t> start;
+    std::vector<int32_t> padded;
+    uint64_t n_dev = 0;
+    try {
+        start.resize((size_t)std::max<int64_t>(n_sets, 1));
+        for (int64_t i = 0; i < n_sets; ++i) {
+            start[(size_t)i] = (uint32_t)n_dev;
+            n_dev += ((uint64_t)(offsets[i + 1] - offsets[i]) + 3u) & ~(uint64_t)3u;
+            if (n_dev >= ((uint64_t)1 << 32))
+                return set_error(SSJ_EINVAL, "collection too large: tokens padded to 16-byte set starts must stay below 2^32");
+        }
+        padded.assign((size_t)std::max<uint64_t>(n_dev, 4), -1);
+        for (int64_t i = 0; i < n_sets; ++i)
+            std::memcpy(padded.data() + start[(size_t)i], tokens + offsets[i],
+                        (size_t)(offsets[i + 1] - offsets[i]) * 4);
+    } catch (const std::bad_alloc&) {
+        return set_error(SSJ_ENOMEM, "host allocation failed");
+    }
     std::lock_guard<std::mutex> g(ctx->mu);
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
     ssj_coll* c = new (std::nothrow) ssj_coll();
@@ -862,17 +884,21 @@ int ssj_upload_collection(ssj_ctx* ctx, const int64_t* offsets, int64_t n_sets,
     c->n_tokens = n_tokens;
     c->max_len = max_len;
     int64_t* d_off = nullptr;
+    uint32_t* d_start = nullptr;
     hipError_t e = hipSuccess;
     do {
-        if ((e = hipMalloc((void**)&c->d_tok, (size_t)std::max<int64_t>(n_tokens, 1) * 4)) != hipSuccess) break;
+        if ((e = hipMalloc((void**)&c->d_tok, padded.size() * 4)) != hipSuccess) break;
         if ((e = hipMalloc((void**)&c->d_heads, (size_t)std::max<int64_t>(n_sets, 1) * 32)) != hipSuccess) break;
         if ((e = hipMalloc((void**)&d_off, (size_t)(n_sets + 1) * 8)) != hipSuccess) break;
-        if (n_tokens > 0 && (e = hipMemcpyAsync(c->d_tok, tokens, (size_t)n_tokens * 4, hipMemcpyHostToDevice, ctx->stream)) != hipSuccess) break;
+        if ((e = hipMalloc((void**)&d_start, start.size() * 4)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(c->d_tok, padded.data(), padded.size() * 4, hipMemcpyHostToDevice, ctx->stream)) != hipSuccess) break;
         if ((e = hipMemcpyAsync(d_off, offsets, (size_t)(n_sets + 1) * 8, hipMemcpyHostToDevice, ctx->stream)) != hipSuccess) break;
-        if ((e = ssj::launch_build_heads(d_off, c->d_tok, c->d_heads, n_sets, ctx->stream)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(d_start, start.data(), start.size() * 4, hipMemcpyHostToDevice, ctx->stream)) != hipSuccess) break;
+        if ((e = ssj::launch_build_heads(d_off, d_start, c->d_tok, c->d_heads, n_sets, ctx->stream)) != hipSuccess) break;
         if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) break;
     } while (0);
     if (d_off) (void)hipFree(d_off);
+    if (d_start) (void)hipFree(d_start);
     if (e != hipSuccess) {
         if (c->d_tok) (void)hipFree(c->d_tok);
         if (c->d_heads) (void)hipFree(c->d_heads);

@@ -67,9 +67,11 @@ struct LaunchArgs {
 
 // Launch helpers (defined in kernels.hip).  Return hipSuccess or the launch
 // error.
-// Set records (2 x uint4 per set) from the CSR offsets and tokens on the device.
-hipError_t launch_build_heads(const int64_t* d_offsets, const int32_t* d_tok, uint4* d_heads,
-                              int64_t n_sets, hipStream_t st);
+// Set records (2 x uint4 per set) on the device from the CSR offsets (for
+// the lengths), the start of each set in the device token array and that
+// array.
+hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start, const int32_t* d_tok,
+                              uint4* d_heads, int64_t n_sets, hipStream_t st);
 // The in-order kernel: every pair of a class below defer_from is verified
 // with inline_lanes lanes; the others are queued for launch_verify_deferred.
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st);
