@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="offline", choices=sorted(WORKLOAD_CFG))
     ap.add_argument("--plan", default="auto",
-                    help="auto (autotuned) | inline:L | defer:L,F,l0,l1,l2,l3,l4")
+                    help="auto (autotuned) | inline:L[hF] | defer:L[hF],D,l0,l1,l2,l3,l4")
     ap.add_argument("--compare-plain", type=int, default=1,
                     help="also time plain one-launch-per-batch verification")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -235,13 +235,14 @@ def main():
     avg_def_ms = def_ms / launches
     deferred = plan.defer_from < 5
     # in-order kernel alone, or with the deferred-class kernel when one runs
-    # (avg_def_ms also holds the one-workgroup finalize kernel)
+    # (kernel durations from events recorded right before and after each
+    # verification kernel; the one-wavefront finalize kernel is not included)
     avg_kernel_ms = avg_in_ms + (avg_def_ms if deferred else 0.0)
     achieved = per_launch_bytes / (avg_kernel_ms * 1e-3) / 1e9 if avg_kernel_ms > 0 else 0.0
     src_hash = kernel_source_hash()
     kernel_name = (f"k_verify_tiles<{plan.inline_lanes},{plan.hard_lanes},"
-                   f"{'true' if deferred else 'false'}>" +
-                   (" + k_verify_deferred" if deferred else ""))
+                   f"{'true' if deferred else 'false'},false>" +
+                   (" + k_verify_deferred<false>" if deferred else ""))
     traffic = traffic_from_profiles(src_hash, args.workload, kernel_name)
 
     extra = {"plan": plan.as_dict()}

@@ -264,15 +264,15 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
 /*
  * Kernel timing, for measurement.  With period > 0, every period-th launch
  * that the library enqueues from ssj_verify, ssj_verify_device and
- * ssj_verify_batch_device has its kernels bracketed by HIP events recorded
- * on the launch stream (period = 1: every launch; event records slow a
- * launch down slightly, so sampling keeps a timed run close to an untimed
- * one).  period = 0 turns timing off.  ssj_timing_read waits for the
- * recorded events and returns the summed elapsed milliseconds of the
- * in-order kernels and of the rest of those launches (deferred-class and
- * finalize kernels), and the number of timed launches; reset != 0 clears
- * the sums.  Do not enable it while the calls are being captured into a
- * graph.
+ * ssj_verify_batch_device has its verification kernels bracketed by HIP
+ * events recorded on the launch stream (period = 1: every launch; event
+ * records slow a launch down slightly, so sampling keeps a timed run close
+ * to an untimed one).  period = 0 turns timing off.
+ * ssj_timing_read waits for the recorded events and returns the summed
+ * elapsed milliseconds of the in-order kernels and of the deferred-class
+ * kernels (0 for launches that defer nothing), and the number of timed
+ * launches; reset != 0 clears the sums.  Do not enable it while the calls
+ * are being captured into a graph.
  */
 int ssj_timing_enable(ssj_ctx* ctx, int period);
 int ssj_timing_read(ssj_ctx* ctx, int reset, double* inorder_ms, double* deferred_ms,

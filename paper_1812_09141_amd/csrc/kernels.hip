@@ -987,11 +987,10 @@ hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st) {
 const void* kernel_finalize() { return (const void*)&k_finalize; }
 
 hipError_t launch_verify_deferred(const LaunchArgs& a, int grid, hipStream_t st) {
-    if (a.cosine)
-        hipLaunchKernelGGL(k_verify_deferred<true>, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_verify_deferred<false>, dim3((unsigned)grid), dim3(kBlock), 0, st, a);
-    return hipGetLastError();
+    const void* f = kernel_verify_deferred(a.cosine != 0);
+    LaunchArgs args = a;
+    void* params[] = {&args};
+    return hipLaunchKernel(f, dim3((unsigned)grid), dim3(kBlock), params, 0, st);
 }
 
 }  // namespace ssj

@@ -180,7 +180,9 @@ struct ssj_ctx {
     std::atomic<uint64_t> timing_tick{0};
     std::mutex tmu;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::array<hipEvent_t, 3>> ev_pending;
+    // sampled launches: start / end of the in-order kernel, start / end of
+    // the deferred kernel (null when none ran)
+    std::vector<std::array<hipEvent_t, 4>> ev_pending;
     double t_inorder_ms = 0.0, t_deferred_ms = 0.0;
     int64_t t_launches = 0;
     std::unique_ptr<StreamEngine> engine;
@@ -383,27 +385,32 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
                               (int64_t)tiles);
     const int g2 = grid_deferred(ctx, a.cosine != 0);
 
-    std::array<hipEvent_t, 3> ev{nullptr, nullptr, nullptr};
+    std::array<hipEvent_t, 4> ev{nullptr, nullptr, nullptr, nullptr};
     const int period = ctx->timing_period.load();
     const bool timing = period > 0 && (ctx->timing_tick.fetch_add(1) % (uint64_t)period) == 0;
     if (timing) {
-        for (auto& e : ev) {
-            e = timing_event(ctx);
-            if (!e) return hip_fail(ctx, "hipEventCreate", hipErrorOutOfMemory);
+        // marker events right before and after each verification kernel (the
+        // finalize kernel is not timed)
+        for (int k = 0; k < (two ? 4 : 2); ++k) {
+            ev[k] = timing_event(ctx);
+            if (!ev[k]) return hip_fail(ctx, "hipEventCreate", hipErrorOutOfMemory);
         }
-        HIP_OR_FAIL(ctx, hipEventRecord(ev[0], st));
     }
     if (plan.use_graph && allow_graph && !timing) {
         int rc = launch_graph(ctx, a, g1, g2, two, st);
         if (rc != SSJ_OK) return rc;
     } else {
+        if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ev[0], st));
         HIP_OR_FAIL(ctx, ssj::launch_verify_tiles(a, g1, st));
         if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ev[1], st));
-        if (two) HIP_OR_FAIL(ctx, ssj::launch_verify_deferred(a, g2, st));
+        if (two) {
+            if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ev[2], st));
+            HIP_OR_FAIL(ctx, ssj::launch_verify_deferred(a, g2, st));
+            if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ev[3], st));
+        }
         HIP_OR_FAIL(ctx, ssj::launch_finalize(a, st));
     }
     if (timing) {
-        HIP_OR_FAIL(ctx, hipEventRecord(ev[2], st));
         std::lock_guard<std::mutex> g(ctx->tmu);
         ctx->ev_pending.push_back(ev);
     }
@@ -820,7 +827,8 @@ int ssj_shutdown(ssj_ctx* ctx) {
         if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     }
     for (auto& ev : ctx->ev_pending)
-        for (auto e : ev) (void)hipEventDestroy(e);
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
     return SSJ_OK;
@@ -968,14 +976,18 @@ int ssj_timing_read(ssj_ctx* ctx, int reset, double* inorder_ms, double* deferre
     if (rc != SSJ_OK) return rc;
     std::lock_guard<std::mutex> g(ctx->tmu);
     for (auto& ev : ctx->ev_pending) {
-        HIP_OR_FAIL(ctx, hipEventSynchronize(ev[2]));
         float a = 0.f, b = 0.f;
+        HIP_OR_FAIL(ctx, hipEventSynchronize(ev[1]));
         HIP_OR_FAIL(ctx, hipEventElapsedTime(&a, ev[0], ev[1]));
-        HIP_OR_FAIL(ctx, hipEventElapsedTime(&b, ev[1], ev[2]));
+        if (ev[2]) {
+            HIP_OR_FAIL(ctx, hipEventSynchronize(ev[3]));
+            HIP_OR_FAIL(ctx, hipEventElapsedTime(&b, ev[2], ev[3]));
+        }
         ctx->t_inorder_ms += a;
         ctx->t_deferred_ms += b;
         ctx->t_launches += 1;
-        for (auto e : ev) ctx->ev_pool.push_back(e);
+        for (auto e : ev)
+            if (e) ctx->ev_pool.push_back(e);
     }
     ctx->ev_pending.clear();
     if (inorder_ms) *inorder_ms = ctx->t_inorder_ms;
