@@ -14,6 +14,7 @@ Prints one JSON line.  --gpus N > 1 is not supported (one GPU only).
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -37,7 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="offline", choices=sorted(WORKLOAD_CFG))
     ap.add_argument("--plan", default="auto",
-                    help="auto (autotuned) | inline:L[hF] | defer:L[hF],D,l0,l1,l2,l3,l4")
+                    help="auto (autotuned) | inline:M | defer:M,D,l0,l1,l2,l3,l4 with M = L[hF][sI[xG]]")
     ap.add_argument("--compare-plain", type=int, default=1,
                     help="also time plain one-launch-per-batch verification")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -54,18 +55,22 @@ def parse():
 
 
 def plan_of(S, spec):
-    """auto | inline:L[hF] | defer:L[hF],D,l0,l1,l2,l3,l4 (F hard lanes, D first deferred class)"""
+    """auto | inline:M | defer:M,D,l0,l1,l2,l3,l4 with M = L[hF][sI[xG]] (L lanes per pair,
+    F hard lanes, I window steps before a merge spills to G lanes, D first deferred class)"""
     if spec == "auto":
         return None
     kind, _, rest = spec.partition(":")
     parts = rest.split(",") if rest else []
-    lanes, _, hard = parts[0].partition("h")
-    L, F = int(lanes), int(hard or 0)
+    m = re.fullmatch(r"(\d+)(?:h(\d+))?(?:s(\d+)(?:x(\d+))?)?", parts[0] if parts else "")
+    if not m:
+        raise SystemExit(f"bad mapping in plan {spec!r}")
+    L, F, I, G = (int(v) if v else d for v, d in zip(m.groups(), (1, 0, 0, 16)))
     vals = [int(v) for v in parts[1:]]
+    kw = dict(inline_lanes=L, hard_lanes=F, spill_iters=I, spill_lanes=G)
     if kind == "inline":
-        return S.make_plan(inline_lanes=L, hard_lanes=F, defer_from=5)
+        return S.make_plan(defer_from=5, **kw)
     if kind == "defer":
-        return S.make_plan(inline_lanes=L, hard_lanes=F, defer_from=vals[0], lanes=vals[1:6])
+        return S.make_plan(defer_from=vals[0], lanes=vals[1:6], **kw)
     raise SystemExit(f"unknown plan {spec!r}")
 
 
@@ -233,8 +238,8 @@ def main():
     per_launch_bytes = b_alg  # one launch per step
     avg_in_ms = in_ms / launches
     avg_def_ms = def_ms / launches
-    deferred = plan.defer_from < 5
-    # in-order kernel alone, or with the deferred-class kernel when one runs
+    deferred = plan.defer_from < 5 or plan.spill_iters > 0
+    # in-order kernel alone, or with the deferred kernel when one runs
     # (kernel durations from events recorded right before and after each
     # verification kernel; the one-wavefront finalize kernel is not included)
     avg_kernel_ms = avg_in_ms + (avg_def_ms if deferred else 0.0)

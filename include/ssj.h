@@ -205,6 +205,11 @@ int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, int wait, uint64_t* t_submit
  *     lanes[class] lanes per pair (256 = one workgroup per pair, handed out
  *     by work stealing).  defer_from = SSJ_N_CLASSES defers nothing and runs
  *     the in-order kernel alone.
+ *  3. with one thread per pair and no hard lanes, spill_iters > 0 bounds the
+ *     merge of each pair in (1) to that many steps over 4-token windows: a
+ *     pair still undecided then is queued and verified again from its start
+ *     by the kernel of (2), with spill_lanes lanes per pair.  This keeps a
+ *     few long merges from holding up their wavefronts.  0: no bound.
  * use_graph != 0 replays the launch through a captured hipGraph whose kernel
  * parameters are updated per call.
  */
@@ -218,6 +223,8 @@ typedef struct {
     int defer_from;              /* 0 .. SSJ_N_CLASSES */
     int lanes[SSJ_N_CLASSES];    /* per deferred class: 1, 4, 8, 16, 32, 64 or 256 */
     int use_graph;
+    int spill_iters;             /* 0 .. 2^20; > 0 only with inline_lanes 1, hard_lanes 0 */
+    int spill_lanes;             /* lanes per spilled pair: 1, 4, 8, 16, 32, 64 or 256 */
 } ssj_plan;
 
 /* Reads / replaces the context's plan.  SSJ_EINVAL for an unsupported
@@ -255,8 +262,9 @@ int ssj_verify_batch_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_reques
  * returns the fastest in *best (its kernel time per launch in *best_ms).
  * apply != 0 also makes it the context's plan.  The search times every
  * in-order mapping with every deferral point (deferred classes starting from
- * mappings suited to their lengths), then refines the mapping of each
- * deferred class of the best plan, one class at a time.  Synchronous.
+ * mappings suited to their lengths), then step budgets (spill_iters) on the
+ * best thread-per-pair plan, then refines the mapping of each deferred class
+ * of the best plan, one class at a time.  Synchronous.
  */
 int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
                  int64_t t_num, int64_t t_den, int apply, ssj_plan* best, double* best_ms);

@@ -80,6 +80,15 @@ __device__ __forceinline__ int bperm(int v, int src) {
     return __builtin_amdgcn_ds_bpermute(src << 2, v);
 }
 
+// Orders one wavefront's LDS accesses: writes by some lanes before reads by
+// others (the LDS serves a wavefront's operations in issue order; the fences
+// keep the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Number of set bits of m below the calling lane.
 __device__ __forceinline__ uint32_t mbcnt(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -285,14 +294,6 @@ __device__ __forceinline__ int request_of_pair(uint32_t gi, const LaunchArgs& a)
 // wave-uniform values held in registers, so the kernel needs no workgroup
 // barrier: a wavefront slowed by a long merge holds up no other.
 
-// Orders one wavefront's LDS accesses: writes by some lanes before reads by
-// others (the LDS serves a wavefront's operations in issue order; the fences
-// keep the compiler from moving them).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Lane 0's value of v (all lanes active).
 __device__ __forceinline__ unsigned long long lane0_u64(unsigned long long v) {
@@ -335,16 +336,26 @@ __device__ __forceinline__ uint32_t dcount(unsigned long long dc, int q) {
     return (uint32_t)(dc >> (8 * q)) & 0xffu;
 }
 
-// Queues deferred pairs (global pair index gi) in the wavefront's LDS queue
-// of their class.
-__device__ __forceinline__ void defer_pass(const LaunchArgs& a, bool defer, int cls, uint32_t gi,
-                                           uint32_t* w_defer, unsigned long long& dc) {
-    for (int q = a.defer_from; q < kClasses; ++q) {
-        const bool mine = defer && cls == q;
-        const unsigned long long m = ballot(mine);
-        if (mine) w_defer[(uint32_t)(q - a.defer_from) * a.defer_cap + dcount(dc, q) + mbcnt(m)] = gi;
-        dc += (unsigned long long)__popcll(m) << (8 * q);
-    }
+// Appends the pairs (global pair index gi) of the lanes with mine set to
+// the wavefront's LDS queue q.
+__device__ __forceinline__ void queue_lanes(const LaunchArgs& a, bool mine, int q, uint32_t gi,
+                                            uint32_t* w_defer, unsigned long long& dc) {
+    const unsigned long long m = ballot(mine);
+    if (mine) w_defer[(uint32_t)(q - a.defer_from) * a.defer_cap + dcount(dc, q) + mbcnt(m)] = gi;
+    dc += (unsigned long long)__popcll(m) << (8 * q);
+}
+
+// Queues deferred pairs in the wavefront's LDS queue of their class, and
+// spilled merges in its spill queue (after the class queues).
+__device__ __forceinline__ void defer_pass(const LaunchArgs& a, bool defer, int cls, bool spill,
+                                           uint32_t gi, uint32_t* w_defer, unsigned long long& dc) {
+    for (int q = a.defer_from; q < kClasses; ++q) queue_lanes(a, defer && cls == q, q, gi, w_defer, dc);
+    if (spilling(a)) queue_lanes(a, spill, kSpillQ, gi, w_defer, dc);
+}
+
+// One past the last LDS queue of the in-order kernel's wavefronts.
+__device__ __forceinline__ int queue_end(const LaunchArgs& a) {
+    return spilling(a) ? kQueues : kClasses;
 }
 
 // Moves the wavefront's c queued pairs of class q to the global queue.
@@ -441,10 +452,13 @@ __device__ __forceinline__ void head_tiles(uint4 a0, uint4 a1, uint4 b0, uint4 b
 // load ends up in a temporary register plus a copy that waits for it).  The
 // scheduling barrier keeps those loads after the selects that read the
 // registers they refill, for the same reason.  The pair must be undecided at (i, j, o), so
-// i < na and j < nb.
+// i < na and j < nb.  After budget steps a merge still undecided stops with
+// *spilled set (all lanes enter together, so the step count is the same in
+// every lane and the cut is a wave-uniform branch).
 __device__ __forceinline__ bool merge_windows(const int32_t* __restrict__ tok, uint32_t sa,
                                               uint32_t na, uint32_t sb, uint32_t nb,
-                                              uint32_t alpha, uint32_t i, uint32_t j, uint32_t o) {
+                                              uint32_t alpha, uint32_t i, uint32_t j, uint32_t o,
+                                              uint32_t budget, bool* spilled) {
     const uint4* __restrict__ t4 = reinterpret_cast<const uint4*>(tok);
     const uint32_t qa = sa >> 2, qb = sb >> 2;              // first window of each set
     const uint32_t la = (na - 1u) >> 2, lb = (nb - 1u) >> 2;  // last window index
@@ -462,7 +476,7 @@ __device__ __forceinline__ bool merge_windows(const int32_t* __restrict__ tok, u
     unpack(t4[qb + wb], b);
     unpack(t4[qa + min(wa + 1u, la)], an);
     unpack(t4[qb + min(wb + 1u, lb)], bn);
-    for (;;) {
+    for (uint32_t step = 1;; ++step) {
         const uint32_t ba = wa << 2, bb = wb << 2;
         const uint32_t ea = min(na - ba, 4u), eb = min(nb - bb, 4u);  // tokens in the windows
         int32_t amax = a[0], bmax = b[0];
@@ -488,6 +502,10 @@ __device__ __forceinline__ bool merge_windows(const int32_t* __restrict__ tok, u
         o += hits;
         if (o >= alpha) return true;
         if (o + min(na - i, nb - j) < alpha) return false;
+        if (step >= budget) {
+            *spilled = true;
+            return false;
+        }
         const bool adv_a = i >= ba + 4u, adv_b = j >= bb + 4u;
         wa += adv_a ? 1u : 0u;
         wb += adv_b ? 1u : 0u;
@@ -530,8 +548,11 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
     head_tiles(rec.ra0, rec.ra1, rec.rb0, rec.rb1, &i, &j, &o);
     bool pass = run && o >= alpha;
     bool act = run && !pass && o + min(na - i, nb - j) >= alpha;
+    bool spill = false;
     if constexpr (F == 0) {
-        if (act) pass = merge_windows(a.tok, rec.ra0.x, na, rec.rb0.x, nb, alpha, i, j, o);
+        if (act)
+            pass = merge_windows(a.tok, rec.ra0.x, na, rec.rb0.x, nb, alpha, i, j, o,
+                                 deferring ? a.spill_iters : 0xffffffffu, &spill);
     }
     // (after the merges: atomics count with loads, so none sits between the
     // record loads in flight and their use)
@@ -546,7 +567,7 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
         hcnt += (uint32_t)__popcll(m);
     }
     stage_pass(pass, pr, w_out, ocnt, R.cap == 0);
-    if (deferring) defer_pass(a, defer, cls, a.pair_off[r] + k, w_defer, dc);
+    if (deferring) defer_pass(a, defer, cls, spill, a.pair_off[r] + k, w_defer, dc);
 }
 
 // Finishes the wavefront's h hard pairs: groups of G lanes resume their
@@ -601,11 +622,13 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     const int lane = lane_id();
     const int grp = lane / G, g = lane % G, gbase = grp * G;
     // dynamic LDS, per wavefront: kWStage staged output pairs, then defer_cap
-    // entries per deferred class q >= defer_from (defer_cap >= 2 * kWave)
+    // entries per queue: the deferred classes q >= defer_from, then the spill
+    // queue when merges are cut off (defer_cap >= 2 * kWave)
     extern __shared__ uint4 s_dyn[];
-    const bool deferring = D && a.defer_from < kClasses;
+    const bool deferring = D && (a.defer_from < kClasses || spilling(a));
     const uint32_t wave_words =
-        (kWStage * 8u + (deferring ? (uint32_t)(kClasses - a.defer_from) * a.defer_cap * 4u : 0u)) / 16u;
+        (kWStage * 8u +
+         (deferring ? (uint32_t)wave_queues(a.defer_from, spilling(a)) * a.defer_cap * 4u : 0u)) / 16u;
     int2* w_out = reinterpret_cast<int2*>(s_dyn + wl * wave_words);
     uint32_t* w_defer = reinterpret_cast<uint32_t*>(w_out + kWStage);
     // hard pairs of the current chunk (thread-per-pair mapping with F > 0)
@@ -711,7 +734,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                     }
                 }
                 stage_pass(pass && g == 0, pq, w_out, ocnt, R.cap == 0);
-                if (deferring) defer_pass(a, defer && g == 0, cls, a.pair_off[r] + k, w_defer, dc);
+                if (deferring) defer_pass(a, defer && g == 0, cls, false, a.pair_off[r] + k, w_defer, dc);
                 pq0 = pq1;
                 pq1 = pq2;
                 pq2 = pq3;
@@ -732,8 +755,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
             ocnt = 0;
         }
         if (deferring) {
-            // the same bound holds for each deferred class
-            for (int q = a.defer_from; q < kClasses; ++q) {
+            // the same bound holds for each queue
+            for (int q = a.defer_from; q < queue_end(a); ++q) {
                 const uint32_t c = dcount(dc, q);
                 if (c > a.defer_cap - kWave) {
                     wave_flush_deferred(a, q, c, w_defer);
@@ -743,7 +766,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
         }
     }
     if (deferring) {
-        for (int q = a.defer_from; q < kClasses; ++q) {
+        for (int q = a.defer_from; q < queue_end(a); ++q) {
             if (dcount(dc, q) > 0) wave_flush_deferred(a, q, dcount(dc, q), w_defer);
         }
     }
@@ -761,7 +784,7 @@ __global__ void k_finalize(LaunchArgs a) {
         a.ctr->out_count[t] = 0ull;
         a.ctr->err[t] = 0u;
     }
-    if (t < kClasses) {
+    if (t < kQueues) {
         a.ctr->head[t] = 0u;
         a.ctr->tail[t] = 0u;
     }
@@ -846,13 +869,21 @@ __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
     }
 }
 
+// Lanes per pair of queue q.
+__device__ __forceinline__ int lanes_of_queue(const LaunchArgs& a, int q) {
+    return q == kSpillQ ? a.spill_lanes : a.lanes[q];
+}
+
+// Queues are drained from the spill queue (the longest merges) down to the
+// first deferred class.
 template <bool C>
 __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
     __shared__ int32_t sb[kBlock];
     __shared__ uint32_t red[16];
     __shared__ uint32_t s_tile;
-    for (int q = kClasses - 1; q >= a.defer_from; --q) {
-        if (a.lanes[q] != kBlock) continue;
+    for (int q = kQueues - 1; q >= 0; --q) {
+        if (q < a.defer_from && q != kSpillQ) break;
+        if (lanes_of_queue(a, q) != kBlock) continue;
         const uint32_t cnt = load_relaxed(&a.ctr->tail[q]);
         const uint32_t* queue = a.queues + (size_t)q * a.qcap;
         for (;;) {
@@ -875,10 +906,11 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
             if (threadIdx.x == 0 && pass) append_one(pr, R, &a.ctr->out_count[r]);
         }
     }
-    for (int q = kClasses - 1; q >= a.defer_from; --q) {
+    for (int q = kQueues - 1; q >= 0; --q) {
+        if (q < a.defer_from && q != kSpillQ) break;
         const uint32_t cnt = load_relaxed(&a.ctr->tail[q]);
         if (cnt == 0) continue;
-        switch (a.lanes[q]) {
+        switch (lanes_of_queue(a, q)) {
             case 1: drain_static<1, C>(a, q, cnt); break;
             case 4: drain_static<4, C>(a, q, cnt); break;
             case 8: drain_static<8, C>(a, q, cnt); break;
@@ -964,15 +996,15 @@ hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start,
 
 size_t tiles_lds_bytes(const LaunchArgs& a) {
     // per wavefront: kWaveStage staged output pairs, then defer_cap entries
-    // per deferred class (a multiple of 16 bytes)
+    // per queue (a multiple of 16 bytes)
     const size_t stage = (size_t)kWaveStage * sizeof(int2);
-    const size_t defer = a.defer_from < kClasses ? (size_t)(kClasses - a.defer_from) * a.defer_cap * 4u : 0u;
+    const size_t defer = (size_t)wave_queues(a.defer_from, spilling(a)) * a.defer_cap * 4u;
     return (size_t)(kBlock / kWave) * (stage + defer);
 }
 
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st) {
-    const void* f = kernel_verify_tiles(a.inline_lanes, a.hard_lanes, a.defer_from < kClasses,
-                                        a.cosine != 0);
+    const void* f = kernel_verify_tiles(a.inline_lanes, a.hard_lanes,
+                                        a.defer_from < kClasses || spilling(a), a.cosine != 0);
     if (!f) return hipErrorInvalidValue;
     LaunchArgs args = a;
     void* params[] = {&args};

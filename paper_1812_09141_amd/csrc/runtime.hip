@@ -42,9 +42,10 @@ uint64_t now_ns() {
 
 constexpr uint64_t kDefaultBudget = 4ull << 30;
 constexpr int64_t kMaxLaunchPairs = ((int64_t)1 << 31) - 1;  // pairs per launch
+constexpr int kMaxSpillIters = 1 << 20;
 // device bytes per candidate pair of a request: the pair, a worst-case output
-// pair, and its deferred-class queue entries
-constexpr size_t kBytesPerPair = 8 + 8 + 4 * ssj::kClasses;
+// pair, and its queue entries
+constexpr size_t kBytesPerPair = 8 + 8 + 4 * ssj::kQueues;
 
 // Threshold range of a similarity function (SSJ_SIM_*): 0 < t_den < 2^31,
 // 0 <= t_num < 2^31, and t <= 1 for the normalised functions.
@@ -115,14 +116,15 @@ hipError_t grow(T*& p, size_t& cap, size_t need) {
 struct Scratch {
     ssj::Counters* d_ctr = nullptr;
     uint32_t* d_queues = nullptr;
-    size_t q_cap = 0;  // entries (kClasses x per-class capacity)
+    size_t q_cap = 0;  // entries (kQueues x per-queue capacity)
 };
 
 struct GraphKey {
-    int inline_lanes, hard_lanes, defer_from, cosine, grid1, grid2;
+    int inline_lanes, hard_lanes, defer_from, spill, cosine, grid1, grid2;
     bool operator<(const GraphKey& o) const {
-        return std::tie(inline_lanes, hard_lanes, defer_from, cosine, grid1, grid2) <
-               std::tie(o.inline_lanes, o.hard_lanes, o.defer_from, o.cosine, o.grid1, o.grid2);
+        return std::tie(inline_lanes, hard_lanes, defer_from, spill, cosine, grid1, grid2) <
+               std::tie(o.inline_lanes, o.hard_lanes, o.defer_from, o.spill, o.cosine, o.grid1,
+                        o.grid2);
     }
 };
 
@@ -158,7 +160,7 @@ struct ssj_ctx {
     int n_cu = 0;
     // in-order kernel workgroups per CU, limited by registers and by its
     // dynamic LDS: [4 * mapping index + 2 * cosine + deferring][deferred classes]
-    int occ_tiles[32][ssj::kClasses + 1] = {};
+    int occ_tiles[32][ssj::kQueues + 1] = {};  // [mapping][LDS queues per wavefront]
     int occ_deferred2[2] = {0};  // [cosine]
     ssj_plan plan{};
     std::mutex mu;  // default scratch, host staging, collections, plan, graphs
@@ -237,6 +239,8 @@ void default_plan(ssj_plan& p) {
     const int lanes[ssj::kClasses] = {4, 16, 64, ssj::kBlock, ssj::kBlock};
     for (int q = 0; q < ssj::kClasses; ++q) p.lanes[q] = lanes[q];
     p.use_graph = 0;
+    p.spill_iters = 0;
+    p.spill_lanes = 16;
 }
 
 bool plan_valid(const ssj_plan& p) {
@@ -244,8 +248,14 @@ bool plan_valid(const ssj_plan& p) {
     if (p.defer_from < 0 || p.defer_from > ssj::kClasses) return false;
     for (int q = 0; q < ssj::kClasses; ++q)
         if (!ssj::lanes_supported(p.lanes[q])) return false;
+    if (p.spill_iters < 0 || p.spill_iters > kMaxSpillIters || !ssj::lanes_supported(p.spill_lanes))
+        return false;
+    if (p.spill_iters > 0 && (p.inline_lanes != 1 || p.hard_lanes != 0)) return false;
     return true;
 }
+
+// A plan runs the deferred kernel when it defers classes or cuts merges off.
+bool plan_two_kernels(const ssj_plan& p) { return p.defer_from < ssj::kClasses || p.spill_iters > 0; }
 
 hipEvent_t timing_event(ssj_ctx* ctx) {
     std::lock_guard<std::mutex> g(ctx->tmu);
@@ -281,11 +291,11 @@ int check_req(const Req& r) {
 
 // Workgroups of the in-order kernel: one per kBlock / kWave chunks, at most
 // what the device holds at once.
-int grid_tiles(const ssj_ctx* ctx, int lanes, int hard_lanes, int defer_from, bool cosine,
-               int64_t n_chunks) {
-    const bool deferring = defer_from < ssj::kClasses;
-    const int occ = ctx->occ_tiles[4 * inline_index(lanes, hard_lanes) + (cosine ? 2 : 0) +
-                                   (deferring ? 1 : 0)][ssj::kClasses - defer_from];
+int grid_tiles(const ssj_ctx* ctx, const ssj_plan& plan, bool cosine, int64_t n_chunks) {
+    const bool deferring = plan_two_kernels(plan);
+    const int nq = ssj::wave_queues(plan.defer_from, plan.spill_iters > 0);
+    const int occ = ctx->occ_tiles[4 * inline_index(plan.inline_lanes, plan.hard_lanes) + (cosine ? 2 : 0) +
+                                   (deferring ? 1 : 0)][nq];
     const int64_t cap = (int64_t)ctx->n_cu * std::max(1, occ);
     const int64_t per_wg = ssj::kBlock / ssj::kWave;
     return (int)std::max<int64_t>(1, std::min<int64_t>((n_chunks + per_wg - 1) / per_wg, cap));
@@ -297,7 +307,8 @@ int grid_deferred(const ssj_ctx* ctx, bool cosine) {
 
 int launch_graph(ssj_ctx* ctx, const ssj::LaunchArgs& a, int g1, int g2, bool two,
                  hipStream_t st) {
-    GraphKey key{a.inline_lanes, a.hard_lanes, a.defer_from, (int)a.cosine, g1, two ? g2 : 0};
+    GraphKey key{a.inline_lanes, a.hard_lanes, a.defer_from, ssj::spilling(a) ? 1 : 0, (int)a.cosine, g1,
+                 two ? g2 : 0};
     ssj::LaunchArgs args = a;
     void* kparams[] = {&args};
     auto it = ctx->graphs.find(key);
@@ -349,6 +360,8 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     a.defer_from = plan.defer_from;
     a.inline_lanes = plan.inline_lanes;
     a.hard_lanes = plan.hard_lanes;
+    a.spill_iters = plan.spill_iters > 0 ? (uint32_t)plan.spill_iters : 0xffffffffu;
+    a.spill_lanes = plan.spill_lanes;
     // in-order work unit: a chunk of kWave pairs of one request per wavefront
     const uint64_t tile_pairs = (uint64_t)ssj::kWave;
     a.defer_cap = (uint32_t)(2 * tile_pairs);
@@ -375,14 +388,13 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     }
     a.tile_off[n_req] = (uint32_t)tiles;
     a.pair_off[n_req] = (uint32_t)pairs;
-    const bool two = plan.defer_from < ssj::kClasses;
+    const bool two = plan_two_kernels(plan);
     if (two) {
-        HIP_OR_FAIL(ctx, grow(sc.d_queues, sc.q_cap, (size_t)ssj::kClasses * std::max<uint64_t>(pairs, 1)));
+        HIP_OR_FAIL(ctx, grow(sc.d_queues, sc.q_cap, (size_t)ssj::kQueues * std::max<uint64_t>(pairs, 1)));
     }
     a.queues = sc.d_queues;
-    a.qcap = (uint32_t)(sc.q_cap / ssj::kClasses);
-    const int g1 = grid_tiles(ctx, plan.inline_lanes, plan.hard_lanes, plan.defer_from, a.cosine != 0,
-                              (int64_t)tiles);
+    a.qcap = (uint32_t)(sc.q_cap / ssj::kQueues);
+    const int g1 = grid_tiles(ctx, plan, a.cosine != 0, (int64_t)tiles);
     const int g2 = grid_deferred(ctx, a.cosine != 0);
 
     std::array<hipEvent_t, 4> ev{nullptr, nullptr, nullptr, nullptr};
@@ -693,7 +705,7 @@ int engine_start(ssj_ctx* ctx) {
         HIP_OR_FAIL(ctx, hipHostMalloc((void**)&s.h_out, (size_t)s.cap * 8, hipHostMallocDefault));
         HIP_OR_FAIL(ctx, hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
         size_t qc = 0;
-        HIP_OR_FAIL(ctx, grow(s.sc.d_queues, qc, (size_t)ssj::kClasses * (size_t)s.cap));
+        HIP_OR_FAIL(ctx, grow(s.sc.d_queues, qc, (size_t)ssj::kQueues * (size_t)s.cap));
         s.sc.q_cap = qc;
     }
     StreamEngine* raw = E.get();
@@ -766,9 +778,12 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
             const bool deferring = (k & 1) != 0;
             const void* f = ssj::kernel_verify_tiles(kInlineLanes[k / 4], kInlineHard[k / 4], deferring,
                                                      (k & 2) != 0);
-            for (int nd = deferring ? 1 : 0; nd <= (deferring ? ssj::kClasses : 0) && rc == SSJ_OK; ++nd) {
+            // by the number of LDS queues per wavefront (deferred classes,
+            // plus the spill queue)
+            for (int nd = deferring ? 1 : 0; nd <= (deferring ? ssj::kQueues : 0) && rc == SSJ_OK; ++nd) {
                 ssj::LaunchArgs la{};
-                la.defer_from = ssj::kClasses - nd;
+                la.defer_from = nd <= ssj::kClasses ? ssj::kClasses - nd : 0;
+                la.spill_iters = nd <= ssj::kClasses ? 0xffffffffu : 1u;
                 la.defer_cap = 2 * ssj::kWave;
                 int occ = 0;
                 if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, ssj::kBlock, ssj::tiles_lds_bytes(la))) != hipSuccess)
@@ -956,7 +971,9 @@ int ssj_set_plan(ssj_ctx* ctx, const ssj_plan* plan) {
     if (!plan_valid(*plan))
         return set_error(SSJ_EINVAL, "inline_lanes must be 1, 4, 8, 16, 32 or 64 (hard_lanes 0, 8 "
                                      "or 16 with 1 lane, else 0); defer_from in [0, 5]; "
-                                     "lanes 1, 4, 8, 16, 32, 64 or 256");
+                                     "lanes and spill_lanes 1, 4, 8, 16, 32, 64 or 256; "
+                                     "spill_iters in [0, 2^20], > 0 only with 1 lane and "
+                                     "hard_lanes 0");
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->plan = *plan;
     return SSJ_OK;
@@ -1143,12 +1160,15 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
     static const int kDeferredDefault[ssj::kClasses] = {4, 8, 16, 32, 64};
     ssj_plan cur = ctx->plan;
     double cur_ms = 1e30;
+    ssj_plan thread_best = ctx->plan;  // best plan with one thread per pair, no hard lanes
+    double thread_ms = 1e30;
     for (int k = 0; k < 8 && rc == SSJ_OK; ++k) {
         for (int d = ssj::kClasses; d >= 1 && rc == SSJ_OK; --d) {
             ssj_plan p = ctx->plan;
             p.inline_lanes = kInlineLanes[k];
             p.hard_lanes = kInlineHard[k];
             p.defer_from = d;
+            p.spill_iters = 0;
             for (int q = 0; q < ssj::kClasses; ++q) p.lanes[q] = kDeferredDefault[q];
             double ms = 0;
             if ((rc = measure(p, &ms)) != SSJ_OK) break;
@@ -1156,9 +1176,45 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
                 cur_ms = ms;
                 cur = p;
             }
+            if (k == 0 && ms < thread_ms) {
+                thread_ms = ms;
+                thread_best = p;
+            }
         }
     }
-    // 2) refine the mapping of each deferred class, one class at a time
+    // 2) thread-per-pair merges cut off after a budget of window steps (the
+    //    rest of such a merge goes to the deferred kernel), tried on the best
+    //    thread-per-pair plan with and without its deferred classes
+    static const int kSpillIters[6] = {4, 8, 12, 16, 24, 32};
+    for (int nodefer = 0; nodefer < 2 && rc == SSJ_OK; ++nodefer) {
+        if (nodefer && thread_best.defer_from == ssj::kClasses) break;
+        for (int it : kSpillIters) {
+            ssj_plan p = thread_best;
+            if (nodefer) p.defer_from = ssj::kClasses;
+            p.spill_iters = it;
+            p.spill_lanes = 16;
+            double ms = 0;
+            if ((rc = measure(p, &ms)) != SSJ_OK) break;
+            if (ms < cur_ms * 0.99) {
+                cur_ms = ms;
+                cur = p;
+            }
+        }
+    }
+    if (cur.spill_iters > 0 && rc == SSJ_OK) {
+        const ssj_plan base = cur;
+        for (int o : {4, 8, 32, 64, (int)ssj::kBlock}) {
+            ssj_plan p = base;
+            p.spill_lanes = o;
+            double ms = 0;
+            if ((rc = measure(p, &ms)) != SSJ_OK) break;
+            if (ms < cur_ms * 0.99) {
+                cur_ms = ms;
+                cur = p;
+            }
+        }
+    }
+    // 3) refine the mapping of each deferred class, one class at a time
     static const int kDeferredOptions[6] = {4, 8, 16, 32, 64, ssj::kBlock};
     for (int q = cur.defer_from; q < ssj::kClasses && rc == SSJ_OK; ++q) {
         const ssj_plan base = cur;

@@ -7,6 +7,8 @@
 namespace ssj {
 
 constexpr int kClasses = 5;      // length classes of |r| + |s|
+constexpr int kSpillQ = kClasses;  // queue of the thread-per-pair merges cut off by the budget
+constexpr int kQueues = kClasses + 1;  // deferred-class queues, then the spill queue
 constexpr int kBlock = 256;      // threads per workgroup of every verify kernel
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kMaxReq = 16;      // requests per launch
@@ -39,9 +41,9 @@ struct Request {
 struct alignas(256) Counters {
     unsigned long long out_count[kMaxReq];  // passing pairs appended so far
     unsigned int err[kMaxReq];              // != 0: an id was out of range
-    unsigned int head[kClasses];            // work-stealing cursors of deferred classes
-    unsigned int tail[kClasses];            // entries in each deferred-class queue
-    unsigned int pad[64 - kMaxReq - 2 * kClasses];
+    unsigned int head[kQueues];             // work-stealing cursors of the queues
+    unsigned int tail[kQueues];             // entries in each queue
+    unsigned int pad[64 - kMaxReq - 2 * kQueues];
 };
 
 // Everything one launch needs (passed by value as the kernel argument).
@@ -49,7 +51,7 @@ struct LaunchArgs {
     const int32_t* tok;                  // collection tokens
     const uint4* heads;                  // per set: {start, len, tok0, tok1}, {tok2..tok5}
     Counters* ctr;
-    uint32_t* queues;                    // deferred-class queues, kClasses x qcap
+    uint32_t* queues;                    // kQueues queues of qcap global pair indices
     uint32_t qcap;
     uint32_t n_sets;
     int n_req;
@@ -58,6 +60,10 @@ struct LaunchArgs {
     int hard_lanes;                      // lanes finishing long merges (inline_lanes == 1)
     uint32_t defer_cap;                  // LDS queue entries per deferred class and wavefront (>= 2 chunks)
     uint32_t cosine;                     // != 0: some request uses the Cosine rule
+    uint32_t spill_iters;                // window steps a thread-per-pair merge may take in the
+                                         // in-order kernel before it is queued whole for the
+                                         // deferred kernel (0xffffffff: no limit)
+    int spill_lanes;                     // lanes per pair of the spill queue
     uint32_t tile_off[kMaxReq + 1];      // prefix sums of per-request chunks (of kWave pairs)
     uint32_t pair_off[kMaxReq + 1];      // prefix sums of per-request pairs
     uint32_t bounds[kClasses];           // inclusive upper bound of |r|+|s| per class
@@ -73,11 +79,13 @@ struct LaunchArgs {
 hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start, const int32_t* d_tok,
                               uint4* d_heads, int64_t n_sets, hipStream_t st);
 // The in-order kernel: every pair of a class below defer_from is verified
-// with inline_lanes lanes; the others are queued for launch_verify_deferred.
+// with inline_lanes lanes; the others are queued for launch_verify_deferred,
+// and so is every thread-per-pair merge still undecided after spill_iters
+// window steps.
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st);
-// Drains the deferred-class queues (needed only when defer_from < kClasses).
+// Drains the queues (needed only when defer_from < kClasses or merges spill).
 hipError_t launch_verify_deferred(const LaunchArgs& a, int grid, hipStream_t st);
-// Dynamic LDS of the in-order kernel for a.defer_from / a.defer_cap.
+// Dynamic LDS of the in-order kernel for a.defer_from / a.spill_iters / a.defer_cap.
 size_t tiles_lds_bytes(const LaunchArgs& a);
 // Publishes the request counts and resets the counters (always last).
 hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st);
@@ -85,6 +93,11 @@ hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st);
 const void* kernel_verify_tiles(int lanes, int hard_lanes, bool deferring, bool cosine);
 const void* kernel_verify_deferred(bool cosine);
 const void* kernel_finalize();
+
+// LDS queues of a wavefront of the in-order kernel: one per deferred class,
+// one more for spilled merges.
+__host__ __device__ inline int wave_queues(int defer_from, bool spill) { return kClasses - defer_from + (spill ? 1 : 0); }
+__host__ __device__ inline bool spilling(const LaunchArgs& a) { return a.spill_iters != 0xffffffffu; }
 
 bool lanes_supported(int lanes);              // deferred classes: 1..64 or kBlock
 bool inline_supported(int lanes, int hard_lanes);  // in-order kernel: 1..64; 0/8/16 hard lanes with 1

@@ -95,3 +95,18 @@ def test_request_struct_matches_header():
               if ln.strip() and not ln.strip().startswith("/")]
     assert fields == [f[0] for f in ssj.ssj_request._fields_]
     assert ctypes.sizeof(ssj.ssj_request) == 64
+
+
+def test_plan_struct_matches_header():
+    # field names and order of the plan struct in the header and the binding
+    import ctypes
+    import paper_1812_09141_amd.ssj as ssj
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{([^}]*)\} ssj_plan;", text).group(1)
+    fields = []
+    for ln in body.strip().splitlines():
+        decl = ln.split("/*")[0].strip().rstrip(";")
+        if decl:
+            fields.append(decl.split()[-1].split("[")[0])
+    assert fields == [f[0] for f in ssj.ssj_plan._fields_]
+    assert ctypes.sizeof(ssj.ssj_plan) == 4 * (6 + ssj.SSJ_N_CLASSES)

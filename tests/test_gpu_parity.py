@@ -59,6 +59,15 @@ def plans():
     out.append(("mixed-graph", dict(inline_lanes=8, defer_from=2, lanes=[4, 16, 16, 64, 256],
                                     use_graph=1)))
     out.append(("inline-graph", dict(inline_lanes=4, defer_from=5, use_graph=1)))
+    # thread-per-pair merges cut off after 1..3 window steps (nearly every
+    # merge past the record tokens is verified again by the deferred kernel)
+    for I, G in [(1, 16), (1, 1), (2, 4), (3, 64), (1, 256)]:
+        out.append((f"spill-{I}x{G}", dict(inline_lanes=1, defer_from=5, spill_iters=I,
+                                           spill_lanes=G)))
+    out.append(("spill-2-defer", dict(inline_lanes=1, defer_from=2, lanes=[4, 8, 32, 64, 256],
+                                      spill_iters=2, spill_lanes=32)))
+    out.append(("spill-graph", dict(inline_lanes=1, defer_from=3, lanes=[4, 8, 16, 32, 256],
+                                    spill_iters=1, spill_lanes=8, use_graph=1)))
     return out
 
 
@@ -207,7 +216,10 @@ def test_config3_long_sets(S, ctx, golden_dir):
     for name, plan in [("default", None), ("inline-16", dict(inline_lanes=16, defer_from=5)),
                        ("inline-64", dict(inline_lanes=64, defer_from=5)),
                        ("deferred-all-256", dict(inline_lanes=4, defer_from=0, lanes=[256] * 5)),
-                       ("deferred-long", dict(inline_lanes=1, defer_from=2, lanes=[4, 8, 16, 64, 256]))]:
+                       ("deferred-long", dict(inline_lanes=1, defer_from=2, lanes=[4, 8, 16, 64, 256])),
+                       ("spill-8x16", dict(inline_lanes=1, defer_from=5, spill_iters=8, spill_lanes=16)),
+                       ("spill-4x64-defer", dict(inline_lanes=1, defer_from=4, lanes=[4, 8, 16, 32, 32],
+                                                 spill_iters=4, spill_lanes=64))]:
         _log(f"config3 {name}")
         set_plan(S, ctx, plan)
         got = run_host(S, ctx, h, cand, tn, td)
@@ -255,6 +267,16 @@ def test_errors_and_edges(S, ctx):
         S.ssj_verify(ctx, h, cand, 1, 2, out_cap=3)
     assert e.value.code == S.SSJ_ETRUNC and e.value.n == 15
     assert S.ssj_verify(ctx, h, cand, 1, 2, out_cap=15).shape[0] == 15
+    # unsupported plans are refused and leave the plan unchanged
+    before = S.ssj_get_plan(ctx).as_dict()
+    for bad in [dict(inline_lanes=3), dict(inline_lanes=4, hard_lanes=8), dict(defer_from=6),
+                dict(lanes=[4, 16, 3, 256, 256]), dict(inline_lanes=4, spill_iters=2),
+                dict(inline_lanes=1, hard_lanes=8, spill_iters=2), dict(spill_iters=-1),
+                dict(spill_iters=(1 << 20) + 1), dict(spill_iters=4, spill_lanes=2)]:
+        with pytest.raises(S.SsjError) as e:
+            S.ssj_set_plan(ctx, S.make_plan(**bad))
+        assert e.value.code == S.SSJ_EINVAL, bad
+    assert S.ssj_get_plan(ctx).as_dict() == before
     S.ssj_free_collection(ctx, h)
 
 
@@ -307,7 +329,8 @@ def test_config4_full_size(S, ctx, golden_dir):
     d_cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
     for name, plan in [("inline-1", dict(inline_lanes=1, defer_from=5)),
                        ("defer-3", dict(inline_lanes=1, defer_from=3, lanes=[4, 16, 64, 256, 256])),
-                       ("defer-1", dict(inline_lanes=1, defer_from=1, lanes=[4, 16, 32, 64, 256]))]:
+                       ("defer-1", dict(inline_lanes=1, defer_from=1, lanes=[4, 16, 32, 64, 256])),
+                       ("spill-2x32", dict(inline_lanes=1, defer_from=5, spill_iters=2, spill_lanes=32))]:
         _log(f"config4 {name}")
         set_plan(S, ctx, plan)
         S.ssj_verify_device(ctx, h, d_cand, tn, td, d_out, d_cnt)

@@ -106,7 +106,8 @@ def test_graph_replay_matches_eager(S, ctx, data):
     cand, tn, td, want = reqs[1]
     d_cand = _dev(torch, cand)
     for plan in [dict(inline_lanes=4, defer_from=5, use_graph=1),
-                 dict(inline_lanes=4, defer_from=1, lanes=[4, 16, 32, 64, 256], use_graph=1)]:
+                 dict(inline_lanes=4, defer_from=1, lanes=[4, 16, 32, 64, 256], use_graph=1),
+                 dict(inline_lanes=1, defer_from=5, spill_iters=1, spill_lanes=16, use_graph=1)]:
         for rep in range(4):
             S.ssj_set_plan(ctx, S.make_plan(**plan))
             d_out = torch.empty((cand.shape[0], 2), dtype=torch.int32, device="cuda:0")

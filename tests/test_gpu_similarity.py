@@ -39,6 +39,9 @@ PLANS = [
     ("deferred-8", dict(inline_lanes=4, defer_from=0, lanes=[8] * 5)),
     ("deferred-32", dict(inline_lanes=4, defer_from=0, lanes=[32] * 5)),
     ("deferred-256", dict(inline_lanes=4, defer_from=0, lanes=[256] * 5)),
+    ("spill-1x16", dict(inline_lanes=1, defer_from=5, spill_iters=1, spill_lanes=16)),
+    ("spill-2x1-defer", dict(inline_lanes=1, defer_from=3, lanes=[4, 8, 16, 32, 256],
+                             spill_iters=2, spill_lanes=1)),
 ]
 
 
