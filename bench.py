@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="offline", choices=sorted(WORKLOAD_CFG))
     ap.add_argument("--plan", default="auto",
-                    help="auto (autotuned) | inline:M | defer:M,D,l0,l1,l2,l3,l4 with M = L[hF][sI[xG]]")
+                    help="auto (autotuned) | inline:M | defer:M,D,l0,l1,l2,l3,l4 with M = L[hF][sI[xG]][wW]")
     ap.add_argument("--compare-plain", type=int, default=1,
                     help="also time plain one-launch-per-batch verification")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -55,18 +55,19 @@ def parse():
 
 
 def plan_of(S, spec):
-    """auto | inline:M | defer:M,D,l0,l1,l2,l3,l4 with M = L[hF][sI[xG]] (L lanes per pair,
-    F hard lanes, I window steps before a merge spills to G lanes, D first deferred class)"""
+    """auto | inline:M | defer:M,D,l0,l1,l2,l3,l4 with M = L[hF][sI[xG]][wW] (L lanes per pair,
+    F hard lanes, I window steps before a merge spills to G lanes, W in-order workgroups per
+    compute unit, D first deferred class)"""
     if spec == "auto":
         return None
     kind, _, rest = spec.partition(":")
     parts = rest.split(",") if rest else []
-    m = re.fullmatch(r"(\d+)(?:h(\d+))?(?:s(\d+)(?:x(\d+))?)?", parts[0] if parts else "")
+    m = re.fullmatch(r"(\d+)(?:h(\d+))?(?:s(\d+)(?:x(\d+))?)?(?:w(\d+))?", parts[0] if parts else "")
     if not m:
         raise SystemExit(f"bad mapping in plan {spec!r}")
-    L, F, I, G = (int(v) if v else d for v, d in zip(m.groups(), (1, 0, 0, 16)))
+    L, F, I, G, W = (int(v) if v else d for v, d in zip(m.groups(), (1, 0, 0, 16, 0)))
     vals = [int(v) for v in parts[1:]]
-    kw = dict(inline_lanes=L, hard_lanes=F, spill_iters=I, spill_lanes=G)
+    kw = dict(inline_lanes=L, hard_lanes=F, spill_iters=I, spill_lanes=G, wg_per_cu=W)
     if kind == "inline":
         return S.make_plan(defer_from=5, **kw)
     if kind == "defer":

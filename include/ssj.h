@@ -211,7 +211,9 @@ int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, int wait, uint64_t* t_submit
  *     by the kernel of (2), with spill_lanes lanes per pair.  This keeps a
  *     few long merges from holding up their wavefronts.  0: no bound.
  * use_graph != 0 replays the launch through a captured hipGraph whose kernel
- * parameters are updated per call.
+ * parameters are updated per call.  wg_per_cu sizes the in-order kernel's
+ * grid (its wavefronts split the chunks evenly; more workgroups than fit at
+ * once start as earlier ones finish).
  */
 #define SSJ_N_CLASSES 5
 #define SSJ_CLASS_BOUNDS {32, 128, 512, 2048, 0x7fffffff}
@@ -225,6 +227,8 @@ typedef struct {
     int use_graph;
     int spill_iters;             /* 0 .. 2^20; > 0 only with inline_lanes 1, hard_lanes 0 */
     int spill_lanes;             /* lanes per spilled pair: 1, 4, 8, 16, 32, 64 or 256 */
+    int wg_per_cu;               /* in-order kernel workgroups per compute unit, 0 .. 64
+                                    (0: as many as the device holds at once) */
 } ssj_plan;
 
 /* Reads / replaces the context's plan.  SSJ_EINVAL for an unsupported
@@ -264,7 +268,8 @@ int ssj_verify_batch_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_reques
  * in-order mapping with every deferral point (deferred classes starting from
  * mappings suited to their lengths), then step budgets (spill_iters) on the
  * best thread-per-pair plan, then refines the mapping of each deferred class
- * of the best plan, one class at a time.  Synchronous.
+ * of the best plan, one class at a time, and last the in-order grid size.
+ * Synchronous.
  */
 int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
                  int64_t t_num, int64_t t_den, int apply, ssj_plan* best, double* best_ms);

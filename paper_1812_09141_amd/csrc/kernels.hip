@@ -371,6 +371,24 @@ __device__ void wave_flush_deferred(const LaunchArgs& a, int q, uint32_t c, cons
     wave_sync();
 }
 
+// Wavefront priority from progress: 3 before the first quarter of its
+// chunks is done, down to 0 in the last quarter.  The SIMD's arbiter favours
+// the oldest wavefronts among those of equal priority, so with equal shares
+// of chunks the youngest ones would otherwise finish long after the rest and
+// leave the end of the launch to a few wavefronts; a wavefront that is ahead
+// now yields to one that is behind.  done, total and level are wave-uniform.
+__device__ __forceinline__ void progress_priority(uint32_t done, uint32_t total, uint32_t& level) {
+    const uint32_t l = 3u - min(3u, (4u * done) / total);
+    if (l == level) return;
+    level = l;
+    switch (l) {
+        case 0: __builtin_amdgcn_s_setprio(0); break;
+        case 1: __builtin_amdgcn_s_setprio(1); break;
+        case 2: __builtin_amdgcn_s_setprio(2); break;
+        default: __builtin_amdgcn_s_setprio(3); break;
+    }
+}
+
 // Request and first pair index of chunk T (prefix sums in tile_off, in
 // chunks of kWave pairs).
 __device__ __forceinline__ void chunk_origin(const LaunchArgs& a, uint32_t T, int* r, uint32_t* kb) {
@@ -660,7 +678,11 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
             p1 = lane_pair(a.req[r1], kb1, lane);
         }
     }
+    const uint32_t share = first < n_chunks ? (n_chunks - 1u - first) / nw + 1u : 1u;
+    uint32_t done = 0, level = 3;
+    __builtin_amdgcn_s_setprio(3);
     for (uint32_t T = first; T < n_chunks; T += nw) {
+        progress_priority(done++, share, level);
         const int r = r_cur;
         const uint32_t kb = kb_cur;
         const uint32_t Tn = T + nw;

@@ -43,6 +43,7 @@ uint64_t now_ns() {
 constexpr uint64_t kDefaultBudget = 4ull << 30;
 constexpr int64_t kMaxLaunchPairs = ((int64_t)1 << 31) - 1;  // pairs per launch
 constexpr int kMaxSpillIters = 1 << 20;
+constexpr int kMaxWgPerCu = 64;
 // device bytes per candidate pair of a request: the pair, a worst-case output
 // pair, and its queue entries
 constexpr size_t kBytesPerPair = 8 + 8 + 4 * ssj::kQueues;
@@ -241,6 +242,7 @@ void default_plan(ssj_plan& p) {
     p.use_graph = 0;
     p.spill_iters = 0;
     p.spill_lanes = 16;
+    p.wg_per_cu = 0;
 }
 
 bool plan_valid(const ssj_plan& p) {
@@ -251,6 +253,7 @@ bool plan_valid(const ssj_plan& p) {
     if (p.spill_iters < 0 || p.spill_iters > kMaxSpillIters || !ssj::lanes_supported(p.spill_lanes))
         return false;
     if (p.spill_iters > 0 && (p.inline_lanes != 1 || p.hard_lanes != 0)) return false;
+    if (p.wg_per_cu < 0 || p.wg_per_cu > kMaxWgPerCu) return false;
     return true;
 }
 
@@ -289,14 +292,32 @@ int check_req(const Req& r) {
     return SSJ_OK;
 }
 
-// Workgroups of the in-order kernel: one per kBlock / kWave chunks, at most
-// what the device holds at once.
-int grid_tiles(const ssj_ctx* ctx, const ssj_plan& plan, bool cosine, int64_t n_chunks) {
+// Workgroups of a kBlock-thread kernel that one compute unit holds at once
+// as far as vector registers go: each workgroup puts one wavefront on each of
+// the four SIMDs, and a SIMD has 512 registers per lane, allocated to a
+// wavefront in blocks of 16 (measured on gfx950: a kernel with 70 registers
+// runs 6 wavefronts per SIMD, where blocks of 8 would allow 7).
+int vgpr_limited_blocks(const void* f) {
+    hipFuncAttributes attr{};
+    if (hipFuncGetAttributes(&attr, f) != hipSuccess || attr.numRegs <= 0) return 1 << 20;
+    const int alloc = (attr.numRegs + 15) / 16 * 16;
+    return std::max(1, std::min(8, 512 / alloc));
+}
+
+// Workgroups of the in-order kernel that the device holds at once per
+// compute unit.
+int tiles_occupancy(const ssj_ctx* ctx, const ssj_plan& plan, bool cosine) {
     const bool deferring = plan_two_kernels(plan);
     const int nq = ssj::wave_queues(plan.defer_from, plan.spill_iters > 0);
-    const int occ = ctx->occ_tiles[4 * inline_index(plan.inline_lanes, plan.hard_lanes) + (cosine ? 2 : 0) +
-                                   (deferring ? 1 : 0)][nq];
-    const int64_t cap = (int64_t)ctx->n_cu * std::max(1, occ);
+    return std::max(1, ctx->occ_tiles[4 * inline_index(plan.inline_lanes, plan.hard_lanes) + (cosine ? 2 : 0) +
+                                      (deferring ? 1 : 0)][nq]);
+}
+
+// Workgroups of the in-order kernel: one per kBlock / kWave chunks, at most
+// plan.wg_per_cu per compute unit, or what the device holds at once.
+int grid_tiles(const ssj_ctx* ctx, const ssj_plan& plan, bool cosine, int64_t n_chunks) {
+    const int per_cu = plan.wg_per_cu > 0 ? plan.wg_per_cu : tiles_occupancy(ctx, plan, cosine);
+    const int64_t cap = (int64_t)ctx->n_cu * per_cu;
     const int64_t per_wg = ssj::kBlock / ssj::kWave;
     return (int)std::max<int64_t>(1, std::min<int64_t>((n_chunks + per_wg - 1) / per_wg, cap));
 }
@@ -788,7 +809,7 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
                 int occ = 0;
                 if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, ssj::kBlock, ssj::tiles_lds_bytes(la))) != hipSuccess)
                     rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
-                ctx->occ_tiles[k][nd] = occ;
+                ctx->occ_tiles[k][nd] = std::min(occ, vgpr_limited_blocks(f));
             }
         }
         if (rc != SSJ_OK) break;
@@ -796,7 +817,7 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
             int occ = 0;
             if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_deferred(k != 0), ssj::kBlock, 0)) != hipSuccess)
                 rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
-            ctx->occ_deferred2[k] = occ;
+            ctx->occ_deferred2[k] = std::min(occ, vgpr_limited_blocks(ssj::kernel_verify_deferred(k != 0)));
         }
         if (rc != SSJ_OK) break;
         if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) { rc = hip_fail(ctx, "hipStreamCreate", e); break; }
@@ -973,7 +994,7 @@ int ssj_set_plan(ssj_ctx* ctx, const ssj_plan* plan) {
                                      "or 16 with 1 lane, else 0); defer_from in [0, 5]; "
                                      "lanes and spill_lanes 1, 4, 8, 16, 32, 64 or 256; "
                                      "spill_iters in [0, 2^20], > 0 only with 1 lane and "
-                                     "hard_lanes 0");
+                                     "hard_lanes 0; wg_per_cu in [0, 64]");
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->plan = *plan;
     return SSJ_OK;
@@ -1164,21 +1185,27 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
     double thread_ms = 1e30;
     for (int k = 0; k < 8 && rc == SSJ_OK; ++k) {
         for (int d = ssj::kClasses; d >= 1 && rc == SSJ_OK; --d) {
-            ssj_plan p = ctx->plan;
-            p.inline_lanes = kInlineLanes[k];
-            p.hard_lanes = kInlineHard[k];
-            p.defer_from = d;
-            p.spill_iters = 0;
-            for (int q = 0; q < ssj::kClasses; ++q) p.lanes[q] = kDeferredDefault[q];
-            double ms = 0;
-            if ((rc = measure(p, &ms)) != SSJ_OK) break;
-            if (ms < cur_ms) {
-                cur_ms = ms;
-                cur = p;
-            }
-            if (k == 0 && ms < thread_ms) {
-                thread_ms = ms;
-                thread_best = p;
+            // each at the resident grid and at twice that (a larger grid
+            // evens out wavefronts that start late or issue slowly)
+            for (int twice = 0; twice < 2 && rc == SSJ_OK; ++twice) {
+                ssj_plan p = ctx->plan;
+                p.inline_lanes = kInlineLanes[k];
+                p.hard_lanes = kInlineHard[k];
+                p.defer_from = d;
+                p.spill_iters = 0;
+                p.wg_per_cu = 0;
+                for (int q = 0; q < ssj::kClasses; ++q) p.lanes[q] = kDeferredDefault[q];
+                if (twice) p.wg_per_cu = std::min(kMaxWgPerCu, 2 * tiles_occupancy(ctx, p, false));
+                double ms = 0;
+                if ((rc = measure(p, &ms)) != SSJ_OK) break;
+                if (ms < cur_ms) {
+                    cur_ms = ms;
+                    cur = p;
+                }
+                if (k == 0 && ms < thread_ms) {
+                    thread_ms = ms;
+                    thread_best = p;
+                }
             }
         }
     }
@@ -1222,6 +1249,23 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
             if (o == base.lanes[q]) continue;
             ssj_plan p = base;
             p.lanes[q] = o;
+            double ms = 0;
+            if ((rc = measure(p, &ms)) != SSJ_OK) break;
+            if (ms < cur_ms * 0.99) {
+                cur_ms = ms;
+                cur = p;
+            }
+        }
+    }
+    // 4) the in-order grid: fewer or more workgroups per compute unit than
+    //    fit at once
+    if (rc == SSJ_OK) {
+        const int occ = cur.wg_per_cu > 0 ? cur.wg_per_cu : tiles_occupancy(ctx, cur, false);
+        const ssj_plan base = cur;
+        for (int wg : {occ - 1, occ + 1, occ + 2, (3 * occ) / 2}) {
+            if (wg < 1 || wg > kMaxWgPerCu) continue;
+            ssj_plan p = base;
+            p.wg_per_cu = wg;
             double ms = 0;
             if ((rc = measure(p, &ms)) != SSJ_OK) break;
             if (ms < cur_ms * 0.99) {

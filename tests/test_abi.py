@@ -103,10 +103,7 @@ def test_plan_struct_matches_header():
     import paper_1812_09141_amd.ssj as ssj
     text = open(HEADER).read()
     body = re.search(r"typedef struct \{([^}]*)\} ssj_plan;", text).group(1)
-    fields = []
-    for ln in body.strip().splitlines():
-        decl = ln.split("/*")[0].strip().rstrip(";")
-        if decl:
-            fields.append(decl.split()[-1].split("[")[0])
+    fields = [m.group(1) for m in re.finditer(r"\bint\s+(\w+)\s*(?:\[[^\]]*\])?\s*;",
+                                                re.sub(r"/\*.*?\*/", "", body, flags=re.S))]
     assert fields == [f[0] for f in ssj.ssj_plan._fields_]
-    assert ctypes.sizeof(ssj.ssj_plan) == 4 * (6 + ssj.SSJ_N_CLASSES)
+    assert ctypes.sizeof(ssj.ssj_plan) == 4 * (7 + ssj.SSJ_N_CLASSES)

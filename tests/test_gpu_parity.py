@@ -68,6 +68,11 @@ def plans():
                                       spill_iters=2, spill_lanes=32)))
     out.append(("spill-graph", dict(inline_lanes=1, defer_from=3, lanes=[4, 8, 16, 32, 256],
                                     spill_iters=1, spill_lanes=8, use_graph=1)))
+    # in-order grids of one and of many workgroups per compute unit
+    out.append(("inline-1-wg1", dict(inline_lanes=1, defer_from=5, wg_per_cu=1)))
+    out.append(("inline-8-wg13", dict(inline_lanes=8, defer_from=5, wg_per_cu=13)))
+    out.append(("spill-2x16-wg20", dict(inline_lanes=1, defer_from=4, lanes=[4, 8, 16, 32, 64],
+                                        spill_iters=2, spill_lanes=16, wg_per_cu=20)))
     return out
 
 
@@ -272,7 +277,8 @@ def test_errors_and_edges(S, ctx):
     for bad in [dict(inline_lanes=3), dict(inline_lanes=4, hard_lanes=8), dict(defer_from=6),
                 dict(lanes=[4, 16, 3, 256, 256]), dict(inline_lanes=4, spill_iters=2),
                 dict(inline_lanes=1, hard_lanes=8, spill_iters=2), dict(spill_iters=-1),
-                dict(spill_iters=(1 << 20) + 1), dict(spill_iters=4, spill_lanes=2)]:
+                dict(spill_iters=(1 << 20) + 1), dict(spill_iters=4, spill_lanes=2),
+                dict(wg_per_cu=-1), dict(wg_per_cu=65)]:
         with pytest.raises(S.SsjError) as e:
             S.ssj_set_plan(ctx, S.make_plan(**bad))
         assert e.value.code == S.SSJ_EINVAL, bad
