@@ -46,11 +46,21 @@ enum {
 typedef struct ssj_ctx ssj_ctx;   /* one per GPU; opaque */
 typedef struct ssj_coll ssj_coll; /* an HBM-resident collection; opaque */
 
-/* One candidate pair: two set ids of the same collection (paper Table 2, C). */
+/* One candidate pair: two set ids (paper Table 2, C) -- of the same
+ * collection in a self-join, r of R and s of S in an R-S join. */
 typedef struct {
     int32_t r;
     int32_t s;
 } ssj_pair;
+
+/* One group of grouped candidates, an entry of the paper's interleaved
+ * C_O (Sec. 3.3.1): the probe set id and the exclusive end of its candidates
+ * in the array of s ids (the group starts where the previous one ends; the
+ * first at 0). */
+typedef struct {
+    int32_t probe;
+    int32_t end;
+} ssj_group;
 
 typedef struct {
     int device;           /* HIP device ordinal */
@@ -151,6 +161,43 @@ int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand
 int ssj_verify_device_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand,
                           int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* d_out,
                           int64_t out_cap, int64_t* d_count, void* hip_stream);
+
+/*
+ * R-S join (Definition 1 with two collections R and S; Sec. 3.3.1 keeps
+ * R_T/R_O and S_T/S_O on the device): each pair's r indexes coll_r and its s
+ * indexes coll_s, both uploaded to ctx (they may be the same collection,
+ * which is the self-join).  Otherwise as ssj_verify_sim / ssj_verify_device_sim:
+ * an r outside coll_r or an s outside coll_s is an id error.
+ */
+int ssj_verify_rs(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s, const ssj_pair* cand,
+                  int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* out,
+                  int64_t out_cap, int64_t* out_n);
+int ssj_verify_rs_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s,
+                         const ssj_pair* d_cand, int64_t n_cand, int sim, int64_t t_num,
+                         int64_t t_den, ssj_pair* d_out, int64_t out_cap, int64_t* d_count,
+                         void* hip_stream);
+
+/*
+ * Grouped candidates (the C / C_O layout of Sec. 3.3.1: every probe's
+ * candidates stored once as s ids after a group entry, 4 bytes per candidate
+ * instead of 8): n_groups entries {probe id in coll_r, exclusive end into
+ * cand} and n_cand s ids of coll_s.  The result is the same as for the flat
+ * pairs (probe, s) in the same order (pass coll_r = coll_s for a self-join).
+ * ssj_verify_groups takes host buffers (groups must cover cand exactly:
+ * ends not decreasing, the last one n_cand, else SSJ_EINVAL; large inputs are
+ * split into batches, a group across a batch border in two);
+ * ssj_verify_groups_device takes device buffers on hip_stream, with the
+ * rules of ssj_verify_device: candidates no group covers, or decreasing
+ * ends, make *d_count -1, like an id out of range.
+ */
+int ssj_verify_groups(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s,
+                      const ssj_group* groups, int64_t n_groups, const int32_t* cand, int64_t n_cand,
+                      int sim, int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap,
+                      int64_t* out_n);
+int ssj_verify_groups_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s,
+                             const ssj_group* d_groups, int64_t n_groups, const int32_t* d_cand,
+                             int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* d_out,
+                             int64_t out_cap, int64_t* d_count, void* hip_stream);
 
 /*
  * Streaming (continuous batching) -- the paper's host/device pipeline

@@ -9,6 +9,8 @@ It shares no code with the GPU library and imports nothing from it.
     oracle (``verify_ref.c``): full-merge overlap + the exact integer test of
     Jaccard, Cosine, Dice or Overlap (``sim``), and the early-terminating
     Jaccard merge replayed for token accounting.
+  * ``select_rs``: the same for an R-S join (Definition 1 with two
+    collections): r ids index R, s ids index S.
   * ``brute``: pure-Python all-pairs join and per-pair verification with
     ``frozenset`` and ``fractions.Fraction`` (tiny inputs only).
 """
@@ -116,6 +118,29 @@ def select(offsets, tokens, pairs, t_num: int, t_den: int, n_threads: int = 1,
     if k < 0:
         raise OracleError("invalid threshold, id out of range or empty set")
     return out[:k].copy()
+
+
+def select_rs(offsets_r, tokens_r, offsets_s, tokens_s, pairs, t_num: int, t_den: int,
+              n_threads: int = 1, sim: str = "jaccard") -> np.ndarray:
+    """The passing pairs of an R-S join (r in R, s in S), in input order.
+
+    The two collections are laid out as one (the sets of S after those of R,
+    so S's set s becomes set |R| + s), and each pair is verified by select;
+    the ids returned are the caller's."""
+    off_r = np.asarray(offsets_r, dtype=np.int64)
+    off_s = np.asarray(offsets_s, dtype=np.int64)
+    n_r, n_s = off_r.shape[0] - 1, off_s.shape[0] - 1
+    pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    if pr.shape[0] and (pr[:, 0].min() < 0 or pr[:, 0].max() >= n_r or pr[:, 1].min() < 0
+                        or pr[:, 1].max() >= n_s):
+        raise OracleError("id out of range")
+    off = np.concatenate([off_r, off_r[-1] + off_s[1:]])
+    tok = np.concatenate([np.asarray(tokens_r, dtype=np.int32), np.asarray(tokens_s, dtype=np.int32)])
+    shifted = pr.copy()
+    shifted[:, 1] += n_r
+    keep = select(off, tok, shifted, t_num, t_den, n_threads=n_threads, sim=sim)
+    keep[:, 1] -= n_r
+    return keep
 
 
 def merge_trace(offsets, tokens, pairs, t_num: int, t_den: int, n_threads: int = 1):

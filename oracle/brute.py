@@ -59,3 +59,11 @@ def brute_verify(offsets, tokens, pairs: Sequence[Sequence[int]], t_num: int, t_
         ov.append(len(a & b))
         dec.append(similar(a, b, t, sim))
     return dec, ov
+
+
+def brute_verify_rs(offsets_r, tokens_r, offsets_s, tokens_s, pairs: Sequence[Sequence[int]],
+                    t_num: int, t_den: int, sim: str = "jaccard"):
+    """Per-pair decision of an R-S join (r a set of R, s a set of S)."""
+    sets_r, sets_s = _sets(offsets_r, tokens_r), _sets(offsets_s, tokens_s)
+    t = Fraction(t_num, t_den)
+    return [similar(sets_r[int(r)], sets_s[int(s)], t, sim) for r, s in pairs]

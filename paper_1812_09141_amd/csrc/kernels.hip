@@ -39,6 +39,8 @@
 // lane's rank among the passing lanes) and moved to the request's output
 // with one global atomic per flush.  The in-order kernel keeps all of this
 // per wavefront, so it has no workgroup barrier.
+#include <algorithm>
+
 #include "ssj_device.h"
 
 namespace ssj {
@@ -99,6 +101,12 @@ __device__ __forceinline__ uint32_t mbcnt(unsigned long long m) {
 // (slots past the end of a shorter set hold -1).
 __device__ __forceinline__ uint2 set_desc(const LaunchArgs& a, int id) {
     const uint4 v = a.heads[2 * id];
+    return make_uint2(v.x, v.y);
+}
+
+// The same for a set of the s-side collection.
+__device__ __forceinline__ uint2 set_desc_s(const LaunchArgs& a, int id) {
+    const uint4 v = a.heads_s[2 * id];
     return make_uint2(v.x, v.y);
 }
 
@@ -268,8 +276,9 @@ __device__ __forceinline__ void append_one(int2 pr, const Request& R, unsigned l
     if (k < R.cap) R.out[k] = pr;
 }
 
-__device__ __forceinline__ bool ids_ok(int2 pr, uint32_t n_sets) {
-    return (uint32_t)pr.x < n_sets && (uint32_t)pr.y < n_sets;
+// Whether r indexes the r-side collection and s the s-side one.
+__device__ __forceinline__ bool ids_ok(int2 pr, const LaunchArgs& a) {
+    return (uint32_t)pr.x < a.n_sets && (uint32_t)pr.y < a.n_sets_s;
 }
 
 __device__ __forceinline__ int class_of(uint32_t L, const LaunchArgs& a) {
@@ -413,12 +422,12 @@ struct LaneRecords {
 };
 
 __device__ __forceinline__ void issue_records(const LaunchArgs& a, int2 pr, LaneRecords& rec) {
-    const bool ok = ids_ok(pr, a.n_sets);
+    const bool ok = ids_ok(pr, a);
     const int ir = ok ? pr.x : 0, is = ok ? pr.y : 0;
     rec.ra0 = a.heads[2 * ir];
     rec.ra1 = a.heads[2 * ir + 1];
-    rec.rb0 = a.heads[2 * is];
-    rec.rb1 = a.heads[2 * is + 1];
+    rec.rb0 = a.heads_s[2 * is];
+    rec.rb1 = a.heads_s[2 * is + 1];
 }
 
 // Merge state after the first tile of one side is consumed, with the six
@@ -457,8 +466,9 @@ __device__ __forceinline__ void head_tiles(uint4 a0, uint4 a1, uint4 b0, uint4 b
 }
 
 // One lane's merge continued from state (i, j, o) over 16-byte windows of
-// the two token lists (every set starts on a 16-byte boundary of the token
-// array): window w of a side holds its tokens 4w .. 4w+3.  A step merges the
+// the two token lists (A from slot sa of tok_a, B from slot sb of tok_b;
+// every set starts on a 16-byte boundary of its token array): window w of a
+// side holds its tokens 4w .. 4w+3.  A step merges the
 // unconsumed tokens of the current windows of both sides (up to 4 x 4
 // comparisons) and consumes, as in the tile merge, every token that can have
 // no partner beyond the two windows: all of the window with the lower end,
@@ -473,11 +483,12 @@ __device__ __forceinline__ void head_tiles(uint4 a0, uint4 a1, uint4 b0, uint4 b
 // i < na and j < nb.  After budget steps a merge still undecided stops with
 // *spilled set (all lanes enter together, so the step count is the same in
 // every lane and the cut is a wave-uniform branch).
-__device__ __forceinline__ bool merge_windows(const int32_t* __restrict__ tok, uint32_t sa,
-                                              uint32_t na, uint32_t sb, uint32_t nb,
-                                              uint32_t alpha, uint32_t i, uint32_t j, uint32_t o,
-                                              uint32_t budget, bool* spilled) {
-    const uint4* __restrict__ t4 = reinterpret_cast<const uint4*>(tok);
+__device__ __forceinline__ bool merge_windows(const int32_t* __restrict__ tok_a, uint32_t sa,
+                                              uint32_t na, const int32_t* __restrict__ tok_b,
+                                              uint32_t sb, uint32_t nb, uint32_t alpha, uint32_t i,
+                                              uint32_t j, uint32_t o, uint32_t budget, bool* spilled) {
+    const uint4* __restrict__ t4a = reinterpret_cast<const uint4*>(tok_a);
+    const uint4* __restrict__ t4b = reinterpret_cast<const uint4*>(tok_b);
     const uint32_t qa = sa >> 2, qb = sb >> 2;              // first window of each set
     const uint32_t la = (na - 1u) >> 2, lb = (nb - 1u) >> 2;  // last window index
     uint32_t wa = i >> 2, wb = j >> 2;
@@ -490,10 +501,10 @@ __device__ __forceinline__ bool merge_windows(const int32_t* __restrict__ tok, u
         d[2] = (int32_t)v.z;
         d[3] = (int32_t)v.w;
     };
-    unpack(t4[qa + wa], a);
-    unpack(t4[qb + wb], b);
-    unpack(t4[qa + min(wa + 1u, la)], an);
-    unpack(t4[qb + min(wb + 1u, lb)], bn);
+    unpack(t4a[qa + wa], a);
+    unpack(t4b[qb + wb], b);
+    unpack(t4a[qa + min(wa + 1u, la)], an);
+    unpack(t4b[qb + min(wb + 1u, lb)], bn);
     for (uint32_t step = 1;; ++step) {
         const uint32_t ba = wa << 2, bb = wb << 2;
         const uint32_t ea = min(na - ba, 4u), eb = min(nb - bb, 4u);  // tokens in the windows
@@ -533,8 +544,8 @@ __device__ __forceinline__ bool merge_windows(const int32_t* __restrict__ tok, u
             b[k] = adv_b ? bn[k] : b[k];
         }
         __builtin_amdgcn_sched_barrier(0);
-        unpack(t4[qa + min(wa + 1u, la)], an);
-        unpack(t4[qb + min(wb + 1u, lb)], bn);
+        unpack(t4a[qa + min(wa + 1u, la)], an);
+        unpack(t4b[qb + min(wb + 1u, lb)], bn);
     }
 }
 
@@ -555,7 +566,7 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
     const int lane = lane_id();
     const uint32_t k = kb + (uint32_t)lane;
     const bool valid = k < R.n;
-    const bool ok = valid && ids_ok(pr, a.n_sets);
+    const bool ok = valid && ids_ok(pr, a);
     const uint32_t na = rec.ra0.y, nb = rec.rb0.y;
     const uint32_t L = na + nb;
     const int cls = deferring ? class_of(L, a) : 0;
@@ -569,7 +580,7 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
     bool spill = false;
     if constexpr (F == 0) {
         if (act)
-            pass = merge_windows(a.tok, rec.ra0.x, na, rec.rb0.x, nb, alpha, i, j, o,
+            pass = merge_windows(a.tok, rec.ra0.x, na, a.tok_s, rec.rb0.x, nb, alpha, i, j, o,
                                  deferring ? a.spill_iters : 0xffffffffu, &spill);
     }
     // (after the merges: atomics count with loads, so none sits between the
@@ -608,9 +619,9 @@ __device__ __forceinline__ void finish_hard(const LaunchArgs& a, const Request& 
             pq = w_hpr[e];
             const uint32_t st = w_hst[e];
             const uint2 dr = set_desc(a, pq.x);
-            const uint2 ds = set_desc(a, pq.y);
+            const uint2 ds = set_desc_s(a, pq.y);
             const uint32_t alpha = required_overlap<C>(dr.y, ds.y, R);
-            pass = merge_group<G>(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y, alpha, g, gbase,
+            pass = merge_group<G>(a.tok + dr.x, dr.y, a.tok_s + ds.x, ds.y, alpha, g, gbase,
                                   st & 0xffu, (st >> 8) & 0xffu, st >> 16);
         }
         stage_pass(pass && g == 0, pq, w_out, ocnt, R.cap == 0);
@@ -720,35 +731,35 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                 return load_pair(R.cand, k < R.n ? k : R.n - 1);
             };
             auto desc_of = [&](int2 pq, uint2* dr, uint2* ds) {
-                const bool ok = ids_ok(pq, a.n_sets);
+                const bool ok = ids_ok(pq, a);
                 *dr = set_desc(a, ok ? pq.x : 0);
-                *ds = set_desc(a, ok ? pq.y : 0);
+                *ds = set_desc_s(a, ok ? pq.y : 0);
             };
             int2 pq0 = pair_at(0), pq1 = pair_at(1), pq2 = pair_at(2);
             uint2 dr0, ds0, dr1, ds1;
             desc_of(pq0, &dr0, &ds0);
             desc_of(pq1, &dr1, &ds1);
-            int32_t wa0 = first_tile_token(a.tok, dr0, g), wb0 = first_tile_token(a.tok, ds0, g);
+            int32_t wa0 = first_tile_token(a.tok, dr0, g), wb0 = first_tile_token(a.tok_s, ds0, g);
             bool bad = false;
             for (int sub = 0; sub < G; ++sub) {
                 const int2 pq3 = pair_at(sub + 3);
                 uint2 dr2, ds2;
                 desc_of(pq2, &dr2, &ds2);
                 const int32_t wa1 = first_tile_token(a.tok, dr1, g);
-                const int32_t wb1 = first_tile_token(a.tok, ds1, g);
+                const int32_t wb1 = first_tile_token(a.tok_s, ds1, g);
                 const uint32_t k = kb + (uint32_t)(sub * GPW + grp);
                 bool pass = false, defer = false;
                 int cls = 0;
                 const int2 pq = pq0;
                 if (k < R.n) {
-                    if (ids_ok(pq, a.n_sets)) {
+                    if (ids_ok(pq, a)) {
                         const uint32_t L = dr0.y + ds0.y;
                         if (deferring) {
                             cls = class_of(L, a);
                             defer = cls >= a.defer_from;
                         }
                         if (!defer)
-                            pass = merge_group_first<G>(a.tok + dr0.x, dr0.y, a.tok + ds0.x, ds0.y,
+                            pass = merge_group_first<G>(a.tok + dr0.x, dr0.y, a.tok_s + ds0.x, ds0.y,
                                                         required_overlap<C>(dr0.y, ds0.y, R), g, gbase,
                                                         wa0, wb0);
                     } else {
@@ -850,28 +861,28 @@ __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
         p1 = pair_of(e1, &r1);
         p2 = pair_of(e2, &r2);
         dr0 = set_desc(a, p0.x);
-        ds0 = set_desc(a, p0.y);
+        ds0 = set_desc_s(a, p0.y);
         dr1 = set_desc(a, p1.x);
-        ds1 = set_desc(a, p1.y);
+        ds1 = set_desc_s(a, p1.y);
         wa0 = first_tile_token(a.tok, dr0, g);
-        wb0 = first_tile_token(a.tok, ds0, g);
+        wb0 = first_tile_token(a.tok_s, ds0, g);
     }
     for (uint32_t t = t0, s = 0; t < cnt; t += stride, ++s) {
         const uint32_t e4 = entry_at(s + 4);
         int r3;
         const int2 p3 = pair_of(e3, &r3);
         const uint2 dr2 = set_desc(a, p2.x);
-        const uint2 ds2 = set_desc(a, p2.y);
+        const uint2 ds2 = set_desc_s(a, p2.y);
         const int32_t wa1 = first_tile_token(a.tok, dr1, g);
-        const int32_t wb1 = first_tile_token(a.tok, ds1, g);
+        const int32_t wb1 = first_tile_token(a.tok_s, ds1, g);
         if (t + (uint32_t)grp < cnt) {
             const Request& R = a.req[r0];
             const uint32_t alpha = required_overlap<C>(dr0.y, ds0.y, R);
             bool pass;
             if constexpr (G == 1)
-                pass = merge_thread(a.tok + dr0.x, dr0.y, a.tok + ds0.x, ds0.y, alpha);
+                pass = merge_thread(a.tok + dr0.x, dr0.y, a.tok_s + ds0.x, ds0.y, alpha);
             else
-                pass = merge_group_first<G>(a.tok + dr0.x, dr0.y, a.tok + ds0.x, ds0.y, alpha, g,
+                pass = merge_group_first<G>(a.tok + dr0.x, dr0.y, a.tok_s + ds0.x, ds0.y, alpha, g,
                                             gbase, wa0, wb0);
             if (pass && g == 0) append_one(p0, R, &a.ctr->out_count[r0]);
         }
@@ -922,8 +933,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
             const Request& R = a.req[r];
             const int2 pr = load_pair(R.cand, gi - a.pair_off[r]);
             const uint2 dr = set_desc(a, pr.x);
-            const uint2 ds = set_desc(a, pr.y);
-            const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok + ds.x, ds.y,
+            const uint2 ds = set_desc_s(a, pr.y);
+            const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok_s + ds.x, ds.y,
                                           required_overlap<C>(dr.y, ds.y, R), sb, red);
             if (threadIdx.x == 0 && pass) append_one(pr, R, &a.ctr->out_count[r]);
         }
@@ -940,6 +951,79 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
             case 32: drain_static<32, C>(a, q, cnt); break;
             case 64: drain_static<64, C>(a, q, cnt); break;
             default: break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grouped candidates (the interleaved C_O / C form of Sec. 3.3.1): group g is
+// {probe id, exclusive end}, and its candidates are the s ids
+// cand[end(g-1) .. end(g)) with end(-1) = 0.  They are expanded into flat
+// pairs before verification.
+
+// First group of each chunk of kWave candidates: the least g with end(g) >
+// kWave * T (binary search over the ends; n_groups when none).
+__global__ void k_chunk_groups(const int2* __restrict__ groups, uint32_t n_groups, uint32_t n_chunks,
+                               uint32_t* __restrict__ chunk_g) {
+    for (uint32_t T = blockIdx.x * blockDim.x + threadIdx.x; T < n_chunks; T += gridDim.x * blockDim.x) {
+        const uint32_t c0 = T * (uint32_t)kWave;
+        uint32_t lo = 0, hi = n_groups;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2u;
+            if ((uint32_t)groups[mid].y <= c0)
+                lo = mid + 1u;
+            else
+                hi = mid;
+        }
+        chunk_g[T] = lo;
+    }
+}
+
+// Flat pairs (probe, s) of grouped candidates, one wavefront per chunk: the
+// lanes load the ends of 64 groups from the chunk's first group, and each
+// lane's group is the number of those ends at or below its candidate index
+// (binary search across the lanes); a lane past all 64 takes the next 64.
+// A candidate that no group covers, or any chunk that sees the ends decrease,
+// gets probe id -1, which the verification reports as an id error.
+__global__ void k_expand_groups(const int2* __restrict__ groups, uint32_t n_groups,
+                                const int32_t* __restrict__ cand, uint32_t n,
+                                const uint32_t* __restrict__ chunk_g, int2* __restrict__ pairs) {
+    const int lane = lane_id();
+    const uint32_t n_chunks = (n + (uint32_t)kWave - 1u) / (uint32_t)kWave;
+    const uint32_t waves = gridDim.x * (blockDim.x / (uint32_t)kWave);
+    for (uint32_t T = (blockIdx.x * blockDim.x + threadIdx.x) / (uint32_t)kWave; T < n_chunks; T += waves) {
+        const uint32_t c = T * (uint32_t)kWave + (uint32_t)lane;
+        const bool valid = c < n;
+        uint32_t g0 = chunk_g[T];
+        uint32_t g = 0xffffffffu;  // the lane's group once found
+        bool bad = false;
+        // all lanes take part in every permute (a permute reads nothing from
+        // an inactive lane); at most n_groups / 64 + 1 rounds
+        for (;;) {
+            const uint32_t gk = g0 + (uint32_t)lane;
+            const uint32_t ek = gk < n_groups ? (uint32_t)groups[gk].y : 0xffffffffu;
+            const uint32_t before = g0 > 0u ? (uint32_t)groups[g0 - 1u].y : 0u;
+            // the permute runs in every lane (lane 0 reads lane 63 and drops it)
+            const uint32_t left = (uint32_t)bperm((int)ek, (lane + kWave - 1) & (kWave - 1));
+            const uint32_t eprev = lane > 0 ? left : before;
+            bad |= gk < n_groups && ek < eprev;
+            uint32_t pos = 0;
+#pragma unroll
+            for (uint32_t step = kWave / 2; step >= 1; step >>= 1) {
+                const uint32_t v = (uint32_t)bperm((int)ek, (int)(pos + step - 1u));
+                pos += (v <= c) ? step : 0u;
+            }
+            const bool beyond = (uint32_t)bperm((int)ek, kWave - 1) <= c;
+            if (g == 0xffffffffu && !beyond) g = g0 + pos;
+            if (ballot(valid && g == 0xffffffffu) == 0ull) break;
+            g0 += (uint32_t)kWave;
+            if (g0 >= n_groups) break;
+        }
+        const bool any_bad = ballot(bad) != 0ull;
+        if (valid) {
+            const bool ok = !any_bad && g < n_groups;
+            const int32_t r = ok ? groups[g].x : -1;
+            pairs[c] = make_int2(r, cand[c]);
         }
     }
 }
@@ -1004,6 +1088,21 @@ const void* kernel_verify_tiles(int lanes, int hard_lanes, bool deferring, bool 
 
 const void* kernel_verify_deferred(bool cosine) {
     return cosine ? (const void*)&k_verify_deferred<true> : (const void*)&k_verify_deferred<false>;
+}
+
+hipError_t launch_expand_groups(const int2* d_groups, int64_t n_groups, const int32_t* d_cand, int64_t n,
+                                uint32_t* d_chunk_g, int2* d_pairs, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t n_chunks = (n + kWave - 1) / kWave;
+    const int64_t b1 = std::min<int64_t>((n_chunks + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(k_chunk_groups, dim3((unsigned)b1), dim3(kBlock), 0, st, d_groups,
+                       (uint32_t)n_groups, (uint32_t)n_chunks, d_chunk_g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t b2 = std::min<int64_t>((n_chunks + kBlock / kWave - 1) / (kBlock / kWave), 65536);
+    hipLaunchKernelGGL(k_expand_groups, dim3((unsigned)b2), dim3(kBlock), 0, st, d_groups,
+                       (uint32_t)n_groups, d_cand, (uint32_t)n, d_chunk_g, d_pairs);
+    return hipGetLastError();
 }
 
 hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start, const int32_t* d_tok,

@@ -174,6 +174,16 @@ struct ssj_ctx {
     size_t out_cap = 0;
     long long* d_count = nullptr;
     long long* h_count = nullptr;  // pinned
+    // grouped candidates: host-call staging of groups and s ids, and the
+    // flat pairs they expand to (with one word per 64 candidates)
+    int2* d_groups = nullptr;
+    size_t groups_cap = 0;
+    int32_t* d_sids = nullptr;
+    size_t sids_cap = 0;
+    int2* d_pairs = nullptr;
+    size_t pairs_cap = 0;
+    uint32_t* d_chunk_g = nullptr;
+    size_t chunk_g_cap = 0;
     std::atomic<bool> failed{false};
     std::vector<ssj_coll*> colls;
     std::map<GraphKey, GraphEntry> graphs;
@@ -369,14 +379,20 @@ int launch_graph(ssj_ctx* ctx, const ssj::LaunchArgs& a, int g1, int g2, bool tw
     return SSJ_OK;
 }
 
-// Enqueues one launch verifying up to kMaxReq requests already on the device.
+// Enqueues one launch verifying up to kMaxReq requests already on the device:
+// r ids index coll, s ids coll_s (null: coll, a self-join).
 int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* reqs, int n_req,
-                   hipStream_t st, const ssj_plan& plan, bool allow_graph = true) {
+                   hipStream_t st, const ssj_plan& plan, bool allow_graph = true,
+                   const ssj_coll* coll_s = nullptr) {
+    const ssj_coll* cs = coll_s ? coll_s : coll;
     ssj::LaunchArgs a{};
     a.tok = coll->d_tok;
     a.heads = coll->d_heads;
+    a.tok_s = cs->d_tok;
+    a.heads_s = cs->d_heads;
     a.ctr = sc.d_ctr;
     a.n_sets = (uint32_t)coll->n_sets;
+    a.n_sets_s = (uint32_t)cs->n_sets;
     a.n_req = n_req;
     a.defer_from = plan.defer_from;
     a.inline_lanes = plan.inline_lanes;
@@ -852,6 +868,10 @@ int ssj_shutdown(ssj_ctx* ctx) {
         scratch_free(ctx->def);
         if (ctx->d_cand) (void)hipFree(ctx->d_cand);
         if (ctx->d_out) (void)hipFree(ctx->d_out);
+        if (ctx->d_groups) (void)hipFree(ctx->d_groups);
+        if (ctx->d_sids) (void)hipFree(ctx->d_sids);
+        if (ctx->d_pairs) (void)hipFree(ctx->d_pairs);
+        if (ctx->d_chunk_g) (void)hipFree(ctx->d_chunk_g);
         if (ctx->d_count) (void)hipFree(ctx->d_count);
         if (ctx->h_count) (void)hipHostFree(ctx->h_count);
         for (auto& kv : ctx->graphs) {
@@ -1061,19 +1081,75 @@ int ssj_verify_batch_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_reques
     return enqueue_launch(ctx, coll, ctx->def, v.data(), n_reqs, (hipStream_t)hip_stream, ctx->plan);
 }
 
-int ssj_verify_device_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand,
-                          int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* d_out,
-                          int64_t out_cap, int64_t* d_count, void* hip_stream) {
+namespace {
+
+// Device-buffer verification of flat pairs, r ids in coll, s ids in coll_s.
+int verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_coll* coll_s, const ssj_pair* d_cand,
+                  int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* d_out,
+                  int64_t out_cap, int64_t* d_count, void* hip_stream) {
     int rc = check_ctx(ctx);
     if (rc != SSJ_OK) return rc;
     if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll_s)) != SSJ_OK) return rc;
     Req r{reinterpret_cast<const int2*>(d_cand), n_cand, t_num, t_den, reinterpret_cast<int2*>(d_out),
           out_cap, reinterpret_cast<long long*>(d_count), sim};
     if ((rc = check_req(r)) != SSJ_OK) return rc;
     if (n_cand > kMaxLaunchPairs) return set_error(SSJ_EINVAL, "n_cand must be below 2^31 per device call");
     std::lock_guard<std::mutex> g(ctx->mu);
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
-    return enqueue_launch(ctx, coll, ctx->def, &r, 1, (hipStream_t)hip_stream, ctx->plan);
+    return enqueue_launch(ctx, coll, ctx->def, &r, 1, (hipStream_t)hip_stream, ctx->plan, true, coll_s);
+}
+
+// Expands grouped candidates already on the device into ctx->d_pairs and
+// enqueues their verification (ctx->mu held).
+int enqueue_groups(ssj_ctx* ctx, const ssj_coll* R, const ssj_coll* S, const int2* d_groups,
+                   int64_t n_groups, const int32_t* d_sids, int64_t n_cand, int sim, int64_t t_num,
+                   int64_t t_den, int2* d_out, int64_t out_cap, long long* d_count, hipStream_t st) {
+    HIP_OR_FAIL(ctx, grow(ctx->d_pairs, ctx->pairs_cap, (size_t)std::max<int64_t>(n_cand, 1)));
+    HIP_OR_FAIL(ctx, grow(ctx->d_chunk_g, ctx->chunk_g_cap,
+                          (size_t)std::max<int64_t>((n_cand + ssj::kWave - 1) / ssj::kWave, 1)));
+    HIP_OR_FAIL(ctx, ssj::launch_expand_groups(d_groups, n_groups, d_sids, n_cand, ctx->d_chunk_g,
+                                               ctx->d_pairs, st));
+    Req r{ctx->d_pairs, n_cand, t_num, t_den, d_out, out_cap, d_count, sim};
+    return enqueue_launch(ctx, R, ctx->def, &r, 1, st, ctx->plan, true, S);
+}
+
+}  // namespace
+
+int ssj_verify_device_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand,
+                          int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* d_out,
+                          int64_t out_cap, int64_t* d_count, void* hip_stream) {
+    return verify_device(ctx, coll, coll, d_cand, n_cand, sim, t_num, t_den, d_out, out_cap, d_count,
+                         hip_stream);
+}
+
+int ssj_verify_rs_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s,
+                         const ssj_pair* d_cand, int64_t n_cand, int sim, int64_t t_num,
+                         int64_t t_den, ssj_pair* d_out, int64_t out_cap, int64_t* d_count,
+                         void* hip_stream) {
+    return verify_device(ctx, coll_r, coll_s, d_cand, n_cand, sim, t_num, t_den, d_out, out_cap,
+                         d_count, hip_stream);
+}
+
+int ssj_verify_groups_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s,
+                             const ssj_group* d_groups, int64_t n_groups, const int32_t* d_cand,
+                             int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* d_out,
+                             int64_t out_cap, int64_t* d_count, void* hip_stream) {
+    int rc = check_ctx(ctx);
+    if (rc != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll_r)) != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll_s)) != SSJ_OK) return rc;
+    if (!valid_threshold(sim, t_num, t_den)) return set_error(SSJ_EINVAL, kThresholdError);
+    if (n_groups < 0 || n_cand < 0 || out_cap < 0) return set_error(SSJ_EINVAL, "negative size");
+    if (n_cand > kMaxLaunchPairs || n_groups > kMaxLaunchPairs)
+        return set_error(SSJ_EINVAL, "n_cand and n_groups must be below 2^31 per device call");
+    if (!d_count || (n_cand > 0 && !d_cand) || (n_groups > 0 && !d_groups))
+        return set_error(SSJ_EINVAL, "null device buffer");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    return enqueue_groups(ctx, coll_r, coll_s, reinterpret_cast<const int2*>(d_groups), n_groups, d_cand,
+                          n_cand, sim, t_num, t_den, reinterpret_cast<int2*>(d_out), out_cap,
+                          reinterpret_cast<long long*>(d_count), (hipStream_t)hip_stream);
 }
 
 int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
@@ -1083,12 +1159,17 @@ int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand
                                  out_cap, d_count, hip_stream);
 }
 
-int ssj_verify_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
-                   int sim, int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap,
-                   int64_t* out_n) {
+namespace {
+
+// Host-buffer verification of flat pairs, r ids in coll, s ids in coll_s, in
+// chunks that fit the HBM budget.
+int verify_host(ssj_ctx* ctx, const ssj_coll* coll, const ssj_coll* coll_s, const ssj_pair* cand,
+                int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap,
+                int64_t* out_n) {
     int rc = check_ctx(ctx);
     if (rc != SSJ_OK) return rc;
     if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll_s)) != SSJ_OK) return rc;
     if (!valid_threshold(sim, t_num, t_den)) return set_error(SSJ_EINVAL, kThresholdError);
     if (n_cand < 0 || out_cap < 0) return set_error(SSJ_EINVAL, "negative size");
     if (!out_n || (n_cand > 0 && !cand) || (out_cap > 0 && !out))
@@ -1108,7 +1189,7 @@ int ssj_verify_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int
         if (n > 0)
             HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->d_cand, cand + done, (size_t)n * 8, hipMemcpyHostToDevice, st));
         Req r{ctx->d_cand, n, t_num, t_den, ctx->d_out, n, ctx->d_count, sim};
-        rc = enqueue_launch(ctx, coll, ctx->def, &r, 1, st, ctx->plan);
+        rc = enqueue_launch(ctx, coll, ctx->def, &r, 1, st, ctx->plan, true, coll_s);
         if (rc != SSJ_OK) return rc;
         HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, ctx->d_count, sizeof(long long), hipMemcpyDeviceToHost, st));
         HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
@@ -1126,6 +1207,96 @@ int ssj_verify_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int
         total += k;
         done += n;
     } while (done < n_cand);
+    if (bad_id) {
+        *out_n = 0;
+        return set_error(SSJ_EINVAL, "candidate id out of range");
+    }
+    *out_n = total;
+    if (total > out_cap) return set_error(SSJ_ETRUNC, "result larger than out_cap");
+    return SSJ_OK;
+}
+
+}  // namespace
+
+int ssj_verify_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t n_cand,
+                   int sim, int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap,
+                   int64_t* out_n) {
+    return verify_host(ctx, coll, coll, cand, n_cand, sim, t_num, t_den, out, out_cap, out_n);
+}
+
+int ssj_verify_rs(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s, const ssj_pair* cand,
+                  int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* out,
+                  int64_t out_cap, int64_t* out_n) {
+    return verify_host(ctx, coll_r, coll_s, cand, n_cand, sim, t_num, t_den, out, out_cap, out_n);
+}
+
+int ssj_verify_groups(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s,
+                      const ssj_group* groups, int64_t n_groups, const int32_t* cand, int64_t n_cand,
+                      int sim, int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap,
+                      int64_t* out_n) {
+    int rc = check_ctx(ctx);
+    if (rc != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll_r)) != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll_s)) != SSJ_OK) return rc;
+    if (!valid_threshold(sim, t_num, t_den)) return set_error(SSJ_EINVAL, kThresholdError);
+    if (n_groups < 0 || n_cand < 0 || out_cap < 0) return set_error(SSJ_EINVAL, "negative size");
+    if (!out_n || (n_cand > 0 && !cand) || (n_groups > 0 && !groups) || (out_cap > 0 && !out))
+        return set_error(SSJ_EINVAL, "null host buffer");
+    // the group list must cover the candidates exactly, in order
+    int64_t prev = 0;
+    for (int64_t g = 0; g < n_groups; ++g) {
+        if (groups[g].end < prev || groups[g].end > n_cand)
+            return set_error(SSJ_EINVAL, "group ends must not decrease and must not pass n_cand");
+        prev = groups[g].end;
+    }
+    if (prev != n_cand) return set_error(SSJ_EINVAL, "the last group must end at n_cand");
+    *out_n = 0;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    // batches of whole groups (a group larger than a batch is split), each
+    // copied as its s ids and its groups with ends relative to the batch
+    const size_t per_cand = 4 + kBytesPerPair;
+    int64_t chunk = (int64_t)std::max<uint64_t>(1, ctx->budget / per_cand);
+    chunk = std::min<int64_t>(chunk, kMaxLaunchPairs);
+    std::vector<ssj_group> bg;
+    int64_t total = 0, c0 = 0, g = 0;
+    bool bad_id = false;
+    while (c0 < n_cand) {
+        const int64_t c1 = std::min<int64_t>(n_cand, c0 + chunk);
+        bg.clear();
+        while (g < n_groups && groups[g].end <= c0) ++g;  // empty groups before the batch
+        for (int64_t h = g; h < n_groups; ++h) {
+            const int64_t e = std::min<int64_t>(groups[h].end, c1);
+            if (e > c0 || bg.empty()) bg.push_back(ssj_group{groups[h].probe, (int32_t)(e - c0)});
+            if (groups[h].end >= c1) break;
+        }
+        const int64_t n = c1 - c0;
+        HIP_OR_FAIL(ctx, grow(ctx->d_sids, ctx->sids_cap, (size_t)n));
+        HIP_OR_FAIL(ctx, grow(ctx->d_groups, ctx->groups_cap, bg.size()));
+        HIP_OR_FAIL(ctx, grow(ctx->d_out, ctx->out_cap, (size_t)n));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->d_sids, cand + c0, (size_t)n * 4, hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->d_groups, bg.data(), bg.size() * sizeof(ssj_group),
+                                        hipMemcpyHostToDevice, st));
+        rc = enqueue_groups(ctx, coll_r, coll_s, ctx->d_groups, (int64_t)bg.size(), ctx->d_sids, n, sim,
+                            t_num, t_den, ctx->d_out, n, ctx->d_count, st);
+        if (rc != SSJ_OK) return rc;
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, ctx->d_count, sizeof(long long), hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+        const long long k = *ctx->h_count;
+        if (k < 0) {
+            bad_id = true;
+            break;
+        }
+        const int64_t room = std::max<int64_t>(0, out_cap - total);
+        const int64_t take = std::min<int64_t>(room, k);
+        if (take > 0) {
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(out + total, ctx->d_out, (size_t)take * 8, hipMemcpyDeviceToHost, st));
+            HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+        }
+        total += k;
+        c0 = c1;
+    }
     if (bad_id) {
         *out_n = 0;
         return set_error(SSJ_EINVAL, "candidate id out of range");

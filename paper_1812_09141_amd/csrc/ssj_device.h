@@ -48,12 +48,15 @@ struct alignas(256) Counters {
 
 // Everything one launch needs (passed by value as the kernel argument).
 struct LaunchArgs {
-    const int32_t* tok;                  // collection tokens
-    const uint4* heads;                  // per set: {start, len, tok0, tok1}, {tok2..tok5}
+    const int32_t* tok;                  // tokens of the collection of the r side of each pair
+    const uint4* heads;                  // its set records: {start, len, tok0, tok1}, {tok2..tok5}
+    const int32_t* tok_s;                // the same for the s side (an R-S join's second
+    const uint4* heads_s;                // collection; the same collection in a self-join)
     Counters* ctr;
     uint32_t* queues;                    // kQueues queues of qcap global pair indices
     uint32_t qcap;
-    uint32_t n_sets;
+    uint32_t n_sets;                     // sets of the r-side collection
+    uint32_t n_sets_s;                   // sets of the s-side collection
     int n_req;
     int defer_from;                      // first deferred class (kClasses: none)
     int inline_lanes;                    // lanes per pair in the in-order kernel
@@ -78,6 +81,11 @@ struct LaunchArgs {
 // array.
 hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start, const int32_t* d_tok,
                               uint4* d_heads, int64_t n_sets, hipStream_t st);
+// Flat pairs d_pairs[0..n) from grouped candidates: groups {probe id,
+// exclusive end into d_cand} and s ids d_cand (d_chunk_g: one word per 64
+// candidates of scratch).  Malformed groups give probe id -1.
+hipError_t launch_expand_groups(const int2* d_groups, int64_t n_groups, const int32_t* d_cand, int64_t n,
+                                uint32_t* d_chunk_g, int2* d_pairs, hipStream_t st);
 // The in-order kernel: every pair of a class below defer_from is verified
 // with inline_lanes lanes; the others are queued for launch_verify_deferred,
 // and so is every thread-per-pair merge still undecided after spill_iters

@@ -47,6 +47,7 @@ EXPORTED = (
     "ssj_stream_poll", "ssj_stream_times", "ssj_get_plan", "ssj_set_plan",
     "ssj_collection_info", "ssj_timing_enable", "ssj_timing_read", "ssj_verify_batch_device",
     "ssj_autotune", "ssj_verify_sim", "ssj_verify_device_sim", "ssj_stream_submit_sim",
+    "ssj_verify_rs", "ssj_verify_rs_device", "ssj_verify_groups", "ssj_verify_groups_device",
 )
 
 _NAMES = {
@@ -126,6 +127,10 @@ def load_library(path: str = LIB_PATH):
         "ssj_verify_sim": ([p, p, p, i64, c_int, i64, i64, p, i64, P(i64)], c_int),
         "ssj_verify_device_sim": ([p, p, p, i64, c_int, i64, i64, p, i64, p, p], c_int),
         "ssj_stream_submit_sim": ([p, p, p, i64, c_int, i64, i64, c_int, P(u64)], c_int),
+        "ssj_verify_rs": ([p, p, p, p, i64, c_int, i64, i64, p, i64, P(i64)], c_int),
+        "ssj_verify_rs_device": ([p, p, p, p, i64, c_int, i64, i64, p, i64, p, p], c_int),
+        "ssj_verify_groups": ([p, p, p, p, i64, p, i64, c_int, i64, i64, p, i64, P(i64)], c_int),
+        "ssj_verify_groups_device": ([p, p, p, p, i64, p, i64, c_int, i64, i64, p, i64, p, p], c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -245,6 +250,90 @@ def ssj_verify_device_sim(ctx, coll, d_cand: "torch.Tensor", sim, t_num: int, t_
                                               d_count.data_ptr(), ctypes.c_void_p(st.cuda_stream))
     if rc != SSJ_OK:
         _err(ctx, rc)
+
+
+def ssj_verify_rs(ctx, coll_r, coll_s, cand, sim, t_num: int, t_den: int,
+                  out_cap: Optional[int] = None) -> np.ndarray:
+    """R-S join verification: r ids index coll_r, s ids coll_s (host buffers)."""
+    c = _pairs(cand)
+    n = c.shape[0]
+    cap = n if out_cap is None else int(out_cap)
+    out = np.zeros((max(cap, 1), 2), dtype=np.int32)
+    out_n = ctypes.c_int64()
+    rc = load_library().ssj_verify_rs(ctx, coll_r, coll_s, c.ctypes.data if n else None, n,
+                                      sim_code(sim), int(t_num), int(t_den), out.ctypes.data, cap,
+                                      ctypes.byref(out_n))
+    if rc != SSJ_OK:
+        _err(ctx, rc, out_n.value)
+    return out[:out_n.value].copy()
+
+
+def ssj_verify_rs_device(ctx, coll_r, coll_s, d_cand: "torch.Tensor", sim, t_num: int, t_den: int,
+                         d_out: "torch.Tensor", d_count: "torch.Tensor", stream=None) -> None:
+    """ssj_verify_device_sim for an R-S join."""
+    assert d_cand.is_cuda and d_cand.dtype == torch.int32 and d_cand.is_contiguous()
+    if d_out is not None:
+        assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
+    assert d_count.is_cuda and d_count.dtype == torch.int64 and d_count.numel() >= 1
+    n = d_cand.numel() // 2
+    cap = d_out.numel() // 2 if d_out is not None else 0
+    st = stream if stream is not None else torch.cuda.current_stream(d_cand.device)
+    rc = load_library().ssj_verify_rs_device(ctx, coll_r, coll_s, d_cand.data_ptr() if n else None,
+                                             n, sim_code(sim), int(t_num), int(t_den),
+                                             d_out.data_ptr() if cap else None, cap,
+                                             d_count.data_ptr(), ctypes.c_void_p(st.cuda_stream))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def ssj_verify_groups(ctx, coll_r, coll_s, groups, cand, sim, t_num: int, t_den: int,
+                      out_cap: Optional[int] = None) -> np.ndarray:
+    """Grouped candidates: groups (n_groups, 2) int32 rows (probe id, exclusive end into
+    cand), cand the s ids (host buffers)."""
+    gr = np.ascontiguousarray(groups, dtype=np.int32).reshape(-1, 2)
+    c = np.ascontiguousarray(cand, dtype=np.int32).reshape(-1)
+    n = c.shape[0]
+    cap = n if out_cap is None else int(out_cap)
+    out = np.zeros((max(cap, 1), 2), dtype=np.int32)
+    out_n = ctypes.c_int64()
+    rc = load_library().ssj_verify_groups(ctx, coll_r, coll_s, gr.ctypes.data if gr.shape[0] else None,
+                                          gr.shape[0], c.ctypes.data if n else None, n, sim_code(sim),
+                                          int(t_num), int(t_den), out.ctypes.data, cap,
+                                          ctypes.byref(out_n))
+    if rc != SSJ_OK:
+        _err(ctx, rc, out_n.value)
+    return out[:out_n.value].copy()
+
+
+def ssj_verify_groups_device(ctx, coll_r, coll_s, d_groups: "torch.Tensor", d_cand: "torch.Tensor",
+                             sim, t_num: int, t_den: int, d_out: "torch.Tensor",
+                             d_count: "torch.Tensor", stream=None) -> None:
+    """Grouped candidates on the device: d_groups (n_groups, 2) int32, d_cand int32 s ids."""
+    assert d_groups.is_cuda and d_groups.dtype == torch.int32 and d_groups.is_contiguous()
+    assert d_cand.is_cuda and d_cand.dtype == torch.int32 and d_cand.is_contiguous()
+    if d_out is not None:
+        assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
+    assert d_count.is_cuda and d_count.dtype == torch.int64 and d_count.numel() >= 1
+    ng = d_groups.numel() // 2
+    n = d_cand.numel()
+    cap = d_out.numel() // 2 if d_out is not None else 0
+    st = stream if stream is not None else torch.cuda.current_stream(d_cand.device)
+    rc = load_library().ssj_verify_groups_device(
+        ctx, coll_r, coll_s, d_groups.data_ptr() if ng else None, ng, d_cand.data_ptr() if n else None,
+        n, sim_code(sim), int(t_num), int(t_den), d_out.data_ptr() if cap else None, cap,
+        d_count.data_ptr(), ctypes.c_void_p(st.cuda_stream))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def groups_of(pairs) -> tuple:
+    """Grouped form (groups, s ids) of flat pairs: one group per run of equal r."""
+    c = _pairs(pairs)
+    if c.shape[0] == 0:
+        return np.zeros((0, 2), np.int32), np.zeros(0, np.int32)
+    starts = np.flatnonzero(np.r_[True, c[1:, 0] != c[:-1, 0]])
+    ends = np.r_[starts[1:], c.shape[0]]
+    return np.stack([c[starts, 0], ends], axis=1).astype(np.int32), c[:, 1].copy()
 
 
 def ssj_stream_submit_sim(ctx, coll, cand, sim, t_num: int, t_den: int,

@@ -107,3 +107,16 @@ def test_plan_struct_matches_header():
                                                 re.sub(r"/\*.*?\*/", "", body, flags=re.S))]
     assert fields == [f[0] for f in ssj.ssj_plan._fields_]
     assert ctypes.sizeof(ssj.ssj_plan) == 4 * (7 + ssj.SSJ_N_CLASSES)
+
+
+def test_groups_of_runs():
+    """The binding's grouped form of flat pairs: one group per run of equal r,
+    ends exclusive, s ids in order (repeated probes make separate groups)."""
+    import numpy as np
+    import paper_1812_09141_amd.ssj as ssj
+    pairs = np.array([[3, 1], [3, 2], [1, 5], [1, 5], [3, 0], [7, 7]], np.int32)
+    g, s = ssj.groups_of(pairs)
+    assert g.tolist() == [[3, 2], [1, 4], [3, 5], [7, 6]]
+    assert s.tolist() == [1, 2, 5, 5, 0, 7]
+    g0, s0 = ssj.groups_of(np.zeros((0, 2), np.int32))
+    assert g0.shape == (0, 2) and s0.shape == (0,)

@@ -356,3 +356,61 @@ def test_sim_rejects_bad_input():
         oracle.verify(c.offsets, c.tokens, pairs, 1, 0, sim="overlap")
     with pytest.raises(oracle.OracleError):
         oracle.verify(c.offsets, c.tokens, pairs, 1, 2, sim="hamming")
+
+
+# --- R-S joins (Definition 1 with two collections) ---------------------------
+
+def _two_collections(rng):
+    """R and S drawn around shared base sets, so many cross pairs are similar."""
+    c = synth.near_duplicate_collection(rng, n_base=20, copies=4, max_size=15, universe=60,
+                                        change_frac=0.25)
+    sets = [c.tokens[c.offsets[i]:c.offsets[i + 1]].tolist() for i in range(c.n_sets)]
+    order = rng.permutation(len(sets))
+    cut = len(sets) // 3
+    r_sets = [sets[i] for i in order[:cut]]
+    s_sets = [sets[i] for i in order[cut:]]
+    return synth.collection_from_sets(r_sets), synth.collection_from_sets(s_sets)
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("sim", ["jaccard", "cosine", "dice", "overlap"])
+def test_rs_oracle_equals_brute(seed, sim):
+    rng = np.random.default_rng(7000 + seed)
+    R, S = _two_collections(rng)
+    pairs = np.stack([rng.integers(0, R.n_sets, 500), rng.integers(0, S.n_sets, 500)],
+                     axis=1).astype(np.int32)
+    ts = {"overlap": [(0, 1), (3, 1), (7, 1)]}.get(sim, [(0, 1), (1, 2), (3, 5), (4, 5), (1, 1)])
+    for tn, td in ts:
+        got = oracle.select_rs(R.offsets, R.tokens, S.offsets, S.tokens, pairs, tn, td, sim=sim)
+        dec = brute.brute_verify_rs(R.offsets, R.tokens, S.offsets, S.tokens, pairs, tn, td, sim)
+        want = pairs[np.array(dec, dtype=bool)]
+        assert np.array_equal(got, want), (sim, tn, td)
+
+
+def test_rs_with_r_equal_s_is_the_self_join():
+    rng = np.random.default_rng(7100)
+    c = synth.near_duplicate_collection(rng, n_base=25, copies=4, max_size=14, universe=60,
+                                        change_frac=0.25)
+    pairs = _random_pairs(rng, c.n_sets, 600)
+    for tn, td in [(1, 2), (3, 5), (4, 5)]:
+        a = oracle.select_rs(c.offsets, c.tokens, c.offsets, c.tokens, pairs, tn, td)
+        b = oracle.select(c.offsets, c.tokens, pairs, tn, td)
+        assert np.array_equal(a, b)
+
+
+def test_rs_is_not_symmetric_in_ids():
+    """An R-S pair names a set of R and a set of S: (0, 1) and (1, 0) are
+    different pairs when R and S differ."""
+    R = _coll([1, 2, 3], [7, 8])
+    S = _coll([9], [1, 2, 3])
+    got = oracle.select_rs(R.offsets, R.tokens, S.offsets, S.tokens, [[0, 1], [1, 0], [0, 0]], 1, 1)
+    assert got.tolist() == [[0, 1]]
+
+
+def test_rs_rejects_ids_outside_their_collection():
+    R = _coll([1, 2], [3, 4], [5, 6])
+    S = _coll([1, 2])
+    with pytest.raises(oracle.OracleError):
+        oracle.select_rs(R.offsets, R.tokens, S.offsets, S.tokens, [[2, 1]], 1, 2)
+    with pytest.raises(oracle.OracleError):
+        oracle.select_rs(R.offsets, R.tokens, S.offsets, S.tokens, [[3, 0]], 1, 2)
