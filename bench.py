@@ -48,6 +48,9 @@ def parse():
                          "collection (0 disables it)")
     ap.add_argument("--sweep", default="",
                     help="semicolon-separated plan specs to time as well (reported under 'sweep')")
+    ap.add_argument("--ppjoin", type=int, default=1,
+                    help="also verify the step's thresholds from PPJoin candidates (positional "
+                         "filter) and report both filters' CPU time")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (5 times), "
                          "the reference for HBM byte counters, and exit")
@@ -284,6 +287,33 @@ def main():
     dt_h = time.perf_counter() - t_h
     extra["host_api_pairs_per_s_pcie_inclusive"] = round(n_pairs * n_host / dt_h, 1)
     extra["host_api_counts_ok"] = bool(host_ok)
+
+    if args.ppjoin:
+        # the same join from fewer candidates: PPJoin's positional filter on top
+        # of the prefix and length filters (CPU, all host threads up to 16)
+        nthr = max(1, min(os.cpu_count() or 1, 16))
+        t1 = time.perf_counter()
+        for (tn, td) in w.thresholds:
+            cfilter.candidates(coll.offsets, coll.tokens, tn, td, n_threads=nthr)
+        t_ap = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        pcands = [cfilter.candidates(coll.offsets, coll.tokens, tn, td, n_threads=nthr, positional=True)
+                  for (tn, td) in w.thresholds]
+        t_pp = time.perf_counter() - t1
+        d_pc = [torch.from_numpy(c).to(dev) for c in pcands]
+        pbatch = [(d_pc[i], tn, td, d_outs[i], d_cnt[i:i + 1]) for i, (tn, td) in enumerate(w.thresholds)]
+
+        def step_pp():
+            S.ssj_verify_batch_device(ctx, h, pbatch)
+
+        n_pp = max(5, args.steps // 2)
+        dt = timed_steps(torch, step_pp, n_pp, 2)
+        n_pc = int(sum(c.shape[0] for c in pcands))
+        extra["ppjoin"] = {
+            "candidates_per_step": n_pc, "allpairs_candidates_per_step": n_pairs,
+            "ms_per_step": round(dt * 1e3 / n_pp, 4), "allpairs_ms_per_step": round(ms_per_step, 4),
+            "parity": bool(check()),
+            "filter_s": {"allpairs": round(t_ap, 4), "ppjoin": round(t_pp, 4), "threads": nthr}}
 
     stream = None
     if args.stream_batches > 0:

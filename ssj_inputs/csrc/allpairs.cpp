@@ -1,8 +1,9 @@
-// CPU candidate generator: the AllPairs prefix + length filter.
+// CPU candidate generators: the AllPairs prefix + length filter, and the
+// same with PPJoin's positional filter.
 //
 // This is the filtering phase that feeds verification (paper Sec. 2.2,
-// "Filters" and "Algorithm outline"; Sec. 3.1, AllPairs).  It is input
-// generation for the verification path, not part of it.
+// "Filters" and "Algorithm outline"; Sec. 3.1, AllPairs and PPJoin).  It is
+// input generation for the verification path, not part of it.
 //
 // Self-join over a collection whose sets are sorted by size (set id order ==
 // non-decreasing size).  For a threshold t = t_num / t_den > 0:
@@ -14,6 +15,16 @@
 // candidate (r, s), in order of first discovery.  The index holds every set's
 // prefix; restricting a list to ids below r is the same as building it
 // incrementally (probe, then insert), as the paper's self-join does.
+//
+// Positional filter (PPJoin; Sec. 2.2 "Filters"): the index also keeps the
+// position j of each prefix token w in s.  When probe r meets s through w at
+// its position i, every token the two sets share below w lies in both
+// prefixes and was met earlier in this probe, so the count A(s) of earlier
+// meetings is exactly that shared part, and the overlap is at most
+// A(s) + 1 + min(|r| - i - 1, |s| - j - 1).  If that is below the overlap
+// Jaccard t requires of the pair, ceil(t / (1 + t) * (|r| + |s|)) (Sec. 2.2,
+// the equivalent overlap), s is dropped for the rest of the probe.  The
+// remaining partners are emitted after the probe, in order of first meeting.
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
@@ -31,6 +42,8 @@ struct Index {
     std::vector<int32_t> tokens;
     std::vector<int64_t> list_off;  // token -> [list_off[w], list_off[w+1]) in list_ids
     std::vector<int32_t> list_ids;  // ascending set ids
+    std::vector<int32_t> list_pos;  // position of the token in that set (positional filter)
+    bool positional = false;
     uint64_t serial = 0;
 };
 
@@ -38,6 +51,13 @@ std::atomic<uint64_t> g_serial{1};
 
 inline int64_t need_of(const Index& ix, int64_t len) {
     return (ix.t_num * len + ix.t_den - 1) / ix.t_den;
+}
+
+// Overlap Jaccard t requires of sets of sizes a and b:
+// ceil(t_num (a + b) / (t_num + t_den)).
+inline int64_t pair_need(const Index& ix, int64_t a, int64_t b) {
+    const int64_t d = ix.t_num + ix.t_den;
+    return (ix.t_num * (a + b) + d - 1) / d;
 }
 
 inline int64_t prefix_of(const Index& ix, int64_t len) {
@@ -51,6 +71,8 @@ struct Stamps {
     uint64_t serial = 0;
     uint32_t cur = 0;
     std::vector<uint32_t> mark;
+    std::vector<int32_t> acc;       // positional filter: meetings so far, -1 once dropped
+    std::vector<int32_t> found;     // positional filter: partners in order of first meeting
     uint32_t next() {
         if (++cur == 0) {
             std::fill(mark.begin(), mark.end(), 0u);
@@ -65,6 +87,7 @@ thread_local Stamps tl_stamps;
 Stamps& stamps_for(const Index& ix) {
     if (tl_stamps.serial != ix.serial || (int64_t)tl_stamps.mark.size() != ix.n_sets) {
         tl_stamps.mark.assign((size_t)ix.n_sets, 0u);
+        tl_stamps.acc.assign(ix.positional ? (size_t)ix.n_sets : 0u, 0);
         tl_stamps.cur = 0;
         tl_stamps.serial = ix.serial;
     }
@@ -90,14 +113,42 @@ int64_t probe_one(const Index& ix, int64_t r, Stamps& st, Emit emit) {
         });
         // only sets indexed before r
         const int32_t* b = std::lower_bound(a, le, (int32_t)r);
-        for (const int32_t* q = a; q < b; ++q) {
+        if (!ix.positional) {
+            for (const int32_t* q = a; q < b; ++q) {
+                const int32_t s = *q;
+                if (mark[s] != stamp) {
+                    mark[s] = stamp;
+                    emit(s);
+                    ++n;
+                }
+            }
+            continue;
+        }
+        const int32_t* pos = ix.list_pos.data() + (a - ix.list_ids.data());
+        for (const int32_t* q = a; q < b; ++q, ++pos) {
             const int32_t s = *q;
             if (mark[s] != stamp) {
                 mark[s] = stamp;
+                st.acc[s] = 0;
+                st.found.push_back(s);
+            }
+            if (st.acc[s] < 0) continue;
+            const int64_t ls = ix.offsets[s + 1] - ix.offsets[s];
+            const int64_t bound = st.acc[s] + 1 + std::min(len - k - 1, ls - *pos - 1);
+            if (bound < pair_need(ix, len, ls))
+                st.acc[s] = -1;
+            else
+                ++st.acc[s];
+        }
+    }
+    if (ix.positional) {
+        for (const int32_t s : st.found) {
+            if (st.acc[s] > 0) {
                 emit(s);
                 ++n;
             }
         }
+        st.found.clear();
     }
     return n;
 }
@@ -130,9 +181,10 @@ extern "C" {
 
 struct ssjf_index;
 
-// Builds the prefix index.  Returns 0, or -1 on invalid arguments/no memory.
-int ssjf_build(const int64_t* offsets, int64_t n_sets, const int32_t* tokens, int64_t t_num,
-               int64_t t_den, ssjf_index** out) {
+// Builds the prefix index (positional != 0: with the positional filter).
+// Returns 0, or -1 on invalid arguments/no memory.
+int ssjf_build2(const int64_t* offsets, int64_t n_sets, const int32_t* tokens, int64_t t_num,
+                int64_t t_den, int positional, ssjf_index** out) {
     if (!out || !offsets || n_sets < 0 || n_sets >= INT32_MAX || t_den <= 0 || t_num <= 0 ||
         t_num > t_den)
         return -1;
@@ -142,6 +194,7 @@ int ssjf_build(const int64_t* offsets, int64_t n_sets, const int32_t* tokens, in
         ix->n_sets = n_sets;
         ix->t_num = t_num;
         ix->t_den = t_den;
+        ix->positional = positional != 0;
         ix->serial = g_serial.fetch_add(1);
         ix->offsets.assign(offsets, offsets + n_sets + 1);
         const int64_t nnz = offsets[n_sets] - offsets[0];
@@ -176,16 +229,27 @@ int ssjf_build(const int64_t* offsets, int64_t n_sets, const int32_t* tokens, in
         }
         for (int64_t w = 0; w < n_tok; ++w) ix->list_off[w + 1] += ix->list_off[w];
         ix->list_ids.resize((size_t)ix->list_off[n_tok]);
+        if (ix->positional) ix->list_pos.resize((size_t)ix->list_off[n_tok]);
         std::vector<int64_t> fill(ix->list_off.begin(), ix->list_off.end() - 1);
         for (int64_t i = 0; i < n_sets; ++i) {
             const int64_t b = offsets[i], p = prefix_of(*ix, offsets[i + 1] - b);
-            for (int64_t k = 0; k < p; ++k) ix->list_ids[(size_t)fill[tokens[b + k]]++] = (int32_t)i;
+            for (int64_t k = 0; k < p; ++k) {
+                const int64_t at = fill[tokens[b + k]]++;
+                ix->list_ids[(size_t)at] = (int32_t)i;
+                if (ix->positional) ix->list_pos[(size_t)at] = (int32_t)k;
+            }
         }
         *out = reinterpret_cast<ssjf_index*>(ix);
         return 0;
     } catch (const std::bad_alloc&) {
         return -1;
     }
+}
+
+// The AllPairs index (no positional filter).
+int ssjf_build(const int64_t* offsets, int64_t n_sets, const int32_t* tokens, int64_t t_num,
+               int64_t t_den, ssjf_index** out) {
+    return ssjf_build2(offsets, n_sets, tokens, t_num, t_den, 0, out);
 }
 
 void ssjf_free(ssjf_index* h) { delete reinterpret_cast<Index*>(h); }

@@ -1,8 +1,10 @@
-"""ctypes binding of the CPU AllPairs prefix + length filter (candidate generator).
+"""ctypes binding of the CPU candidate generators: the AllPairs prefix + length
+filter, optionally with PPJoin's positional filter.
 
-The filter is the paper's filtering phase (Sec. 2.2 "Filters", Sec. 3.1
-AllPairs); it produces the candidate pairs that verification consumes.  It is
-input generation: it holds no verification arithmetic.
+The filters are the paper's filtering phase (Sec. 2.2 "Filters", Sec. 3.1
+AllPairs and PPJoin); they produce the candidate pairs that verification
+consumes.  They are input generation: they decide no pair, they only drop pairs
+that cannot pass.
 """
 from __future__ import annotations
 
@@ -41,6 +43,8 @@ def _load():
     i64 = ctypes.c_int64
     lib.ssjf_build.argtypes = [p, i64, p, i64, i64, ctypes.POINTER(p)]
     lib.ssjf_build.restype = ctypes.c_int
+    lib.ssjf_build2.argtypes = [p, i64, p, i64, i64, ctypes.c_int, ctypes.POINTER(p)]
+    lib.ssjf_build2.restype = ctypes.c_int
     lib.ssjf_free.argtypes = [p]
     lib.ssjf_free.restype = None
     lib.ssjf_probe.argtypes = [p, i64, i64, p, i64, ctypes.POINTER(i64)]
@@ -59,16 +63,18 @@ def default_threads() -> int:
 
 
 class PrefixIndex:
-    """Prefix inverted index over one collection at one threshold."""
+    """Prefix inverted index over one collection at one threshold
+    (positional=True adds PPJoin's positional filter)."""
 
-    def __init__(self, offsets: np.ndarray, tokens: np.ndarray, t_num: int, t_den: int):
+    def __init__(self, offsets: np.ndarray, tokens: np.ndarray, t_num: int, t_den: int,
+                 positional: bool = False):
         lib = _load()
         self._off = np.ascontiguousarray(offsets, dtype=np.int64)
         self._tok = np.ascontiguousarray(tokens, dtype=np.int32)
         self.n_sets = int(self._off.shape[0] - 1)
         h = ctypes.c_void_p()
-        rc = lib.ssjf_build(self._off.ctypes.data, self.n_sets, self._tok.ctypes.data,
-                            int(t_num), int(t_den), ctypes.byref(h))
+        rc = lib.ssjf_build2(self._off.ctypes.data, self.n_sets, self._tok.ctypes.data,
+                             int(t_num), int(t_den), int(bool(positional)), ctypes.byref(h))
         if rc != 0:
             raise ValueError("ssjf_build rejected the collection or threshold")
         self._h = h
@@ -113,33 +119,36 @@ class PrefixIndex:
 
 
 def candidates(offsets: np.ndarray, tokens: np.ndarray, t_num: int, t_den: int,
-               n_threads: Optional[int] = None) -> np.ndarray:
-    ix = PrefixIndex(offsets, tokens, t_num, t_den)
+               n_threads: Optional[int] = None, positional: bool = False) -> np.ndarray:
+    ix = PrefixIndex(offsets, tokens, t_num, t_den, positional=positional)
     try:
         return ix.all_candidates(n_threads)
     finally:
         ix.close()
 
 
-def _cache_path(cfg: int, t_num: int, t_den: int) -> Optional[str]:
+def _cache_path(cfg: int, t_num: int, t_den: int, positional: bool = False) -> Optional[str]:
     from . import synth
     d = synth._cache_dir()
     if d is None:
         return None
-    return os.path.join(d, f"cand_cfg{cfg}_t{t_num}_{t_den}_v{synth.GEN_VERSION}_np{np.__version__}.npy")
+    kind = "ppj" if positional else "cand"
+    return os.path.join(d, f"{kind}_cfg{cfg}_t{t_num}_{t_den}_v{synth.GEN_VERSION}_np{np.__version__}.npy")
 
 
-def workload_candidates(cfg: int, t_num: int, t_den: int, use_cache: bool = True) -> np.ndarray:
-    """Candidates of a workload collection at one threshold (cached on disk)."""
+def workload_candidates(cfg: int, t_num: int, t_den: int, use_cache: bool = True,
+                        positional: bool = False) -> np.ndarray:
+    """Candidates of a workload collection at one threshold (cached on disk);
+    positional=True adds PPJoin's positional filter."""
     from . import synth
-    path = _cache_path(cfg, t_num, t_den) if use_cache else None
+    path = _cache_path(cfg, t_num, t_den, positional) if use_cache else None
     if path and os.path.exists(path):
         try:
             return np.load(path, allow_pickle=False)
         except Exception:
             pass
     c = synth.workload_collection(cfg, use_cache=use_cache)
-    cand = candidates(c.offsets, c.tokens, t_num, t_den)
+    cand = candidates(c.offsets, c.tokens, t_num, t_den, positional=positional)
     if path:
         tmp = path + f".tmp{os.getpid()}.npy"
         try:

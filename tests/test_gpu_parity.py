@@ -368,3 +368,24 @@ def test_config5_stream_batches(S, golden_dir):
             assert np.array_equal(got, want), (tn, td, b.shape[0])
     finally:
         S.ssj_shutdown(ctx)
+
+
+def test_ppjoin_candidates_same_join(S, ctx, golden_dir):
+    """Candidates thinned by PPJoin's positional filter give the manifest's join
+    result on the GPU (offline and long-set collections, every threshold)."""
+    import json
+    for cfg in (2, 3):
+        man = json.load(open(os.path.join(golden_dir, "manifest.json")))[str(cfg)]
+        c = synth.workload_collection(cfg)
+        h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+        try:
+            set_plan(S, ctx, None)
+            for (tn, td) in synth.WORKLOADS[cfg].thresholds:
+                cand = cfilter.workload_candidates(cfg, tn, td, positional=True)
+                m = man["thresholds"][f"{tn}/{td}"]
+                _log(f"ppjoin config{cfg} t={tn}/{td}: {cand.shape[0]} candidates")
+                got = run_host(S, ctx, h, cand, tn, td)
+                assert got.shape[0] == m["n_result"]
+                assert oracle.result_digest(got) == m["result_sha256"]
+        finally:
+            S.ssj_free_collection(ctx, h)

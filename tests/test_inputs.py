@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 
+import oracle
 from oracle import brute
 from ssj_inputs import filter as cfilter
 from ssj_inputs import synth
@@ -135,3 +136,68 @@ def test_serving_batches_cover_the_candidate_stream():
     if got.shape[0] > full.shape[0]:
         assert np.array_equal(got[full.shape[0]:], full[:got.shape[0] - full.shape[0]])
     assert all(b[1:] == (1, 2) for b in batches)
+
+
+# --- PPJoin's positional filter (Sec. 2.2 "Filters") -------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ppjoin_safe_and_inside_allpairs(seed):
+    """Every similar pair survives the positional filter (brute force), and
+    its candidates are the AllPairs candidates minus some, in the same order."""
+    rng = np.random.default_rng(800 + seed)
+    if seed % 2:
+        c = synth.near_duplicate_collection(rng, n_base=40, copies=5, max_size=18, universe=90,
+                                            change_frac=0.25)
+    else:
+        c = synth.random_collection(rng, n_sets=300, max_size=14, universe=70)
+    for (tn, td) in [(1, 3), (1, 2), (3, 5), (7, 10), (4, 5), (9, 10), (1, 1)]:
+        ap = cfilter.candidates(c.offsets, c.tokens, tn, td)
+        pp = cfilter.candidates(c.offsets, c.tokens, tn, td, positional=True)
+        want = brute.brute_join(c.offsets, c.tokens, tn, td)
+        ps = set(map(tuple, pp.tolist()))
+        assert all(p in ps for p in want), (tn, td)
+        # a subsequence of the AllPairs candidates
+        k = 0
+        for pair in ap.tolist():
+            if k < pp.shape[0] and pair == pp[k].tolist():
+                k += 1
+        assert k == pp.shape[0], (tn, td)
+
+
+def test_ppjoin_prunes_and_keeps_the_join():
+    """Fewer candidates on the offline collection's thresholds, same join result."""
+    c = synth.workload_collection(2)
+    for (tn, td) in synth.WORKLOADS[2].thresholds:
+        ap = cfilter.workload_candidates(2, tn, td)
+        pp = cfilter.workload_candidates(2, tn, td, positional=True)
+        assert pp.shape[0] < ap.shape[0]
+        a = oracle.sort_pairs(oracle.select(c.offsets, c.tokens, ap, tn, td, n_threads=8))
+        b = oracle.sort_pairs(oracle.select(c.offsets, c.tokens, pp, tn, td, n_threads=8))
+        assert np.array_equal(a, b), (tn, td)
+
+
+def test_ppjoin_hand_example():
+    """Two 10-token sets at t = 1/2: prefixes of 10 - 5 + 1 = 6 tokens, and a
+    pair needs overlap ceil(20 / 3) = 7.  x = {1..5, 50, 60..63} (set 0 by the
+    lexicographic order) and y = {50..59} (set 1, the probe) share only 50,
+    at position 0 of y and position 5 of x, both inside the prefixes, so
+    AllPairs keeps (1, 0); the positional bound is 0 + 1 + min(9, 4) = 5 < 7,
+    so PPJoin drops it.  With 50 at position 1 of x instead, the bound is
+    1 + min(9, 8) = 9 and both keep the pair."""
+    x = [1, 2, 3, 4, 5, 50, 60, 61, 62, 63]
+    y = list(range(50, 60))
+    c = synth.collection_from_sets([x, y])
+    assert c.tokens[:10].tolist() == x
+    assert cfilter.candidates(c.offsets, c.tokens, 1, 2).tolist() == [[1, 0]]
+    assert cfilter.candidates(c.offsets, c.tokens, 1, 2, positional=True).shape[0] == 0
+    x2 = [1, 50, 60, 61, 62, 63, 64, 65, 66, 67]
+    c2 = synth.collection_from_sets([x2, y])
+    assert c2.tokens[:10].tolist() == x2
+    assert cfilter.candidates(c2.offsets, c2.tokens, 1, 2, positional=True).tolist() == [[1, 0]]
+
+
+def test_ppjoin_thread_count_does_not_change_output():
+    c = synth.workload_collection(1)
+    a = cfilter.candidates(c.offsets, c.tokens, 3, 5, n_threads=1, positional=True)
+    b = cfilter.candidates(c.offsets, c.tokens, 3, 5, n_threads=8, positional=True)
+    assert np.array_equal(a, b)
