@@ -200,6 +200,31 @@ int ssj_verify_groups_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_col
                              int64_t out_cap, int64_t* d_count, void* hip_stream);
 
 /*
+ * The whole self-join on the GPU: candidate generation by the prefix filter
+ * with the length filter (Sec. 2.2 "Filters"; Sec. 3.1 AllPairs) and, with
+ * positional != 0, PPJoin's positional filter -- the filtering phase the
+ * paper leaves on the CPU and names as future work for the GPU -- followed by
+ * the verification of ssj_verify_device (Jaccard t = t_num / t_den, which
+ * must be above 0).  Each similar pair {x, y} (x != y) is found once, as
+ * (r, s) with r the larger set id.  The candidates are the same set as those
+ * of the CPU prefix filter at the same threshold (with the positional filter:
+ * of the CPU PPJoin filter), produced in probe order.
+ * ssj_candidates_device writes the candidates themselves (*d_count: their
+ * number, possibly above out_cap; then out_cap of them are written);
+ * ssj_join_device verifies them into d_out / d_count like
+ * ssj_verify_device; ssj_join does the same with host output buffers.  All
+ * three synchronise the stream twice to size their buffers (the prefix index
+ * and the candidate count) and share the context's device scratch.
+ */
+int ssj_candidates_device(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_den,
+                          int positional, ssj_pair* d_out, int64_t out_cap, int64_t* d_count,
+                          void* hip_stream);
+int ssj_join_device(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_den, int positional,
+                    ssj_pair* d_out, int64_t out_cap, int64_t* d_count, void* hip_stream);
+int ssj_join(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_den, int positional,
+             ssj_pair* out, int64_t out_cap, int64_t* out_n);
+
+/*
  * Streaming (continuous batching) -- the paper's host/device pipeline
  * (Sec. 3.2, threads H0/H1/H2; Sec. 4.1.2) as a request loop.
  * submit copies cand into library-owned pinned staging and returns a ticket

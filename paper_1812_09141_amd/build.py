@@ -8,7 +8,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libssj.so")
-SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "runtime.hip")]
+SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "filter.hip"),
+           os.path.join(CSRC, "runtime.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -1,0 +1,225 @@
+// Candidate generation on the GPU: the prefix filter of a self-join, with the
+// length filter and, optionally, PPJoin's positional filter (paper Sec. 2.2
+// "Filters" and "Algorithm outline"; Sec. 3.1 AllPairs and PPJoin).  The
+// paper keeps filtering on the CPU and names moving it to the GPU as future
+// work; this is that step, built from the same definitions as the CPU
+// filters of the candidate generator.
+//
+// For t = num / den > 0 a set x of |x| tokens has prefix length
+// p(x) = |x| - ceil(t |x|) + 1.  Two sets with Jaccard similarity >= t share a
+// token within their prefixes (prefix-filter lemma).  The index holds every
+// prefix token as a 64-bit key (token << 32 | set id) with its position,
+// sorted, so the list of a token is a contiguous range ordered by set id.
+// Every prefix position (r, i) of every set r is one probe: it walks the list
+// of its token up to set r (each unordered pair is found from its larger id)
+// and meets each set s there at the token's position j in s.
+//
+//  * A pair is emitted once, at its first meeting: when the prefixes hold no
+//    common token before positions i and j.
+//  * The length filter drops pairs with |s| < ceil(t |r|) or
+//    |r| < ceil(t |s|).
+//  * With the positional filter, every meeting of the two prefixes from the
+//    first one on is checked in token order: at a meeting with A earlier
+//    meetings at positions (x, y) the overlap is at most
+//    A + 1 + min(|r| - x - 1, |s| - y - 1), and a pair whose bound falls
+//    below the overlap it needs, ceil(num (|r| + |s|) / (num + den)), is
+//    dropped.  This is the candidate set of the CPU PPJoin filter.
+//
+// Two passes over the probes (count, then fill at the exclusive prefix sum of
+// the counts) write the candidates in probe order with no atomics.
+#include <hipcub/hipcub.hpp>
+
+#include "ssj_device.h"
+
+namespace ssj {
+namespace {
+
+struct Thr {
+    unsigned long long num, den;
+};
+
+__device__ __forceinline__ uint32_t need_of(uint32_t len, Thr t) {
+    return (uint32_t)((t.num * len + t.den - 1ull) / t.den);
+}
+
+__device__ __forceinline__ uint32_t prefix_of(uint32_t len, Thr t) {
+    const uint32_t need = need_of(len, t);
+    return need > len ? 0u : len - need + 1u;
+}
+
+__global__ void k_prefix_len(const uint4* __restrict__ heads, uint32_t n, Thr t,
+                             uint32_t* __restrict__ plen) {
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x)
+        plen[x] = prefix_of(heads[2 * x].y, t);
+}
+
+// Index entries of set x at pre[x] .. pre[x] + plen[x]: sort key (token << 32
+// | x) and position; the probe arrays hold (x, position) in the same order.
+__global__ void k_prefix_entries(const uint4* __restrict__ heads, const int32_t* __restrict__ tok,
+                                 uint32_t n, const uint32_t* __restrict__ plen,
+                                 const uint32_t* __restrict__ pre, unsigned long long* __restrict__ keys,
+                                 uint32_t* __restrict__ pos, uint2* __restrict__ probes) {
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+        const uint32_t start = heads[2 * x].x, p = plen[x], base = pre[x];
+        for (uint32_t j = 0; j < p; ++j) {
+            keys[base + j] = ((unsigned long long)(uint32_t)tok[start + j] << 32) | x;
+            pos[base + j] = j;
+            probes[base + j] = make_uint2(x, j);
+        }
+    }
+}
+
+// First index in keys[0, m) not below v.
+__device__ __forceinline__ uint32_t lower_bound64(const unsigned long long* __restrict__ keys,
+                                                  uint32_t m, unsigned long long v) {
+    uint32_t lo = 0, hi = m;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2u;
+        if (keys[mid] < v)
+            lo = mid + 1u;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Whether the meeting of r and s at prefix positions (i, j) is their first
+// and, with POS, whether every meeting of their prefixes passes the
+// positional bound.
+template <bool POS>
+__device__ bool keep_pair(const int32_t* __restrict__ R, uint32_t lr, uint32_t pr,
+                          const int32_t* __restrict__ S, uint32_t ls, uint32_t ps, uint32_t i,
+                          uint32_t j, Thr t) {
+    // first meeting: no common token in R[0, i) and S[0, j)
+    uint32_t x = 0, y = 0;
+    while (x < i && y < j) {
+        const int32_t a = R[x], b = S[y];
+        if (a == b) return false;
+        x += a < b ? 1u : 0u;
+        y += b < a ? 1u : 0u;
+    }
+    if constexpr (POS) {
+        const uint32_t alpha = (uint32_t)((t.num * ((unsigned long long)lr + ls) + t.num + t.den - 1ull) /
+                                          (t.num + t.den));
+        uint32_t A = 0;
+        x = i;
+        y = j;
+        while (x < pr && y < ps) {
+            const int32_t a = R[x], b = S[y];
+            if (a == b) {
+                if (A + 1u + min(lr - x - 1u, ls - y - 1u) < alpha) return false;
+                ++A;
+                ++x;
+                ++y;
+            } else {
+                x += a < b ? 1u : 0u;
+                y += b < a ? 1u : 0u;
+            }
+        }
+    }
+    return true;
+}
+
+template <bool FILL, bool POS>
+__global__ void k_probe(const uint4* __restrict__ heads, const int32_t* __restrict__ tok,
+                        const uint2* __restrict__ probes, uint32_t m,
+                        const unsigned long long* __restrict__ keys, const uint32_t* __restrict__ pos,
+                        const uint32_t* __restrict__ plen, Thr t, uint32_t* __restrict__ counts,
+                        const uint32_t* __restrict__ off, int2* __restrict__ out,
+                        unsigned long long cap) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+        const uint2 pe = probes[e];
+        const uint32_t r = pe.x, i = pe.y;
+        const uint4 hr = heads[2 * r];
+        const uint32_t lr = hr.y, pr = plen[r];
+        const int32_t* R = tok + hr.x;
+        const unsigned long long w = (unsigned long long)(uint32_t)R[i] << 32;
+        const uint32_t lo = lower_bound64(keys, m, w);
+        const uint32_t hi = lower_bound64(keys, m, w | r);  // sets below r
+        const uint32_t need_r = need_of(lr, t);
+        uint32_t c = 0;
+        const unsigned long long base = FILL ? off[e] : 0ull;
+        for (uint32_t q = lo; q < hi; ++q) {
+            const uint32_t s = (uint32_t)keys[q];
+            const uint4 hs = heads[2 * s];
+            const uint32_t ls = hs.y;
+            if (ls < need_r || lr < need_of(ls, t)) continue;
+            if (!keep_pair<POS>(R, lr, pr, tok + hs.x, ls, plen[s], i, pos[q], t)) continue;
+            if constexpr (FILL) {
+                if (base + c < cap) out[base + c] = make_int2((int)r, (int)s);
+            }
+            ++c;
+        }
+        if constexpr (!FILL) counts[e] = c;
+    }
+}
+
+int blocks_for(uint64_t n) {
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>((n + kBlock - 1) / kBlock, 65536));
+}
+
+}  // namespace
+
+hipError_t filter_prefix_lengths(const uint4* d_heads, uint32_t n, uint64_t num, uint64_t den,
+                                 uint32_t* d_plen, uint32_t* d_pre, void* d_temp, size_t* temp_bytes,
+                                 hipStream_t st) {
+    if (!d_temp) return hipcub::DeviceScan::ExclusiveSum(nullptr, *temp_bytes, d_plen, d_pre, n + 1, st);
+    hipLaunchKernelGGL(k_prefix_len, dim3(blocks_for(n)), dim3(kBlock), 0, st, d_heads, n, Thr{num, den},
+                       d_plen);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // d_plen[n] is 0, so d_pre[n] is the number of index entries
+    e = hipMemsetAsync(d_plen + n, 0, sizeof(uint32_t), st);
+    if (e != hipSuccess) return e;
+    return hipcub::DeviceScan::ExclusiveSum(d_temp, *temp_bytes, d_plen, d_pre, n + 1, st);
+}
+
+hipError_t filter_build_index(const uint4* d_heads, const int32_t* d_tok, uint32_t n, uint32_t m,
+                              const uint32_t* d_plen, const uint32_t* d_pre, unsigned long long* d_keys,
+                              uint32_t* d_pos, unsigned long long* d_keys2, uint32_t* d_pos2, uint2* d_probes,
+                              void* d_temp, size_t* temp_bytes, hipStream_t st) {
+    if (!d_temp)
+        return hipcub::DeviceRadixSort::SortPairs(nullptr, *temp_bytes, d_keys, d_keys2, d_pos, d_pos2, m, 0,
+                                                  64, st);
+    hipLaunchKernelGGL(k_prefix_entries, dim3(blocks_for(n)), dim3(kBlock), 0, st, d_heads, d_tok, n, d_plen,
+                       d_pre, d_keys, d_pos, d_probes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipcub::DeviceRadixSort::SortPairs(d_temp, *temp_bytes, d_keys, d_keys2, d_pos, d_pos2, m, 0, 64,
+                                              st);
+}
+
+hipError_t filter_probe(const uint4* d_heads, const int32_t* d_tok, const uint2* d_probes, uint32_t m,
+                        const unsigned long long* d_keys, const uint32_t* d_pos, const uint32_t* d_plen,
+                        uint64_t num, uint64_t den, bool positional, uint32_t* d_counts,
+                        const uint32_t* d_off, int2* d_out, uint64_t cap, hipStream_t st) {
+    const Thr t{num, den};
+    const dim3 g(blocks_for(m)), b(kBlock);
+    if (!d_off) {
+        if (positional)
+            hipLaunchKernelGGL((k_probe<false, true>), g, b, 0, st, d_heads, d_tok, d_probes, m, d_keys, d_pos,
+                               d_plen, t, d_counts, nullptr, nullptr, 0ull);
+        else
+            hipLaunchKernelGGL((k_probe<false, false>), g, b, 0, st, d_heads, d_tok, d_probes, m, d_keys, d_pos,
+                               d_plen, t, d_counts, nullptr, nullptr, 0ull);
+    } else {
+        if (positional)
+            hipLaunchKernelGGL((k_probe<true, true>), g, b, 0, st, d_heads, d_tok, d_probes, m, d_keys, d_pos,
+                               d_plen, t, nullptr, d_off, d_out, (unsigned long long)cap);
+        else
+            hipLaunchKernelGGL((k_probe<true, false>), g, b, 0, st, d_heads, d_tok, d_probes, m, d_keys, d_pos,
+                               d_plen, t, nullptr, d_off, d_out, (unsigned long long)cap);
+    }
+    return hipGetLastError();
+}
+
+hipError_t filter_scan_counts(uint32_t* d_counts, uint32_t* d_off, uint32_t m, void* d_temp, size_t* temp_bytes,
+                              hipStream_t st) {
+    // d_counts[m] is 0, so d_off[m] is the number of candidates
+    if (!d_temp) return hipcub::DeviceScan::ExclusiveSum(nullptr, *temp_bytes, d_counts, d_off, m + 1, st);
+    hipError_t e = hipMemsetAsync(d_counts + m, 0, sizeof(uint32_t), st);
+    if (e != hipSuccess) return e;
+    return hipcub::DeviceScan::ExclusiveSum(d_temp, *temp_bytes, d_counts, d_off, m + 1, st);
+}
+
+}  // namespace ssj

@@ -184,6 +184,16 @@ struct ssj_ctx {
     size_t pairs_cap = 0;
     uint32_t* d_chunk_g = nullptr;
     size_t chunk_g_cap = 0;
+    // GPU candidate generation (prefix index and probe counts)
+    struct {
+        uint32_t *plen = nullptr, *pre = nullptr, *pos = nullptr, *pos2 = nullptr, *counts = nullptr,
+                 *off = nullptr;
+        unsigned long long *keys = nullptr, *keys2 = nullptr;
+        uint2* probes = nullptr;
+        unsigned char* temp = nullptr;
+        size_t plen_cap = 0, pre_cap = 0, pos_cap = 0, pos2_cap = 0, counts_cap = 0, off_cap = 0,
+               keys_cap = 0, keys2_cap = 0, probes_cap = 0, temp_cap = 0;
+    } flt;
     std::atomic<bool> failed{false};
     std::vector<ssj_coll*> colls;
     std::map<GraphKey, GraphEntry> graphs;
@@ -872,6 +882,10 @@ int ssj_shutdown(ssj_ctx* ctx) {
         if (ctx->d_sids) (void)hipFree(ctx->d_sids);
         if (ctx->d_pairs) (void)hipFree(ctx->d_pairs);
         if (ctx->d_chunk_g) (void)hipFree(ctx->d_chunk_g);
+        for (void* q : {(void*)ctx->flt.plen, (void*)ctx->flt.pre, (void*)ctx->flt.pos, (void*)ctx->flt.pos2,
+                        (void*)ctx->flt.counts, (void*)ctx->flt.off, (void*)ctx->flt.keys,
+                        (void*)ctx->flt.keys2, (void*)ctx->flt.probes, (void*)ctx->flt.temp})
+            if (q) (void)hipFree(q);
         if (ctx->d_count) (void)hipFree(ctx->d_count);
         if (ctx->h_count) (void)hipHostFree(ctx->h_count);
         for (auto& kv : ctx->graphs) {
@@ -1150,6 +1164,136 @@ int ssj_verify_groups_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_col
     return enqueue_groups(ctx, coll_r, coll_s, reinterpret_cast<const int2*>(d_groups), n_groups, d_cand,
                           n_cand, sim, t_num, t_den, reinterpret_cast<int2*>(d_out), out_cap,
                           reinterpret_cast<long long*>(d_count), (hipStream_t)hip_stream);
+}
+
+namespace {
+
+// GPU prefix-filter candidates of coll at t = t_num / t_den into ctx->d_pairs;
+// *n_cand receives their number (two host synchronisations on st: the index
+// size and the candidate count).  ctx->mu held.
+int gpu_candidates(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_den, bool positional,
+                   hipStream_t st, int64_t* n_cand) {
+    auto& F = ctx->flt;
+    const uint32_t n = (uint32_t)coll->n_sets;
+    const uint64_t num = (uint64_t)t_num, den = (uint64_t)t_den;
+    *n_cand = 0;
+    if (n == 0) return SSJ_OK;
+    auto temp_for = [&](size_t need) -> hipError_t { return grow(F.temp, F.temp_cap, std::max<size_t>(need, 1)); };
+    HIP_OR_FAIL(ctx, grow(F.plen, F.plen_cap, (size_t)n + 1));
+    HIP_OR_FAIL(ctx, grow(F.pre, F.pre_cap, (size_t)n + 1));
+    size_t tb = 0;
+    HIP_OR_FAIL(ctx, ssj::filter_prefix_lengths(coll->d_heads, n, num, den, F.plen, F.pre, nullptr, &tb, st));
+    HIP_OR_FAIL(ctx, temp_for(tb));
+    tb = F.temp_cap;
+    HIP_OR_FAIL(ctx, ssj::filter_prefix_lengths(coll->d_heads, n, num, den, F.plen, F.pre, F.temp, &tb, st));
+    uint32_t m = 0;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, F.pre + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+    std::memcpy(&m, ctx->h_count, sizeof(uint32_t));
+    if (m == 0) return SSJ_OK;
+    HIP_OR_FAIL(ctx, grow(F.keys, F.keys_cap, m));
+    HIP_OR_FAIL(ctx, grow(F.keys2, F.keys2_cap, m));
+    HIP_OR_FAIL(ctx, grow(F.pos, F.pos_cap, m));
+    HIP_OR_FAIL(ctx, grow(F.pos2, F.pos2_cap, m));
+    HIP_OR_FAIL(ctx, grow(F.probes, F.probes_cap, m));
+    HIP_OR_FAIL(ctx, grow(F.counts, F.counts_cap, (size_t)m + 1));
+    HIP_OR_FAIL(ctx, grow(F.off, F.off_cap, (size_t)m + 1));
+    tb = 0;
+    HIP_OR_FAIL(ctx, ssj::filter_build_index(coll->d_heads, coll->d_tok, n, m, F.plen, F.pre, F.keys, F.pos,
+                                             F.keys2, F.pos2, F.probes, nullptr, &tb, st));
+    size_t tb2 = 0;
+    HIP_OR_FAIL(ctx, ssj::filter_scan_counts(F.counts, F.off, m, nullptr, &tb2, st));
+    HIP_OR_FAIL(ctx, temp_for(std::max(tb, tb2)));
+    tb = F.temp_cap;
+    HIP_OR_FAIL(ctx, ssj::filter_build_index(coll->d_heads, coll->d_tok, n, m, F.plen, F.pre, F.keys, F.pos,
+                                             F.keys2, F.pos2, F.probes, F.temp, &tb, st));
+    HIP_OR_FAIL(ctx, ssj::filter_probe(coll->d_heads, coll->d_tok, F.probes, m, F.keys2, F.pos2, F.plen, num,
+                                       den, positional, F.counts, nullptr, nullptr, 0, st));
+    tb = F.temp_cap;
+    HIP_OR_FAIL(ctx, ssj::filter_scan_counts(F.counts, F.off, m, F.temp, &tb, st));
+    uint32_t total = 0;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, F.off + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+    std::memcpy(&total, ctx->h_count, sizeof(uint32_t));
+    if ((int64_t)total > kMaxLaunchPairs)
+        return set_error(SSJ_ENOMEM, "more than 2^31 candidates");
+    HIP_OR_FAIL(ctx, grow(ctx->d_pairs, ctx->pairs_cap, std::max<size_t>(total, 1)));
+    HIP_OR_FAIL(ctx, ssj::filter_probe(coll->d_heads, coll->d_tok, F.probes, m, F.keys2, F.pos2, F.plen, num,
+                                       den, positional, nullptr, F.off, ctx->d_pairs, total, st));
+    *n_cand = total;
+    return SSJ_OK;
+}
+
+int check_filter_args(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_den) {
+    int rc = check_ctx(ctx);
+    if (rc != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
+    if (!valid_threshold(SSJ_SIM_JACCARD, t_num, t_den) || t_num == 0)
+        return set_error(SSJ_EINVAL, "the prefix filter needs 0 < t_num <= t_den < 2^31");
+    return SSJ_OK;
+}
+
+}  // namespace
+
+int ssj_candidates_device(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_den, int positional,
+                          ssj_pair* d_out, int64_t out_cap, int64_t* d_count, void* hip_stream) {
+    int rc = check_filter_args(ctx, coll, t_num, t_den);
+    if (rc != SSJ_OK) return rc;
+    if (out_cap < 0 || !d_count || (out_cap > 0 && !d_out)) return set_error(SSJ_EINVAL, "bad output buffer");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    int64_t n = 0;
+    if ((rc = gpu_candidates(ctx, coll, t_num, t_den, positional != 0, st, &n)) != SSJ_OK) return rc;
+    const int64_t k = std::min(n, out_cap);
+    if (k > 0) HIP_OR_FAIL(ctx, hipMemcpyAsync(d_out, ctx->d_pairs, (size_t)k * 8, hipMemcpyDeviceToDevice, st));
+    *ctx->h_count = n;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(d_count, ctx->h_count, sizeof(long long), hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(st));  // h_count is reused
+    return SSJ_OK;
+}
+
+int ssj_join_device(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_den, int positional,
+                    ssj_pair* d_out, int64_t out_cap, int64_t* d_count, void* hip_stream) {
+    int rc = check_filter_args(ctx, coll, t_num, t_den);
+    if (rc != SSJ_OK) return rc;
+    if (out_cap < 0 || !d_count || (out_cap > 0 && !d_out)) return set_error(SSJ_EINVAL, "bad output buffer");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    int64_t n = 0;
+    if ((rc = gpu_candidates(ctx, coll, t_num, t_den, positional != 0, st, &n)) != SSJ_OK) return rc;
+    Req r{ctx->d_pairs, n, t_num, t_den, reinterpret_cast<int2*>(d_out), out_cap,
+          reinterpret_cast<long long*>(d_count), SSJ_SIM_JACCARD};
+    return enqueue_launch(ctx, coll, ctx->def, &r, 1, st, ctx->plan);
+}
+
+int ssj_join(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_den, int positional, ssj_pair* out,
+             int64_t out_cap, int64_t* out_n) {
+    int rc = check_filter_args(ctx, coll, t_num, t_den);
+    if (rc != SSJ_OK) return rc;
+    if (out_cap < 0 || !out_n || (out_cap > 0 && !out)) return set_error(SSJ_EINVAL, "bad output buffer");
+    *out_n = 0;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    int64_t n = 0;
+    if ((rc = gpu_candidates(ctx, coll, t_num, t_den, positional != 0, st, &n)) != SSJ_OK) return rc;
+    HIP_OR_FAIL(ctx, grow(ctx->d_out, ctx->out_cap, (size_t)std::max<int64_t>(n, 1)));
+    Req r{ctx->d_pairs, n, t_num, t_den, ctx->d_out, n, ctx->d_count, SSJ_SIM_JACCARD};
+    if ((rc = enqueue_launch(ctx, coll, ctx->def, &r, 1, st, ctx->plan)) != SSJ_OK) return rc;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, ctx->d_count, sizeof(long long), hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+    const long long k = *ctx->h_count;
+    if (k < 0) return set_error(SSJ_EDEVICE, "id error in generated candidates");
+    const int64_t take = std::min<int64_t>(k, out_cap);
+    if (take > 0) {
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(out, ctx->d_out, (size_t)take * 8, hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+    }
+    *out_n = k;
+    if (k > out_cap) return set_error(SSJ_ETRUNC, "result larger than out_cap");
+    return SSJ_OK;
 }
 
 int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,

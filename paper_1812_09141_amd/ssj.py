@@ -48,6 +48,7 @@ EXPORTED = (
     "ssj_collection_info", "ssj_timing_enable", "ssj_timing_read", "ssj_verify_batch_device",
     "ssj_autotune", "ssj_verify_sim", "ssj_verify_device_sim", "ssj_stream_submit_sim",
     "ssj_verify_rs", "ssj_verify_rs_device", "ssj_verify_groups", "ssj_verify_groups_device",
+    "ssj_candidates_device", "ssj_join_device", "ssj_join",
 )
 
 _NAMES = {
@@ -131,6 +132,9 @@ def load_library(path: str = LIB_PATH):
         "ssj_verify_rs_device": ([p, p, p, p, i64, c_int, i64, i64, p, i64, p, p], c_int),
         "ssj_verify_groups": ([p, p, p, p, i64, p, i64, c_int, i64, i64, p, i64, P(i64)], c_int),
         "ssj_verify_groups_device": ([p, p, p, p, i64, p, i64, c_int, i64, i64, p, i64, p, p], c_int),
+        "ssj_candidates_device": ([p, p, i64, i64, c_int, p, i64, p, p], c_int),
+        "ssj_join_device": ([p, p, i64, i64, c_int, p, i64, p, p], c_int),
+        "ssj_join": ([p, p, i64, i64, c_int, p, i64, P(i64)], c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -324,6 +328,55 @@ def ssj_verify_groups_device(ctx, coll_r, coll_s, d_groups: "torch.Tensor", d_ca
         d_count.data_ptr(), ctypes.c_void_p(st.cuda_stream))
     if rc != SSJ_OK:
         _err(ctx, rc)
+
+
+def ssj_candidates_device(ctx, coll, t_num: int, t_den: int, positional: bool,
+                          d_out: "torch.Tensor", d_count: "torch.Tensor", stream=None) -> None:
+    """GPU prefix-filter candidates (with PPJoin's positional filter if positional)."""
+    if d_out is not None:
+        assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
+    assert d_count.is_cuda and d_count.dtype == torch.int64 and d_count.numel() >= 1
+    cap = d_out.numel() // 2 if d_out is not None else 0
+    st = stream if stream is not None else torch.cuda.current_stream(d_count.device)
+    rc = load_library().ssj_candidates_device(ctx, coll, int(t_num), int(t_den), int(bool(positional)),
+                                              d_out.data_ptr() if cap else None, cap, d_count.data_ptr(),
+                                              ctypes.c_void_p(st.cuda_stream))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def ssj_join_device(ctx, coll, t_num: int, t_den: int, positional: bool, d_out: "torch.Tensor",
+                    d_count: "torch.Tensor", stream=None) -> None:
+    """The whole self-join on the GPU (filter, then verification)."""
+    if d_out is not None:
+        assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
+    assert d_count.is_cuda and d_count.dtype == torch.int64 and d_count.numel() >= 1
+    cap = d_out.numel() // 2 if d_out is not None else 0
+    st = stream if stream is not None else torch.cuda.current_stream(d_count.device)
+    rc = load_library().ssj_join_device(ctx, coll, int(t_num), int(t_den), int(bool(positional)),
+                                        d_out.data_ptr() if cap else None, cap, d_count.data_ptr(),
+                                        ctypes.c_void_p(st.cuda_stream))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def ssj_join(ctx, coll, t_num: int, t_den: int, positional: bool = True,
+             out_cap: Optional[int] = None) -> np.ndarray:
+    """The whole self-join on the GPU, results in host memory (grows the buffer once
+    when out_cap is too small)."""
+    cap = 1 << 16 if out_cap is None else int(out_cap)
+    for _ in range(2):
+        out = np.zeros((max(cap, 1), 2), dtype=np.int32)
+        out_n = ctypes.c_int64()
+        rc = load_library().ssj_join(ctx, coll, int(t_num), int(t_den), int(bool(positional)),
+                                     out.ctypes.data, cap, ctypes.byref(out_n))
+        if rc == SSJ_ETRUNC and out_cap is None:
+            cap = int(out_n.value)
+            continue
+        if rc != SSJ_OK:
+            _err(ctx, rc, out_n.value)
+        return out[:out_n.value].copy()
+    _err(ctx, SSJ_ETRUNC, out_n.value)
 
 
 def groups_of(pairs) -> tuple:
