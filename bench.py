@@ -315,6 +315,28 @@ def main():
             "parity": bool(check()),
             "filter_s": {"allpairs": round(t_ap, 4), "ppjoin": round(t_pp, 4), "threads": nthr}}
 
+    if args.ppjoin:
+        # the whole join on the GPU: candidates from the prefix, length and
+        # positional filters built on the device, then verified (two host
+        # synchronisations per call size its buffers)
+        d_jout = [torch.empty((max(man["thresholds"][f"{tn}/{td}"]["n_result"], 1), 2), dtype=torch.int32,
+                              device=dev) for (tn, td) in w.thresholds]
+        d_jcnt = torch.zeros(len(w.thresholds), dtype=torch.int64, device=dev)
+
+        def step_join():
+            for i, (tn, td) in enumerate(w.thresholds):
+                S.ssj_join_device(ctx, h, tn, td, True, d_jout[i], d_jcnt[i:i + 1])
+
+        n_j = max(3, args.steps // 10)
+        dt = timed_steps(torch, step_join, n_j, 1)
+        cnt = d_jcnt.cpu().numpy()
+        join_ok = all(int(cnt[i]) == man["thresholds"][f"{tn}/{td}"]["n_result"] and
+                      pairs_digest(d_jout[i][:int(cnt[i])].cpu().numpy()) ==
+                      man["thresholds"][f"{tn}/{td}"]["result_sha256"]
+                      for i, (tn, td) in enumerate(w.thresholds))
+        extra["gpu_join"] = {"ms_per_step": round(dt * 1e3 / n_j, 4), "parity": bool(join_ok),
+                             "cpu_filter_ms_per_step": round(extra["ppjoin"]["filter_s"]["ppjoin"] * 1e3, 3)}
+
     stream = None
     if args.stream_batches > 0:
         from paper_1812_09141_amd import serving
