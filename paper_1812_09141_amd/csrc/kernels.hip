@@ -1,10 +1,13 @@
 // Verification kernels for gfx950 (CDNA4, wave64).
 //
-// A candidate pair (r, s) is similar iff its overlap o = |r & s| satisfies
-// o * (t_num + t_den) >= t_num * (|r| + |s|)  (paper Sec. 3, Definition 1 with
-// the Jaccard row of Table 1, rearranged into integers).  Equivalently o must
-// reach the required overlap
-//     alpha = ceil(t_num * (|r| + |s|) / (t_num + t_den)).
+// A candidate pair (r, s) is similar iff its overlap o = |r & s| reaches the
+// required overlap alpha of its similarity function (paper Sec. 3, Definition
+// 1; the equivalent overlaps of Table 1 in integers): for Jaccard
+//     alpha = ceil(t_num * (|r| + |s|) / (t_num + t_den)),
+// for Dice ceil(t_num (|r| + |s|) / (2 t_den)), for Cosine the least o with
+// o^2 t_den^2 >= t_num^2 |r| |s|, for Overlap ceil(t_num / t_den).  The r side
+// of a pair reads one collection, the s side another in an R-S join (the same
+// one in a self-join).
 // The overlap is found by walking the two sorted token lists and stopping as
 // soon as o >= alpha (accept) or o + min(tokens left in r, tokens left in s)
 // < alpha (reject: alpha is out of reach) -- the early-terminating merge of
@@ -12,7 +15,12 @@
 //
 // Mappings of pairs onto lanes (the paper's alternatives A/B/C of Sec. 3.3.2
 // give a probe set to a thread or a block; here the unit is one pair):
-//   * one thread per pair: a sequential early-exit merge;
+//   * one thread per pair: the merge of the first six tokens of both sets,
+//     kept in their 32-byte set records, in straight-line code, then, for a
+//     pair still undecided, a merge over 16-byte windows of the token arrays
+//     (every set starts on a 16-byte boundary) with the next window in
+//     flight; optionally cut off after a budget of window steps, the pair
+//     then being queued for the second kernel;
 //   * a group of G lanes (G = 4..64) of one wavefront per pair: tile merge;
 //   * one 256-thread workgroup per pair: the same tile merge over LDS.
 // The tile merge advances in rounds.  A round loads the next G tokens of r
@@ -38,7 +46,9 @@
 // Passing pairs are compacted in LDS (a ballot of the pass flags and each
 // lane's rank among the passing lanes) and moved to the request's output
 // with one global atomic per flush.  The in-order kernel keeps all of this
-// per wavefront, so it has no workgroup barrier.
+// per wavefront, so it has no workgroup barrier, and each wavefront lowers
+// its priority as it works through its share, so that the youngest
+// wavefronts of a SIMD do not finish long after the rest.
 #include <algorithm>
 
 #include "ssj_device.h"
@@ -108,17 +118,6 @@ __device__ __forceinline__ uint2 set_desc(const LaunchArgs& a, int id) {
 __device__ __forceinline__ uint2 set_desc_s(const LaunchArgs& a, int id) {
     const uint4 v = a.heads_s[2 * id];
     return make_uint2(v.x, v.y);
-}
-
-// Token i of a set whose record words are w0, w1 (i < kHeadTokens).
-__device__ __forceinline__ int32_t head_token(uint4 w0, uint4 w1, uint32_t i) {
-    int32_t v = (int32_t)w0.z;
-    v = (i == 1) ? (int32_t)w0.w : v;
-    v = (i == 2) ? (int32_t)w1.x : v;
-    v = (i == 3) ? (int32_t)w1.y : v;
-    v = (i == 4) ? (int32_t)w1.z : v;
-    v = (i == 5) ? (int32_t)w1.w : v;
-    return v;
 }
 
 // Candidate pair k of a request.
