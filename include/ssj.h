@@ -213,8 +213,9 @@ int ssj_verify_groups_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_col
  * number, possibly above out_cap; then out_cap of them are written);
  * ssj_join_device verifies them into d_out / d_count like
  * ssj_verify_device; ssj_join does the same with host output buffers.  All
- * three synchronise the stream twice to size their buffers (the prefix index
- * and the candidate count) and share the context's device scratch.
+ * three synchronise the stream three times to size their buffers (the
+ * prefix index, the probe work items and the candidate count) and share the
+ * context's device scratch.
  */
 int ssj_candidates_device(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_den,
                           int positional, ssj_pair* d_out, int64_t out_cap, int64_t* d_count,

@@ -25,8 +25,13 @@
 //    below the overlap it needs, ceil(num (|r| + |s|) / (num + den)), is
 //    dropped.  This is the candidate set of the CPU PPJoin filter.
 //
-// Two passes over the probes (count, then fill at the exclusive prefix sum of
-// the counts) write the candidates in probe order with no atomics.
+// Work items: a probe position whose list holds more than kPiece sets below
+// the probe is split into pieces of kPiece list entries, one thread each, so a
+// long list does not hold up its wavefront; every other position is one item.
+// Items are numbered in (probe position, piece) order by a scan over the
+// pieces per position, and two passes over them (count, then fill at the
+// exclusive prefix sum of the counts) write the candidates in probe order --
+// the order of the CPU filters -- with no atomics.
 #include <hipcub/hipcub.hpp>
 
 #include "ssj_device.h"
@@ -120,25 +125,67 @@ __device__ bool keep_pair(const int32_t* __restrict__ R, uint32_t lr, uint32_t p
     return true;
 }
 
+constexpr uint32_t kPiece = 64;  // list entries per work item of a split list
+
+// List range of each probe position (the entries of its token for sets below
+// the probe) and its number of work items.
+__global__ void k_probe_ranges(const uint4* __restrict__ heads, const int32_t* __restrict__ tok,
+                               const uint2* __restrict__ probes, uint32_t m,
+                               const unsigned long long* __restrict__ keys, uint2* __restrict__ range,
+                               uint32_t* __restrict__ items) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+        const uint2 pe = probes[e];
+        const uint32_t r = pe.x;
+        const unsigned long long w = (unsigned long long)(uint32_t)tok[heads[2 * r].x + pe.y] << 32;
+        const uint32_t lo = lower_bound64(keys, m, w);
+        const uint32_t hi = lower_bound64(keys, m, w | r);
+        range[e] = make_uint2(lo, hi);
+        items[e] = max(1u, (hi - lo + kPiece - 1u) / kPiece);
+    }
+}
+
+// Item i belongs to the last probe position e with istart[e] <= i; every
+// position has at least one item, so e <= i: galloping down from i.
+__device__ __forceinline__ uint32_t item_owner(const uint32_t* __restrict__ istart, uint32_t m, uint32_t i) {
+    uint32_t hi = min(i, m - 1u);  // istart[hi] may exceed i
+    if (istart[hi] <= i) return hi;
+    uint32_t step = 1, lo = hi;
+    while (true) {  // find lo with istart[lo] <= i (istart[0] = 0 <= i ends it)
+        lo = hi >= step ? hi - step : 0u;
+        if (istart[lo] <= i) break;
+        hi = lo;
+        step *= 2u;
+    }
+    while (hi - lo > 1u) {  // istart[lo] <= i < istart[hi]
+        const uint32_t mid = lo + (hi - lo) / 2u;
+        if (istart[mid] <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 template <bool FILL, bool POS>
 __global__ void k_probe(const uint4* __restrict__ heads, const int32_t* __restrict__ tok,
-                        const uint2* __restrict__ probes, uint32_t m,
+                        const uint2* __restrict__ probes, uint32_t m, uint32_t n_items,
                         const unsigned long long* __restrict__ keys, const uint32_t* __restrict__ pos,
-                        const uint32_t* __restrict__ plen, Thr t, uint32_t* __restrict__ counts,
-                        const uint32_t* __restrict__ off, int2* __restrict__ out,
-                        unsigned long long cap) {
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
+                        const uint32_t* __restrict__ plen, const uint2* __restrict__ range,
+                        const uint32_t* __restrict__ istart, Thr t, uint32_t* __restrict__ counts,
+                        const uint32_t* __restrict__ off, int2* __restrict__ out, unsigned long long cap) {
+    for (uint32_t it = blockIdx.x * blockDim.x + threadIdx.x; it < n_items; it += gridDim.x * blockDim.x) {
+        const uint32_t e = item_owner(istart, m, it);
+        const uint32_t piece = it - istart[e];
         const uint2 pe = probes[e];
         const uint32_t r = pe.x, i = pe.y;
         const uint4 hr = heads[2 * r];
         const uint32_t lr = hr.y, pr = plen[r];
         const int32_t* R = tok + hr.x;
-        const unsigned long long w = (unsigned long long)(uint32_t)R[i] << 32;
-        const uint32_t lo = lower_bound64(keys, m, w);
-        const uint32_t hi = lower_bound64(keys, m, w | r);  // sets below r
+        const uint2 rg = range[e];
+        const uint32_t lo = rg.x + piece * kPiece, hi = min(rg.y, lo + kPiece);
         const uint32_t need_r = need_of(lr, t);
         uint32_t c = 0;
-        const unsigned long long base = FILL ? off[e] : 0ull;
+        const unsigned long long base = FILL ? off[it] : 0ull;
         for (uint32_t q = lo; q < hi; ++q) {
             const uint32_t s = (uint32_t)keys[q];
             const uint4 hs = heads[2 * s];
@@ -150,7 +197,7 @@ __global__ void k_probe(const uint4* __restrict__ heads, const int32_t* __restri
             }
             ++c;
         }
-        if constexpr (!FILL) counts[e] = c;
+        if constexpr (!FILL) counts[it] = c;
     }
 }
 
@@ -189,37 +236,53 @@ hipError_t filter_build_index(const uint4* d_heads, const int32_t* d_tok, uint32
                                               st);
 }
 
+hipError_t filter_probe_items(const uint4* d_heads, const int32_t* d_tok, const uint2* d_probes, uint32_t m,
+                              const unsigned long long* d_keys, uint2* d_range, uint32_t* d_items,
+                              uint32_t* d_istart, void* d_temp, size_t* temp_bytes, hipStream_t st) {
+    // d_items[m] is 0, so d_istart[m] is the number of work items
+    if (!d_temp) return hipcub::DeviceScan::ExclusiveSum(nullptr, *temp_bytes, d_items, d_istart, m + 1, st);
+    hipLaunchKernelGGL(k_probe_ranges, dim3(blocks_for(m)), dim3(kBlock), 0, st, d_heads, d_tok, d_probes, m,
+                       d_keys, d_range, d_items);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(d_items + m, 0, sizeof(uint32_t), st);
+    if (e != hipSuccess) return e;
+    return hipcub::DeviceScan::ExclusiveSum(d_temp, *temp_bytes, d_items, d_istart, m + 1, st);
+}
+
 hipError_t filter_probe(const uint4* d_heads, const int32_t* d_tok, const uint2* d_probes, uint32_t m,
-                        const unsigned long long* d_keys, const uint32_t* d_pos, const uint32_t* d_plen,
-                        uint64_t num, uint64_t den, bool positional, uint32_t* d_counts,
-                        const uint32_t* d_off, int2* d_out, uint64_t cap, hipStream_t st) {
+                        uint32_t n_items, const unsigned long long* d_keys, const uint32_t* d_pos,
+                        const uint32_t* d_plen, const uint2* d_range, const uint32_t* d_istart, uint64_t num,
+                        uint64_t den, bool positional, uint32_t* d_counts, const uint32_t* d_off, int2* d_out,
+                        uint64_t cap, hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
     const Thr t{num, den};
-    const dim3 g(blocks_for(m)), b(kBlock);
+    const dim3 g(blocks_for(n_items)), b(kBlock);
     if (!d_off) {
         if (positional)
-            hipLaunchKernelGGL((k_probe<false, true>), g, b, 0, st, d_heads, d_tok, d_probes, m, d_keys, d_pos,
-                               d_plen, t, d_counts, nullptr, nullptr, 0ull);
+            hipLaunchKernelGGL((k_probe<false, true>), g, b, 0, st, d_heads, d_tok, d_probes, m, n_items, d_keys,
+                               d_pos, d_plen, d_range, d_istart, t, d_counts, nullptr, nullptr, 0ull);
         else
-            hipLaunchKernelGGL((k_probe<false, false>), g, b, 0, st, d_heads, d_tok, d_probes, m, d_keys, d_pos,
-                               d_plen, t, d_counts, nullptr, nullptr, 0ull);
+            hipLaunchKernelGGL((k_probe<false, false>), g, b, 0, st, d_heads, d_tok, d_probes, m, n_items,
+                               d_keys, d_pos, d_plen, d_range, d_istart, t, d_counts, nullptr, nullptr, 0ull);
     } else {
         if (positional)
-            hipLaunchKernelGGL((k_probe<true, true>), g, b, 0, st, d_heads, d_tok, d_probes, m, d_keys, d_pos,
-                               d_plen, t, nullptr, d_off, d_out, (unsigned long long)cap);
+            hipLaunchKernelGGL((k_probe<true, true>), g, b, 0, st, d_heads, d_tok, d_probes, m, n_items, d_keys,
+                               d_pos, d_plen, d_range, d_istart, t, nullptr, d_off, d_out, (unsigned long long)cap);
         else
-            hipLaunchKernelGGL((k_probe<true, false>), g, b, 0, st, d_heads, d_tok, d_probes, m, d_keys, d_pos,
-                               d_plen, t, nullptr, d_off, d_out, (unsigned long long)cap);
+            hipLaunchKernelGGL((k_probe<true, false>), g, b, 0, st, d_heads, d_tok, d_probes, m, n_items, d_keys,
+                               d_pos, d_plen, d_range, d_istart, t, nullptr, d_off, d_out, (unsigned long long)cap);
     }
     return hipGetLastError();
 }
 
-hipError_t filter_scan_counts(uint32_t* d_counts, uint32_t* d_off, uint32_t m, void* d_temp, size_t* temp_bytes,
+hipError_t filter_scan_counts(uint32_t* d_counts, uint32_t* d_off, uint32_t n, void* d_temp, size_t* temp_bytes,
                               hipStream_t st) {
-    // d_counts[m] is 0, so d_off[m] is the number of candidates
-    if (!d_temp) return hipcub::DeviceScan::ExclusiveSum(nullptr, *temp_bytes, d_counts, d_off, m + 1, st);
-    hipError_t e = hipMemsetAsync(d_counts + m, 0, sizeof(uint32_t), st);
+    // d_counts[n] is 0, so d_off[n] is the number of candidates
+    if (!d_temp) return hipcub::DeviceScan::ExclusiveSum(nullptr, *temp_bytes, d_counts, d_off, n + 1, st);
+    hipError_t e = hipMemsetAsync(d_counts + n, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return e;
-    return hipcub::DeviceScan::ExclusiveSum(d_temp, *temp_bytes, d_counts, d_off, m + 1, st);
+    return hipcub::DeviceScan::ExclusiveSum(d_temp, *temp_bytes, d_counts, d_off, n + 1, st);
 }
 
 }  // namespace ssj

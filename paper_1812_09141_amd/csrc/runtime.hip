@@ -187,12 +187,13 @@ struct ssj_ctx {
     // GPU candidate generation (prefix index and probe counts)
     struct {
         uint32_t *plen = nullptr, *pre = nullptr, *pos = nullptr, *pos2 = nullptr, *counts = nullptr,
-                 *off = nullptr;
+                 *off = nullptr, *items = nullptr, *istart = nullptr;
         unsigned long long *keys = nullptr, *keys2 = nullptr;
-        uint2* probes = nullptr;
+        uint2 *probes = nullptr, *range = nullptr;
         unsigned char* temp = nullptr;
         size_t plen_cap = 0, pre_cap = 0, pos_cap = 0, pos2_cap = 0, counts_cap = 0, off_cap = 0,
-               keys_cap = 0, keys2_cap = 0, probes_cap = 0, temp_cap = 0;
+               keys_cap = 0, keys2_cap = 0, probes_cap = 0, temp_cap = 0, items_cap = 0, istart_cap = 0,
+               range_cap = 0;
     } flt;
     std::atomic<bool> failed{false};
     std::vector<ssj_coll*> colls;
@@ -884,7 +885,8 @@ int ssj_shutdown(ssj_ctx* ctx) {
         if (ctx->d_chunk_g) (void)hipFree(ctx->d_chunk_g);
         for (void* q : {(void*)ctx->flt.plen, (void*)ctx->flt.pre, (void*)ctx->flt.pos, (void*)ctx->flt.pos2,
                         (void*)ctx->flt.counts, (void*)ctx->flt.off, (void*)ctx->flt.keys,
-                        (void*)ctx->flt.keys2, (void*)ctx->flt.probes, (void*)ctx->flt.temp})
+                        (void*)ctx->flt.keys2, (void*)ctx->flt.probes, (void*)ctx->flt.temp,
+                        (void*)ctx->flt.items, (void*)ctx->flt.istart, (void*)ctx->flt.range})
             if (q) (void)hipFree(q);
         if (ctx->d_count) (void)hipFree(ctx->d_count);
         if (ctx->h_count) (void)hipHostFree(ctx->h_count);
@@ -1169,8 +1171,8 @@ int ssj_verify_groups_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_col
 namespace {
 
 // GPU prefix-filter candidates of coll at t = t_num / t_den into ctx->d_pairs;
-// *n_cand receives their number (two host synchronisations on st: the index
-// size and the candidate count).  ctx->mu held.
+// *n_cand receives their number (three host synchronisations on st: the index
+// size, the probe work items and the candidate count).  ctx->mu held.
 int gpu_candidates(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_den, bool positional,
                    hipStream_t st, int64_t* n_cand) {
     auto& F = ctx->flt;
@@ -1196,30 +1198,45 @@ int gpu_candidates(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_
     HIP_OR_FAIL(ctx, grow(F.pos, F.pos_cap, m));
     HIP_OR_FAIL(ctx, grow(F.pos2, F.pos2_cap, m));
     HIP_OR_FAIL(ctx, grow(F.probes, F.probes_cap, m));
-    HIP_OR_FAIL(ctx, grow(F.counts, F.counts_cap, (size_t)m + 1));
-    HIP_OR_FAIL(ctx, grow(F.off, F.off_cap, (size_t)m + 1));
+    HIP_OR_FAIL(ctx, grow(F.range, F.range_cap, m));
+    HIP_OR_FAIL(ctx, grow(F.items, F.items_cap, (size_t)m + 1));
+    HIP_OR_FAIL(ctx, grow(F.istart, F.istart_cap, (size_t)m + 1));
     tb = 0;
     HIP_OR_FAIL(ctx, ssj::filter_build_index(coll->d_heads, coll->d_tok, n, m, F.plen, F.pre, F.keys, F.pos,
                                              F.keys2, F.pos2, F.probes, nullptr, &tb, st));
     size_t tb2 = 0;
-    HIP_OR_FAIL(ctx, ssj::filter_scan_counts(F.counts, F.off, m, nullptr, &tb2, st));
+    HIP_OR_FAIL(ctx, ssj::filter_probe_items(coll->d_heads, coll->d_tok, F.probes, m, F.keys2, F.range, F.items,
+                                             F.istart, nullptr, &tb2, st));
     HIP_OR_FAIL(ctx, temp_for(std::max(tb, tb2)));
     tb = F.temp_cap;
     HIP_OR_FAIL(ctx, ssj::filter_build_index(coll->d_heads, coll->d_tok, n, m, F.plen, F.pre, F.keys, F.pos,
                                              F.keys2, F.pos2, F.probes, F.temp, &tb, st));
-    HIP_OR_FAIL(ctx, ssj::filter_probe(coll->d_heads, coll->d_tok, F.probes, m, F.keys2, F.pos2, F.plen, num,
-                                       den, positional, F.counts, nullptr, nullptr, 0, st));
     tb = F.temp_cap;
-    HIP_OR_FAIL(ctx, ssj::filter_scan_counts(F.counts, F.off, m, F.temp, &tb, st));
+    HIP_OR_FAIL(ctx, ssj::filter_probe_items(coll->d_heads, coll->d_tok, F.probes, m, F.keys2, F.range, F.items,
+                                             F.istart, F.temp, &tb, st));
+    uint32_t n_items = 0;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, F.istart + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+    std::memcpy(&n_items, ctx->h_count, sizeof(uint32_t));
+    HIP_OR_FAIL(ctx, grow(F.counts, F.counts_cap, (size_t)n_items + 1));
+    HIP_OR_FAIL(ctx, grow(F.off, F.off_cap, (size_t)n_items + 1));
+    tb = 0;
+    HIP_OR_FAIL(ctx, ssj::filter_scan_counts(F.counts, F.off, n_items, nullptr, &tb, st));
+    HIP_OR_FAIL(ctx, temp_for(tb));
+    HIP_OR_FAIL(ctx, ssj::filter_probe(coll->d_heads, coll->d_tok, F.probes, m, n_items, F.keys2, F.pos2, F.plen,
+                                       F.range, F.istart, num, den, positional, F.counts, nullptr, nullptr, 0, st));
+    tb = F.temp_cap;
+    HIP_OR_FAIL(ctx, ssj::filter_scan_counts(F.counts, F.off, n_items, F.temp, &tb, st));
     uint32_t total = 0;
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, F.off + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, F.off + n_items, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
     std::memcpy(&total, ctx->h_count, sizeof(uint32_t));
     if ((int64_t)total > kMaxLaunchPairs)
         return set_error(SSJ_ENOMEM, "more than 2^31 candidates");
     HIP_OR_FAIL(ctx, grow(ctx->d_pairs, ctx->pairs_cap, std::max<size_t>(total, 1)));
-    HIP_OR_FAIL(ctx, ssj::filter_probe(coll->d_heads, coll->d_tok, F.probes, m, F.keys2, F.pos2, F.plen, num,
-                                       den, positional, nullptr, F.off, ctx->d_pairs, total, st));
+    HIP_OR_FAIL(ctx, ssj::filter_probe(coll->d_heads, coll->d_tok, F.probes, m, n_items, F.keys2, F.pos2, F.plen,
+                                       F.range, F.istart, num, den, positional, nullptr, F.off, ctx->d_pairs, total,
+                                       st));
     *n_cand = total;
     return SSJ_OK;
 }

@@ -92,14 +92,21 @@ hipError_t filter_build_index(const uint4* d_heads, const int32_t* d_tok, uint32
                               const uint32_t* d_plen, const uint32_t* d_pre, unsigned long long* d_keys,
                               uint32_t* d_pos, unsigned long long* d_keys2, uint32_t* d_pos2, uint2* d_probes,
                               void* d_temp, size_t* temp_bytes, hipStream_t st);
-// Count pass (d_off null: candidates per probe into d_counts) or fill pass
-// (candidates written at d_off, at most cap).
+// The list range of each probe position in d_range, its work items in
+// d_items (m + 1 words) and their exclusive prefix sum in d_istart[0, m]
+// (d_istart[m]: work items).
+hipError_t filter_probe_items(const uint4* d_heads, const int32_t* d_tok, const uint2* d_probes, uint32_t m,
+                              const unsigned long long* d_keys, uint2* d_range, uint32_t* d_items,
+                              uint32_t* d_istart, void* d_temp, size_t* temp_bytes, hipStream_t st);
+// Count pass (d_off null: candidates per work item into d_counts) or fill
+// pass (candidates written at d_off, at most cap).
 hipError_t filter_probe(const uint4* d_heads, const int32_t* d_tok, const uint2* d_probes, uint32_t m,
-                        const unsigned long long* d_keys, const uint32_t* d_pos, const uint32_t* d_plen,
-                        uint64_t num, uint64_t den, bool positional, uint32_t* d_counts,
-                        const uint32_t* d_off, int2* d_out, uint64_t cap, hipStream_t st);
-// Exclusive prefix sum of d_counts[0, m) into d_off[0, m] (d_counts needs m + 1 words).
-hipError_t filter_scan_counts(uint32_t* d_counts, uint32_t* d_off, uint32_t m, void* d_temp, size_t* temp_bytes,
+                        uint32_t n_items, const unsigned long long* d_keys, const uint32_t* d_pos,
+                        const uint32_t* d_plen, const uint2* d_range, const uint32_t* d_istart, uint64_t num,
+                        uint64_t den, bool positional, uint32_t* d_counts, const uint32_t* d_off, int2* d_out,
+                        uint64_t cap, hipStream_t st);
+// Exclusive prefix sum of d_counts[0, n) into d_off[0, n] (d_counts needs n + 1 words).
+hipError_t filter_scan_counts(uint32_t* d_counts, uint32_t* d_off, uint32_t n, void* d_temp, size_t* temp_bytes,
                               hipStream_t st);
 
 hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start, const int32_t* d_tok,
