@@ -132,7 +132,7 @@ constexpr uint32_t kPiece = 64;  // list entries per work item of a split list
 __global__ void k_probe_ranges(const uint4* __restrict__ heads, const int32_t* __restrict__ tok,
                                const uint2* __restrict__ probes, uint32_t m,
                                const unsigned long long* __restrict__ keys, uint2* __restrict__ range,
-                               uint32_t* __restrict__ items) {
+                               unsigned long long* __restrict__ items) {
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
         const uint2 pe = probes[e];
         const uint32_t r = pe.x;
@@ -140,13 +140,14 @@ __global__ void k_probe_ranges(const uint4* __restrict__ heads, const int32_t* _
         const uint32_t lo = lower_bound64(keys, m, w);
         const uint32_t hi = lower_bound64(keys, m, w | r);
         range[e] = make_uint2(lo, hi);
-        items[e] = max(1u, (hi - lo + kPiece - 1u) / kPiece);
+        items[e] = max(1ull, ((unsigned long long)(hi - lo) + kPiece - 1ull) / kPiece);
     }
 }
 
 // Item i belongs to the last probe position e with istart[e] <= i; every
 // position has at least one item, so e <= i: galloping down from i.
-__device__ __forceinline__ uint32_t item_owner(const uint32_t* __restrict__ istart, uint32_t m, uint32_t i) {
+__device__ __forceinline__ uint32_t item_owner(const unsigned long long* __restrict__ istart, uint32_t m,
+                                               uint32_t i) {
     uint32_t hi = min(i, m - 1u);  // istart[hi] may exceed i
     if (istart[hi] <= i) return hi;
     uint32_t step = 1, lo = hi;
@@ -171,11 +172,12 @@ __global__ void k_probe(const uint4* __restrict__ heads, const int32_t* __restri
                         const uint2* __restrict__ probes, uint32_t m, uint32_t n_items,
                         const unsigned long long* __restrict__ keys, const uint32_t* __restrict__ pos,
                         const uint32_t* __restrict__ plen, const uint2* __restrict__ range,
-                        const uint32_t* __restrict__ istart, Thr t, uint32_t* __restrict__ counts,
-                        const uint32_t* __restrict__ off, int2* __restrict__ out, unsigned long long cap) {
+                        const unsigned long long* __restrict__ istart, Thr t,
+                        unsigned long long* __restrict__ counts, const unsigned long long* __restrict__ off,
+                        int2* __restrict__ out, unsigned long long cap) {
     for (uint32_t it = blockIdx.x * blockDim.x + threadIdx.x; it < n_items; it += gridDim.x * blockDim.x) {
         const uint32_t e = item_owner(istart, m, it);
-        const uint32_t piece = it - istart[e];
+        const uint32_t piece = (uint32_t)(it - istart[e]);
         const uint2 pe = probes[e];
         const uint32_t r = pe.x, i = pe.y;
         const uint4 hr = heads[2 * r];
@@ -237,24 +239,24 @@ hipError_t filter_build_index(const uint4* d_heads, const int32_t* d_tok, uint32
 }
 
 hipError_t filter_probe_items(const uint4* d_heads, const int32_t* d_tok, const uint2* d_probes, uint32_t m,
-                              const unsigned long long* d_keys, uint2* d_range, uint32_t* d_items,
-                              uint32_t* d_istart, void* d_temp, size_t* temp_bytes, hipStream_t st) {
+                              const unsigned long long* d_keys, uint2* d_range, unsigned long long* d_items,
+                              unsigned long long* d_istart, void* d_temp, size_t* temp_bytes, hipStream_t st) {
     // d_items[m] is 0, so d_istart[m] is the number of work items
     if (!d_temp) return hipcub::DeviceScan::ExclusiveSum(nullptr, *temp_bytes, d_items, d_istart, m + 1, st);
     hipLaunchKernelGGL(k_probe_ranges, dim3(blocks_for(m)), dim3(kBlock), 0, st, d_heads, d_tok, d_probes, m,
                        d_keys, d_range, d_items);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hipMemsetAsync(d_items + m, 0, sizeof(uint32_t), st);
+    e = hipMemsetAsync(d_items + m, 0, sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
     return hipcub::DeviceScan::ExclusiveSum(d_temp, *temp_bytes, d_items, d_istart, m + 1, st);
 }
 
 hipError_t filter_probe(const uint4* d_heads, const int32_t* d_tok, const uint2* d_probes, uint32_t m,
                         uint32_t n_items, const unsigned long long* d_keys, const uint32_t* d_pos,
-                        const uint32_t* d_plen, const uint2* d_range, const uint32_t* d_istart, uint64_t num,
-                        uint64_t den, bool positional, uint32_t* d_counts, const uint32_t* d_off, int2* d_out,
-                        uint64_t cap, hipStream_t st) {
+                        const uint32_t* d_plen, const uint2* d_range, const unsigned long long* d_istart,
+                        uint64_t num, uint64_t den, bool positional, unsigned long long* d_counts,
+                        const unsigned long long* d_off, int2* d_out, uint64_t cap, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
     const Thr t{num, den};
     const dim3 g(blocks_for(n_items)), b(kBlock);
@@ -276,11 +278,11 @@ hipError_t filter_probe(const uint4* d_heads, const int32_t* d_tok, const uint2*
     return hipGetLastError();
 }
 
-hipError_t filter_scan_counts(uint32_t* d_counts, uint32_t* d_off, uint32_t n, void* d_temp, size_t* temp_bytes,
-                              hipStream_t st) {
+hipError_t filter_scan_counts(unsigned long long* d_counts, unsigned long long* d_off, uint32_t n, void* d_temp,
+                              size_t* temp_bytes, hipStream_t st) {
     // d_counts[n] is 0, so d_off[n] is the number of candidates
     if (!d_temp) return hipcub::DeviceScan::ExclusiveSum(nullptr, *temp_bytes, d_counts, d_off, n + 1, st);
-    hipError_t e = hipMemsetAsync(d_counts + n, 0, sizeof(uint32_t), st);
+    hipError_t e = hipMemsetAsync(d_counts + n, 0, sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
     return hipcub::DeviceScan::ExclusiveSum(d_temp, *temp_bytes, d_counts, d_off, n + 1, st);
 }

@@ -186,9 +186,9 @@ struct ssj_ctx {
     size_t chunk_g_cap = 0;
     // GPU candidate generation (prefix index and probe counts)
     struct {
-        uint32_t *plen = nullptr, *pre = nullptr, *pos = nullptr, *pos2 = nullptr, *counts = nullptr,
-                 *off = nullptr, *items = nullptr, *istart = nullptr;
-        unsigned long long *keys = nullptr, *keys2 = nullptr;
+        uint32_t *plen = nullptr, *pre = nullptr, *pos = nullptr, *pos2 = nullptr;
+        unsigned long long *keys = nullptr, *keys2 = nullptr, *counts = nullptr, *off = nullptr,
+                           *items = nullptr, *istart = nullptr;
         uint2 *probes = nullptr, *range = nullptr;
         unsigned char* temp = nullptr;
         size_t plen_cap = 0, pre_cap = 0, pos_cap = 0, pos2_cap = 0, counts_cap = 0, off_cap = 0,
@@ -1214,10 +1214,14 @@ int gpu_candidates(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_
     tb = F.temp_cap;
     HIP_OR_FAIL(ctx, ssj::filter_probe_items(coll->d_heads, coll->d_tok, F.probes, m, F.keys2, F.range, F.items,
                                              F.istart, F.temp, &tb, st));
-    uint32_t n_items = 0;
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, F.istart + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    unsigned long long items64 = 0;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, F.istart + m, sizeof(items64), hipMemcpyDeviceToHost, st));
     HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
-    std::memcpy(&n_items, ctx->h_count, sizeof(uint32_t));
+    std::memcpy(&items64, ctx->h_count, sizeof(items64));
+    // (prefixes that many sets share make the probe work grow as the square of
+    // those sets)
+    if (items64 >= ((unsigned long long)1 << 31)) return set_error(SSJ_ENOMEM, "too many prefix meetings");
+    const uint32_t n_items = (uint32_t)items64;
     HIP_OR_FAIL(ctx, grow(F.counts, F.counts_cap, (size_t)n_items + 1));
     HIP_OR_FAIL(ctx, grow(F.off, F.off_cap, (size_t)n_items + 1));
     tb = 0;
@@ -1227,17 +1231,17 @@ int gpu_candidates(ssj_ctx* ctx, const ssj_coll* coll, int64_t t_num, int64_t t_
                                        F.range, F.istart, num, den, positional, F.counts, nullptr, nullptr, 0, st));
     tb = F.temp_cap;
     HIP_OR_FAIL(ctx, ssj::filter_scan_counts(F.counts, F.off, n_items, F.temp, &tb, st));
-    uint32_t total = 0;
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, F.off + n_items, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    unsigned long long total = 0;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, F.off + n_items, sizeof(total), hipMemcpyDeviceToHost, st));
     HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
-    std::memcpy(&total, ctx->h_count, sizeof(uint32_t));
-    if ((int64_t)total > kMaxLaunchPairs)
+    std::memcpy(&total, ctx->h_count, sizeof(total));
+    if (total > (unsigned long long)kMaxLaunchPairs)
         return set_error(SSJ_ENOMEM, "more than 2^31 candidates");
-    HIP_OR_FAIL(ctx, grow(ctx->d_pairs, ctx->pairs_cap, std::max<size_t>(total, 1)));
+    HIP_OR_FAIL(ctx, grow(ctx->d_pairs, ctx->pairs_cap, std::max<size_t>((size_t)total, 1)));
     HIP_OR_FAIL(ctx, ssj::filter_probe(coll->d_heads, coll->d_tok, F.probes, m, n_items, F.keys2, F.pos2, F.plen,
                                        F.range, F.istart, num, den, positional, nullptr, F.off, ctx->d_pairs, total,
                                        st));
-    *n_cand = total;
+    *n_cand = (int64_t)total;
     return SSJ_OK;
 }
 

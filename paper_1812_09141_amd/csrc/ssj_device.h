@@ -96,18 +96,18 @@ hipError_t filter_build_index(const uint4* d_heads, const int32_t* d_tok, uint32
 // d_items (m + 1 words) and their exclusive prefix sum in d_istart[0, m]
 // (d_istart[m]: work items).
 hipError_t filter_probe_items(const uint4* d_heads, const int32_t* d_tok, const uint2* d_probes, uint32_t m,
-                              const unsigned long long* d_keys, uint2* d_range, uint32_t* d_items,
-                              uint32_t* d_istart, void* d_temp, size_t* temp_bytes, hipStream_t st);
+                              const unsigned long long* d_keys, uint2* d_range, unsigned long long* d_items,
+                              unsigned long long* d_istart, void* d_temp, size_t* temp_bytes, hipStream_t st);
 // Count pass (d_off null: candidates per work item into d_counts) or fill
 // pass (candidates written at d_off, at most cap).
 hipError_t filter_probe(const uint4* d_heads, const int32_t* d_tok, const uint2* d_probes, uint32_t m,
                         uint32_t n_items, const unsigned long long* d_keys, const uint32_t* d_pos,
-                        const uint32_t* d_plen, const uint2* d_range, const uint32_t* d_istart, uint64_t num,
-                        uint64_t den, bool positional, uint32_t* d_counts, const uint32_t* d_off, int2* d_out,
-                        uint64_t cap, hipStream_t st);
+                        const uint32_t* d_plen, const uint2* d_range, const unsigned long long* d_istart,
+                        uint64_t num, uint64_t den, bool positional, unsigned long long* d_counts,
+                        const unsigned long long* d_off, int2* d_out, uint64_t cap, hipStream_t st);
 // Exclusive prefix sum of d_counts[0, n) into d_off[0, n] (d_counts needs n + 1 words).
-hipError_t filter_scan_counts(uint32_t* d_counts, uint32_t* d_off, uint32_t n, void* d_temp, size_t* temp_bytes,
-                              hipStream_t st);
+hipError_t filter_scan_counts(unsigned long long* d_counts, unsigned long long* d_off, uint32_t n, void* d_temp,
+                              size_t* temp_bytes, hipStream_t st);
 
 hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start, const int32_t* d_tok,
                               uint4* d_heads, int64_t n_sets, hipStream_t st);
