@@ -35,6 +35,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "ssj_device.h"
+#include "filter.h"
 
 namespace ssj {
 namespace {

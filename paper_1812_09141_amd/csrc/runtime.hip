@@ -24,6 +24,7 @@
 
 #include "ssj.h"
 #include "ssj_device.h"
+#include "filter.h"
 
 namespace {
 
