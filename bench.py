@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--ppjoin", type=int, default=1,
                     help="also verify the step's thresholds from PPJoin candidates (positional "
                          "filter) and report both filters' CPU time")
+    ap.add_argument("--ingest", type=int, default=1,
+                    help="also time grouped candidates (probe id + s ids) and an R-S join "
+                         "(even-numbered against odd-numbered sets)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (5 times), "
                          "the reference for HBM byte counters, and exit")
@@ -288,7 +291,90 @@ def main():
     extra["host_api_pairs_per_s_pcie_inclusive"] = round(n_pairs * n_host / dt_h, 1)
     extra["host_api_counts_ok"] = bool(host_ok)
 
-    if args.ppjoin:
+    if args.ingest:
+        # grouped candidates (a probe id and the end of its candidates, then
+        # 4-byte s ids; Sec. 3.3.1's C / C_O): device time of the step's four
+        # thresholds against flat launches, and the host-buffer rate with its
+        # PCIe copies (half the candidate bytes)
+        grp = [S.groups_of(c) for c in cands]
+        d_grp = [(torch.from_numpy(g).to(dev), torch.from_numpy(si).to(dev)) for g, si in grp]
+
+        def step_groups():
+            for i, (tn, td) in enumerate(w.thresholds):
+                S.ssj_verify_groups_device(ctx, h, h, d_grp[i][0], d_grp[i][1], "jaccard", tn, td, d_outs[i],
+                                           d_cnt[i:i + 1])
+
+        n_g = max(5, args.steps // 2)
+        dt_g = timed_steps(torch, step_groups, n_g, 2)
+        g_ok = check()
+        dt_f = timed_steps(torch, step_plain, n_g, 2)
+        t1 = time.perf_counter()
+        host_g_ok = True
+        for i, (tn, td) in enumerate(w.thresholds):
+            res = S.ssj_verify_groups(ctx, h, h, grp[i][0], grp[i][1], "jaccard", tn, td)
+            host_g_ok &= pairs_digest(res) == man["thresholds"][f"{tn}/{td}"]["result_sha256"]
+        dt_hg = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        for i, (tn, td) in enumerate(w.thresholds):
+            S.ssj_verify(ctx, h, cands[i], tn, td)
+        dt_hf = time.perf_counter() - t1
+        extra["grouped"] = {
+            "groups_per_step": int(sum(g.shape[0] for g, _ in grp)),
+            "ms_per_step": round(dt_g * 1e3 / n_g, 4), "flat_one_launch_per_batch_ms_per_step": round(dt_f * 1e3 / n_g, 4),
+            "parity": bool(g_ok and host_g_ok),
+            "host_pairs_per_s_pcie_inclusive": round(n_pairs / dt_hg, 1),
+            "flat_host_pairs_per_s_pcie_inclusive": round(n_pairs / dt_hf, 1)}
+
+        # R-S join: R = the even-numbered sets, S = the odd-numbered ones, the
+        # candidates the self-join candidates between them; the result must be
+        # the (manifest-checked) self-join result restricted to those pairs
+        sizes = coll.sizes()
+        ev, od = np.arange(0, coll.n_sets, 2), np.arange(1, coll.n_sets, 2)
+
+        def sub(ids):
+            offs = np.zeros(ids.shape[0] + 1, dtype=np.int64)
+            np.cumsum(sizes[ids], out=offs[1:])
+            toks = np.concatenate([coll.tokens[coll.offsets[x]:coll.offsets[x + 1]] for x in ids])
+            return offs, toks
+
+        (ro, rt), (so, st_) = sub(ev), sub(od)
+        hr = S.ssj_upload_collection(ctx, ro, rt)
+        hs = S.ssj_upload_collection(ctx, so, st_)
+        tn, td = w.thresholds[0]
+        c0 = cands[0]
+        a_ev = (c0[:, 0] % 2 == 0) & (c0[:, 1] % 2 == 1)
+        b_ev = (c0[:, 0] % 2 == 1) & (c0[:, 1] % 2 == 0)
+        rs = np.concatenate([np.stack([c0[a_ev, 0] // 2, c0[a_ev, 1] // 2], axis=1),
+                             np.stack([c0[b_ev, 1] // 2, c0[b_ev, 0] // 2], axis=1)]).astype(np.int32)
+        d_rs = torch.from_numpy(rs).to(dev)
+        d_rs_out = torch.empty_like(d_rs)
+        d_rs_cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def step_rs():
+            S.ssj_verify_rs_device(ctx, hr, hs, d_rs, "jaccard", tn, td, d_rs_out, d_rs_cnt)
+
+        n_r = max(5, args.steps // 2)
+        dt_r = timed_steps(torch, step_rs, n_r, 2)
+        k = int(d_rs_cnt.item())
+        got = d_rs_out[:k].cpu().numpy().astype(np.int64)
+        got_orig = np.stack([2 * got[:, 0], 2 * got[:, 1] + 1], axis=1)
+        S.ssj_verify_device(ctx, h, d_cands[0], tn, td, d_outs[0], d_cnt[0:1])
+        torch.cuda.synchronize()
+        self_res = d_outs[0][:int(d_cnt[0].item())].cpu().numpy().astype(np.int64)
+        self_ok = pairs_digest(self_res.astype(np.int32)) == man["thresholds"][f"{tn}/{td}"]["result_sha256"]
+        lo_, hi_ = np.minimum(self_res[:, 0], self_res[:, 1]), np.maximum(self_res[:, 0], self_res[:, 1])
+        keep = (lo_ % 2) != (hi_ % 2)
+        ev_side = np.where(lo_[keep] % 2 == 0, lo_[keep], hi_[keep])
+        od_side = np.where(lo_[keep] % 2 == 0, hi_[keep], lo_[keep])
+        want = np.sort(ev_side * (1 << 32) + od_side)
+        have = np.sort(got_orig[:, 0] * (1 << 32) + got_orig[:, 1])
+        extra["rs"] = {"workload": f"R = even sets ({ev.shape[0]}), S = odd sets ({od.shape[0]}) of the offline "
+                                   f"collection, t = {tn}/{td}, {rs.shape[0]} cross candidates",
+                       "pairs_per_s": round(rs.shape[0] * n_r / dt_r, 1), "ms_per_step": round(dt_r * 1e3 / n_r, 4),
+                       "parity": bool(self_ok and np.array_equal(want, have))}
+        S.ssj_free_collection(ctx, hr)
+        S.ssj_free_collection(ctx, hs)
+
         # the same join from fewer candidates: PPJoin's positional filter on top
         # of the prefix and length filters (CPU, all host threads up to 16)
         nthr = max(1, min(os.cpu_count() or 1, 16))
