@@ -960,52 +960,70 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
 // cand[end(g-1) .. end(g)) with end(-1) = 0.  They are expanded into flat
 // pairs before verification.
 
-// First group of each chunk of kWave candidates: the least g with end(g) >
-// kWave * T (binary search over the ends; n_groups when none).
-__global__ void k_chunk_groups(const int2* __restrict__ groups, uint32_t n_groups, uint32_t n_chunks,
-                               uint32_t* __restrict__ chunk_g) {
-    for (uint32_t T = blockIdx.x * blockDim.x + threadIdx.x; T < n_chunks; T += gridDim.x * blockDim.x) {
-        const uint32_t c0 = T * (uint32_t)kWave;
-        uint32_t lo = 0, hi = n_groups;
-        while (lo < hi) {
-            const uint32_t mid = lo + (hi - lo) / 2u;
-            if ((uint32_t)groups[mid].y <= c0)
-                lo = mid + 1u;
-            else
-                hi = mid;
-        }
-        chunk_g[T] = lo;
-    }
+__device__ __forceinline__ uint32_t group_end(const int2* groups, uint32_t g) {
+    return (uint32_t)reinterpret_cast<const int32_t*>(groups)[2u * g + 1u];
 }
 
-// Flat pairs (probe, s) of grouped candidates, one wavefront per chunk: the
-// lanes load the ends of 64 groups from the chunk's first group, and each
-// lane's group is the number of those ends at or below its candidate index
-// (binary search across the lanes); a lane past all 64 takes the next 64.
-// A candidate that no group covers, or any chunk that sees the ends decrease,
-// gets probe id -1, which the verification reports as an id error.
+// Least g with end(g) > c0 (n_groups when none) for ends not decreasing, by a
+// 64-way search: each round the lanes read 64 evenly spaced ends of the
+// range [lo, hi] that holds the answer and keep the stretch before the first
+// end above c0, until at most kWave groups remain; the caller then scans
+// from lo.  Wave-uniform; with malformed ends it still returns some
+// lo <= n_groups.
+__device__ uint32_t first_group_above(const int2* __restrict__ groups, uint32_t n_groups, uint32_t c0,
+                                      int lane) {
+    uint32_t lo = 0, hi = n_groups;
+    while (hi - lo > (uint32_t)kWave) {
+        const uint32_t step = (hi - lo + (uint32_t)kWave - 1u) / (uint32_t)kWave;
+        const uint64_t p = (uint64_t)lo + (uint64_t)(lane + 1) * step - 1u;  // sample of lane k
+        const bool above = p >= hi || group_end(groups, (uint32_t)p) > c0;
+        const unsigned long long m = ballot(above);
+        if (m == 0ull) {  // every sampled end is at or below c0: the answer is hi
+            lo = hi;
+            break;
+        }
+        const uint32_t f = (uint32_t)__builtin_ctzll(m);
+        const uint64_t pf = (uint64_t)lo + (uint64_t)(f + 1u) * step - 1u;
+        const uint32_t nlo = f == 0u ? lo : (uint32_t)((uint64_t)lo + (uint64_t)f * step);
+        hi = pf < hi ? (uint32_t)pf : hi;
+        lo = nlo;
+    }
+    return lo;
+}
+
+// Flat pairs (probe, s) of grouped candidates, one wavefront per chunk of
+// kWave candidates: the wavefront finds the first group of its chunk, the
+// lanes load the ends of 64 groups from there, and each lane's group is the
+// number of those ends at or below its candidate index (binary search across
+// the lanes); a lane past all 64 takes the next 64.  A candidate that no
+// group covers gets probe id -1, which the verification reports as an id
+// error.  Every thread also checks a share of the ends (not decreasing, none
+// above n, the last one n) and flags request 0 of ctr on a violation.
 __global__ void k_expand_groups(const int2* __restrict__ groups, uint32_t n_groups,
-                                const int32_t* __restrict__ cand, uint32_t n,
-                                const uint32_t* __restrict__ chunk_g, int2* __restrict__ pairs) {
+                                const int32_t* __restrict__ cand, uint32_t n, int2* __restrict__ pairs,
+                                Counters* __restrict__ ctr) {
     const int lane = lane_id();
+    bool bad = false;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_groups; g += gridDim.x * blockDim.x) {
+        const int32_t e = (int32_t)group_end(groups, g);
+        const int32_t prev = g > 0u ? (int32_t)group_end(groups, g - 1u) : 0;
+        bad |= e < prev || (uint32_t)e > n || (g + 1u == n_groups && (uint32_t)e != n);
+    }
+    if (ballot(bad) != 0ull && lane == 0) atomicOr(&ctr->err[0], 1u);
+
     const uint32_t n_chunks = (n + (uint32_t)kWave - 1u) / (uint32_t)kWave;
     const uint32_t waves = gridDim.x * (blockDim.x / (uint32_t)kWave);
     for (uint32_t T = (blockIdx.x * blockDim.x + threadIdx.x) / (uint32_t)kWave; T < n_chunks; T += waves) {
         const uint32_t c = T * (uint32_t)kWave + (uint32_t)lane;
         const bool valid = c < n;
-        uint32_t g0 = chunk_g[T];
+        uint32_t g0 = first_group_above(groups, n_groups, T * (uint32_t)kWave, lane);
         uint32_t g = 0xffffffffu;  // the lane's group once found
-        bool bad = false;
         // all lanes take part in every permute (a permute reads nothing from
-        // an inactive lane); at most n_groups / 64 + 1 rounds
-        for (;;) {
+        // an inactive lane); the window moves past at most kWave empty groups
+        // per round
+        while (g0 < n_groups) {
             const uint32_t gk = g0 + (uint32_t)lane;
-            const uint32_t ek = gk < n_groups ? (uint32_t)groups[gk].y : 0xffffffffu;
-            const uint32_t before = g0 > 0u ? (uint32_t)groups[g0 - 1u].y : 0u;
-            // the permute runs in every lane (lane 0 reads lane 63 and drops it)
-            const uint32_t left = (uint32_t)bperm((int)ek, (lane + kWave - 1) & (kWave - 1));
-            const uint32_t eprev = lane > 0 ? left : before;
-            bad |= gk < n_groups && ek < eprev;
+            const uint32_t ek = gk < n_groups ? group_end(groups, gk) : 0xffffffffu;
             uint32_t pos = 0;
 #pragma unroll
             for (uint32_t step = kWave / 2; step >= 1; step >>= 1) {
@@ -1016,12 +1034,9 @@ __global__ void k_expand_groups(const int2* __restrict__ groups, uint32_t n_grou
             if (g == 0xffffffffu && !beyond) g = g0 + pos;
             if (ballot(valid && g == 0xffffffffu) == 0ull) break;
             g0 += (uint32_t)kWave;
-            if (g0 >= n_groups) break;
         }
-        const bool any_bad = ballot(bad) != 0ull;
         if (valid) {
-            const bool ok = !any_bad && g < n_groups;
-            const int32_t r = ok ? groups[g].x : -1;
+            const int32_t r = g < n_groups ? groups[g].x : -1;
             pairs[c] = make_int2(r, cand[c]);
         }
     }
@@ -1090,17 +1105,12 @@ const void* kernel_verify_deferred(bool cosine) {
 }
 
 hipError_t launch_expand_groups(const int2* d_groups, int64_t n_groups, const int32_t* d_cand, int64_t n,
-                                uint32_t* d_chunk_g, int2* d_pairs, hipStream_t st) {
+                                Counters* d_ctr, int2* d_pairs, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const int64_t n_chunks = (n + kWave - 1) / kWave;
-    const int64_t b1 = std::min<int64_t>((n_chunks + kBlock - 1) / kBlock, 65536);
-    hipLaunchKernelGGL(k_chunk_groups, dim3((unsigned)b1), dim3(kBlock), 0, st, d_groups,
-                       (uint32_t)n_groups, (uint32_t)n_chunks, d_chunk_g);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t b2 = std::min<int64_t>((n_chunks + kBlock / kWave - 1) / (kBlock / kWave), 65536);
-    hipLaunchKernelGGL(k_expand_groups, dim3((unsigned)b2), dim3(kBlock), 0, st, d_groups,
-                       (uint32_t)n_groups, d_cand, (uint32_t)n, d_chunk_g, d_pairs);
+    const int64_t b = std::min<int64_t>((n_chunks + kBlock / kWave - 1) / (kBlock / kWave), 65536);
+    hipLaunchKernelGGL(k_expand_groups, dim3((unsigned)b), dim3(kBlock), 0, st, d_groups,
+                       (uint32_t)n_groups, d_cand, (uint32_t)n, d_pairs, d_ctr);
     return hipGetLastError();
 }
 

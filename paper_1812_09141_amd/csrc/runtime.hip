@@ -183,8 +183,6 @@ struct ssj_ctx {
     size_t sids_cap = 0;
     int2* d_pairs = nullptr;
     size_t pairs_cap = 0;
-    uint32_t* d_chunk_g = nullptr;
-    size_t chunk_g_cap = 0;
     // GPU candidate generation (prefix index and probe counts)
     struct {
         uint32_t *plen = nullptr, *pre = nullptr, *pos = nullptr, *pos2 = nullptr;
@@ -883,7 +881,6 @@ int ssj_shutdown(ssj_ctx* ctx) {
         if (ctx->d_groups) (void)hipFree(ctx->d_groups);
         if (ctx->d_sids) (void)hipFree(ctx->d_sids);
         if (ctx->d_pairs) (void)hipFree(ctx->d_pairs);
-        if (ctx->d_chunk_g) (void)hipFree(ctx->d_chunk_g);
         for (void* q : {(void*)ctx->flt.plen, (void*)ctx->flt.pre, (void*)ctx->flt.pos, (void*)ctx->flt.pos2,
                         (void*)ctx->flt.counts, (void*)ctx->flt.off, (void*)ctx->flt.keys,
                         (void*)ctx->flt.keys2, (void*)ctx->flt.probes, (void*)ctx->flt.temp,
@@ -1123,9 +1120,7 @@ int enqueue_groups(ssj_ctx* ctx, const ssj_coll* R, const ssj_coll* S, const int
                    int64_t n_groups, const int32_t* d_sids, int64_t n_cand, int sim, int64_t t_num,
                    int64_t t_den, int2* d_out, int64_t out_cap, long long* d_count, hipStream_t st) {
     HIP_OR_FAIL(ctx, grow(ctx->d_pairs, ctx->pairs_cap, (size_t)std::max<int64_t>(n_cand, 1)));
-    HIP_OR_FAIL(ctx, grow(ctx->d_chunk_g, ctx->chunk_g_cap,
-                          (size_t)std::max<int64_t>((n_cand + ssj::kWave - 1) / ssj::kWave, 1)));
-    HIP_OR_FAIL(ctx, ssj::launch_expand_groups(d_groups, n_groups, d_sids, n_cand, ctx->d_chunk_g,
+    HIP_OR_FAIL(ctx, ssj::launch_expand_groups(d_groups, n_groups, d_sids, n_cand, ctx->def.d_ctr,
                                                ctx->d_pairs, st));
     Req r{ctx->d_pairs, n_cand, t_num, t_den, d_out, out_cap, d_count, sim};
     return enqueue_launch(ctx, R, ctx->def, &r, 1, st, ctx->plan, true, S);

@@ -265,3 +265,65 @@ def test_groups_malformed(S, ctx):
     finally:
         S.ssj_free_collection(ctx, hr)
         S.ssj_free_collection(ctx, hs)
+
+
+def test_groups_many_and_malformed_large(S, ctx):
+    """Tens of thousands of groups (several rounds of the chunk's group search)
+    with runs of hundreds of empty groups; then malformed ends deep inside the
+    list, where no chunk's own groups reach them, still give -1, and a
+    well-formed call afterwards is unaffected."""
+    import torch
+    rng, R, Sc = _two(7, 30)
+    hr = S.ssj_upload_collection(ctx, R.offsets, R.tokens)
+    hs = S.ssj_upload_collection(ctx, Sc.offsets, Sc.tokens)
+    try:
+        S.ssj_set_plan(ctx, S.make_plan(inline_lanes=1, defer_from=5))
+        sizes = []
+        while len(sizes) < 30000:
+            kind = rng.integers(0, 10)
+            if kind == 0:
+                sizes += [0] * int(rng.integers(64, 400))
+            elif kind == 1:
+                sizes.append(int(rng.integers(100, 300)))
+            else:
+                sizes += rng.integers(0, 6, 50).tolist()
+        groups = _uneven_groups(rng, R.n_sets, sizes)
+        n = int(groups[-1, 1])
+        sids = rng.integers(0, Sc.n_sets, n).astype(np.int32)
+        flat = np.stack([np.repeat(groups[:, 0], sizes), sids], axis=1).astype(np.int32)
+        want = oracle.sort_pairs(oracle.select_rs(R.offsets, R.tokens, Sc.offsets, Sc.tokens, flat, 0, 1))
+        dev = torch.device("cuda:0")
+        d_s = torch.from_numpy(sids).to(dev)
+        d_out = torch.empty((n, 2), dtype=torch.int32, device=dev)
+        d_cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def run(g):
+            S.ssj_verify_groups_device(ctx, hr, hs, torch.from_numpy(g).to(dev), d_s, "jaccard", 0, 1,
+                                       d_out, d_cnt)
+            torch.cuda.synchronize()
+            return int(d_cnt.item())
+
+        _log(f"groups many: {groups.shape[0]} groups, {n} candidates")
+        assert run(groups) == want.shape[0]
+        assert np.array_equal(oracle.sort_pairs(d_out[:want.shape[0]].cpu().numpy()), want)
+        mid = int(np.flatnonzero((groups[:, 1] > 0) & (np.arange(groups.shape[0]) > 15000))[0]) + 1
+        bad = []
+        g = groups.copy()
+        g[mid, 1] = g[mid - 1, 1] - 1           # one end below the one before
+        bad.append(("decrease", g))
+        g = groups.copy()
+        g[mid, 1] = n + 7                       # an end past n_cand
+        bad.append(("past n", g))
+        g = groups.copy()
+        g[-1, 1] = n - 1                        # the last end short of n_cand
+        bad.append(("short", g))
+        g = groups.copy()
+        g[mid, 1] = -5                          # a negative end
+        bad.append(("negative", g))
+        for name, g in bad:
+            _log(f"groups many malformed: {name} at group {mid}")
+            assert run(g) == -1, name
+        assert run(groups) == want.shape[0]
+    finally:
+        S.ssj_free_collection(ctx, hr)
+        S.ssj_free_collection(ctx, hs)
