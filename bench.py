@@ -54,6 +54,11 @@ def parse():
     ap.add_argument("--ingest", type=int, default=1,
                     help="also time grouped candidates (probe id + s ids) and an R-S join "
                          "(even-numbered against odd-numbered sets)")
+    ap.add_argument("--modes", type=int, default=1,
+                    help="also time the output-count mode and the other similarity functions of "
+                         "Table 1 on the step's candidates")
+    ap.add_argument("--cpu1-seconds", type=float, default=3.0,
+                    help="CPU work budget of the single-core oracle baseline (0 disables it)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (5 times), "
                          "the reference for HBM byte counters, and exit")
@@ -110,6 +115,24 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, "paper_1812_09141_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def copy_gbs(torch, mib=1024, reps=5):
+    """Device-to-device copy rate (bytes read + written per second, GB/s): the
+    practical HBM peak on this device."""
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
 
 
 def pairs_digest(pairs):
@@ -277,6 +300,80 @@ def main():
             sweep[spec] = {"pairs_per_s": round(n_pairs * n_sw / dt, 1), "parity": bool(check())}
         extra["sweep"] = sweep
         S.ssj_set_plan(ctx, plan)
+
+    if args.modes:
+        # output-count mode (no pair writes; the mode the paper measured) on the
+        # same batched launch, and the other similarity functions of Table 1
+        d_cnt_c = torch.zeros(len(cands), dtype=torch.int64, device=dev)
+        batch_c = [(d_cands[i], tn, td, None, d_cnt_c[i:i + 1]) for i, (tn, td) in enumerate(w.thresholds)]
+        n_m = max(5, args.steps // 2)
+        dt_c = timed_steps(torch, lambda: S.ssj_verify_batch_device(ctx, h, batch_c), n_m, 2)
+        cnt_c = d_cnt_c.cpu().numpy()
+        extra["count_mode"] = {
+            "pairs_per_s": round(n_pairs * n_m / dt_c, 1), "ms_per_step": round(dt_c * 1e3 / n_m, 4),
+            "parity": bool(all(int(cnt_c[i]) == man["thresholds"][f"{tn}/{td}"]["n_result"]
+                               for i, (tn, td) in enumerate(w.thresholds)))}
+        if "sims" in man:
+            sims = {}
+            key = man["sims"]["candidates"]
+            i0 = [f"{tn}/{td}" for tn, td in w.thresholds].index(key)
+            n0 = cands[i0].shape[0]
+            for name in ["jaccard " + key] + [k for k in man["sims"] if k != "candidates"]:
+                sim, frac = name.split()
+                sn, sd = (int(x) for x in frac.split("/"))
+                one = [(d_cands[i0], sn, sd, d_outs[i0], d_cnt[i0:i0 + 1], sim)]
+                dt_s = timed_steps(torch, lambda: S.ssj_verify_batch_device(ctx, h, one), n_m, 2)
+                k = int(d_cnt[i0].item())
+                ref = man["thresholds"][key] if sim == "jaccard" else man["sims"][name]
+                sims[name] = {"pairs_per_s": round(n0 * n_m / dt_s, 1), "ms": round(dt_s * 1e3 / n_m, 4),
+                              "n_result": k,
+                              "parity": bool(k == ref["n_result"] and
+                                             pairs_digest(d_outs[i0][:k].cpu().numpy()) == ref["result_sha256"])}
+            extra["similarities"] = {"candidates": f"the t = {key} list ({n0} pairs), one launch each",
+                                     **sims}
+            step()  # restore the outputs of the main step
+            torch.cuda.synchronize()
+
+    buckets = [man["thresholds"][f"{tn}/{td}"].get("buckets") for tn, td in w.thresholds]
+    if all(b is not None for b in buckets):
+        # kernel time and B_alg rate per bucket of |r| + |s| (each bucket's
+        # candidates alone, in their order, one launch per step)
+        bounds = [b["upper_bound"] for b in buckets[0][:-1]]
+        per = []
+        b_of = [np.searchsorted(np.asarray(bounds), sizes[c[:, 0]] + sizes[c[:, 1]], side="left") for c in cands]
+        for q in range(len(bounds) + 1):
+            sub = [np.ascontiguousarray(c[b_of[i] == q]) for i, c in enumerate(cands)]
+            nq = int(sum(x.shape[0] for x in sub))
+            if nq == 0:
+                continue
+            d_sub = [torch.from_numpy(x).to(dev) for x in sub]
+            d_so = [torch.empty((max(x.shape[0], 1), 2), dtype=torch.int32, device=dev) for x in sub]
+            d_sc = torch.zeros(len(sub), dtype=torch.int64, device=dev)
+            bb = [(d_sub[i], tn, td, d_so[i], d_sc[i:i + 1]) for i, (tn, td) in enumerate(w.thresholds)]
+            n_b = 5
+            S.ssj_verify_batch_device(ctx, h, bb)
+            torch.cuda.synchronize()
+            S.ssj_timing_enable(ctx, 1)
+            S.ssj_timing_read(ctx, reset=True)
+            for _ in range(n_b):
+                S.ssj_verify_batch_device(ctx, h, bb)
+            torch.cuda.synchronize()
+            q_in, q_def, q_l = S.ssj_timing_read(ctx, reset=True)
+            S.ssj_timing_enable(ctx, 0)
+            q_ms = (q_in + (q_def if deferred else 0.0)) / max(q_l, 1)
+            ok = True
+            b_q = 0
+            for i, (tn, td) in enumerate(w.thresholds):
+                m = buckets[i][q]
+                k = int(d_sc[i].item())
+                ok &= k == m["n_result"] and pairs_digest(d_so[i][:k].cpu().numpy()) == m["result_sha256"]
+                b_q += 24 * m["n_candidates"] + 4 * m["sum_consumed_tokens"] + 8 * m["n_result"]
+            per.append({"sizes": f"|r|+|s| <= {bounds[q]}" if q < len(bounds) else f"|r|+|s| > {bounds[-1]}",
+                        "pairs": nq, "kernel_ms": round(q_ms, 5), "alg_bytes": int(b_q),
+                        "alg_gbs": round(b_q / (q_ms * 1e-3) / 1e9, 2) if q_ms > 0 else None,
+                        "parity": bool(ok)})
+            del d_sub, d_so, d_sc
+        extra["buckets"] = per
 
     # PCIe-inclusive rate of the host-buffer entry point (candidates copied in,
     # results copied out, synchronous per call); context only, never `value`
@@ -472,7 +569,22 @@ def main():
                "sample": f"{reps} full passes over the step's {n_pairs} candidate pairs "
                          f"(all four thresholds), {dt:.1f}s of CPU work"}
 
+    if args.cpu1_seconds > 0:
+        import oracle
+        t_c = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t_c < args.cpu1_seconds:
+            for i, (tn, td) in enumerate(w.thresholds):
+                oracle.verify(coll.offsets, coll.tokens, cands[i][:200000], tn, td, n_threads=1)
+                done += min(cands[i].shape[0], 200000)
+        dt = time.perf_counter() - t_c
+        extra["cpu_baseline_1core"] = {"value": round(done / dt, 1), "unit": "pairs/s", "cores": 1,
+                                       "kind": "oracle",
+                                       "sample": f"the first 200000 candidates of each threshold, "
+                                                 f"{done} pairs, {dt:.1f}s"}
+
     S.ssj_shutdown(ctx)
+    copy_peak = copy_gbs(torch)
 
     rec = {
         "metric": METRIC,
@@ -508,6 +620,8 @@ def main():
             "avg_inorder_ms": round(avg_in_ms, 5),
             "avg_deferred_ms": round(avg_def_ms, 5),
             "timed_launches": launches,
+            "copy_gbs_measured": round(copy_peak, 1),
+            "frac_of_copy": round(achieved / copy_peak, 5),
         },
         "cpu_baseline": cpu,
         "stream": stream,

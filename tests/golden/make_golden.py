@@ -21,6 +21,29 @@ from ssj_inputs import synth  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "manifest.json")
 
+# Other similarity functions of Table 1 over the offline workload's t = 0.6
+# candidates (the overlap threshold is a count).
+SIM_CASES = {2: ((3, 5), (("dice", 7, 10), ("cosine", 3, 5), ("overlap", 8, 1)))}
+# Buckets of |r| + |s| for per-bucket figures on the heavy-tail workload
+# (inclusive upper bounds; the last bucket is open).
+SIZE_BUCKETS = {4: (32, 128, 512, 2048)}
+
+
+def bucket_stats(c, cand, res, cr, cs, bounds):
+    """Candidates, consumed tokens, results and the result digest per bucket of |r| + |s|."""
+    sizes = np.diff(c.offsets)
+    b_cand = np.searchsorted(np.asarray(bounds), sizes[cand[:, 0]] + sizes[cand[:, 1]], side="left")
+    b_res = np.searchsorted(np.asarray(bounds), sizes[res[:, 0]] + sizes[res[:, 1]], side="left")
+    consumed = cr.astype(np.int64) + cs.astype(np.int64)
+    out = []
+    for q in range(len(bounds) + 1):
+        rq = res[b_res == q]
+        out.append({"upper_bound": int(bounds[q]) if q < len(bounds) else None,
+                    "n_candidates": int((b_cand == q).sum()),
+                    "sum_consumed_tokens": int(consumed[b_cand == q].sum()),
+                    "n_result": int(rq.shape[0]), "result_sha256": oracle.result_digest(rq)})
+    return out
+
 
 def main(cfgs):
     man = {}
@@ -45,7 +68,19 @@ def main(cfgs):
                 "result_sha256": oracle.result_digest(res),
                 "sum_consumed_tokens": int(cr.astype(np.int64).sum() + cs.astype(np.int64).sum()),
             }
+            if cfg in SIZE_BUCKETS:
+                entry["thresholds"][f"{tn}/{td}"]["buckets"] = bucket_stats(c, cand, res, cr, cs,
+                                                                            SIZE_BUCKETS[cfg])
             print(cfg, tn, td, entry["thresholds"][f"{tn}/{td}"], round(time.time() - t0, 1), flush=True)
+        if cfg in SIM_CASES:
+            (tn, td), cases = SIM_CASES[cfg]
+            cand = cfilter.workload_candidates(cfg, tn, td)
+            entry["sims"] = {"candidates": f"{tn}/{td}"}
+            for sim, sn, sd in cases:
+                res = oracle.select(c.offsets, c.tokens, cand, sn, sd, n_threads=nt, sim=sim)
+                entry["sims"][f"{sim} {sn}/{sd}"] = {"n_result": int(res.shape[0]),
+                                                      "result_sha256": oracle.result_digest(res)}
+            print(cfg, entry["sims"], flush=True)
         man[str(cfg)] = entry
     with open(OUT, "w") as f:
         json.dump(man, f, indent=1, sort_keys=True)
