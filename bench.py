@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--modes", type=int, default=1,
                     help="also time the output-count mode and the other similarity functions of "
                          "Table 1 on the step's candidates")
+    ap.add_argument("--buckets", type=int, default=1,
+                    help="per-bucket kernel time and B_alg rate, for workloads whose manifest "
+                         "has per-bucket figures")
     ap.add_argument("--cpu1-seconds", type=float, default=3.0,
                     help="CPU work budget of the single-core oracle baseline (0 disables it)")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -335,7 +338,7 @@ def main():
             torch.cuda.synchronize()
 
     buckets = [man["thresholds"][f"{tn}/{td}"].get("buckets") for tn, td in w.thresholds]
-    if all(b is not None for b in buckets):
+    if args.buckets and all(b is not None for b in buckets):
         # kernel time and B_alg rate per bucket of |r| + |s| (each bucket's
         # candidates alone, in their order, one launch per step)
         bounds = [b["upper_bound"] for b in buckets[0][:-1]]
