@@ -239,6 +239,32 @@ def test_config3_long_sets(S, ctx, golden_dir):
     S.ssj_free_collection(ctx, h)
 
 
+def test_extreme_tokens_and_very_long_sets(S, ctx):
+    """Token ids at both ends of the allowed range (0 and 2^31 - 1), and sets
+    of 120,000 tokens (far past the longest length class bound) against each
+    other and against one-token sets, in every mapping."""
+    top = (1 << 31) - 1
+    long1 = list(range(0, 120000))
+    long2 = list(range(0, 119000)) + list(range(top - 999, top + 1))   # overlap 119,000 with long1
+    long3 = list(range(0, 240000, 2))                                     # overlap 60,000 with long1
+    sets = [[top], [top - 1, top], [0, top], list(range(top - 999, top + 1)), [0],
+            long1, long2, long3, list(range(top - 99, top + 1))]
+    c = synth.collection_from_sets(sets)
+    n = c.n_sets
+    cand = np.array([(i, j) for i in range(n) for j in range(n)], dtype=np.int32)
+    h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+    try:
+        for (tn, td) in [(0, 1), (1, 1000), (1, 2), (99, 100), (1, 1)]:
+            want = want_of(c, cand, tn, td)
+            for name, plan in plans():
+                _log(f"extreme tokens t={tn}/{td} {name}")
+                set_plan(S, ctx, plan)
+                assert np.array_equal(run_device(S, ctx, h, cand, tn, td), want), (name, tn, td)
+            assert np.array_equal(run_host(S, ctx, h, cand, tn, td), want), (tn, td)
+    finally:
+        S.ssj_free_collection(ctx, h)
+
+
 def test_errors_and_edges(S, ctx):
     import torch
     c = synth.collection_from_sets([[1, 2, 3], [2, 3, 4], [7]])
