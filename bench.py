@@ -634,6 +634,13 @@ def main():
         "alg_bytes_per_step": int(b_alg),
     }
     rec.update(extra)
+    # the paper's own figures (other hardware, other data): context, not a target
+    rec["paper_context"] = {
+        "speedup_total_join_up_to": 2.6,
+        "speedup_verification_phase_up_to": 5.0,
+        "versus": "the CPU-only join framework it builds on (single-threaded), Sec. 6",
+        "hardware": "Intel i7 5820k at 3.3 GHz, 32 GB RAM; NVIDIA Titan Xp (3840 CUDA cores, 12 GB)",
+    }
     print(json.dumps(rec), flush=True)
     if not parity:
         sys.exit(1)
