@@ -187,8 +187,12 @@ int ssj_verify_rs_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* c
  * ends not decreasing, the last one n_cand, else SSJ_EINVAL; large inputs are
  * split into batches, a group across a batch border in two);
  * ssj_verify_groups_device takes device buffers on hip_stream, with the
- * rules of ssj_verify_device: candidates no group covers, or decreasing
- * ends, make *d_count -1, like an id out of range.
+ * rules of ssj_verify_device: ends that decrease, are negative, exceed n_cand
+ * or stop short of it (the last one must be n_cand), and candidates no group
+ * covers, make *d_count -1, like an id out of range (checked on the device
+ * over every group; with n_cand = 0 nothing is launched and *d_count is 0).
+ * The groups are expanded into flat pairs in the context's scratch before the
+ * usual launch, so device calls on one context must not overlap.
  */
 int ssj_verify_groups(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s,
                       const ssj_group* groups, int64_t n_groups, const int32_t* cand, int64_t n_cand,
