@@ -190,7 +190,8 @@ int ssj_verify_rs_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* c
  * rules of ssj_verify_device: ends that decrease, are negative, exceed n_cand
  * or stop short of it (the last one must be n_cand), and candidates no group
  * covers, make *d_count -1, like an id out of range (checked on the device
- * over every group; with n_cand = 0 nothing is launched and *d_count is 0).
+ * over every group; with n_cand = 0 the ends are not checked and *d_count
+ * is 0).
  * The groups are expanded into flat pairs in the context's scratch before the
  * usual launch, so device calls on one context must not overlap.
  */
