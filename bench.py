@@ -85,6 +85,8 @@ def plan_of(S, spec):
     if kind == "inline":
         return S.make_plan(defer_from=5, **kw)
     if kind == "defer":
+        if len(vals) != 6:
+            raise SystemExit(f"plan {spec!r}: defer needs the first deferred class and five lane counts")
         return S.make_plan(defer_from=vals[0], lanes=vals[1:6], **kw)
     raise SystemExit(f"unknown plan {spec!r}")
 
