@@ -538,10 +538,12 @@ def main():
         t_filter = time.time() - t1
         log(f"stream inputs ready in {time.time() - t0:.1f}s ({len(batches)} batches)")
         h5 = S.ssj_upload_collection(ctx, c5.offsets, c5.tokens)
-        serving.run_stream(S, ctx, h5, batches[:8], None)  # warm-up
-        sat = serving.run_stream(S, ctx, h5, batches, None)
+        # several submitting threads, as filter threads each submit their own batches
+        subs = 4
+        serving.run_stream(S, ctx, h5, batches[:8], None, n_submitters=subs)  # warm-up
+        sat = serving.run_stream(S, ctx, h5, batches, None, n_submitters=subs)
         offered = 0.8 * sat["pairs_per_s"]
-        loaded = serving.run_stream(S, ctx, h5, batches, offered, seed=1)
+        loaded = serving.run_stream(S, ctx, h5, batches, offered, seed=1, n_submitters=subs)
         n5 = sum(b[0].shape[0] for b in batches)
         stream = {
             "workload": (f"{w5.name}: {w5.n_sets} sets, lognormal(mean 12, sigma 0.5) sizes, "

@@ -80,9 +80,14 @@ def build_batches(offsets, tokens, sizes: Sequence[int], thresholds: Sequence[Tu
 
 
 def run_stream(S, ctx, coll, batches, rate_pairs_per_s: Optional[float] = None, seed: int = 0,
-               timeout_s: float = 120.0) -> dict:
+               timeout_s: float = 120.0, n_submitters: int = 1) -> dict:
     """Submits the batches (at Poisson arrivals of the given offered load, or
     as fast as admission allows when rate is None) and collects them.
+
+    n_submitters threads share the arrivals (batch i goes to thread
+    i % n_submitters at its arrival time), as several filter threads each
+    submit the batches they produce; each submit copies its batch into the
+    engine's pinned staging in the submitting thread.
 
     Returns per-batch latency percentiles (ms), the end-to-end rate (pairs/s
     from the first submit to the last completion) and the result count.
@@ -93,14 +98,15 @@ def run_stream(S, ctx, coll, batches, rate_pairs_per_s: Optional[float] = None, 
     mean = float(np.mean([b[0].shape[0] for b in batches])) if n else 1.0
     rng = np.random.default_rng(seed)
     gaps = (rng.exponential(mean / rate_pairs_per_s, size=n) if rate_pairs_per_s else np.zeros(n))
+    arrival = np.cumsum(gaps)
     errors: List[BaseException] = []
+    t0 = time.perf_counter()
 
-    def submitter():
+    def submitter(k):
         try:
-            t_next = time.perf_counter()
-            for i, (cand, tn, td) in enumerate(batches):
-                t_next += gaps[i]
-                delay = t_next - time.perf_counter()
+            for i in range(k, n, n_submitters):
+                cand, tn, td = batches[i]
+                delay = t0 + arrival[i] - time.perf_counter()
                 if delay > 0:
                     time.sleep(delay)
                 tickets[i] = S.ssj_stream_submit(ctx, coll, cand, tn, td)
@@ -114,8 +120,10 @@ def run_stream(S, ctx, coll, batches, rate_pairs_per_s: Optional[float] = None, 
     t_sub = np.zeros(n)
     t_done = np.zeros(n)
     n_result = 0
-    th = threading.Thread(target=submitter, daemon=True)
-    th.start()
+    ths = [threading.Thread(target=submitter, args=(k,), daemon=True) for k in range(max(1, n_submitters))]
+    n_submitters = len(ths)
+    for th in ths:
+        th.start()
     deadline = time.perf_counter() + timeout_s
     for i in range(n):
         if not ready[i].wait(max(0.0, deadline - time.perf_counter())) or errors:
@@ -125,7 +133,8 @@ def run_stream(S, ctx, coll, batches, rate_pairs_per_s: Optional[float] = None, 
         n_result += res.shape[0]
         t_sub[i], t_done[i] = ts, td
         lat[i] = (td - ts) / 1e6
-    th.join(timeout=max(0.0, deadline - time.perf_counter()))
+    for th in ths:
+        th.join(timeout=max(0.0, deadline - time.perf_counter()))
     if errors:
         raise errors[0]
     pairs = int(sum(b[0].shape[0] for b in batches))
@@ -139,4 +148,5 @@ def run_stream(S, ctx, coll, batches, rate_pairs_per_s: Optional[float] = None, 
         "pairs_per_s": round(pairs / span, 1) if span > 0 else None,
         "offered_pairs_per_s": rate_pairs_per_s,
         "results": n_result,
+        "submit_threads": n_submitters,
     }

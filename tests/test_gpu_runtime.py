@@ -172,6 +172,26 @@ def _collect(S, ctx, t):
     return oracle.sort_pairs(S.ssj_stream_collect(ctx, t))
 
 
+def test_run_stream_several_submitters(S, data):
+    """The serving replay with several submitting threads, saturated and at a
+    Poisson offered load, returns every result (counts against the oracle)."""
+    from paper_1812_09141_amd import serving
+    c, reqs = data
+    ctx = S.ssj_init(0, n_slots=3, queue_depth=16)
+    try:
+        h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+        batches = [(cand, tn, td) for (cand, tn, td, _) in reqs] * 3
+        want = 3 * sum(w.shape[0] for (_, _, _, w) in reqs)
+        for rate, subs in [(None, 4), (None, 1), (2e8, 3)]:
+            _log(f"run_stream rate={rate} submitters={subs}")
+            out = serving.run_stream(S, ctx, h, batches, rate, seed=2, n_submitters=subs)
+            assert out["results"] == want and out["batches"] == len(batches)
+            assert out["submit_threads"] == subs
+        S.ssj_free_collection(ctx, h)
+    finally:
+        S.ssj_shutdown(ctx)
+
+
 def test_stream_alone_equals_mix(S, data):
     """Each request's result is identical alone and inside a concurrent mix."""
     c, reqs = data
