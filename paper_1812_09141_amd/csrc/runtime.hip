@@ -49,6 +49,10 @@ constexpr int kMaxWgPerCu = 64;
 // device bytes per candidate pair of a request: the pair, a worst-case output
 // pair, and its queue entries
 constexpr size_t kBytesPerPair = 8 + 8 + 4 * ssj::kQueues;
+// host-buffer verification: candidates pass through a ring of two pinned
+// buffers of kRingPiece pairs, at most kMaxPieces pieces per device batch
+constexpr int64_t kRingPiece = (int64_t)1 << 20;
+constexpr int64_t kMaxPieces = 64;
 
 // Threshold range of a similarity function (SSJ_SIM_*): 0 < t_den < 2^31,
 // 0 <= t_num < 2^31, and t <= 1 for the normalised functions.
@@ -176,6 +180,13 @@ struct ssj_ctx {
     size_t out_cap = 0;
     long long* d_count = nullptr;
     long long* h_count = nullptr;  // pinned
+    // the pinned ring of the host-buffer path (allocated on first use), one
+    // event per buffer (its last copy to the device), per-piece counts
+    int2* h_ring[2] = {nullptr, nullptr};
+    hipEvent_t ring_ev[2] = {nullptr, nullptr};
+    long long* d_counts = nullptr;  // kMaxPieces
+    long long* h_counts = nullptr;  // pinned, kMaxPieces
+    uint64_t ring_seq = 0;
     // grouped candidates: host-call staging of groups and s ids, and the
     // flat pairs they expand to (with one word per 64 candidates)
     int2* d_groups = nullptr;
@@ -893,6 +904,12 @@ int ssj_shutdown(ssj_ctx* ctx) {
             if (q) (void)hipFree(q);
         if (ctx->d_count) (void)hipFree(ctx->d_count);
         if (ctx->h_count) (void)hipHostFree(ctx->h_count);
+        for (int k = 0; k < 2; ++k) {
+            if (ctx->h_ring[k]) (void)hipHostFree(ctx->h_ring[k]);
+            if (ctx->ring_ev[k]) (void)hipEventDestroy(ctx->ring_ev[k]);
+        }
+        if (ctx->d_counts) (void)hipFree(ctx->d_counts);
+        if (ctx->h_counts) (void)hipHostFree(ctx->h_counts);
         for (auto& kv : ctx->graphs) {
             if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
             if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
@@ -1329,6 +1346,53 @@ namespace {
 
 // Host-buffer verification of flat pairs, r ids in coll, s ids in coll_s, in
 // chunks that fit the HBM budget.
+// Copies bytes from pageable to pinned host memory, in up to four threads
+// for large copies (one thread copies at a fraction of what PCIe takes).
+void host_copy(void* dst, const void* src, size_t bytes) {
+    constexpr size_t kSplit = (size_t)4 << 20;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned T = bytes >= kSplit ? std::min(4u, hw) : 1u;
+    if (T <= 1) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t part = ((bytes + T - 1) / T + 63) & ~(size_t)63;
+    auto copy_part = [=](unsigned t) {
+        const size_t b = (size_t)t * part;
+        if (b < bytes) std::memcpy((char*)dst + b, (const char*)src + b, std::min(bytes - b, part));
+    };
+    std::vector<std::thread> th;
+    unsigned t = 1;
+    try {
+        for (; t < T; ++t) th.emplace_back(copy_part, t);
+    } catch (...) {  // no thread: the rest in this one
+        for (; t < T; ++t) copy_part(t);
+    }
+    copy_part(0);
+    for (auto& x : th) x.join();
+}
+
+// The pinned ring and per-piece counts of the host-buffer path (ctx->mu held).
+hipError_t ring_init(ssj_ctx* ctx) {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        if (!ctx->h_ring[k])
+            e = hipHostMalloc((void**)&ctx->h_ring[k], (size_t)kRingPiece * sizeof(int2), hipHostMallocDefault);
+        if (e == hipSuccess && !ctx->ring_ev[k]) e = hipEventCreateWithFlags(&ctx->ring_ev[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess && !ctx->d_counts) e = hipMalloc((void**)&ctx->d_counts, sizeof(long long) * kMaxPieces);
+    if (e == hipSuccess && !ctx->h_counts)
+        e = hipHostMalloc((void**)&ctx->h_counts, sizeof(long long) * kMaxPieces, hipHostMallocDefault);
+    return e;
+}
+
+// Host-buffer verification.  Each device batch (bounded by the HBM budget)
+// of more than kRingPiece pairs is sent in pieces of kRingPiece pairs through
+// two pinned buffers: while the device copies piece k and verifies it (one
+// launch per piece, its own count slot), the host fills the other buffer with
+// piece k + 1.  A batch of one piece is copied straight from the caller's
+// buffer.  The counts of a batch come back in one copy, then each piece's
+// passing pairs.
 int verify_host(ssj_ctx* ctx, const ssj_coll* coll, const ssj_coll* coll_s, const ssj_pair* cand,
                 int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap,
                 int64_t* out_n) {
@@ -1341,38 +1405,57 @@ int verify_host(ssj_ctx* ctx, const ssj_coll* coll, const ssj_coll* coll_s, cons
     if (!out_n || (n_cand > 0 && !cand) || (out_cap > 0 && !out))
         return set_error(SSJ_EINVAL, "null host buffer");
     *out_n = 0;
+    if (n_cand == 0) return SSJ_OK;
     std::lock_guard<std::mutex> g(ctx->mu);
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    HIP_OR_FAIL(ctx, ring_init(ctx));
     hipStream_t st = ctx->stream;
     int64_t chunk = (int64_t)std::max<uint64_t>(1, ctx->budget / kBytesPerPair);
-    chunk = std::min<int64_t>(chunk, kMaxLaunchPairs);
+    chunk = std::min<int64_t>({chunk, kMaxLaunchPairs, kRingPiece * kMaxPieces});
     int64_t total = 0, done = 0;
     bool bad_id = false;
-    do {
+    while (done < n_cand && !bad_id) {
         const int64_t n = std::min<int64_t>(chunk, n_cand - done);
-        HIP_OR_FAIL(ctx, grow(ctx->d_cand, ctx->cand_cap, (size_t)std::max<int64_t>(n, 1)));
-        HIP_OR_FAIL(ctx, grow(ctx->d_out, ctx->out_cap, (size_t)std::max<int64_t>(n, 1)));
-        if (n > 0)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->d_cand, cand + done, (size_t)n * 8, hipMemcpyHostToDevice, st));
-        Req r{ctx->d_cand, n, t_num, t_den, ctx->d_out, n, ctx->d_count, sim};
-        rc = enqueue_launch(ctx, coll, ctx->def, &r, 1, st, ctx->plan, true, coll_s);
-        if (rc != SSJ_OK) return rc;
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_count, ctx->d_count, sizeof(long long), hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(ctx, grow(ctx->d_cand, ctx->cand_cap, (size_t)n));
+        HIP_OR_FAIL(ctx, grow(ctx->d_out, ctx->out_cap, (size_t)n));
+        const int64_t pieces = (n + kRingPiece - 1) / kRingPiece;  // <= kMaxPieces
+        if (pieces == 1) {
+            // nothing to overlap: one copy straight from the caller's buffer
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->d_cand, cand + done, (size_t)n * sizeof(int2),
+                                            hipMemcpyHostToDevice, st));
+            Req r{ctx->d_cand, n, t_num, t_den, ctx->d_out, n, ctx->d_counts, sim};
+            rc = enqueue_launch(ctx, coll, ctx->def, &r, 1, st, ctx->plan, true, coll_s);
+            if (rc != SSJ_OK) return rc;
+        }
+        for (int64_t k = 0; k < pieces && pieces > 1; ++k) {
+            const int64_t off = k * kRingPiece, m = std::min(kRingPiece, n - off);
+            const int slot = (int)(ctx->ring_seq++ & 1u);
+            // the copy out of this buffer issued two pieces ago has finished
+            HIP_OR_FAIL(ctx, hipEventSynchronize(ctx->ring_ev[slot]));
+            host_copy(ctx->h_ring[slot], cand + done + off, (size_t)m * sizeof(int2));
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->d_cand + off, ctx->h_ring[slot], (size_t)m * sizeof(int2),
+                                            hipMemcpyHostToDevice, st));
+            HIP_OR_FAIL(ctx, hipEventRecord(ctx->ring_ev[slot], st));
+            Req r{ctx->d_cand + off, m, t_num, t_den, ctx->d_out + off, m, ctx->d_counts + k, sim};
+            rc = enqueue_launch(ctx, coll, ctx->def, &r, 1, st, ctx->plan, true, coll_s);
+            if (rc != SSJ_OK) return rc;
+        }
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_counts, ctx->d_counts, sizeof(long long) * (size_t)pieces,
+                                        hipMemcpyDeviceToHost, st));
         HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
-        const long long k = *ctx->h_count;
-        if (k < 0) {
-            bad_id = true;
-            break;
+        for (int64_t k = 0; k < pieces; ++k) bad_id |= ctx->h_counts[k] < 0;
+        if (bad_id) break;
+        for (int64_t k = 0; k < pieces; ++k) {
+            const long long c = ctx->h_counts[k];
+            const int64_t take = std::min<int64_t>(std::max<int64_t>(0, out_cap - total), c);
+            if (take > 0)
+                HIP_OR_FAIL(ctx, hipMemcpyAsync(out + total, ctx->d_out + k * kRingPiece, (size_t)take * sizeof(int2),
+                                                hipMemcpyDeviceToHost, st));
+            total += c;
         }
-        const int64_t room = std::max<int64_t>(0, out_cap - total);
-        const int64_t take = std::min<int64_t>(room, k);
-        if (take > 0) {
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(out + total, ctx->d_out, (size_t)take * 8, hipMemcpyDeviceToHost, st));
-            HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
-        }
-        total += k;
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
         done += n;
-    } while (done < n_cand);
+    }
     if (bad_id) {
         *out_n = 0;
         return set_error(SSJ_EINVAL, "candidate id out of range");
