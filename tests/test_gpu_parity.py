@@ -210,6 +210,41 @@ def test_config2_default_plan_matches_manifest(S, ctx, golden_dir):
     S.ssj_free_collection(ctx, h)
 
 
+def test_host_ring_batches_pieces_errors(S, golden_dir):
+    """Host buffers of millions of pairs: several device batches (a budget of
+    2.5M pairs) of several 1M-pair pieces each, against the manifest-checked
+    result; an id error in a late piece; truncation over pieces."""
+    import json
+    man = json.load(open(os.path.join(golden_dir, "manifest.json")))["2"]
+    c = synth.workload_collection(2)
+    cand = cfilter.workload_candidates(2, 3, 5)
+    m = man["thresholds"]["3/5"]
+    ctx = S.ssj_init(0, hbm_budget=40 * 2_500_000)
+    try:
+        h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+        S.ssj_set_plan(ctx, S.make_plan(inline_lanes=1, defer_from=5))
+        one = run_device(S, ctx, h, cand, 3, 5)
+        assert one.shape[0] == m["n_result"] and oracle.result_digest(one) == m["result_sha256"]
+        two = np.concatenate([cand, cand[::-1]])                       # 6.1M pairs
+        _log(f"host ring: {two.shape[0]} pairs")
+        got = oracle.sort_pairs(S.ssj_verify(ctx, h, two, 3, 5))
+        assert np.array_equal(got, oracle.sort_pairs(np.concatenate([one, one])))
+        bad = two.copy()
+        bad[6_100_000] = [c.n_sets, 0]                                 # third batch, second piece
+        with pytest.raises(S.SsjError) as e:
+            S.ssj_verify(ctx, h, bad, 3, 5)
+        assert e.value.code == S.SSJ_EINVAL
+        k = 2 * m["n_result"]
+        with pytest.raises(S.SsjError) as e:
+            S.ssj_verify(ctx, h, two, 3, 5, out_cap=k // 3)
+        assert e.value.code == S.SSJ_ETRUNC and e.value.n == k
+        # the context keeps working
+        assert oracle.sort_pairs(S.ssj_verify(ctx, h, cand, 3, 5)).shape[0] == m["n_result"]
+        S.ssj_free_collection(ctx, h)
+    finally:
+        S.ssj_shutdown(ctx)
+
+
 def test_config3_long_sets(S, ctx, golden_dir):
     import json
     man = json.load(open(os.path.join(golden_dir, "manifest.json")))["3"]
