@@ -564,19 +564,23 @@ struct StreamEngine {
 
 namespace {
 
-void* pinned_get(StreamEngine* E, size_t bytes, size_t* got) {
-    size_t cls = 4096;
-    while (cls < bytes) cls <<= 1;
-    auto& v = E->pool[cls];
-    *got = cls;
-    if (!v.empty()) {
-        void* p = v.back();
-        v.pop_back();
+// A pooled pinned buffer of at least bytes (E->mu held): one of the
+// power-of-two size class holding bytes, else an idle one of a larger class
+// (*cls: the class it returns to), else null: the caller then allocates one
+// of *cls bytes after releasing the lock, since a pinned allocation can take
+// milliseconds and stalls the runtime's other work meanwhile.
+void* pinned_take(StreamEngine* E, size_t bytes, size_t* cls) {
+    size_t c = 4096;
+    while (c < bytes) c <<= 1;
+    *cls = c;
+    for (auto it = E->pool.lower_bound(c); it != E->pool.end(); ++it) {
+        if (it->second.empty()) continue;
+        void* p = it->second.back();
+        it->second.pop_back();
+        *cls = it->first;
         return p;
     }
-    void* p = nullptr;
-    if (hipHostMalloc(&p, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
-    return p;
+    return nullptr;
 }
 
 void pinned_put(StreamEngine* E, void* p, size_t cls) {
@@ -1739,14 +1743,18 @@ int ssj_stream_submit_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* ca
     r->sim = sim;
     r->n = n_cand;
     r->t_submit = now_ns();
-    r->h_cand = (int2*)pinned_get(E, (size_t)std::max<int64_t>(n_cand, 1) * 8, &r->h_cand_bytes);
-    if (!r->h_cand) {
-        delete r;
-        return set_error(SSJ_ENOMEM, "pinned staging allocation failed");
-    }
-    // the copy into staging runs outside the lock; the request is not yet
-    // visible to the engine
+    r->h_cand = (int2*)pinned_take(E, (size_t)std::max<int64_t>(n_cand, 1) * 8, &r->h_cand_bytes);
+    // a new staging buffer and the copy into staging come outside the lock;
+    // the request is not yet visible to the engine
     lk.unlock();
+    if (!r->h_cand) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, r->h_cand_bytes, hipHostMallocDefault) != hipSuccess || !p) {
+            delete r;
+            return set_error(SSJ_ENOMEM, "pinned staging allocation failed");
+        }
+        r->h_cand = (int2*)p;
+    }
     if (n_cand > 0) std::memcpy(r->h_cand, cand, (size_t)n_cand * 8);
     lk.lock();
     coll->inflight.fetch_add(1);
