@@ -991,17 +991,20 @@ __device__ uint32_t first_group_above(const int2* __restrict__ groups, uint32_t 
     return lo;
 }
 
-// Flat pairs (probe, s) of grouped candidates, one wavefront per chunk of
-// kWave candidates: the wavefront finds the first group of its chunk, the
-// lanes load the ends of 64 groups from there, and each lane's group is the
-// number of those ends at or below its candidate index (binary search across
-// the lanes); a lane past all 64 takes the next 64.  A candidate that no
-// group covers gets probe id -1, which the verification reports as an id
-// error.  Every thread also checks a share of the ends (not decreasing, none
-// above n, the last one n) and flags request 0 of ctr on a violation.
+// Flat pairs (probe, s) of grouped candidates.  A wavefront expands a run of
+// `run` consecutive chunks of kWave candidates: it finds the first
+// group of the run, and for each chunk the lanes load the ends of 64 groups
+// from the current group, each lane's group being the number of those ends
+// at or below its candidate index (binary search across the lanes; a lane
+// past all 64 takes the next 64); the next chunk starts from the group of
+// this chunk's last candidate, so a chunk costs one dependent load.  A
+// candidate that no group covers gets probe id -1, which the verification
+// reports as an id error.  Every thread also checks a share of the ends (not
+// decreasing, none above n, the last one n) and flags request 0 of ctr on a
+// violation.
 __global__ void k_expand_groups(const int2* __restrict__ groups, uint32_t n_groups,
-                                const int32_t* __restrict__ cand, uint32_t n, int2* __restrict__ pairs,
-                                Counters* __restrict__ ctr) {
+                                const int32_t* __restrict__ cand, uint32_t n, uint32_t run,
+                                int2* __restrict__ pairs, Counters* __restrict__ ctr) {
     const int lane = lane_id();
     bool bad = false;
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_groups; g += gridDim.x * blockDim.x) {
@@ -1012,32 +1015,39 @@ __global__ void k_expand_groups(const int2* __restrict__ groups, uint32_t n_grou
     if (ballot(bad) != 0ull && lane == 0) atomicOr(&ctr->err[0], 1u);
 
     const uint32_t n_chunks = (n + (uint32_t)kWave - 1u) / (uint32_t)kWave;
+    const uint32_t n_runs = (n_chunks + run - 1u) / run;
     const uint32_t waves = gridDim.x * (blockDim.x / (uint32_t)kWave);
-    for (uint32_t T = (blockIdx.x * blockDim.x + threadIdx.x) / (uint32_t)kWave; T < n_chunks; T += waves) {
-        const uint32_t c = T * (uint32_t)kWave + (uint32_t)lane;
-        const bool valid = c < n;
-        uint32_t g0 = first_group_above(groups, n_groups, T * (uint32_t)kWave, lane);
-        uint32_t g = 0xffffffffu;  // the lane's group once found
-        // all lanes take part in every permute (a permute reads nothing from
-        // an inactive lane); the window moves past at most kWave empty groups
-        // per round
-        while (g0 < n_groups) {
-            const uint32_t gk = g0 + (uint32_t)lane;
-            const uint32_t ek = gk < n_groups ? group_end(groups, gk) : 0xffffffffu;
-            uint32_t pos = 0;
+    for (uint32_t R = (blockIdx.x * blockDim.x + threadIdx.x) / (uint32_t)kWave; R < n_runs; R += waves) {
+        const uint32_t T0 = R * run, T1 = min(T0 + run, n_chunks);
+        uint32_t g0 = first_group_above(groups, n_groups, T0 * (uint32_t)kWave, lane);
+        for (uint32_t T = T0; T < T1; ++T) {
+            const uint32_t c = T * (uint32_t)kWave + (uint32_t)lane;
+            const bool valid = c < n;
+            const int32_t sv = valid ? cand[c] : 0;
+            uint32_t g = 0xffffffffu;  // the lane's group once found
+            // all lanes take part in every permute (a permute reads nothing
+            // from an inactive lane); the window moves past at most kWave
+            // empty groups per round
+            uint32_t w0 = g0;
+            while (w0 < n_groups) {
+                const uint32_t gk = w0 + (uint32_t)lane;
+                const uint32_t ek = gk < n_groups ? group_end(groups, gk) : 0xffffffffu;
+                uint32_t pos = 0;
 #pragma unroll
-            for (uint32_t step = kWave / 2; step >= 1; step >>= 1) {
-                const uint32_t v = (uint32_t)bperm((int)ek, (int)(pos + step - 1u));
-                pos += (v <= c) ? step : 0u;
+                for (uint32_t step = kWave / 2; step >= 1; step >>= 1) {
+                    const uint32_t v = (uint32_t)bperm((int)ek, (int)(pos + step - 1u));
+                    pos += (v <= c) ? step : 0u;
+                }
+                const bool beyond = (uint32_t)bperm((int)ek, kWave - 1) <= c;
+                if (g == 0xffffffffu && !beyond) g = w0 + pos;
+                if (ballot(valid && g == 0xffffffffu) == 0ull) break;
+                w0 += (uint32_t)kWave;
             }
-            const bool beyond = (uint32_t)bperm((int)ek, kWave - 1) <= c;
-            if (g == 0xffffffffu && !beyond) g = g0 + pos;
-            if (ballot(valid && g == 0xffffffffu) == 0ull) break;
-            g0 += (uint32_t)kWave;
-        }
-        if (valid) {
-            const int32_t r = g < n_groups ? groups[g].x : -1;
-            pairs[c] = make_int2(r, cand[c]);
+            if (valid) pairs[c] = make_int2(g < n_groups ? groups[g].x : -1, sv);
+            // the next chunk's first group is at or after this chunk's last
+            // candidate's group (ends not decreasing; any start keeps the
+            // search in bounds otherwise)
+            g0 = min((uint32_t)__builtin_amdgcn_readlane((int)g, kWave - 1), n_groups);
         }
     }
 }
@@ -1108,9 +1118,14 @@ hipError_t launch_expand_groups(const int2* d_groups, int64_t n_groups, const in
                                 Counters* d_ctr, int2* d_pairs, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const int64_t n_chunks = (n + kWave - 1) / kWave;
-    const int64_t b = std::min<int64_t>((n_chunks + kBlock / kWave - 1) / (kBlock / kWave), 65536);
+    // chunks per wavefront: one while the chunks alone fill the device (every
+    // chunk then waits for its own search in parallel), up to 8 beyond that
+    // (later chunks of a run skip the search but wait for the chunk before)
+    const int64_t run = std::min<int64_t>(8, std::max<int64_t>(1, (n_chunks + 8191) / 8192));
+    const int64_t n_runs = (n_chunks + run - 1) / run;
+    const int64_t b = std::min<int64_t>((n_runs + kBlock / kWave - 1) / (kBlock / kWave), 65536);
     hipLaunchKernelGGL(k_expand_groups, dim3((unsigned)b), dim3(kBlock), 0, st, d_groups,
-                       (uint32_t)n_groups, d_cand, (uint32_t)n, d_pairs, d_ctr);
+                       (uint32_t)n_groups, d_cand, (uint32_t)n, (uint32_t)run, d_pairs, d_ctr);
     return hipGetLastError();
 }
 
