@@ -578,7 +578,8 @@ def main():
         dt = time.perf_counter() - t_c
         cpu = {"value": round(done / dt, 1), "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
                "sample": f"{reps} full passes over the step's {n_pairs} candidate pairs "
-                         f"(all four thresholds), {dt:.1f}s of CPU work"}
+                         f"({len(w.thresholds)} threshold{'s' if len(w.thresholds) > 1 else ''}), "
+                         f"{dt:.1f}s of CPU work"}
 
     if args.cpu1_seconds > 0:
         import oracle
