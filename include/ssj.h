@@ -204,6 +204,35 @@ int ssj_verify_groups_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_col
                              int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* d_out,
                              int64_t out_cap, int64_t* d_count, void* hip_stream);
 
+/* One request of a batched grouped launch: device buffers owned by the
+ * caller, with the meaning of the ssj_verify_groups_device arguments of the
+ * same names (sim = 0 is SSJ_SIM_JACCARD). */
+typedef struct {
+    const ssj_group* d_groups;
+    int64_t n_groups;
+    const int32_t* d_cand;
+    int64_t n_cand;
+    int64_t t_num;
+    int64_t t_den;
+    ssj_pair* d_out;
+    int64_t out_cap;
+    int64_t* d_count;
+    int32_t sim;
+} ssj_group_request;
+
+/*
+ * Batched grouped verification (Sec. 3.3.1 C / C_O per request): up to
+ * SSJ_MAX_BATCH requests over one pair of collections, each expanded into
+ * flat pairs in the context's scratch, then verified together by one launch
+ * on hip_stream (as ssj_verify_batch_device).  Each d_count receives its
+ * request's count, or -1 when that request's groups are malformed (the
+ * rules of ssj_verify_groups_device) or an id is out of range; the other
+ * requests are unaffected.  The candidates of all requests together must
+ * stay below 2^31.  Device calls on one context must not overlap.
+ */
+int ssj_verify_groups_batch_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s,
+                                   const ssj_group_request* reqs, int n_reqs, void* hip_stream);
+
 /*
  * The whole self-join on the GPU: candidate generation by the prefix filter
  * with the length filter (Sec. 2.2 "Filters"; Sec. 3.1 AllPairs) and, with

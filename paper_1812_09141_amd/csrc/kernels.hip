@@ -1000,11 +1000,11 @@ __device__ uint32_t first_group_above(const int2* __restrict__ groups, uint32_t 
 // this chunk's last candidate, so a chunk costs one dependent load.  A
 // candidate that no group covers gets probe id -1, which the verification
 // reports as an id error.  Every thread also checks a share of the ends (not
-// decreasing, none above n, the last one n) and flags request 0 of ctr on a
-// violation.
+// decreasing, none above n, the last one n) and flags request req of ctr on
+// a violation.
 __global__ void k_expand_groups(const int2* __restrict__ groups, uint32_t n_groups,
                                 const int32_t* __restrict__ cand, uint32_t n, uint32_t run,
-                                int2* __restrict__ pairs, Counters* __restrict__ ctr) {
+                                int2* __restrict__ pairs, Counters* __restrict__ ctr, int req) {
     const int lane = lane_id();
     bool bad = false;
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_groups; g += gridDim.x * blockDim.x) {
@@ -1012,7 +1012,7 @@ __global__ void k_expand_groups(const int2* __restrict__ groups, uint32_t n_grou
         const int32_t prev = g > 0u ? (int32_t)group_end(groups, g - 1u) : 0;
         bad |= e < prev || (uint32_t)e > n || (g + 1u == n_groups && (uint32_t)e != n);
     }
-    if (ballot(bad) != 0ull && lane == 0) atomicOr(&ctr->err[0], 1u);
+    if (ballot(bad) != 0ull && lane == 0) atomicOr(&ctr->err[req], 1u);
 
     const uint32_t n_chunks = (n + (uint32_t)kWave - 1u) / (uint32_t)kWave;
     const uint32_t n_runs = (n_chunks + run - 1u) / run;
@@ -1115,7 +1115,7 @@ const void* kernel_verify_deferred(bool cosine) {
 }
 
 hipError_t launch_expand_groups(const int2* d_groups, int64_t n_groups, const int32_t* d_cand, int64_t n,
-                                Counters* d_ctr, int2* d_pairs, hipStream_t st) {
+                                Counters* d_ctr, int req, int2* d_pairs, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const int64_t n_chunks = (n + kWave - 1) / kWave;
     // chunks per wavefront: one while the chunks alone fill the device (every
@@ -1125,7 +1125,7 @@ hipError_t launch_expand_groups(const int2* d_groups, int64_t n_groups, const in
     const int64_t n_runs = (n_chunks + run - 1) / run;
     const int64_t b = std::min<int64_t>((n_runs + kBlock / kWave - 1) / (kBlock / kWave), 65536);
     hipLaunchKernelGGL(k_expand_groups, dim3((unsigned)b), dim3(kBlock), 0, st, d_groups,
-                       (uint32_t)n_groups, d_cand, (uint32_t)n, (uint32_t)run, d_pairs, d_ctr);
+                       (uint32_t)n_groups, d_cand, (uint32_t)n, (uint32_t)run, d_pairs, d_ctr, req);
     return hipGetLastError();
 }
 

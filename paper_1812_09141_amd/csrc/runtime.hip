@@ -1146,7 +1146,7 @@ int enqueue_groups(ssj_ctx* ctx, const ssj_coll* R, const ssj_coll* S, const int
                    int64_t n_groups, const int32_t* d_sids, int64_t n_cand, int sim, int64_t t_num,
                    int64_t t_den, int2* d_out, int64_t out_cap, long long* d_count, hipStream_t st) {
     HIP_OR_FAIL(ctx, grow(ctx->d_pairs, ctx->pairs_cap, (size_t)std::max<int64_t>(n_cand, 1)));
-    HIP_OR_FAIL(ctx, ssj::launch_expand_groups(d_groups, n_groups, d_sids, n_cand, ctx->def.d_ctr,
+    HIP_OR_FAIL(ctx, ssj::launch_expand_groups(d_groups, n_groups, d_sids, n_cand, ctx->def.d_ctr, 0,
                                                ctx->d_pairs, st));
     Req r{ctx->d_pairs, n_cand, t_num, t_den, d_out, out_cap, d_count, sim};
     return enqueue_launch(ctx, R, ctx->def, &r, 1, st, ctx->plan, true, S);
@@ -1188,6 +1188,44 @@ int ssj_verify_groups_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_col
     return enqueue_groups(ctx, coll_r, coll_s, reinterpret_cast<const int2*>(d_groups), n_groups, d_cand,
                           n_cand, sim, t_num, t_den, reinterpret_cast<int2*>(d_out), out_cap,
                           reinterpret_cast<long long*>(d_count), (hipStream_t)hip_stream);
+}
+
+int ssj_verify_groups_batch_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s,
+                                   const ssj_group_request* reqs, int n_reqs, void* hip_stream) {
+    int rc = check_ctx(ctx);
+    if (rc != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll_r)) != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll_s)) != SSJ_OK) return rc;
+    if (n_reqs < 0 || n_reqs > ssj::kMaxReq || (n_reqs > 0 && !reqs))
+        return set_error(SSJ_EINVAL, "n_reqs must be in [0, SSJ_MAX_BATCH]");
+    int64_t total = 0;
+    for (int i = 0; i < n_reqs; ++i) {
+        const ssj_group_request& q = reqs[i];
+        if (!valid_threshold(q.sim, q.t_num, q.t_den)) return set_error(SSJ_EINVAL, kThresholdError);
+        if (q.n_groups < 0 || q.n_cand < 0 || q.out_cap < 0) return set_error(SSJ_EINVAL, "negative size");
+        if (q.n_groups > kMaxLaunchPairs) return set_error(SSJ_EINVAL, "n_groups must be below 2^31");
+        if (!q.d_count || (q.n_cand > 0 && !q.d_cand) || (q.n_groups > 0 && !q.d_groups))
+            return set_error(SSJ_EINVAL, "null device buffer");
+        total += q.n_cand;
+        if (total > kMaxLaunchPairs) return set_error(SSJ_EINVAL, "a batch must hold fewer than 2^31 candidates");
+    }
+    if (n_reqs == 0) return SSJ_OK;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_OR_FAIL(ctx, grow(ctx->d_pairs, ctx->pairs_cap, (size_t)std::max<int64_t>(total, 1)));
+    std::vector<Req> v((size_t)n_reqs);
+    int64_t off = 0;
+    for (int i = 0; i < n_reqs; ++i) {
+        const ssj_group_request& q = reqs[i];
+        // request i's expansion flags malformed groups in request i's error word
+        HIP_OR_FAIL(ctx, ssj::launch_expand_groups(reinterpret_cast<const int2*>(q.d_groups), q.n_groups, q.d_cand,
+                                                   q.n_cand, ctx->def.d_ctr, i, ctx->d_pairs + off, st));
+        v[i] = Req{ctx->d_pairs + off, q.n_cand, q.t_num, q.t_den, reinterpret_cast<int2*>(q.d_out), q.out_cap,
+                   reinterpret_cast<long long*>(q.d_count), q.sim};
+        off += q.n_cand;
+    }
+    return enqueue_launch(ctx, coll_r, ctx->def, v.data(), n_reqs, st, ctx->plan, true, coll_s);
 }
 
 namespace {

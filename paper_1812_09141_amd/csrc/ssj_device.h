@@ -84,10 +84,11 @@ hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start,
 // Flat pairs d_pairs[0..n) from grouped candidates: groups {probe id,
 // exclusive end into d_cand} and s ids d_cand (n > 0).  Candidates no group
 // covers get probe id -1; malformed ends (decreasing, above n, the last one
-// not n) set the error flag of request 0 in d_ctr, which the launch that
-// verifies d_pairs with these counters then reports and clears.
+// not n) set the error flag of request req in d_ctr, which the launch that
+// verifies d_pairs as its request req with these counters then reports and
+// clears.
 hipError_t launch_expand_groups(const int2* d_groups, int64_t n_groups, const int32_t* d_cand, int64_t n,
-                                Counters* d_ctr, int2* d_pairs, hipStream_t st);
+                                Counters* d_ctr, int req, int2* d_pairs, hipStream_t st);
 // The in-order kernel: every pair of a class below defer_from is verified
 // with inline_lanes lanes; the others are queued for launch_verify_deferred,
 // and so is every thread-per-pair merge still undecided after spill_iters

@@ -48,6 +48,7 @@ EXPORTED = (
     "ssj_collection_info", "ssj_timing_enable", "ssj_timing_read", "ssj_verify_batch_device",
     "ssj_autotune", "ssj_verify_sim", "ssj_verify_device_sim", "ssj_stream_submit_sim",
     "ssj_verify_rs", "ssj_verify_rs_device", "ssj_verify_groups", "ssj_verify_groups_device",
+    "ssj_verify_groups_batch_device",
     "ssj_candidates_device", "ssj_join_device", "ssj_join",
 )
 
@@ -94,6 +95,14 @@ class ssj_request(ctypes.Structure):
                 ("d_count", ctypes.c_void_p), ("sim", ctypes.c_int32)]
 
 
+class ssj_group_request(ctypes.Structure):
+    _fields_ = [("d_groups", ctypes.c_void_p), ("n_groups", ctypes.c_int64),
+                ("d_cand", ctypes.c_void_p), ("n_cand", ctypes.c_int64),
+                ("t_num", ctypes.c_int64), ("t_den", ctypes.c_int64),
+                ("d_out", ctypes.c_void_p), ("out_cap", ctypes.c_int64),
+                ("d_count", ctypes.c_void_p), ("sim", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -132,6 +141,7 @@ def load_library(path: str = LIB_PATH):
         "ssj_verify_rs_device": ([p, p, p, p, i64, c_int, i64, i64, p, i64, p, p], c_int),
         "ssj_verify_groups": ([p, p, p, p, i64, p, i64, c_int, i64, i64, p, i64, P(i64)], c_int),
         "ssj_verify_groups_device": ([p, p, p, p, i64, p, i64, c_int, i64, i64, p, i64, p, p], c_int),
+        "ssj_verify_groups_batch_device": ([p, p, p, P(ssj_group_request), c_int, p], c_int),
         "ssj_candidates_device": ([p, p, i64, i64, c_int, p, i64, p, p], c_int),
         "ssj_join_device": ([p, p, i64, i64, c_int, p, i64, p, p], c_int),
         "ssj_join": ([p, p, i64, i64, c_int, p, i64, P(i64)], c_int),
@@ -326,6 +336,32 @@ def ssj_verify_groups_device(ctx, coll_r, coll_s, d_groups: "torch.Tensor", d_ca
         ctx, coll_r, coll_s, d_groups.data_ptr() if ng else None, ng, d_cand.data_ptr() if n else None,
         n, sim_code(sim), int(t_num), int(t_den), d_out.data_ptr() if cap else None, cap,
         d_count.data_ptr(), ctypes.c_void_p(st.cuda_stream))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def ssj_verify_groups_batch_device(ctx, coll_r, coll_s, requests, stream=None) -> None:
+    """requests: list of (d_groups, d_cand, t_num, t_den, d_out, d_count[, sim]) with
+    d_groups (n_groups, 2) int32 and d_cand int32 s ids on the device; one launch."""
+    n = len(requests)
+    arr = (ssj_group_request * max(n, 1))()
+    dev = None
+    for i, req in enumerate(requests):
+        d_groups, d_cand, tn, td, d_out, d_count = req[:6]
+        sim = sim_code(req[6]) if len(req) > 6 else SSJ_SIM_JACCARD
+        assert d_groups.is_cuda and d_groups.dtype == torch.int32 and d_groups.is_contiguous()
+        assert d_cand.is_cuda and d_cand.dtype == torch.int32 and d_cand.is_contiguous()
+        if d_out is not None:
+            assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
+        assert d_count.is_cuda and d_count.dtype == torch.int64
+        ng = d_groups.numel() // 2
+        nc = d_cand.numel()
+        cap = d_out.numel() // 2 if d_out is not None else 0
+        arr[i] = ssj_group_request(d_groups.data_ptr() if ng else None, ng, d_cand.data_ptr() if nc else None, nc,
+                                   int(tn), int(td), d_out.data_ptr() if cap else None, cap, d_count.data_ptr(), sim)
+        dev = d_cand.device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    rc = load_library().ssj_verify_groups_batch_device(ctx, coll_r, coll_s, arr, n, ctypes.c_void_p(st.cuda_stream))
     if rc != SSJ_OK:
         _err(ctx, rc)
 

@@ -120,3 +120,20 @@ def test_groups_of_runs():
     assert s.tolist() == [1, 2, 5, 5, 0, 7]
     g0, s0 = ssj.groups_of(np.zeros((0, 2), np.int32))
     assert g0.shape == (0, 2) and s0.shape == (0,)
+
+
+def test_group_request_layout():
+    """ssj_group_request in the binding matches the C layout of include/ssj.h
+    (pointers and int64 fields in declaration order, then an int32; 80 bytes)."""
+    import ctypes
+    from paper_1812_09141_amd import ssj as S
+    t = S.ssj_group_request
+    names = [f[0] for f in t._fields_]
+    assert names == ["d_groups", "n_groups", "d_cand", "n_cand", "t_num", "t_den", "d_out", "out_cap",
+                     "d_count", "sim"]
+    assert [getattr(t, n).offset for n in names] == [0, 8, 16, 24, 32, 40, 48, 56, 64, 72]
+    assert ctypes.sizeof(t) == 80
+    src = open(os.path.join(ROOT, "include", "ssj.h")).read()
+    body = src[src.index("typedef struct {\n    const ssj_group* d_groups;"):]
+    body = body[:body.index("} ssj_group_request;")]
+    assert [ln.strip().rstrip(";").split()[-1].lstrip("*") for ln in body.splitlines()[1:] if ln.strip()] == names

@@ -327,3 +327,66 @@ def test_groups_many_and_malformed_large(S, ctx):
     finally:
         S.ssj_free_collection(ctx, hr)
         S.ssj_free_collection(ctx, hs)
+
+
+def test_groups_batch_one_launch(S, ctx, golden_dir):
+    """The offline step's four threshold lists as grouped requests of one
+    batched launch give the manifest results; a malformed request inside a
+    batch gets -1 and leaves the others exact; a mixed-function batch equals
+    the single calls."""
+    import json
+    import torch
+    man = json.load(open(os.path.join(golden_dir, "manifest.json")))["2"]
+    c = synth.workload_collection(2)
+    h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+    dev = torch.device("cuda:0")
+    try:
+        S.ssj_set_plan(ctx, S.make_plan(inline_lanes=1, defer_from=5))
+        reqs, meta = [], []
+        for tn, td in synth.WORKLOADS[2].thresholds:
+            g, si = S.groups_of(cfilter.workload_candidates(2, tn, td))
+            d_out = torch.empty((si.shape[0], 2), dtype=torch.int32, device=dev)
+            d_cnt = torch.full((1,), -7, dtype=torch.int64, device=dev)
+            reqs.append((torch.from_numpy(g).to(dev), torch.from_numpy(si).to(dev), tn, td, d_out, d_cnt))
+            meta.append(man["thresholds"][f"{tn}/{td}"])
+        _log("groups batch: four thresholds")
+        S.ssj_verify_groups_batch_device(ctx, h, h, reqs)
+        torch.cuda.synchronize()
+        for (_, _, tn, td, d_out, d_cnt), m in zip(reqs, meta):
+            k = int(d_cnt.item())
+            assert k == m["n_result"], (tn, td)
+            assert oracle.result_digest(d_out[:k].cpu().numpy()) == m["result_sha256"]
+        # a malformed request (decreasing ends) in the middle of the batch
+        bad_g = reqs[1][0].clone()
+        bad_g[5, 1] = bad_g[4, 1] - 1
+        mixed = [reqs[0], (bad_g,) + reqs[1][1:], reqs[2], reqs[3]]
+        for r in mixed:
+            r[5].fill_(-7)
+        _log("groups batch: malformed second request")
+        S.ssj_verify_groups_batch_device(ctx, h, h, mixed)
+        torch.cuda.synchronize()
+        assert int(mixed[1][5].item()) == -1
+        for i in (0, 2, 3):
+            k = int(mixed[i][5].item())
+            assert k == meta[i]["n_result"]
+            assert oracle.result_digest(mixed[i][4][:k].cpu().numpy()) == meta[i]["result_sha256"]
+        # other similarity functions in one batch, against single grouped calls
+        g0, s0 = reqs[1][0], reqs[1][1]
+        sims = [("dice", 7, 10), ("cosine", 3, 5), ("overlap", 8, 1), ("jaccard", 1, 2)]
+        outs = [(torch.empty((s0.numel(), 2), dtype=torch.int32, device=dev),
+                 torch.zeros(1, dtype=torch.int64, device=dev)) for _ in sims]
+        S.ssj_verify_groups_batch_device(ctx, h, h, [(g0, s0, tn, td, o, n, sim)
+                                                     for (sim, tn, td), (o, n) in zip(sims, outs)])
+        torch.cuda.synchronize()
+        for (sim, tn, td), (o, n) in zip(sims, outs):
+            o1 = torch.empty_like(o)
+            n1 = torch.zeros(1, dtype=torch.int64, device=dev)
+            S.ssj_verify_groups_device(ctx, h, h, g0, s0, sim, tn, td, o1, n1)
+            torch.cuda.synchronize()
+            k = int(n.item())
+            assert k == int(n1.item()) >= 0, sim
+            assert np.array_equal(oracle.sort_pairs(o[:k].cpu().numpy()), oracle.sort_pairs(o1[:k].cpu().numpy()))
+        with pytest.raises(S.SsjError):
+            S.ssj_verify_groups_batch_device(ctx, h, h, [reqs[0]] * 17)
+    finally:
+        S.ssj_free_collection(ctx, h)
