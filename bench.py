@@ -1,15 +1,25 @@
 #!/usr/bin/env python3
 """Verification throughput on one MI355X: verified candidate pairs per second.
 
-Workload (default): the offline verification collection -- 100,000 sets,
-lognormal sizes (arithmetic mean 12, sigma 0.5) clipped to 2..200, tokens
-Zipf(1.0) over 200,000 ids -- joined at Jaccard t in {0.6, 0.7, 0.8, 0.9};
-all prefix+length filter candidates of each threshold verified in one call
-per threshold.  One step = the four calls.  The collection and the candidate
-pairs are resident in HBM before the timed region starts; output pairs and
-counts stay in HBM (ssj_verify_device).
+Workloads (synthetic stand-ins for the paper's datasets, all Jaccard
+self-joins; candidates from the AllPairs prefix + length filter):
+  * heavytail (the headline, the largest configuration that fits one GPU):
+    500,000 sets, sizes Pareto(alpha 1.5, minimum 3) clipped to 5,000, tokens
+    Zipf(1.2) over 2,000,000 ids, t = 3/4: 168,588,056 candidates per step;
+  * longsets: 50,000 sets, lognormal sizes (arithmetic mean 130, sigma 0.8)
+    clipped to 10..2,000, Zipf(0.9) over 1,000,000 ids, t = 7/10;
+  * offline: 100,000 sets, lognormal sizes (mean 12, sigma 0.5) clipped to
+    2..200, Zipf(1.0) over 200,000 ids, t in {0.6, 0.7, 0.8, 0.9}, the four
+    thresholds' candidates in one batched launch per step.
+One step of a workload = one batched launch over all of its candidates
+(ssj_verify_batch_device).  The collection and the candidate pairs are
+resident in HBM before the timed region starts; outputs stay in HBM.  Every
+workload's result is checked against the oracle's digests in the golden
+manifest.  The streamed-serving phase uses the 1,000,000-set collection.
 
-Prints one JSON line.  --gpus N > 1 is not supported (one GPU only).
+Prints one JSON line: the headline workload's figures at the top level, the
+other workloads under "workloads".  --gpus N > 1 is not supported (one GPU
+only).
 """
 import argparse
 import json
@@ -25,63 +35,70 @@ METRIC = "verified candidate pairs/sec + achieved HBM GB/s; p50/p99 batch latenc
 PEAK_HBM_GBS = 8000.0
 TIMING_PERIOD = 5
 WORKLOAD_CFG = {"offline": 2, "tiny": 1, "longsets": 3, "heavytail": 4}
+DEFAULT_WORKLOADS = "heavytail,longsets,offline"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="offline", choices=sorted(WORKLOAD_CFG))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOADS,
+                    help="comma-separated workloads; the first is the headline "
+                         f"({', '.join(sorted(WORKLOAD_CFG))})")
     ap.add_argument("--plan", default="auto",
-                    help="auto (autotuned) | inline:M | defer:M,D,l0,l1,l2,l3,l4 with M = L[hF][sI[xG]][wW]")
+                    help="auto (autotuned per workload) | inline:M | defer:M,D,l0,l1,l2,l3,l4 with "
+                         "M = L[b][hF][sI[xG]][wW]")
     ap.add_argument("--compare-plain", type=int, default=1,
-                    help="also time plain one-launch-per-batch verification")
+                    help="also time plain one-launch-per-batch verification (multi-threshold workloads)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="CPU work budget of the oracle baseline (0 disables it)")
+                    help="CPU work budget of the oracle baseline on the headline workload (0 disables it)")
     ap.add_argument("--stream-batches", type=int, default=200,
                     help="streamed-serving phase: batches drawn from the 1,000,000-set "
                          "collection (0 disables it)")
     ap.add_argument("--sweep", default="",
                     help="semicolon-separated plan specs to time as well (reported under 'sweep')")
     ap.add_argument("--ppjoin", type=int, default=1,
-                    help="also verify the step's thresholds from PPJoin candidates (positional "
-                         "filter) and report both filters' CPU time")
+                    help="offline workload: the whole join on the GPU (device filters + verification)")
     ap.add_argument("--ingest", type=int, default=1,
-                    help="also time grouped candidates (probe id + s ids) and an R-S join "
-                         "(even-numbered against odd-numbered sets)")
+                    help="offline workload: grouped candidates (probe id + s ids), an R-S join and "
+                         "PPJoin candidates")
     ap.add_argument("--modes", type=int, default=1,
-                    help="also time the output-count mode and the other similarity functions of "
-                         "Table 1 on the step's candidates")
+                    help="output-count mode, and the other similarity functions of Table 1 on the "
+                         "offline workload")
     ap.add_argument("--buckets", type=int, default=1,
                     help="per-bucket kernel time and B_alg rate, for workloads whose manifest "
                          "has per-bucket figures")
     ap.add_argument("--cpu1-seconds", type=float, default=3.0,
                     help="CPU work budget of the single-core oracle baseline (0 disables it)")
+    ap.add_argument("--host-api", type=int, default=1,
+                    help="PCIe-inclusive rate of the host-buffer entry point (context only)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (5 times), "
                          "the reference for HBM byte counters, and exit")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def plan_of(S, spec):
-    """auto | inline:M | defer:M,D,l0,l1,l2,l3,l4 with M = L[hF][sI[xG]][wW] (L lanes per pair,
-    F hard lanes, I window steps before a merge spills to G lanes, W in-order workgroups per
-    compute unit, D first deferred class)"""
+    """auto | inline:M | defer:M,D,l0,l1,l2,l3,l4 with M = L[b][hF][sI[xG]][wW] (L lanes per pair,
+    b the staged kernel (token blocks in LDS), F hard lanes, I window steps (staged: block
+    rounds) before a merge spills to G lanes, W in-order workgroups per compute unit, D first
+    deferred class)"""
     if spec == "auto":
         return None
     kind, _, rest = spec.partition(":")
     parts = rest.split(",") if rest else []
-    m = re.fullmatch(r"(\d+)(?:h(\d+))?(?:s(\d+)(?:x(\d+))?)?(?:w(\d+))?", parts[0] if parts else "")
+    m = re.fullmatch(r"(\d+)(b)?(?:h(\d+))?(?:s(\d+)(?:x(\d+))?)?(?:w(\d+))?", parts[0] if parts else "")
     if not m:
         raise SystemExit(f"bad mapping in plan {spec!r}")
-    L, F, I, G, W = (int(v) if v else d for v, d in zip(m.groups(), (1, 0, 0, 16, 0)))
+    L, F, I, G, W = (int(v) if v else d for v, d in zip(m.groups()[:1] + m.groups()[2:], (1, 0, 0, 16, 0)))
     vals = [int(v) for v in parts[1:]]
-    kw = dict(inline_lanes=L, hard_lanes=F, spill_iters=I, spill_lanes=G, wg_per_cu=W)
+    kw = dict(inline_lanes=L, hard_lanes=F, spill_iters=I, spill_lanes=G, wg_per_cu=W,
+              staged=1 if m.group(2) else 0)
     if kind == "inline":
         return S.make_plan(defer_from=5, **kw)
     if kind == "defer":
@@ -97,20 +114,24 @@ def load_manifest(cfg):
 
 
 def traffic_from_profiles(kernel_src_hash, workload, kernel):
-    """HBM bytes per verify launch from committed PMC summaries, if they were
-    taken for this kernel source, workload and kernel instance."""
-    p = os.path.join(ROOT, "profiles", "verify_tiles_offline_traffic.json")
-    if not os.path.exists(p):
+    """HBM bytes per verify launch from the committed PMC summaries
+    (profiles/*_traffic.json), if one was taken for this kernel source,
+    workload and kernel instance."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
         return None
-    try:
-        with open(p) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if (d.get("kernel_source_sha256") != kernel_src_hash or d.get("workload_key") != workload
-            or d.get("kernel") != kernel):
-        return None
-    return d.get("bytes_per_launch")
+    for name in sorted(os.listdir(d)):
+        if not name.endswith("_traffic.json"):
+            continue
+        try:
+            with open(os.path.join(d, name)) as f:
+                t = json.load(f)
+        except (OSError, ValueError):
+            continue
+        if (t.get("kernel_source_sha256") == kernel_src_hash and t.get("workload_key") == workload
+                and t.get("kernel") == kernel):
+            return t.get("bytes_per_launch")
+    return None
 
 
 def kernel_source_hash():
@@ -120,6 +141,17 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, "paper_1812_09141_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def kernel_name_of(plan):
+    """The verification kernels a plan runs (as rocprofv3 names their instances)."""
+    deferred = plan.defer_from < 5 or plan.spill_iters > 0
+    if plan.staged:
+        first = f"k_verify_staged<{'true' if deferred else 'false'},false>"
+    else:
+        first = (f"k_verify_tiles<{plan.inline_lanes},{plan.hard_lanes},"
+                 f"{'true' if deferred else 'false'},false>")
+    return first + (" + k_verify_deferred<false>" if deferred else "")
 
 
 def copy_gbs(torch, mib=1024, reps=5):
@@ -160,6 +192,530 @@ def timed_steps(torch, step, steps, warmup):
     return time.perf_counter() - t0
 
 
+def host_cpu():
+    """The host's CPU model and thread counts (affinity, os.cpu_count)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        nproc = os.cpu_count() or 1
+    return {"model": model, "nproc": nproc, "cpu_count": os.cpu_count()}
+
+
+def workload_text(cfg, w, n_pairs):
+    law = w.size_law
+    if law[0] == "lognormal":
+        sizes = f"sizes lognormal(mean {law[1]:g}, sigma {law[2]:g}) clipped {law[3]}-{law[4]}"
+    elif law[0] == "pareto":
+        sizes = f"sizes Pareto(alpha {law[1]:g}, min {law[2]}) clipped to {law[3]}"
+    else:
+        sizes = f"sizes uniform {law[1]}-{law[2]}"
+    ts = ",".join(f"{tn}/{td}" for tn, td in w.thresholds)
+    return (f"{w.name} (config {cfg}): {w.n_sets} sets, {sizes}, Zipf({w.zipf_s:g}) over {w.universe} "
+            f"tokens; Jaccard t in {{{ts}}}; {n_pairs} prefix+length candidates per step, one launch")
+
+
+class Workload:
+    """Inputs of one workload in HBM, its batched step and its manifest check."""
+
+    def __init__(self, S, torch, ctx, name):
+        import numpy as np
+        from ssj_inputs import filter as cfilter
+        from ssj_inputs import synth
+        self.S, self.torch, self.ctx, self.name = S, torch, ctx, name
+        self.cfg = WORKLOAD_CFG[name]
+        self.w = synth.WORKLOADS[self.cfg]
+        self.man = load_manifest(self.cfg)
+        t0 = time.time()
+        self.coll = synth.workload_collection(self.cfg)
+        if self.coll.digest() != self.man["collection_sha256"]:
+            raise SystemExit(f"{name}: generated collection differs from the manifest")
+        self.cands = [cfilter.workload_candidates(self.cfg, tn, td) for (tn, td) in self.w.thresholds]
+        self.n_pairs = int(sum(c.shape[0] for c in self.cands))
+        log(f"{name}: inputs ready in {time.time() - t0:.1f}s: {self.coll.n_sets} sets, "
+            f"{self.coll.n_tokens} tokens, {self.n_pairs} candidate pairs per step")
+        dev = torch.device("cuda:0")
+        self.dev = dev
+        self.h = S.ssj_upload_collection(ctx, self.coll.offsets, self.coll.tokens)
+        self.d_cands = [torch.from_numpy(c).to(dev) for c in self.cands]
+        self.d_outs = [torch.empty((max(self.man["thresholds"][f"{tn}/{td}"]["n_result"], 1) + 64, 2),
+                                   dtype=torch.int32, device=dev) for (tn, td) in self.w.thresholds]
+        self.d_cnt = torch.zeros(len(self.cands), dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        self.batch = [(self.d_cands[i], tn, td, self.d_outs[i], self.d_cnt[i:i + 1])
+                      for i, (tn, td) in enumerate(self.w.thresholds)]
+        self.sizes = np.diff(self.coll.offsets)
+
+    def step(self):  # batched: every threshold's candidates in one launch
+        self.S.ssj_verify_batch_device(self.ctx, self.h, self.batch)
+
+    def step_plain(self):  # one launch per batch
+        for i, (tn, td) in enumerate(self.w.thresholds):
+            self.S.ssj_verify_device(self.ctx, self.h, self.d_cands[i], tn, td, self.d_outs[i],
+                                     self.d_cnt[i:i + 1])
+
+    def check(self):
+        cnt = self.d_cnt.cpu().numpy()
+        ok = True
+        for i, (tn, td) in enumerate(self.w.thresholds):
+            m = self.man["thresholds"][f"{tn}/{td}"]
+            k = int(cnt[i])
+            if k != m["n_result"]:
+                ok = False
+                continue
+            ok &= pairs_digest(self.d_outs[i][:k].cpu().numpy()) == m["result_sha256"]
+        return bool(ok)
+
+    def alg_bytes(self):
+        """B_alg per step: pair ids (8) and two set descriptors (16) per pair, 4
+        per token the early-terminating merge consumes, 8 per result; and the
+        same with whole sets read (B_full)."""
+        b_alg = b_full = 0
+        for i, (tn, td) in enumerate(self.w.thresholds):
+            m = self.man["thresholds"][f"{tn}/{td}"]
+            b_alg += 24 * m["n_candidates"] + 4 * m["sum_consumed_tokens"] + 8 * m["n_result"]
+            c = self.cands[i]
+            b_full += (24 * c.shape[0] + 4 * int(self.sizes[c[:, 0]].sum() + self.sizes[c[:, 1]].sum())
+                       + 8 * m["n_result"])
+        return b_alg, b_full
+
+    def close(self):
+        self.S.ssj_free_collection(self.ctx, self.h)
+        del self.d_cands, self.d_outs, self.batch
+
+
+def measure(W, args, src_hash):
+    """Autotune (or take the given plan), time args.steps batched steps with
+    sampled kernel events, check parity; the workload's record."""
+    S, torch, ctx = W.S, W.torch, W.ctx
+    plan = plan_of(S, args.plan)
+    tuned = None
+    if plan is None:
+        big = max(range(len(W.cands)), key=lambda i: W.cands[i].shape[0])
+        tn, td = W.w.thresholds[big]
+        plan, tuned_ms = S.ssj_autotune(ctx, W.h, W.d_cands[big], tn, td, apply=False)
+        tuned = {"plan": plan.as_dict(), "kernel_ms": round(tuned_ms, 5),
+                 "tuned_on": f"t={tn}/{td}, {W.cands[big].shape[0]} pairs"}
+        log(f"{W.name}: autotuned plan: {tuned}")
+    S.ssj_set_plan(ctx, plan)
+    # every TIMING_PERIOD-th launch is bracketed by HIP events on the launch
+    # stream (sampled: event records perturb a launch)
+    S.ssj_timing_enable(ctx, TIMING_PERIOD)
+    for _ in range(args.warmup):
+        W.step()
+    torch.cuda.synchronize()
+    S.ssj_timing_read(ctx, reset=True)
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        W.step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    in_ms, def_ms, launches = S.ssj_timing_read(ctx, reset=True)
+    S.ssj_timing_enable(ctx, 0)
+    parity = W.check()
+    if not parity:
+        log(f"{W.name}: RESULT MISMATCH against the oracle manifest")
+    value = W.n_pairs * args.steps / elapsed
+    b_alg, b_full = W.alg_bytes()
+    launches = max(launches, 1)
+    deferred = plan.defer_from < 5 or plan.spill_iters > 0
+    avg_in_ms = in_ms / launches
+    avg_def_ms = def_ms / launches
+    # in-order kernel alone, or with the deferred kernel when one runs (events
+    # right before and after each verification kernel; the one-wavefront
+    # finalize kernel is not included)
+    avg_kernel_ms = avg_in_ms + (avg_def_ms if deferred else 0.0)
+    achieved = b_alg / (avg_kernel_ms * 1e-3) / 1e9 if avg_kernel_ms > 0 else 0.0
+    kname = kernel_name_of(plan)
+    traffic = traffic_from_profiles(src_hash, W.name, kname)
+    rate = (lambda b: b / (avg_kernel_ms * 1e-3) / 1e9) if avg_kernel_ms > 0 else None
+    rec = {
+        "workload": workload_text(W.cfg, W.w, W.n_pairs),
+        "pairs_per_step": W.n_pairs,
+        "value": round(value, 1),
+        "unit": "pairs/s",
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 5),
+        "parity": parity,
+        "plan": plan.as_dict(),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kname,
+            "achieved": round(achieved, 2),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 5),
+            "traffic": traffic,
+            # measured DRAM bytes (copy-scaled FETCH_SIZE + WRITE_SIZE of the
+            # committed counters) over the same kernel time
+            "traffic_gbs": round(rate(traffic), 2) if traffic and rate else None,
+            "traffic_frac": round(rate(traffic) / PEAK_HBM_GBS, 5) if traffic and rate else None,
+            "alg_bytes_per_launch": int(b_alg),
+            "full_read_bytes_per_launch": int(b_full),
+            "avg_kernel_ms": round(avg_kernel_ms, 5),
+            "avg_inorder_ms": round(avg_in_ms, 5),
+            "avg_deferred_ms": round(avg_def_ms, 5),
+            "timed_launches": launches,
+        },
+        "alg_gbs_whole_step": round(b_alg * args.steps / elapsed / 1e9, 2),
+    }
+    if tuned:
+        rec["autotune"] = tuned
+    if args.sweep:
+        sweep = {}
+        for spec in args.sweep.split(";"):
+            p = plan_of(S, spec)
+            S.ssj_set_plan(ctx, p)
+            S.ssj_timing_enable(ctx, 1)
+            n_sw = max(5, args.steps // 2)
+            dt = timed_steps(torch, W.step, n_sw, 2)
+            a_in, a_def, a_l = S.ssj_timing_read(ctx, reset=True)
+            S.ssj_timing_enable(ctx, 0)
+            dfr = p.defer_from < 5 or p.spill_iters > 0
+            k_ms = (a_in + (a_def if dfr else 0.0)) / max(a_l, 1)
+            sweep[spec] = {"pairs_per_s": round(W.n_pairs * n_sw / dt, 1), "parity": W.check(),
+                           "kernel_ms": round(k_ms, 5),
+                           "frac": round(b_alg / (k_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if k_ms > 0 else None}
+        rec["sweep"] = sweep
+        S.ssj_set_plan(ctx, plan)
+    return rec, plan
+
+
+def count_mode(W, args):
+    """The same batched launch in the output-count mode (no pair writes; the
+    mode the paper measured), parity by count."""
+    torch, S = W.torch, W.S
+    d_cnt_c = torch.zeros(len(W.cands), dtype=torch.int64, device=W.dev)
+    batch_c = [(W.d_cands[i], tn, td, None, d_cnt_c[i:i + 1]) for i, (tn, td) in enumerate(W.w.thresholds)]
+    n_m = max(5, args.steps // 2)
+    dt_c = timed_steps(torch, lambda: S.ssj_verify_batch_device(W.ctx, W.h, batch_c), n_m, 2)
+    cnt_c = d_cnt_c.cpu().numpy()
+    return {"pairs_per_s": round(W.n_pairs * n_m / dt_c, 1), "ms_per_step": round(dt_c * 1e3 / n_m, 5),
+            "parity": bool(all(int(cnt_c[i]) == W.man["thresholds"][f"{tn}/{td}"]["n_result"]
+                               for i, (tn, td) in enumerate(W.w.thresholds)))}
+
+
+def buckets(W, plan):
+    """Kernel time and B_alg rate per bucket of |r| + |s| (each bucket's
+    candidates alone, in their order, one launch per step)."""
+    import numpy as np
+    torch, S = W.torch, W.S
+    bks = [W.man["thresholds"][f"{tn}/{td}"].get("buckets") for tn, td in W.w.thresholds]
+    if not all(b is not None for b in bks):
+        return None
+    deferred = plan.defer_from < 5 or plan.spill_iters > 0
+    bounds = [b["upper_bound"] for b in bks[0][:-1]]
+    per = []
+    b_of = [np.searchsorted(np.asarray(bounds), W.sizes[c[:, 0]] + W.sizes[c[:, 1]], side="left") for c in W.cands]
+    for q in range(len(bounds) + 1):
+        sub = [np.ascontiguousarray(c[b_of[i] == q]) for i, c in enumerate(W.cands)]
+        nq = int(sum(x.shape[0] for x in sub))
+        if nq == 0:
+            continue
+        d_sub = [torch.from_numpy(x).to(W.dev) for x in sub]
+        d_so = [torch.empty((max(x.shape[0], 1), 2), dtype=torch.int32, device=W.dev) for x in sub]
+        d_sc = torch.zeros(len(sub), dtype=torch.int64, device=W.dev)
+        bb = [(d_sub[i], tn, td, d_so[i], d_sc[i:i + 1]) for i, (tn, td) in enumerate(W.w.thresholds)]
+        S.ssj_verify_batch_device(W.ctx, W.h, bb)
+        torch.cuda.synchronize()
+        S.ssj_timing_enable(W.ctx, 1)
+        S.ssj_timing_read(W.ctx, reset=True)
+        for _ in range(5):
+            S.ssj_verify_batch_device(W.ctx, W.h, bb)
+        torch.cuda.synchronize()
+        q_in, q_def, q_l = S.ssj_timing_read(W.ctx, reset=True)
+        S.ssj_timing_enable(W.ctx, 0)
+        q_ms = (q_in + (q_def if deferred else 0.0)) / max(q_l, 1)
+        ok = True
+        b_q = 0
+        for i, (tn, td) in enumerate(W.w.thresholds):
+            m = bks[i][q]
+            k = int(d_sc[i].item())
+            ok &= k == m["n_result"] and pairs_digest(d_so[i][:k].cpu().numpy()) == m["result_sha256"]
+            b_q += 24 * m["n_candidates"] + 4 * m["sum_consumed_tokens"] + 8 * m["n_result"]
+        per.append({"sizes": f"|r|+|s| <= {bounds[q]}" if q < len(bounds) else f"|r|+|s| > {bounds[-1]}",
+                    "pairs": nq, "kernel_ms": round(q_ms, 5), "alg_bytes": int(b_q),
+                    "alg_gbs": round(b_q / (q_ms * 1e-3) / 1e9, 2) if q_ms > 0 else None,
+                    "parity": bool(ok)})
+        del d_sub, d_so, d_sc
+    return per
+
+
+def host_api(W, reps):
+    """PCIe-inclusive rate of the host-buffer entry point (candidates copied
+    in, results copied out, synchronous per call); context only."""
+    S = W.S
+    for i, (tn, td) in enumerate(W.w.thresholds):  # untimed: allocates the pinned staging ring
+        S.ssj_verify(W.ctx, W.h, W.cands[i], tn, td)
+    t_h = time.perf_counter()
+    ok = True
+    for _ in range(reps):
+        for i, (tn, td) in enumerate(W.w.thresholds):
+            res = S.ssj_verify(W.ctx, W.h, W.cands[i], tn, td)
+            ok &= res.shape[0] == W.man["thresholds"][f"{tn}/{td}"]["n_result"]
+    dt_h = time.perf_counter() - t_h
+    return {"pairs_per_s": round(W.n_pairs * reps / dt_h, 1), "counts_ok": bool(ok),
+            "ms_per_step": round(dt_h * 1e3 / reps, 3)}
+
+
+def offline_extras(W, args, rec):
+    """The offline workload's comparisons: plain one launch per threshold,
+    the Table 1 functions, grouped candidates, an R-S join, PPJoin
+    candidates and the whole join on the device."""
+    import numpy as np
+    from ssj_inputs import filter as cfilter
+    S, torch, ctx, dev, w, man = W.S, W.torch, W.ctx, W.dev, W.w, W.man
+    value = rec["value"]
+    if args.compare_plain and len(w.thresholds) > 1:
+        n_plain = max(5, args.steps // 2)
+        dt = timed_steps(torch, W.step_plain, n_plain, 2)
+        rec["plain_one_launch_per_batch_pairs_per_s"] = round(W.n_pairs * n_plain / dt, 1)
+        rec["plain_ms_per_step"] = round(dt * 1e3 / n_plain, 5)
+        rec["plain_parity"] = W.check()
+        rec["batched_over_plain"] = round(value / (W.n_pairs * n_plain / dt), 3)
+    if args.modes and "sims" in man:
+        sims = {}
+        key = man["sims"]["candidates"]
+        i0 = [f"{tn}/{td}" for tn, td in w.thresholds].index(key)
+        n0 = W.cands[i0].shape[0]
+        n_m = max(5, args.steps // 2)
+        d_o = torch.empty((n0, 2), dtype=torch.int32, device=dev)
+        for name in ["jaccard " + key] + [k for k in man["sims"] if k != "candidates"]:
+            sim, frac = name.split()
+            sn, sd = (int(x) for x in frac.split("/"))
+            one = [(W.d_cands[i0], sn, sd, d_o, W.d_cnt[i0:i0 + 1], sim)]
+            dt_s = timed_steps(torch, lambda: S.ssj_verify_batch_device(ctx, W.h, one), n_m, 2)
+            k = int(W.d_cnt[i0].item())
+            ref = man["thresholds"][key] if sim == "jaccard" else man["sims"][name]
+            sims[name] = {"pairs_per_s": round(n0 * n_m / dt_s, 1), "ms": round(dt_s * 1e3 / n_m, 5),
+                          "n_result": k,
+                          "parity": bool(k == ref["n_result"] and
+                                         pairs_digest(d_o[:k].cpu().numpy()) == ref["result_sha256"])}
+        rec["similarities"] = {"candidates": f"the t = {key} list ({n0} pairs), one launch each", **sims}
+        del d_o
+    if not args.ingest:
+        return
+    # grouped candidates (a probe id and the end of its candidates, then 4-byte
+    # s ids; Sec. 3.3.1's C / C_O): device time of the step's thresholds
+    grp = [S.groups_of(c) for c in W.cands]
+    d_grp = [(torch.from_numpy(g).to(dev), torch.from_numpy(si).to(dev)) for g, si in grp]
+    greqs = [(d_grp[i][0], d_grp[i][1], tn, td, W.d_outs[i], W.d_cnt[i:i + 1])
+             for i, (tn, td) in enumerate(w.thresholds)]
+
+    def step_groups_batch():  # every list's groups verified in one launch
+        S.ssj_verify_groups_batch_device(ctx, W.h, W.h, greqs)
+
+    def step_groups():
+        for i, (tn, td) in enumerate(w.thresholds):
+            S.ssj_verify_groups_device(ctx, W.h, W.h, d_grp[i][0], d_grp[i][1], "jaccard", tn, td, W.d_outs[i],
+                                       W.d_cnt[i:i + 1])
+
+    n_g = max(5, args.steps // 2)
+    dt_gb = timed_steps(torch, step_groups_batch, n_g, 2)
+    gb_ok = W.check()
+    dt_g = timed_steps(torch, step_groups, n_g, 2)
+    g_ok = W.check()
+    dt_f = timed_steps(torch, W.step, n_g, 2)
+    t1 = time.perf_counter()
+    host_g_ok = True
+    for i, (tn, td) in enumerate(w.thresholds):
+        res = S.ssj_verify_groups(ctx, W.h, W.h, grp[i][0], grp[i][1], "jaccard", tn, td)
+        host_g_ok &= pairs_digest(res) == man["thresholds"][f"{tn}/{td}"]["result_sha256"]
+    dt_hg = time.perf_counter() - t1
+    rec["grouped"] = {
+        "groups_per_step": int(sum(g.shape[0] for g, _ in grp)),
+        "batched_ms_per_step": round(dt_gb * 1e3 / n_g, 5),
+        "ms_per_step": round(dt_g * 1e3 / n_g, 5),
+        "flat_batched_ms_per_step": round(dt_f * 1e3 / n_g, 5),
+        "parity": bool(gb_ok and g_ok and host_g_ok),
+        "host_pairs_per_s_pcie_inclusive": round(W.n_pairs / dt_hg, 1)}
+
+    # R-S join: R = the even-numbered sets, S = the odd-numbered ones, the
+    # candidates the self-join candidates between them; the result must be
+    # the (manifest-checked) self-join result restricted to those pairs
+    coll, sizes = W.coll, W.sizes
+    ev, od = np.arange(0, coll.n_sets, 2), np.arange(1, coll.n_sets, 2)
+
+    def sub(ids):
+        offs = np.zeros(ids.shape[0] + 1, dtype=np.int64)
+        np.cumsum(sizes[ids], out=offs[1:])
+        toks = np.concatenate([coll.tokens[coll.offsets[x]:coll.offsets[x + 1]] for x in ids])
+        return offs, toks
+
+    (ro, rt), (so, st_) = sub(ev), sub(od)
+    hr = S.ssj_upload_collection(ctx, ro, rt)
+    hs = S.ssj_upload_collection(ctx, so, st_)
+    tn, td = w.thresholds[0]
+    c0 = W.cands[0]
+    a_ev = (c0[:, 0] % 2 == 0) & (c0[:, 1] % 2 == 1)
+    b_ev = (c0[:, 0] % 2 == 1) & (c0[:, 1] % 2 == 0)
+    rs = np.concatenate([np.stack([c0[a_ev, 0] // 2, c0[a_ev, 1] // 2], axis=1),
+                         np.stack([c0[b_ev, 1] // 2, c0[b_ev, 0] // 2], axis=1)]).astype(np.int32)
+    d_rs = torch.from_numpy(rs).to(dev)
+    d_rs_out = torch.empty_like(d_rs)
+    d_rs_cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def step_rs():
+        S.ssj_verify_rs_device(ctx, hr, hs, d_rs, "jaccard", tn, td, d_rs_out, d_rs_cnt)
+
+    n_r = max(5, args.steps // 2)
+    dt_r = timed_steps(torch, step_rs, n_r, 2)
+    k = int(d_rs_cnt.item())
+    got = d_rs_out[:k].cpu().numpy().astype(np.int64)
+    got_orig = np.stack([2 * got[:, 0], 2 * got[:, 1] + 1], axis=1)
+    W.step()
+    torch.cuda.synchronize()
+    self_res = W.d_outs[0][:int(W.d_cnt[0].item())].cpu().numpy().astype(np.int64)
+    self_ok = pairs_digest(self_res.astype(np.int32)) == man["thresholds"][f"{tn}/{td}"]["result_sha256"]
+    lo_, hi_ = np.minimum(self_res[:, 0], self_res[:, 1]), np.maximum(self_res[:, 0], self_res[:, 1])
+    keep = (lo_ % 2) != (hi_ % 2)
+    ev_side = np.where(lo_[keep] % 2 == 0, lo_[keep], hi_[keep])
+    od_side = np.where(lo_[keep] % 2 == 0, hi_[keep], lo_[keep])
+    want = np.sort(ev_side * (1 << 32) + od_side)
+    have = np.sort(got_orig[:, 0] * (1 << 32) + got_orig[:, 1])
+    rec["rs"] = {"workload": f"R = even sets ({ev.shape[0]}), S = odd sets ({od.shape[0]}) of the offline "
+                             f"collection, t = {tn}/{td}, {rs.shape[0]} cross candidates",
+                 "pairs_per_s": round(rs.shape[0] * n_r / dt_r, 1), "ms_per_step": round(dt_r * 1e3 / n_r, 5),
+                 "parity": bool(self_ok and np.array_equal(want, have))}
+    S.ssj_free_collection(ctx, hr)
+    S.ssj_free_collection(ctx, hs)
+
+    # the same join from fewer candidates: PPJoin's positional filter on top
+    # of the prefix and length filters (CPU, host threads)
+    nthr = host_cpu()["nproc"]
+    t1 = time.perf_counter()
+    for (tn, td) in w.thresholds:
+        cfilter.candidates(coll.offsets, coll.tokens, tn, td, n_threads=nthr)
+    t_ap = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    pcands = [cfilter.candidates(coll.offsets, coll.tokens, tn, td, n_threads=nthr, positional=True)
+              for (tn, td) in w.thresholds]
+    t_pp = time.perf_counter() - t1
+    d_pc = [torch.from_numpy(c).to(dev) for c in pcands]
+    pbatch = [(d_pc[i], tn, td, W.d_outs[i], W.d_cnt[i:i + 1]) for i, (tn, td) in enumerate(w.thresholds)]
+    n_pp = max(5, args.steps // 2)
+    dt = timed_steps(torch, lambda: S.ssj_verify_batch_device(ctx, W.h, pbatch), n_pp, 2)
+    rec["ppjoin"] = {
+        "candidates_per_step": int(sum(c.shape[0] for c in pcands)), "allpairs_candidates_per_step": W.n_pairs,
+        "ms_per_step": round(dt * 1e3 / n_pp, 5), "allpairs_ms_per_step": rec["ms_per_step"],
+        "parity": W.check(),
+        "filter_s": {"allpairs": round(t_ap, 4), "ppjoin": round(t_pp, 4), "threads": nthr}}
+    if args.ppjoin:
+        # the whole join on the GPU: candidates from the prefix, length and
+        # positional filters built on the device, then verified
+        d_jout = [torch.empty((max(man["thresholds"][f"{tn}/{td}"]["n_result"], 1), 2), dtype=torch.int32,
+                              device=dev) for (tn, td) in w.thresholds]
+        d_jcnt = torch.zeros(len(w.thresholds), dtype=torch.int64, device=dev)
+
+        def step_join():
+            for i, (tn, td) in enumerate(w.thresholds):
+                S.ssj_join_device(ctx, W.h, tn, td, True, d_jout[i], d_jcnt[i:i + 1])
+
+        n_j = max(3, args.steps // 10)
+        dt = timed_steps(torch, step_join, n_j, 1)
+        cnt = d_jcnt.cpu().numpy()
+        join_ok = all(int(cnt[i]) == man["thresholds"][f"{tn}/{td}"]["n_result"] and
+                      pairs_digest(d_jout[i][:int(cnt[i])].cpu().numpy()) ==
+                      man["thresholds"][f"{tn}/{td}"]["result_sha256"]
+                      for i, (tn, td) in enumerate(w.thresholds))
+        rec["gpu_join"] = {"ms_per_step": round(dt * 1e3 / n_j, 5), "parity": bool(join_ok),
+                           "cpu_filter_ms_per_step": round(t_pp * 1e3, 3)}
+
+
+def stream_phase(S, ctx, args):
+    """Streamed serving over the 1,000,000-set collection: saturated and at
+    0.8 of the saturated rate, every batch's result checked against the
+    manifest's oracle digests (after the runs)."""
+    from paper_1812_09141_amd import serving
+    from ssj_inputs import synth
+    w5 = synth.WORKLOADS[5]
+    man5 = load_manifest(5)
+    t0 = time.time()
+    c5 = synth.workload_collection(5)
+    if c5.digest() != man5["collection_sha256"]:
+        raise SystemExit("stream: generated collection differs from the manifest")
+    sizes5, ts5, _ = synth.stream_schedule(args.stream_batches, seed=0, thresholds=w5.thresholds)
+    nthr = host_cpu()["nproc"]
+    t1 = time.time()
+    batches = serving.build_batches(c5.offsets, c5.tokens, sizes5, ts5, n_threads=nthr)
+    t_filter = time.time() - t1
+    log(f"stream inputs ready in {time.time() - t0:.1f}s ({len(batches)} batches)")
+    pins = man5.get("stream")
+    pinned = (pins is not None and pins["seed"] == 0 and pins["n_batches"] >= len(batches))
+    h5 = S.ssj_upload_collection(ctx, c5.offsets, c5.tokens)
+    # several submitting threads, as filter threads each submit their own batches
+    subs = 4
+    runs = {}
+    res = []
+    ok = pinned
+    # warm-up: one untimed pass over all batches, so that the engine's pinned
+    # staging pool holds buffers of every size class (steady state)
+    for name in ("warmup", "saturated", "offered_load_0.8"):
+        rate = 0.8 * runs["saturated"]["pairs_per_s"] if name == "offered_load_0.8" else None
+        r = serving.run_stream(S, ctx, h5, batches, rate, seed=1 if rate else 0, n_submitters=subs, results=res)
+        if pinned:
+            ok &= all(x is not None and x.shape[0] == p["n_result"] and pairs_digest(x) == p["result_sha256"]
+                      for x, p in zip(res, pins["batches"]))
+        if name != "warmup":
+            runs[name] = r
+    S.ssj_free_collection(ctx, h5)
+    n5 = sum(b[0].shape[0] for b in batches)
+    return {
+        "workload": (f"{w5.name}: {w5.n_sets} sets, lognormal(mean 12, sigma 0.5) sizes, "
+                     f"Zipf(1.0) over {w5.universe} tokens; batches of 1e3-1e6 pairs "
+                     f"(log-uniform), t in {{0.6,0.8,0.9}}"),
+        "filter_threads": nthr,
+        "filter_pairs_per_s": round(n5 / t_filter, 1) if t_filter > 0 else None,
+        "parity": bool(ok),
+        **runs,
+    }
+
+
+def cpu_baselines(W, args):
+    """The oracle (full-merge C, OpenMP) on the host: every host thread over
+    repeated full steps for about cpu_seconds, and one thread over the first
+    candidates for about cpu1_seconds."""
+    import oracle
+    cpu = host_cpu()
+    out = {}
+    if args.cpu_seconds > 0:
+        nthreads = cpu["nproc"]
+        t_c = time.perf_counter()
+        done = reps = 0
+        while True:
+            for i, (tn, td) in enumerate(W.w.thresholds):
+                oracle.verify(W.coll.offsets, W.coll.tokens, W.cands[i], tn, td, n_threads=nthreads)
+                done += W.cands[i].shape[0]
+            reps += 1
+            if time.perf_counter() - t_c >= args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t_c
+        out["all"] = {"value": round(done / dt, 1), "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
+                      "cpu_model": cpu["model"], "nproc": cpu["nproc"], "cpu_count": cpu["cpu_count"],
+                      "sample": f"{reps} full pass{'es' if reps > 1 else ''} over the {W.name} step's "
+                                f"{W.n_pairs} candidate pairs, {dt:.1f}s of CPU work on {nthreads} threads"}
+    if args.cpu1_seconds > 0:
+        first = 200000
+        t_c = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t_c < args.cpu1_seconds:
+            for i, (tn, td) in enumerate(W.w.thresholds):
+                oracle.verify(W.coll.offsets, W.coll.tokens, W.cands[i][:first], tn, td, n_threads=1)
+                done += min(W.cands[i].shape[0], first)
+        dt = time.perf_counter() - t_c
+        out["one"] = {"value": round(done / dt, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                      "cpu_model": cpu["model"],
+                      "sample": f"the first {first} candidates of the {W.name} step, {done} pairs, {dt:.1f}s"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -167,7 +723,6 @@ def main():
               "(the verification path has no multi-GPU form in this build)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.copy_mb:
@@ -182,484 +737,87 @@ def main():
         return
 
     import paper_1812_09141_amd.ssj as S
-    from ssj_inputs import filter as cfilter
-    from ssj_inputs import synth
 
-    cfg = WORKLOAD_CFG[args.workload]
-    w = synth.WORKLOADS[cfg]
-    man = load_manifest(cfg)
-    t0 = time.time()
-    coll = synth.workload_collection(cfg)
-    if coll.digest() != man["collection_sha256"]:
-        raise SystemExit("generated collection differs from the manifest")
-    cands = [cfilter.workload_candidates(cfg, tn, td) for (tn, td) in w.thresholds]
-    n_pairs = int(sum(c.shape[0] for c in cands))
-    log(f"inputs ready in {time.time() - t0:.1f}s: {coll.n_sets} sets, {coll.n_tokens} tokens, "
-        f"{n_pairs} candidate pairs per step")
-
-    dev = torch.device("cuda:0")
-    ctx = S.ssj_init(0)
-    h = S.ssj_upload_collection(ctx, coll.offsets, coll.tokens)
-    d_cands = [torch.from_numpy(c).to(dev) for c in cands]
-    d_outs = [torch.empty((max(c.shape[0], 1), 2), dtype=torch.int32, device=dev) for c in cands]
-    d_cnt = torch.zeros(len(cands), dtype=torch.int64, device=dev)
-    torch.cuda.synchronize()
-
-    batch = [(d_cands[i], tn, td, d_outs[i], d_cnt[i:i + 1]) for i, (tn, td) in enumerate(w.thresholds)]
-
-    def step():  # batched: every threshold's candidates in one launch
-        S.ssj_verify_batch_device(ctx, h, batch)
-
-    def step_plain():  # one launch per batch
-        for i, (tn, td) in enumerate(w.thresholds):
-            S.ssj_verify_device(ctx, h, d_cands[i], tn, td, d_outs[i], d_cnt[i:i + 1])
-
-    def check():
-        cnt = d_cnt.cpu().numpy()
-        ok = True
-        for i, (tn, td) in enumerate(w.thresholds):
-            m = man["thresholds"][f"{tn}/{td}"]
-            k = int(cnt[i])
-            if k != m["n_result"]:
-                ok = False
-                continue
-            got = d_outs[i][:k].cpu().numpy()
-            ok &= pairs_digest(got) == m["result_sha256"]
-        return ok
-
-    plan = plan_of(S, args.plan)
-    tuned = None
-    if plan is None:
-        big = max(range(len(cands)), key=lambda i: cands[i].shape[0])
-        tn, td = w.thresholds[big]
-        plan, tuned_ms = S.ssj_autotune(ctx, h, d_cands[big], tn, td, apply=False)
-        tuned = {"plan": plan.as_dict(), "kernel_ms": round(tuned_ms, 5),
-                 "tuned_on": f"t={tn}/{td}, {cands[big].shape[0]} pairs"}
-        log(f"autotuned plan: {tuned}")
-    S.ssj_set_plan(ctx, plan)
-
-    # main timed region; every TIMING_PERIOD-th launch is bracketed by HIP
-    # events on the launch stream (sampled: event records perturb a launch)
-    S.ssj_timing_enable(ctx, TIMING_PERIOD)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    S.ssj_timing_read(ctx, reset=True)
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    in_ms, def_ms, launches = S.ssj_timing_read(ctx, reset=True)
-    S.ssj_timing_enable(ctx, 0)
-    parity = check()
-    if not parity:
-        log("RESULT MISMATCH against the oracle manifest")
-
-    value = n_pairs * args.steps / elapsed
-    ms_per_step = elapsed * 1e3 / args.steps
-
-    # algorithmic bytes per step: pair ids (8) + two descriptors (16) per pair,
-    # the tokens the early-terminating merge consumes (4 each), 8 per result
-    b_alg = 0
-    b_full = 0
-    sizes = coll.sizes()
-    for i, (tn, td) in enumerate(w.thresholds):
-        m = man["thresholds"][f"{tn}/{td}"]
-        b_alg += 24 * m["n_candidates"] + 4 * m["sum_consumed_tokens"] + 8 * m["n_result"]
-        c = cands[i]
-        b_full += 24 * c.shape[0] + 4 * int(sizes[c[:, 0]].sum() + sizes[c[:, 1]].sum()) + 8 * m["n_result"]
-    launches = max(launches, 1)
-    per_launch_bytes = b_alg  # one launch per step
-    avg_in_ms = in_ms / launches
-    avg_def_ms = def_ms / launches
-    deferred = plan.defer_from < 5 or plan.spill_iters > 0
-    # in-order kernel alone, or with the deferred kernel when one runs
-    # (kernel durations from events recorded right before and after each
-    # verification kernel; the one-wavefront finalize kernel is not included)
-    avg_kernel_ms = avg_in_ms + (avg_def_ms if deferred else 0.0)
-    achieved = per_launch_bytes / (avg_kernel_ms * 1e-3) / 1e9 if avg_kernel_ms > 0 else 0.0
+    names = [x for x in args.workload.split(",") if x]
+    for n in names:
+        if n not in WORKLOAD_CFG:
+            raise SystemExit(f"unknown workload {n!r}")
     src_hash = kernel_source_hash()
-    kernel_name = (f"k_verify_tiles<{plan.inline_lanes},{plan.hard_lanes},"
-                   f"{'true' if deferred else 'false'},false>" +
-                   (" + k_verify_deferred<false>" if deferred else ""))
-    traffic = traffic_from_profiles(src_hash, args.workload, kernel_name)
+    ctx = S.ssj_init(0)
+    head = None
+    others = {}
+    cpu = {}
+    parity = True
+    for idx, name in enumerate(names):
+        W = Workload(S, torch, ctx, name)
+        rec, plan = measure(W, args, src_hash)
+        parity &= rec["parity"]
+        if args.modes:
+            rec["count_mode"] = count_mode(W, args)
+            parity &= rec["count_mode"]["parity"]
+        if args.buckets:
+            per = buckets(W, plan)
+            if per is not None:
+                rec["buckets"] = per
+        if W.cfg == 2:
+            offline_extras(W, args, rec)
+        if args.host_api:
+            rec["host_api_pcie_inclusive"] = host_api(W, 1 if W.n_pairs > 10_000_000 else 3)
+        if idx == 0:
+            cpu = cpu_baselines(W, args)
+        W.close()
+        del W
+        torch.cuda.empty_cache()
+        if idx == 0:
+            head = (name, rec)
+        else:
+            others[name] = rec
+        log(f"{name}: {rec['value'] / 1e9:.2f} G pairs/s, B_alg frac {rec['roofline']['frac']}, "
+            f"parity {rec['parity']}")
 
-    extra = {"plan": plan.as_dict()}
-    if tuned:
-        extra["autotune"] = tuned
-    if args.compare_plain:
-        n_plain = max(5, args.steps // 2)
-        dt = timed_steps(torch, step_plain, n_plain, 2)
-        extra["plain_one_launch_per_batch_pairs_per_s"] = round(n_pairs * n_plain / dt, 1)
-        extra["plain_ms_per_step"] = round(dt * 1e3 / n_plain, 4)
-        extra["plain_parity"] = bool(check())
-        extra["batched_over_plain"] = round(value / (n_pairs * n_plain / dt), 3)
-
-    if args.sweep:
-        sweep = {}
-        for spec in args.sweep.split(";"):
-            S.ssj_set_plan(ctx, plan_of(S, spec))
-            n_sw = max(5, args.steps // 2)
-            dt = timed_steps(torch, step, n_sw, 2)
-            sweep[spec] = {"pairs_per_s": round(n_pairs * n_sw / dt, 1), "parity": bool(check())}
-        extra["sweep"] = sweep
-        S.ssj_set_plan(ctx, plan)
-
-    if args.modes:
-        # output-count mode (no pair writes; the mode the paper measured) on the
-        # same batched launch, and the other similarity functions of Table 1
-        d_cnt_c = torch.zeros(len(cands), dtype=torch.int64, device=dev)
-        batch_c = [(d_cands[i], tn, td, None, d_cnt_c[i:i + 1]) for i, (tn, td) in enumerate(w.thresholds)]
-        n_m = max(5, args.steps // 2)
-        dt_c = timed_steps(torch, lambda: S.ssj_verify_batch_device(ctx, h, batch_c), n_m, 2)
-        cnt_c = d_cnt_c.cpu().numpy()
-        extra["count_mode"] = {
-            "pairs_per_s": round(n_pairs * n_m / dt_c, 1), "ms_per_step": round(dt_c * 1e3 / n_m, 4),
-            "parity": bool(all(int(cnt_c[i]) == man["thresholds"][f"{tn}/{td}"]["n_result"]
-                               for i, (tn, td) in enumerate(w.thresholds)))}
-        if "sims" in man:
-            sims = {}
-            key = man["sims"]["candidates"]
-            i0 = [f"{tn}/{td}" for tn, td in w.thresholds].index(key)
-            n0 = cands[i0].shape[0]
-            for name in ["jaccard " + key] + [k for k in man["sims"] if k != "candidates"]:
-                sim, frac = name.split()
-                sn, sd = (int(x) for x in frac.split("/"))
-                one = [(d_cands[i0], sn, sd, d_outs[i0], d_cnt[i0:i0 + 1], sim)]
-                dt_s = timed_steps(torch, lambda: S.ssj_verify_batch_device(ctx, h, one), n_m, 2)
-                k = int(d_cnt[i0].item())
-                ref = man["thresholds"][key] if sim == "jaccard" else man["sims"][name]
-                sims[name] = {"pairs_per_s": round(n0 * n_m / dt_s, 1), "ms": round(dt_s * 1e3 / n_m, 4),
-                              "n_result": k,
-                              "parity": bool(k == ref["n_result"] and
-                                             pairs_digest(d_outs[i0][:k].cpu().numpy()) == ref["result_sha256"])}
-            extra["similarities"] = {"candidates": f"the t = {key} list ({n0} pairs), one launch each",
-                                     **sims}
-            step()  # restore the outputs of the main step
-            torch.cuda.synchronize()
-
-    buckets = [man["thresholds"][f"{tn}/{td}"].get("buckets") for tn, td in w.thresholds]
-    if args.buckets and all(b is not None for b in buckets):
-        # kernel time and B_alg rate per bucket of |r| + |s| (each bucket's
-        # candidates alone, in their order, one launch per step)
-        bounds = [b["upper_bound"] for b in buckets[0][:-1]]
-        per = []
-        b_of = [np.searchsorted(np.asarray(bounds), sizes[c[:, 0]] + sizes[c[:, 1]], side="left") for c in cands]
-        for q in range(len(bounds) + 1):
-            sub = [np.ascontiguousarray(c[b_of[i] == q]) for i, c in enumerate(cands)]
-            nq = int(sum(x.shape[0] for x in sub))
-            if nq == 0:
-                continue
-            d_sub = [torch.from_numpy(x).to(dev) for x in sub]
-            d_so = [torch.empty((max(x.shape[0], 1), 2), dtype=torch.int32, device=dev) for x in sub]
-            d_sc = torch.zeros(len(sub), dtype=torch.int64, device=dev)
-            bb = [(d_sub[i], tn, td, d_so[i], d_sc[i:i + 1]) for i, (tn, td) in enumerate(w.thresholds)]
-            n_b = 5
-            S.ssj_verify_batch_device(ctx, h, bb)
-            torch.cuda.synchronize()
-            S.ssj_timing_enable(ctx, 1)
-            S.ssj_timing_read(ctx, reset=True)
-            for _ in range(n_b):
-                S.ssj_verify_batch_device(ctx, h, bb)
-            torch.cuda.synchronize()
-            q_in, q_def, q_l = S.ssj_timing_read(ctx, reset=True)
-            S.ssj_timing_enable(ctx, 0)
-            q_ms = (q_in + (q_def if deferred else 0.0)) / max(q_l, 1)
-            ok = True
-            b_q = 0
-            for i, (tn, td) in enumerate(w.thresholds):
-                m = buckets[i][q]
-                k = int(d_sc[i].item())
-                ok &= k == m["n_result"] and pairs_digest(d_so[i][:k].cpu().numpy()) == m["result_sha256"]
-                b_q += 24 * m["n_candidates"] + 4 * m["sum_consumed_tokens"] + 8 * m["n_result"]
-            per.append({"sizes": f"|r|+|s| <= {bounds[q]}" if q < len(bounds) else f"|r|+|s| > {bounds[-1]}",
-                        "pairs": nq, "kernel_ms": round(q_ms, 5), "alg_bytes": int(b_q),
-                        "alg_gbs": round(b_q / (q_ms * 1e-3) / 1e9, 2) if q_ms > 0 else None,
-                        "parity": bool(ok)})
-            del d_sub, d_so, d_sc
-        extra["buckets"] = per
-
-    # PCIe-inclusive rate of the host-buffer entry point (candidates copied in,
-    # results copied out, synchronous per call); context only, never `value`
-    n_host = 3
-    for i, (tn, td) in enumerate(w.thresholds):  # untimed: allocates the pinned staging ring
-        S.ssj_verify(ctx, h, cands[i], tn, td)
-    t_h = time.perf_counter()
-    host_ok = True
-    for _ in range(n_host):
-        for i, (tn, td) in enumerate(w.thresholds):
-            res = S.ssj_verify(ctx, h, cands[i], tn, td)
-            host_ok &= res.shape[0] == man["thresholds"][f"{tn}/{td}"]["n_result"]
-    dt_h = time.perf_counter() - t_h
-    extra["host_api_pairs_per_s_pcie_inclusive"] = round(n_pairs * n_host / dt_h, 1)
-    extra["host_api_counts_ok"] = bool(host_ok)
-
-    if args.ingest:
-        # grouped candidates (a probe id and the end of its candidates, then
-        # 4-byte s ids; Sec. 3.3.1's C / C_O): device time of the step's four
-        # thresholds against flat launches, and the host-buffer rate with its
-        # PCIe copies (half the candidate bytes)
-        grp = [S.groups_of(c) for c in cands]
-        d_grp = [(torch.from_numpy(g).to(dev), torch.from_numpy(si).to(dev)) for g, si in grp]
-
-        def step_groups():
-            for i, (tn, td) in enumerate(w.thresholds):
-                S.ssj_verify_groups_device(ctx, h, h, d_grp[i][0], d_grp[i][1], "jaccard", tn, td, d_outs[i],
-                                           d_cnt[i:i + 1])
-
-        greqs = [(d_grp[i][0], d_grp[i][1], tn, td, d_outs[i], d_cnt[i:i + 1])
-                 for i, (tn, td) in enumerate(w.thresholds)]
-
-        def step_groups_batch():  # every list's expansion, then one verification launch
-            S.ssj_verify_groups_batch_device(ctx, h, h, greqs)
-
-        n_g = max(5, args.steps // 2)
-        dt_gb = timed_steps(torch, step_groups_batch, n_g, 2)
-        gb_ok = check()
-        dt_g = timed_steps(torch, step_groups, n_g, 2)
-        g_ok = check()
-        dt_f = timed_steps(torch, step_plain, n_g, 2)
-        t1 = time.perf_counter()
-        host_g_ok = True
-        for i, (tn, td) in enumerate(w.thresholds):
-            res = S.ssj_verify_groups(ctx, h, h, grp[i][0], grp[i][1], "jaccard", tn, td)
-            host_g_ok &= pairs_digest(res) == man["thresholds"][f"{tn}/{td}"]["result_sha256"]
-        dt_hg = time.perf_counter() - t1
-        t1 = time.perf_counter()
-        for i, (tn, td) in enumerate(w.thresholds):
-            S.ssj_verify(ctx, h, cands[i], tn, td)
-        dt_hf = time.perf_counter() - t1
-        extra["grouped"] = {
-            "groups_per_step": int(sum(g.shape[0] for g, _ in grp)),
-            "batched_ms_per_step": round(dt_gb * 1e3 / n_g, 4),
-            "ms_per_step": round(dt_g * 1e3 / n_g, 4), "flat_one_launch_per_batch_ms_per_step": round(dt_f * 1e3 / n_g, 4),
-            "parity": bool(gb_ok and g_ok and host_g_ok),
-            "host_pairs_per_s_pcie_inclusive": round(n_pairs / dt_hg, 1),
-            "flat_host_pairs_per_s_pcie_inclusive": round(n_pairs / dt_hf, 1)}
-
-        # R-S join: R = the even-numbered sets, S = the odd-numbered ones, the
-        # candidates the self-join candidates between them; the result must be
-        # the (manifest-checked) self-join result restricted to those pairs
-        sizes = coll.sizes()
-        ev, od = np.arange(0, coll.n_sets, 2), np.arange(1, coll.n_sets, 2)
-
-        def sub(ids):
-            offs = np.zeros(ids.shape[0] + 1, dtype=np.int64)
-            np.cumsum(sizes[ids], out=offs[1:])
-            toks = np.concatenate([coll.tokens[coll.offsets[x]:coll.offsets[x + 1]] for x in ids])
-            return offs, toks
-
-        (ro, rt), (so, st_) = sub(ev), sub(od)
-        hr = S.ssj_upload_collection(ctx, ro, rt)
-        hs = S.ssj_upload_collection(ctx, so, st_)
-        tn, td = w.thresholds[0]
-        c0 = cands[0]
-        a_ev = (c0[:, 0] % 2 == 0) & (c0[:, 1] % 2 == 1)
-        b_ev = (c0[:, 0] % 2 == 1) & (c0[:, 1] % 2 == 0)
-        rs = np.concatenate([np.stack([c0[a_ev, 0] // 2, c0[a_ev, 1] // 2], axis=1),
-                             np.stack([c0[b_ev, 1] // 2, c0[b_ev, 0] // 2], axis=1)]).astype(np.int32)
-        d_rs = torch.from_numpy(rs).to(dev)
-        d_rs_out = torch.empty_like(d_rs)
-        d_rs_cnt = torch.zeros(1, dtype=torch.int64, device=dev)
-
-        def step_rs():
-            S.ssj_verify_rs_device(ctx, hr, hs, d_rs, "jaccard", tn, td, d_rs_out, d_rs_cnt)
-
-        n_r = max(5, args.steps // 2)
-        dt_r = timed_steps(torch, step_rs, n_r, 2)
-        k = int(d_rs_cnt.item())
-        got = d_rs_out[:k].cpu().numpy().astype(np.int64)
-        got_orig = np.stack([2 * got[:, 0], 2 * got[:, 1] + 1], axis=1)
-        S.ssj_verify_device(ctx, h, d_cands[0], tn, td, d_outs[0], d_cnt[0:1])
-        torch.cuda.synchronize()
-        self_res = d_outs[0][:int(d_cnt[0].item())].cpu().numpy().astype(np.int64)
-        self_ok = pairs_digest(self_res.astype(np.int32)) == man["thresholds"][f"{tn}/{td}"]["result_sha256"]
-        lo_, hi_ = np.minimum(self_res[:, 0], self_res[:, 1]), np.maximum(self_res[:, 0], self_res[:, 1])
-        keep = (lo_ % 2) != (hi_ % 2)
-        ev_side = np.where(lo_[keep] % 2 == 0, lo_[keep], hi_[keep])
-        od_side = np.where(lo_[keep] % 2 == 0, hi_[keep], lo_[keep])
-        want = np.sort(ev_side * (1 << 32) + od_side)
-        have = np.sort(got_orig[:, 0] * (1 << 32) + got_orig[:, 1])
-        extra["rs"] = {"workload": f"R = even sets ({ev.shape[0]}), S = odd sets ({od.shape[0]}) of the offline "
-                                   f"collection, t = {tn}/{td}, {rs.shape[0]} cross candidates",
-                       "pairs_per_s": round(rs.shape[0] * n_r / dt_r, 1), "ms_per_step": round(dt_r * 1e3 / n_r, 4),
-                       "parity": bool(self_ok and np.array_equal(want, have))}
-        S.ssj_free_collection(ctx, hr)
-        S.ssj_free_collection(ctx, hs)
-
-        # the same join from fewer candidates: PPJoin's positional filter on top
-        # of the prefix and length filters (CPU, all host threads up to 16)
-        nthr = max(1, min(os.cpu_count() or 1, 16))
-        t1 = time.perf_counter()
-        for (tn, td) in w.thresholds:
-            cfilter.candidates(coll.offsets, coll.tokens, tn, td, n_threads=nthr)
-        t_ap = time.perf_counter() - t1
-        t1 = time.perf_counter()
-        pcands = [cfilter.candidates(coll.offsets, coll.tokens, tn, td, n_threads=nthr, positional=True)
-                  for (tn, td) in w.thresholds]
-        t_pp = time.perf_counter() - t1
-        d_pc = [torch.from_numpy(c).to(dev) for c in pcands]
-        pbatch = [(d_pc[i], tn, td, d_outs[i], d_cnt[i:i + 1]) for i, (tn, td) in enumerate(w.thresholds)]
-
-        def step_pp():
-            S.ssj_verify_batch_device(ctx, h, pbatch)
-
-        n_pp = max(5, args.steps // 2)
-        dt = timed_steps(torch, step_pp, n_pp, 2)
-        n_pc = int(sum(c.shape[0] for c in pcands))
-        extra["ppjoin"] = {
-            "candidates_per_step": n_pc, "allpairs_candidates_per_step": n_pairs,
-            "ms_per_step": round(dt * 1e3 / n_pp, 4), "allpairs_ms_per_step": round(ms_per_step, 4),
-            "parity": bool(check()),
-            "filter_s": {"allpairs": round(t_ap, 4), "ppjoin": round(t_pp, 4), "threads": nthr}}
-
-    if args.ppjoin:
-        # the whole join on the GPU: candidates from the prefix, length and
-        # positional filters built on the device, then verified (two host
-        # synchronisations per call size its buffers)
-        d_jout = [torch.empty((max(man["thresholds"][f"{tn}/{td}"]["n_result"], 1), 2), dtype=torch.int32,
-                              device=dev) for (tn, td) in w.thresholds]
-        d_jcnt = torch.zeros(len(w.thresholds), dtype=torch.int64, device=dev)
-
-        def step_join():
-            for i, (tn, td) in enumerate(w.thresholds):
-                S.ssj_join_device(ctx, h, tn, td, True, d_jout[i], d_jcnt[i:i + 1])
-
-        n_j = max(3, args.steps // 10)
-        dt = timed_steps(torch, step_join, n_j, 1)
-        cnt = d_jcnt.cpu().numpy()
-        join_ok = all(int(cnt[i]) == man["thresholds"][f"{tn}/{td}"]["n_result"] and
-                      pairs_digest(d_jout[i][:int(cnt[i])].cpu().numpy()) ==
-                      man["thresholds"][f"{tn}/{td}"]["result_sha256"]
-                      for i, (tn, td) in enumerate(w.thresholds))
-        extra["gpu_join"] = {"ms_per_step": round(dt * 1e3 / n_j, 4), "parity": bool(join_ok),
-                             "cpu_filter_ms_per_step": round(extra["ppjoin"]["filter_s"]["ppjoin"] * 1e3, 3)}
-
-    stream = None
-    if args.stream_batches > 0:
-        from paper_1812_09141_amd import serving
-        w5 = synth.WORKLOADS[5]
-        t0 = time.time()
-        c5 = synth.workload_collection(5)
-        sizes5, ts5, _ = synth.stream_schedule(args.stream_batches, seed=0, thresholds=w5.thresholds)
-        nthr = max(1, min(os.cpu_count() or 1, 16))
-        t1 = time.time()
-        batches = serving.build_batches(c5.offsets, c5.tokens, sizes5, ts5, n_threads=nthr)
-        t_filter = time.time() - t1
-        log(f"stream inputs ready in {time.time() - t0:.1f}s ({len(batches)} batches)")
-        h5 = S.ssj_upload_collection(ctx, c5.offsets, c5.tokens)
-        # several submitting threads, as filter threads each submit their own batches
-        subs = 4
-        # warm-up: one untimed pass over all batches, so that the engine's pinned
-        # staging pool holds buffers of every size class (steady state)
-        serving.run_stream(S, ctx, h5, batches, None, n_submitters=subs)
-        sat = serving.run_stream(S, ctx, h5, batches, None, n_submitters=subs)
-        offered = 0.8 * sat["pairs_per_s"]
-        loaded = serving.run_stream(S, ctx, h5, batches, offered, seed=1, n_submitters=subs)
-        n5 = sum(b[0].shape[0] for b in batches)
-        stream = {
-            "workload": (f"{w5.name}: {w5.n_sets} sets, lognormal(mean 12, sigma 0.5) sizes, "
-                         f"Zipf(1.0) over {w5.universe} tokens; batches of 1e3-1e6 pairs "
-                         f"(log-uniform), t in {{0.6,0.8,0.9}}"),
-            "filter_threads": nthr,
-            "filter_pairs_per_s": round(n5 / t_filter, 1) if t_filter > 0 else None,
-            "saturated": sat,
-            "offered_load_0.8": loaded,
-        }
-        S.ssj_free_collection(ctx, h5)
-
-    # CPU baseline: the oracle (full merge, plain C) on the host cores
-    cpu = None
-    if args.cpu_seconds > 0:
-        import oracle
-        nthreads = max(1, min(os.cpu_count() or 1, 16))
-        t_c = time.perf_counter()
-        done = 0
-        reps = 0
-        while True:
-            for i, (tn, td) in enumerate(w.thresholds):
-                oracle.verify(coll.offsets, coll.tokens, cands[i], tn, td, n_threads=nthreads)
-                done += cands[i].shape[0]
-            reps += 1
-            if time.perf_counter() - t_c >= args.cpu_seconds:
-                break
-        dt = time.perf_counter() - t_c
-        cpu = {"value": round(done / dt, 1), "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
-               "sample": f"{reps} full passes over the step's {n_pairs} candidate pairs "
-                         f"({len(w.thresholds)} threshold{'s' if len(w.thresholds) > 1 else ''}), "
-                         f"{dt:.1f}s of CPU work"}
-
-    if args.cpu1_seconds > 0:
-        import oracle
-        t_c = time.perf_counter()
-        done = 0
-        while time.perf_counter() - t_c < args.cpu1_seconds:
-            for i, (tn, td) in enumerate(w.thresholds):
-                oracle.verify(coll.offsets, coll.tokens, cands[i][:200000], tn, td, n_threads=1)
-                done += min(cands[i].shape[0], 200000)
-        dt = time.perf_counter() - t_c
-        extra["cpu_baseline_1core"] = {"value": round(done / dt, 1), "unit": "pairs/s", "cores": 1,
-                                       "kind": "oracle",
-                                       "sample": f"the first 200000 candidates of each threshold, "
-                                                 f"{done} pairs, {dt:.1f}s"}
-
+    stream = stream_phase(S, ctx, args) if args.stream_batches > 0 else None
+    if stream is not None:
+        parity &= stream["parity"]
     S.ssj_shutdown(ctx)
     copy_peak = copy_gbs(torch)
+    name, hrec = head
+    for r in [hrec] + list(others.values()):
+        r["roofline"]["copy_gbs_measured"] = round(copy_peak, 1)
+        r["roofline"]["frac_of_copy"] = round(r["roofline"]["achieved"] / copy_peak, 5)
 
-    rec = {
+    out = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": hrec["value"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": hrec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "i32",
         "data": "synthetic",
-        "config": {
-            "workload": (f"{w.name}: {w.n_sets} sets, sizes lognormal(mean 12, sigma 0.5) clipped "
-                         f"2-200, Zipf(1.0) over {w.universe} tokens; Jaccard t in "
-                         f"{{0.6,0.7,0.8,0.9}}; {n_pairs} prefix+length candidates per step"
-                         if cfg == 2 else f"{w.name} (config {cfg}), {n_pairs} candidates per step"),
-            "pairs_per_step": n_pairs,
-            "launches_per_step": 1,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": kernel_name,
-            "achieved": round(achieved, 2),
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 5),
-            "traffic": traffic,
-            "alg_bytes_per_launch": int(per_launch_bytes),
-            "avg_kernel_ms": round(avg_kernel_ms, 5),
-            "avg_inorder_ms": round(avg_in_ms, 5),
-            "avg_deferred_ms": round(avg_def_ms, 5),
-            "timed_launches": launches,
-            "copy_gbs_measured": round(copy_peak, 1),
-            "frac_of_copy": round(achieved / copy_peak, 5),
-        },
-        "cpu_baseline": cpu,
-        "stream": stream,
+        "config": {"workload": hrec["workload"], "pairs_per_step": hrec["pairs_per_step"],
+                   "launches_per_step": 1},
+        "roofline": hrec["roofline"],
+        "cpu_baseline": cpu.get("all"),
+        "cpu_baseline_1core": cpu.get("one"),
         "parity": bool(parity),
-        "alg_gbs_whole_step": round(b_alg * args.steps / elapsed / 1e9, 2),
-        "full_read_bytes_per_step": int(b_full),
-        "alg_bytes_per_step": int(b_alg),
     }
-    rec.update(extra)
+    for k, v in hrec.items():
+        if k not in ("workload", "value", "unit", "ms_per_step", "roofline", "pairs_per_step"):
+            out[k if k != "parity" else "headline_parity"] = v
+    out["workloads"] = others
+    out["stream"] = stream
     # the paper's own figures (other hardware, other data): context, not a target
-    rec["paper_context"] = {
+    out["paper_context"] = {
         "speedup_total_join_up_to": 2.6,
         "speedup_verification_phase_up_to": 5.0,
         "versus": "the CPU-only join framework it builds on (single-threaded), Sec. 6",
         "hardware": "Intel i7 5820k at 3.3 GHz, 32 GB RAM; NVIDIA Titan Xp (3840 CUDA cores, 12 GB)",
     }
-    print(json.dumps(rec), flush=True)
+    print(json.dumps(out), flush=True)
     if not parity:
         sys.exit(1)
 

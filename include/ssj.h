@@ -317,6 +317,11 @@ int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, int wait, uint64_t* t_submit
  *     pair still undecided then is queued and verified again from its start
  *     by the kernel of (2), with spill_lanes lanes per pair.  This keeps a
  *     few long merges from holding up their wavefronts.  0: no bound.
+ *  4. staged != 0 (with one thread per pair and no hard lanes) runs (1) as
+ *     the staged kernel for long sets: each lane merges its pair from 16-token
+ *     blocks of both sets held in LDS, which the wavefront loads together
+ *     (four lanes per 64-byte block) whenever merges leave their blocks;
+ *     spill_iters then bounds the rounds of block loads per chunk of 64 pairs.
  * use_graph != 0 replays the launch through a captured hipGraph whose kernel
  * parameters are updated per call.  wg_per_cu sizes the in-order kernel's
  * grid (its wavefronts split the chunks evenly; more workgroups than fit at
@@ -336,6 +341,7 @@ typedef struct {
     int spill_lanes;             /* lanes per spilled pair: 1, 4, 8, 16, 32, 64 or 256 */
     int wg_per_cu;               /* in-order kernel workgroups per compute unit, 0 .. 64
                                     (0: as many as the device holds at once) */
+    int staged;                  /* 0 or 1 (1 only with inline_lanes 1, hard_lanes 0) */
 } ssj_plan;
 
 /* Reads / replaces the context's plan.  SSJ_EINVAL for an unsupported

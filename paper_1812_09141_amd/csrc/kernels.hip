@@ -804,6 +804,251 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Staged thread-per-pair kernel (long sets).  One lane per pair as in the
+// in-order kernel with G == 1, but a lane never loads its own tokens: each
+// side of its pair has a 64-byte block (16 tokens, aligned to 16 tokens from
+// the set's start) in the wavefront's LDS, and the blocks are filled by the
+// whole wavefront together, four lanes per block, so that one load
+// instruction fetches 16 whole blocks instead of 64 scattered 16-byte
+// windows.  A chunk of 64 pairs then alternates between
+//   * a refill round: every undecided lane whose merge position on a side
+//     has left the block it holds posts a request for the block holding that
+//     position (a list in LDS, ranked by ballot), and the wavefront serves
+//     the list with coalesced loads;
+//   * a merge phase: every undecided lane whose two current windows lie in
+//     its blocks takes window steps from LDS (the step of merge_windows)
+//     until it is decided or a window leaves its block.
+// With a step budget (spill_iters), pairs still undecided after that many
+// refill rounds are queued whole for the deferred kernel.
+constexpr uint32_t kBlkTok = 16;                    // tokens per staged block
+constexpr uint32_t kLaneBuf = 80;                   // LDS bytes per lane and side: a block plus
+                                                    // 16 bytes, so that lanes 1..15 apart start
+                                                    // on distinct banks
+constexpr uint32_t kStagedTok = 2u * kWave * kLaneBuf;  // both sides' blocks of one wavefront
+constexpr uint32_t kStagedReq = 2u * kWave;         // block requests per round (two per lane)
+constexpr uint32_t kStagedOut = 2u * kWave;         // staged output pairs per wavefront
+constexpr uint32_t kStagedFixed = kStagedTok + kStagedReq * 8u + kStagedOut * 8u;
+
+// One window step of the tile merge on the current 4-token windows va (of
+// the r side, tokens 4*(i/4).. of a set of na tokens) and vb (s side): the
+// side whose window ends lower is consumed whole, the other up to that end
+// (both on equal ends); equal tokens inside the unconsumed parts are matches.
+// Same rule as the steps of merge_windows.
+__device__ __forceinline__ void window_step(uint4 va, uint4 vb, uint32_t na, uint32_t nb, uint32_t& i,
+                                            uint32_t& j, uint32_t& o) {
+    const int32_t a[4] = {(int32_t)va.x, (int32_t)va.y, (int32_t)va.z, (int32_t)va.w};
+    const int32_t b[4] = {(int32_t)vb.x, (int32_t)vb.y, (int32_t)vb.z, (int32_t)vb.w};
+    const uint32_t ba = i & ~3u, bb = j & ~3u;
+    const uint32_t ea = min(na - ba, 4u), eb = min(nb - bb, 4u);
+    int32_t amax = a[0], bmax = b[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        amax = ((uint32_t)k < ea) ? a[k] : amax;
+        bmax = ((uint32_t)k < eb) ? b[k] : bmax;
+    }
+    uint32_t hits = 0, na_le = 0, nb_le = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool va_k = ba + k >= i && (uint32_t)k < ea;
+        const bool vb_k = bb + k >= j && (uint32_t)k < eb;
+        bool hit = false;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) hit |= (bb + t >= j && (uint32_t)t < eb) && a[k] == b[t];
+        hits += (va_k && hit) ? 1u : 0u;
+        na_le += (va_k && a[k] <= bmax) ? 1u : 0u;
+        nb_le += (vb_k && b[k] <= amax) ? 1u : 0u;
+    }
+    i = bmax < amax ? i + na_le : ba + ea;
+    j = amax < bmax ? j + nb_le : bb + eb;
+    o += hits;
+}
+
+// Serves the wavefront's r block requests in w_req: request k = {first
+// token of the block in its side's token array, LDS byte offset of the
+// destination | side << 16 | 16-byte parts to copy << 17}.  Part p of the
+// list (request p / 4, quarter p % 4) is copied by lane p % 64, four
+// lanes per block, up to four parts per lane in flight.  Parts past the
+// end of a set's (16-byte padded) tokens are not read.
+__device__ __forceinline__ void serve_blocks(const LaunchArgs& a, const uint2* w_req, uint32_t r,
+                                             unsigned char* w_tok) {
+    wave_sync();
+    const int lane = lane_id();
+    const uint4* __restrict__ t4a = reinterpret_cast<const uint4*>(a.tok);
+    const uint4* __restrict__ t4b = reinterpret_cast<const uint4*>(a.tok_s);
+    const uint32_t parts = 4u * r;
+    for (uint32_t p0 = 0; p0 < parts; p0 += 4u * kWave) {
+        uint4 v[4];
+        uint32_t dst[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t p = p0 + (uint32_t)u * kWave + (uint32_t)lane;
+            ok[u] = false;
+            dst[u] = 0;
+            v[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (p < parts) {
+                const uint2 e = w_req[p >> 2];
+                const uint32_t q = p & 3u;
+                ok[u] = q < ((e.y >> 17) & 7u);
+                dst[u] = (e.y & 0xffffu) + q * 16u;
+                if (ok[u]) v[u] = ((e.y >> 16) & 1u) ? t4b[(e.x >> 2) + q] : t4a[(e.x >> 2) + q];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (ok[u]) *reinterpret_cast<uint4*>(w_tok + dst[u]) = v[u];
+    }
+    wave_sync();
+}
+
+template <bool D, bool C>
+__global__ __launch_bounds__(kBlock) void k_verify_staged(LaunchArgs a) {
+    constexpr uint32_t kWaves = (uint32_t)(kBlock / kWave);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t wl = threadIdx.x >> 6;
+    const int lane = lane_id();
+    // dynamic LDS, per wavefront: the token blocks (r side of lanes 0..63,
+    // then the s side), the request list, the staged output pairs, then
+    // defer_cap entries per deferred queue
+    extern __shared__ uint4 s_dyn[];
+    const bool deferring = D && (a.defer_from < kClasses || spilling(a));
+    const uint32_t wave_bytes =
+        kStagedFixed + (deferring ? (uint32_t)wave_queues(a.defer_from, spilling(a)) * a.defer_cap * 4u : 0u);
+    unsigned char* w_tok = reinterpret_cast<unsigned char*>(s_dyn) + wl * wave_bytes;
+    uint2* w_req = reinterpret_cast<uint2*>(w_tok + kStagedTok);
+    int2* w_out = reinterpret_cast<int2*>(w_req + kStagedReq);
+    uint32_t* w_defer = reinterpret_cast<uint32_t*>(w_out + kStagedOut);
+    const uint32_t dst_a = (uint32_t)lane * kLaneBuf;                   // this lane's r block
+    const uint32_t dst_b = (uint32_t)(kWave + lane) * kLaneBuf;         // and its s block
+    uint32_t ocnt = 0;
+    unsigned long long dc = 0ull;
+    const uint32_t n_chunks = a.tile_off[a.n_req];
+    const uint32_t nw = gridDim.x * kWaves;
+    const uint32_t first = blockIdx.x * kWaves + (uint32_t)w;
+    // pipeline as in the in-order kernel: while chunk T is verified, the
+    // records of chunk T + nw and the pairs of chunk T + 2 nw are in flight
+    int2 p0 = make_int2(0, 0), p1 = make_int2(0, 0);
+    uint4 ra0 = make_uint4(0u, 0u, 0u, 0u), rb0 = ra0, ra1 = ra0, rb1 = ra0;
+    int r_cur = 0, r1 = 0;
+    uint32_t kb_cur = 0, kb1 = 0;
+    auto records = [&](int2 pr, uint4& ra, uint4& rb) {
+        const bool ok = ids_ok(pr, a);
+        ra = a.heads[2 * (ok ? pr.x : 0)];
+        rb = a.heads_s[2 * (ok ? pr.y : 0)];
+    };
+    if (first < n_chunks) {
+        chunk_origin(a, first, &r_cur, &kb_cur);
+        p0 = lane_pair(a.req[r_cur], kb_cur, lane);
+        records(p0, ra0, rb0);
+        chunk_origin(a, min(first + nw, n_chunks - 1), &r1, &kb1);
+        p1 = lane_pair(a.req[r1], kb1, lane);
+    }
+    const uint32_t share = first < n_chunks ? (n_chunks - 1u - first) / nw + 1u : 1u;
+    uint32_t done = 0, level = 3;
+    __builtin_amdgcn_s_setprio(3);
+    for (uint32_t T = first; T < n_chunks; T += nw) {
+        progress_priority(done++, share, level);
+        const int r = r_cur;
+        const uint32_t kb = kb_cur;
+        const uint32_t Tn = T + nw;
+        const Request& R = a.req[r];
+        records(p1, ra1, rb1);
+        int r2 = 0;
+        uint32_t kb2 = 0;
+        chunk_origin(a, min(Tn + nw, n_chunks - 1), &r2, &kb2);
+        const int2 p2 = lane_pair(a.req[r2], kb2, lane);
+
+        const int2 pr = p0;
+        const uint32_t k = kb + (uint32_t)lane;
+        const bool valid = k < R.n;
+        const bool ok = valid && ids_ok(pr, a);
+        const uint32_t sa = ra0.x, na = ra0.y, sb = rb0.x, nb = rb0.y;
+        const int cls = deferring ? class_of(na + nb, a) : 0;
+        const bool defer = ok && deferring && cls >= a.defer_from;
+        const bool run = ok && !defer;
+        const uint32_t alpha = run ? required_overlap<C>(na, nb, R) : 0u;
+        bool pass = run && alpha == 0u;
+        bool act = run && !pass && min(na, nb) >= alpha;
+        bool spill = false;
+        uint32_t i = 0, j = 0, o = 0;
+        uint32_t blk_a = 0xffffffffu, blk_b = 0xffffffffu;  // blocks held (none yet)
+        for (uint32_t round = 0;; ++round) {
+            if (ballot(act) == 0ull) break;
+            if (deferring && round >= a.spill_iters) {
+                spill = act;
+                act = false;
+                break;
+            }
+            // requests for the blocks holding positions i and j
+            const bool need_a = act && (i / kBlkTok) != blk_a;
+            const bool need_b = act && (j / kBlkTok) != blk_b;
+            const unsigned long long ma = ballot(need_a), mb = ballot(need_b);
+            const uint32_t n_a = (uint32_t)__popcll(ma);
+            if (need_a) {
+                const uint32_t t0 = i & ~(kBlkTok - 1u);
+                const uint32_t np = min(4u, (na - t0 + 3u) >> 2);
+                w_req[mbcnt(ma)] = make_uint2(sa + t0, dst_a | (np << 17));
+                blk_a = i / kBlkTok;
+            }
+            if (need_b) {
+                const uint32_t t0 = j & ~(kBlkTok - 1u);
+                const uint32_t np = min(4u, (nb - t0 + 3u) >> 2);
+                w_req[n_a + mbcnt(mb)] = make_uint2(sb + t0, dst_b | (1u << 16) | (np << 17));
+                blk_b = j / kBlkTok;
+            }
+            serve_blocks(a, w_req, n_a + (uint32_t)__popcll(mb), w_tok);
+            // merge phase
+            for (;;) {
+                const bool can = act && (i / kBlkTok) == blk_a && (j / kBlkTok) == blk_b;
+                if (ballot(can) == 0ull) break;
+                if (can) {
+                    const uint4 va = *reinterpret_cast<const uint4*>(w_tok + dst_a + ((i >> 2) & 3u) * 16u);
+                    const uint4 vb = *reinterpret_cast<const uint4*>(w_tok + dst_b + ((j >> 2) & 3u) * 16u);
+                    window_step(va, vb, na, nb, i, j, o);
+                    if (o >= alpha) {
+                        pass = true;
+                        act = false;
+                    } else if (o + min(na - i, nb - j) < alpha) {
+                        act = false;
+                    }
+                }
+            }
+        }
+        if (ballot(valid && !ok) != 0ull && lane == 0) atomicOr(&a.ctr->err[r], 1u);
+        stage_pass(pass, pr, w_out, ocnt, R.cap == 0);
+        if (deferring) defer_pass(a, defer, cls, spill, a.pair_off[r] + k, w_defer, dc);
+        // rotate the pipeline
+        p0 = p1;
+        p1 = p2;
+        ra0 = ra1;
+        rb0 = rb1;
+        r_cur = r1;
+        kb_cur = kb1;
+        r1 = r2;
+        kb1 = kb2;
+        const bool same_next = Tn < n_chunks && r_cur == r;
+        if (ocnt > 0 && ((R.cap != 0 && ocnt > kStagedOut - kWave) || !same_next)) {
+            wave_flush_out(a, r, ocnt, w_out);
+            ocnt = 0;
+        }
+        if (deferring) {
+            for (int q = a.defer_from; q < queue_end(a); ++q) {
+                const uint32_t c = dcount(dc, q);
+                if (c > a.defer_cap - kWave) {
+                    wave_flush_deferred(a, q, c, w_defer);
+                    dc &= ~(0xffull << (8 * q));
+                }
+            }
+        }
+    }
+    if (deferring) {
+        for (int q = a.defer_from; q < queue_end(a); ++q) {
+            if (dcount(dc, q) > 0) wave_flush_deferred(a, q, dcount(dc, q), w_defer);
+        }
+    }
+}
+
 // Publishes each request's count (-1 after an id error) and returns the
 // counters to zero for the next launch.  One workgroup, after the verify
 // kernels of the launch (the kernel boundary makes their atomics visible).
@@ -1077,8 +1322,8 @@ bool lanes_supported(int lanes) {
     }
 }
 
-bool inline_supported(int lanes, int hard_lanes) {
-    return kernel_verify_tiles(lanes, hard_lanes, false, false) != nullptr;
+bool inline_supported(int lanes, int hard_lanes, bool staged) {
+    return kernel_verify_tiles(lanes, hard_lanes, staged, false, false) != nullptr;
 }
 
 template <bool D, bool C>
@@ -1102,7 +1347,13 @@ const void* verify_tiles_instance(int lanes, int hard_lanes) {
     }
 }
 
-const void* kernel_verify_tiles(int lanes, int hard_lanes, bool deferring, bool cosine) {
+const void* kernel_verify_tiles(int lanes, int hard_lanes, bool staged, bool deferring, bool cosine) {
+    if (staged) {
+        if (lanes != 1 || hard_lanes != 0) return nullptr;
+        if (cosine)
+            return deferring ? (const void*)&k_verify_staged<true, true> : (const void*)&k_verify_staged<false, true>;
+        return deferring ? (const void*)&k_verify_staged<true, false> : (const void*)&k_verify_staged<false, false>;
+    }
     if (cosine)
         return deferring ? verify_tiles_instance<true, true>(lanes, hard_lanes)
                          : verify_tiles_instance<false, true>(lanes, hard_lanes);
@@ -1140,15 +1391,16 @@ hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start,
 }
 
 size_t tiles_lds_bytes(const LaunchArgs& a) {
-    // per wavefront: kWaveStage staged output pairs, then defer_cap entries
-    // per queue (a multiple of 16 bytes)
-    const size_t stage = (size_t)kWaveStage * sizeof(int2);
+    // per wavefront: kWaveStage staged output pairs (the staged kernel: its
+    // token blocks, block requests and kStagedOut output pairs), then
+    // defer_cap entries per queue (a multiple of 16 bytes)
+    const size_t stage = a.staged ? (size_t)kStagedFixed : (size_t)kWaveStage * sizeof(int2);
     const size_t defer = (size_t)wave_queues(a.defer_from, spilling(a)) * a.defer_cap * 4u;
     return (size_t)(kBlock / kWave) * (stage + defer);
 }
 
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st) {
-    const void* f = kernel_verify_tiles(a.inline_lanes, a.hard_lanes,
+    const void* f = kernel_verify_tiles(a.inline_lanes, a.hard_lanes, a.staged != 0,
                                         a.defer_from < kClasses || spilling(a), a.cosine != 0);
     if (!f) return hipErrorInvalidValue;
     LaunchArgs args = a;

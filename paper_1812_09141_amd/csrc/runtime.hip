@@ -127,10 +127,10 @@ struct Scratch {
 };
 
 struct GraphKey {
-    int inline_lanes, hard_lanes, defer_from, spill, cosine, grid1, grid2;
+    int inline_lanes, hard_lanes, staged, defer_from, spill, cosine, grid1, grid2;
     bool operator<(const GraphKey& o) const {
-        return std::tie(inline_lanes, hard_lanes, defer_from, spill, cosine, grid1, grid2) <
-               std::tie(o.inline_lanes, o.hard_lanes, o.defer_from, o.spill, o.cosine, o.grid1,
+        return std::tie(inline_lanes, hard_lanes, staged, defer_from, spill, cosine, grid1, grid2) <
+               std::tie(o.inline_lanes, o.hard_lanes, o.staged, o.defer_from, o.spill, o.cosine, o.grid1,
                         o.grid2);
     }
 };
@@ -167,7 +167,7 @@ struct ssj_ctx {
     int n_cu = 0;
     // in-order kernel workgroups per CU, limited by registers and by its
     // dynamic LDS: [4 * mapping index + 2 * cosine + deferring][deferred classes]
-    int occ_tiles[32][ssj::kQueues + 1] = {};  // [mapping][LDS queues per wavefront]
+    int occ_tiles[4 * 9][ssj::kQueues + 1] = {};  // [mapping][LDS queues per wavefront]
     int occ_deferred2[2] = {0};  // [cosine]
     ssj_plan plan{};
     std::mutex mu;  // default scratch, host staging, collections, plan, graphs
@@ -237,7 +237,8 @@ int hip_fail(ssj_ctx* ctx, const char* what, hipError_t e) {
     } while (0)
 
 // index of an in-order mapping in occ_tiles
-int inline_index(int lanes, int hard_lanes) {
+int inline_index(int lanes, int hard_lanes, int staged) {
+    if (staged) return 8;
     if (lanes == 1) return hard_lanes == 0 ? 0 : (hard_lanes == 8 ? 6 : 7);
     switch (lanes) {
         case 4: return 1;
@@ -249,8 +250,10 @@ int inline_index(int lanes, int hard_lanes) {
     }
 }
 
-const int kInlineLanes[8] = {1, 4, 8, 16, 32, 64, 1, 1};
-const int kInlineHard[8] = {0, 0, 0, 0, 0, 0, 8, 16};
+constexpr int kMappings = 9;  // in-order mappings: by lanes, hard lanes and staging
+const int kInlineLanes[kMappings] = {1, 4, 8, 16, 32, 64, 1, 1, 1};
+const int kInlineHard[kMappings] = {0, 0, 0, 0, 0, 0, 8, 16, 0};
+const int kInlineStaged[kMappings] = {0, 0, 0, 0, 0, 0, 0, 0, 1};
 
 int scratch_init(ssj_ctx* ctx, Scratch& s) {
     HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_ctr, sizeof(ssj::Counters)));
@@ -275,10 +278,12 @@ void default_plan(ssj_plan& p) {
     p.spill_iters = 0;
     p.spill_lanes = 16;
     p.wg_per_cu = 0;
+    p.staged = 0;
 }
 
 bool plan_valid(const ssj_plan& p) {
-    if (!ssj::inline_supported(p.inline_lanes, p.hard_lanes)) return false;
+    if (p.staged != 0 && p.staged != 1) return false;
+    if (!ssj::inline_supported(p.inline_lanes, p.hard_lanes, p.staged != 0)) return false;
     if (p.defer_from < 0 || p.defer_from > ssj::kClasses) return false;
     for (int q = 0; q < ssj::kClasses; ++q)
         if (!ssj::lanes_supported(p.lanes[q])) return false;
@@ -341,7 +346,7 @@ int vgpr_limited_blocks(const void* f) {
 int tiles_occupancy(const ssj_ctx* ctx, const ssj_plan& plan, bool cosine) {
     const bool deferring = plan_two_kernels(plan);
     const int nq = ssj::wave_queues(plan.defer_from, plan.spill_iters > 0);
-    return std::max(1, ctx->occ_tiles[4 * inline_index(plan.inline_lanes, plan.hard_lanes) + (cosine ? 2 : 0) +
+    return std::max(1, ctx->occ_tiles[4 * inline_index(plan.inline_lanes, plan.hard_lanes, plan.staged) + (cosine ? 2 : 0) +
                                       (deferring ? 1 : 0)][nq]);
 }
 
@@ -360,15 +365,16 @@ int grid_deferred(const ssj_ctx* ctx, bool cosine) {
 
 int launch_graph(ssj_ctx* ctx, const ssj::LaunchArgs& a, int g1, int g2, bool two,
                  hipStream_t st) {
-    GraphKey key{a.inline_lanes, a.hard_lanes, a.defer_from, ssj::spilling(a) ? 1 : 0, (int)a.cosine, g1,
-                 two ? g2 : 0};
+    GraphKey key{a.inline_lanes, a.hard_lanes, (int)a.staged, a.defer_from, ssj::spilling(a) ? 1 : 0,
+                 (int)a.cosine, g1, two ? g2 : 0};
     ssj::LaunchArgs args = a;
     void* kparams[] = {&args};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         GraphEntry ge;
         HIP_OR_FAIL(ctx, hipGraphCreate(&ge.graph, 0));
-        const void* funcs[3] = {ssj::kernel_verify_tiles(a.inline_lanes, a.hard_lanes, two, a.cosine != 0),
+        const void* funcs[3] = {ssj::kernel_verify_tiles(a.inline_lanes, a.hard_lanes, a.staged != 0, two,
+                                                         a.cosine != 0),
                                 ssj::kernel_verify_deferred(a.cosine != 0), ssj::kernel_finalize()};
         const int grids[3] = {g1, g2, 1};
         const int blocks[3] = {ssj::kBlock, ssj::kBlock, ssj::kWave};
@@ -421,6 +427,7 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     a.hard_lanes = plan.hard_lanes;
     a.spill_iters = plan.spill_iters > 0 ? (uint32_t)plan.spill_iters : 0xffffffffu;
     a.spill_lanes = plan.spill_lanes;
+    a.staged = plan.staged ? 1u : 0u;
     // in-order work unit: a chunk of kWave pairs of one request per wavefront
     const uint64_t tile_pairs = (uint64_t)ssj::kWave;
     a.defer_cap = (uint32_t)(2 * tile_pairs);
@@ -841,10 +848,10 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
         hipDeviceProp_t prop;
         if ((e = hipGetDeviceProperties(&prop, ctx->device)) != hipSuccess) { rc = hip_fail(ctx, "hipGetDeviceProperties", e); break; }
         ctx->n_cu = prop.multiProcessorCount;
-        for (int k = 0; k < 32 && rc == SSJ_OK; ++k) {
+        for (int k = 0; k < 4 * kMappings && rc == SSJ_OK; ++k) {
             const bool deferring = (k & 1) != 0;
-            const void* f = ssj::kernel_verify_tiles(kInlineLanes[k / 4], kInlineHard[k / 4], deferring,
-                                                     (k & 2) != 0);
+            const void* f = ssj::kernel_verify_tiles(kInlineLanes[k / 4], kInlineHard[k / 4],
+                                                     kInlineStaged[k / 4] != 0, deferring, (k & 2) != 0);
             // by the number of LDS queues per wavefront (deferred classes,
             // plus the spill queue)
             for (int nd = deferring ? 1 : 0; nd <= (deferring ? ssj::kQueues : 0) && rc == SSJ_OK; ++nd) {
@@ -852,6 +859,7 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
                 la.defer_from = nd <= ssj::kClasses ? ssj::kClasses - nd : 0;
                 la.spill_iters = nd <= ssj::kClasses ? 0xffffffffu : 1u;
                 la.defer_cap = 2 * ssj::kWave;
+                la.staged = (uint32_t)kInlineStaged[k / 4];
                 int occ = 0;
                 if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, ssj::kBlock, ssj::tiles_lds_bytes(la))) != hipSuccess)
                     rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
@@ -1054,7 +1062,8 @@ int ssj_set_plan(ssj_ctx* ctx, const ssj_plan* plan) {
                                      "or 16 with 1 lane, else 0); defer_from in [0, 5]; "
                                      "lanes and spill_lanes 1, 4, 8, 16, 32, 64 or 256; "
                                      "spill_iters in [0, 2^20], > 0 only with 1 lane and "
-                                     "hard_lanes 0; wg_per_cu in [0, 64]");
+                                     "hard_lanes 0; wg_per_cu in [0, 64]; staged 0 or 1, "
+                                     "1 only with 1 lane and hard_lanes 0");
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->plan = *plan;
     return SSJ_OK;
@@ -1645,7 +1654,9 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
     double cur_ms = 1e30;
     ssj_plan thread_best = ctx->plan;  // best plan with one thread per pair, no hard lanes
     double thread_ms = 1e30;
-    for (int k = 0; k < 8 && rc == SSJ_OK; ++k) {
+    ssj_plan staged_best = ctx->plan;  // best staged plan
+    double staged_ms = 1e30;
+    for (int k = 0; k < kMappings && rc == SSJ_OK; ++k) {
         for (int d = ssj::kClasses; d >= 1 && rc == SSJ_OK; --d) {
             // each at the resident grid and at twice that (a larger grid
             // evens out wavefronts that start late or issue slowly)
@@ -1653,6 +1664,7 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
                 ssj_plan p = ctx->plan;
                 p.inline_lanes = kInlineLanes[k];
                 p.hard_lanes = kInlineHard[k];
+                p.staged = kInlineStaged[k];
                 p.defer_from = d;
                 p.spill_iters = 0;
                 p.wg_per_cu = 0;
@@ -1667,6 +1679,10 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
                 if (k == 0 && ms < thread_ms) {
                     thread_ms = ms;
                     thread_best = p;
+                }
+                if (kInlineStaged[k] && ms < staged_ms) {
+                    staged_ms = ms;
+                    staged_best = p;
                 }
             }
         }
@@ -1688,6 +1704,20 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
                 cur_ms = ms;
                 cur = p;
             }
+        }
+    }
+    // the staged kernel's budget counts rounds of block loads per chunk
+    static const int kStagedRounds[4] = {4, 6, 8, 12};
+    for (int it : kStagedRounds) {
+        if (rc != SSJ_OK) break;
+        ssj_plan p = staged_best;
+        p.spill_iters = it;
+        p.spill_lanes = 16;
+        double ms = 0;
+        if ((rc = measure(p, &ms)) != SSJ_OK) break;
+        if (ms < cur_ms * 0.99) {
+            cur_ms = ms;
+            cur = p;
         }
     }
     if (cur.spill_iters > 0 && rc == SSJ_OK) {

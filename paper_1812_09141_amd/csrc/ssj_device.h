@@ -67,6 +67,9 @@ struct LaunchArgs {
                                          // in-order kernel before it is queued whole for the
                                          // deferred kernel (0xffffffff: no limit)
     int spill_lanes;                     // lanes per pair of the spill queue
+    uint32_t staged;                     // != 0: thread-per-pair merges over token blocks staged
+                                         // in LDS (k_verify_staged); spill_iters then counts
+                                         // block rounds
     uint32_t tile_off[kMaxReq + 1];      // prefix sums of per-request chunks (of kWave pairs)
     uint32_t pair_off[kMaxReq + 1];      // prefix sums of per-request pairs
     uint32_t bounds[kClasses];           // inclusive upper bound of |r|+|s| per class
@@ -101,7 +104,9 @@ size_t tiles_lds_bytes(const LaunchArgs& a);
 // Publishes the request counts and resets the counters (always last).
 hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st);
 
-const void* kernel_verify_tiles(int lanes, int hard_lanes, bool deferring, bool cosine);
+// The in-order kernel of a mapping: lanes per pair and hard lanes, or the
+// staged thread-per-pair kernel (staged, lanes 1, hard_lanes 0).
+const void* kernel_verify_tiles(int lanes, int hard_lanes, bool staged, bool deferring, bool cosine);
 const void* kernel_verify_deferred(bool cosine);
 const void* kernel_finalize();
 
@@ -111,6 +116,7 @@ __host__ __device__ inline int wave_queues(int defer_from, bool spill) { return 
 __host__ __device__ inline bool spilling(const LaunchArgs& a) { return a.spill_iters != 0xffffffffu; }
 
 bool lanes_supported(int lanes);              // deferred classes: 1..64 or kBlock
-bool inline_supported(int lanes, int hard_lanes);  // in-order kernel: 1..64; 0/8/16 hard lanes with 1
+bool inline_supported(int lanes, int hard_lanes, bool staged);  // in-order kernel: 1..64; 0/8/16 hard
+                                                                 // lanes with 1; staged with 1 and 0
 
 }  // namespace ssj

@@ -80,7 +80,7 @@ def build_batches(offsets, tokens, sizes: Sequence[int], thresholds: Sequence[Tu
 
 
 def run_stream(S, ctx, coll, batches, rate_pairs_per_s: Optional[float] = None, seed: int = 0,
-               timeout_s: float = 120.0, n_submitters: int = 1) -> dict:
+               timeout_s: float = 120.0, n_submitters: int = 1, results: Optional[list] = None) -> dict:
     """Submits the batches (at Poisson arrivals of the given offered load, or
     as fast as admission allows when rate is None) and collects them.
 
@@ -89,8 +89,11 @@ def run_stream(S, ctx, coll, batches, rate_pairs_per_s: Optional[float] = None, 
     submit the batches they produce; each submit copies its batch into the
     engine's pinned staging in the submitting thread.
 
-    Returns per-batch latency percentiles (ms), the end-to-end rate (pairs/s
-    from the first submit to the last completion) and the result count.
+    Returns per-batch latency percentiles and maximum (ms), the slowest
+    batch's submit / admission / completion times (ms after the first
+    submit), the end-to-end rate (pairs/s from the first submit to the last
+    completion) and the result count.  With a list in `results`, batch i's
+    result pairs are stored in results[i].
     """
     n = len(batches)
     tickets: List[Optional[int]] = [None] * n
@@ -118,7 +121,10 @@ def run_stream(S, ctx, coll, batches, rate_pairs_per_s: Optional[float] = None, 
 
     lat = np.zeros(n)
     t_sub = np.zeros(n)
+    t_adm = np.zeros(n)
     t_done = np.zeros(n)
+    if results is not None:
+        results[:] = [None] * n
     n_result = 0
     ths = [threading.Thread(target=submitter, args=(k,), daemon=True) for k in range(max(1, n_submitters))]
     n_submitters = len(ths)
@@ -131,7 +137,9 @@ def run_stream(S, ctx, coll, batches, rate_pairs_per_s: Optional[float] = None, 
         ts, ta, td = S.ssj_stream_times(ctx, tickets[i], wait=True)
         res = S.ssj_stream_collect(ctx, tickets[i])
         n_result += res.shape[0]
-        t_sub[i], t_done[i] = ts, td
+        if results is not None:
+            results[i] = res
+        t_sub[i], t_adm[i], t_done[i] = ts, ta, td
         lat[i] = (td - ts) / 1e6
     for th in ths:
         th.join(timeout=max(0.0, deadline - time.perf_counter()))
@@ -139,12 +147,19 @@ def run_stream(S, ctx, coll, batches, rate_pairs_per_s: Optional[float] = None, 
         raise errors[0]
     pairs = int(sum(b[0].shape[0] for b in batches))
     span = (t_done.max() - t_sub.min()) / 1e9 if n else 0.0
+    slow = int(np.argmax(lat)) if n else 0
+    base = t_sub.min() if n else 0.0
     return {
         "batches": n,
         "pairs": pairs,
         "mean_batch_pairs": round(mean, 1),
         "p50_ms": round(float(np.percentile(lat, 50)), 4) if n else None,
         "p99_ms": round(float(np.percentile(lat, 99)), 4) if n else None,
+        "max_ms": round(float(lat.max()), 4) if n else None,
+        "slowest": ({"batch": slow, "pairs": int(batches[slow][0].shape[0]),
+                     "submit_ms": round((t_sub[slow] - base) / 1e6, 4),
+                     "admit_ms": round((t_adm[slow] - base) / 1e6, 4),
+                     "done_ms": round((t_done[slow] - base) / 1e6, 4)} if n else None),
         "pairs_per_s": round(pairs / span, 1) if span > 0 else None,
         "offered_pairs_per_s": rate_pairs_per_s,
         "results": n_result,

@@ -79,13 +79,13 @@ class ssj_plan(ctypes.Structure):
     _fields_ = [("inline_lanes", ctypes.c_int), ("hard_lanes", ctypes.c_int),
                 ("defer_from", ctypes.c_int), ("lanes", ctypes.c_int * SSJ_N_CLASSES),
                 ("use_graph", ctypes.c_int), ("spill_iters", ctypes.c_int),
-                ("spill_lanes", ctypes.c_int), ("wg_per_cu", ctypes.c_int)]
+                ("spill_lanes", ctypes.c_int), ("wg_per_cu", ctypes.c_int), ("staged", ctypes.c_int)]
 
     def as_dict(self):
         return {"inline_lanes": self.inline_lanes, "hard_lanes": self.hard_lanes,
                 "defer_from": self.defer_from, "lanes": list(self.lanes),
                 "use_graph": self.use_graph, "spill_iters": self.spill_iters,
-                "spill_lanes": self.spill_lanes, "wg_per_cu": self.wg_per_cu}
+                "spill_lanes": self.spill_lanes, "wg_per_cu": self.wg_per_cu, "staged": self.staged}
 
 
 class ssj_request(ctypes.Structure):
@@ -503,7 +503,7 @@ def ssj_get_plan(ctx) -> ssj_plan:
 
 def make_plan(inline_lanes: int = 1, defer_from: int = SSJ_N_CLASSES, lanes=(4, 16, 64, 256, 256),
               use_graph: int = 0, hard_lanes: int = 0, spill_iters: int = 0,
-              spill_lanes: int = 16, wg_per_cu: int = 0) -> ssj_plan:
+              spill_lanes: int = 16, wg_per_cu: int = 0, staged: int = 0) -> ssj_plan:
     p = ssj_plan()
     p.inline_lanes = int(inline_lanes)
     p.hard_lanes = int(hard_lanes)
@@ -514,6 +514,7 @@ def make_plan(inline_lanes: int = 1, defer_from: int = SSJ_N_CLASSES, lanes=(4, 
     p.spill_iters = int(spill_iters)
     p.spill_lanes = int(spill_lanes)
     p.wg_per_cu = int(wg_per_cu)
+    p.staged = int(staged)
     return p
 
 

@@ -106,7 +106,7 @@ def test_plan_struct_matches_header():
     fields = [m.group(1) for m in re.finditer(r"\bint\s+(\w+)\s*(?:\[[^\]]*\])?\s*;",
                                                 re.sub(r"/\*.*?\*/", "", body, flags=re.S))]
     assert fields == [f[0] for f in ssj.ssj_plan._fields_]
-    assert ctypes.sizeof(ssj.ssj_plan) == 4 * (7 + ssj.SSJ_N_CLASSES)
+    assert ctypes.sizeof(ssj.ssj_plan) == 4 * (8 + ssj.SSJ_N_CLASSES)
 
 
 def test_groups_of_runs():

@@ -27,7 +27,11 @@ def test_plan_specs():
     assert (p["inline_lanes"], p["spill_iters"], p["spill_lanes"], p["wg_per_cu"], p["defer_from"]) == (1, 32, 16, 4, 4)
     assert list(p["lanes"]) == [4, 8, 16, 32, 64]
     p = bench.plan_of(S, "inline:8").as_dict()
-    assert p["inline_lanes"] == 8 and p["spill_lanes"] == 16
+    assert p["inline_lanes"] == 8 and p["spill_lanes"] == 16 and p["staged"] == 0
+    p = bench.plan_of(S, "inline:1bs6x64w2").as_dict()
+    assert (p["staged"], p["spill_iters"], p["spill_lanes"], p["wg_per_cu"], p["defer_from"]) == (1, 6, 64, 2, 5)
+    p = bench.plan_of(S, "defer:1b,3,4,8,16,32,64").as_dict()
+    assert p["staged"] == 1 and p["defer_from"] == 3 and p["spill_iters"] == 0
     for bad in ["inline:x", "inline:", "foo:1", "defer:1", "defer:1,2,4,4", "inline:1q3"]:
         with pytest.raises(SystemExit):
             bench.plan_of(S, bad)
@@ -53,6 +57,30 @@ def test_traffic_lookup_requires_matching_source():
     assert bench.traffic_from_profiles("0" * 64, d["workload_key"], d["kernel"]) is None
     assert bench.traffic_from_profiles(d["kernel_source_sha256"], "heavytail", d["kernel"]) is None
     assert bench.traffic_from_profiles(d["kernel_source_sha256"], d["workload_key"], "k_other") is None
+
+
+def test_kernel_names_follow_the_plan():
+    """The kernel names the bench reports (and looks traffic up by) are the
+    instances a plan launches."""
+    assert bench.kernel_name_of(bench.plan_of(S, "inline:1w5")) == "k_verify_tiles<1,0,false,false>"
+    assert bench.kernel_name_of(bench.plan_of(S, "inline:1bs6x16")) == \
+        "k_verify_staged<true,false> + k_verify_deferred<false>"
+    assert bench.kernel_name_of(bench.plan_of(S, "inline:1b")) == "k_verify_staged<false,false>"
+    assert bench.kernel_name_of(bench.plan_of(S, "defer:16,3,4,8,16,32,64")) == \
+        "k_verify_tiles<16,0,true,false> + k_verify_deferred<false>"
+
+
+def test_default_workloads_lead_with_the_largest():
+    """The headline is the heavy-tail workload (the largest configuration),
+    with the long-set and offline workloads in the same line."""
+    a = bench.parse([])
+    assert a.workload.split(",") == ["heavytail", "longsets", "offline"]
+    assert a.steps == 20 and a.gpus == 1
+
+
+def test_host_cpu_reports_threads():
+    c = bench.host_cpu()
+    assert c["nproc"] >= 1 and c["cpu_count"] >= 1
 
 
 def test_more_than_one_gpu_is_refused():

@@ -68,6 +68,19 @@ def plans():
                                       spill_iters=2, spill_lanes=32)))
     out.append(("spill-graph", dict(inline_lanes=1, defer_from=3, lanes=[4, 8, 16, 32, 256],
                                     spill_iters=1, spill_lanes=8, use_graph=1)))
+    # the staged kernel (token blocks in LDS): alone, cut off after one or two
+    # rounds of block loads (the rest verified again by the deferred
+    # kernel), with deferred classes, in a graph and on a one-workgroup grid
+    out.append(("staged", dict(inline_lanes=1, defer_from=5, staged=1)))
+    for I, G in [(1, 16), (2, 1), (1, 256)]:
+        out.append((f"staged-spill-{I}x{G}", dict(inline_lanes=1, defer_from=5, staged=1, spill_iters=I,
+                                                  spill_lanes=G)))
+    out.append(("staged-defer", dict(inline_lanes=1, defer_from=2, lanes=[4, 8, 32, 64, 256], staged=1)))
+    out.append(("staged-spill-2-defer", dict(inline_lanes=1, defer_from=3, lanes=[4, 8, 16, 64, 256],
+                                             staged=1, spill_iters=2, spill_lanes=64)))
+    out.append(("staged-graph", dict(inline_lanes=1, defer_from=4, lanes=[4, 8, 16, 32, 64], staged=1,
+                                     use_graph=1)))
+    out.append(("staged-wg1", dict(inline_lanes=1, defer_from=5, staged=1, wg_per_cu=1)))
     # in-order grids of one and of many workgroups per compute unit
     out.append(("inline-1-wg1", dict(inline_lanes=1, defer_from=5, wg_per_cu=1)))
     out.append(("inline-8-wg13", dict(inline_lanes=8, defer_from=5, wg_per_cu=13)))
@@ -105,17 +118,26 @@ def want_of(coll, cand, tn, td):
     return oracle.sort_pairs(oracle.select(coll.offsets, coll.tokens, cand, tn, td, n_threads=8))
 
 
-def test_config1_all_plans(S, ctx):
+def test_config1_all_plans(S, ctx, golden_dir):
+    """The tiny collection at its stated threshold (no similar pairs) and at
+    t = 1/2 (six), against brute force and the manifest, in every plan."""
+    import json
+    man = json.load(open(os.path.join(golden_dir, "manifest.json")))["1"]
     c = synth.workload_collection(1)
-    (tn, td), = synth.WORKLOADS[1].thresholds
-    cand = cfilter.workload_candidates(1, tn, td)
-    want = want_of(c, cand, tn, td)
-    assert want.tolist() == sorted(brute.brute_join(c.offsets, c.tokens, tn, td))
     h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
-    for name, plan in plans():
-        _log(f"config1 {name}")
-        set_plan(S, ctx, plan)
-        assert np.array_equal(run_host(S, ctx, h, cand, tn, td), want), name
+    (tn0, td0), = synth.WORKLOADS[1].thresholds
+    for (tn, td) in [(tn0, td0), (1, 2)]:
+        key = f"{tn}/{td}"
+        m = man["thresholds"].get(key) or man["extra_thresholds"][key]
+        cand = cfilter.workload_candidates(1, tn, td)
+        assert cand.shape[0] == m["n_candidates"]
+        want = want_of(c, cand, tn, td)
+        assert want.tolist() == sorted(brute.brute_join(c.offsets, c.tokens, tn, td))
+        assert want.shape[0] == m["n_result"] and oracle.result_digest(want) == m["result_sha256"]
+        for name, plan in plans():
+            _log(f"config1 t={key} {name}")
+            set_plan(S, ctx, plan)
+            assert np.array_equal(run_host(S, ctx, h, cand, tn, td), want), (name, key)
     S.ssj_free_collection(ctx, h)
 
 
@@ -253,25 +275,63 @@ def test_config3_long_sets(S, ctx, golden_dir):
     (tn, td), = synth.WORKLOADS[3].thresholds
     cand = cfilter.workload_candidates(3, tn, td)
     m = man["thresholds"][f"{tn}/{td}"]
-    for name, plan in [("default", None), ("inline-16", dict(inline_lanes=16, defer_from=5)),
-                       ("inline-64", dict(inline_lanes=64, defer_from=5)),
-                       ("deferred-all-256", dict(inline_lanes=4, defer_from=0, lanes=[256] * 5)),
-                       ("deferred-long", dict(inline_lanes=1, defer_from=2, lanes=[4, 8, 16, 64, 256])),
-                       ("spill-8x16", dict(inline_lanes=1, defer_from=5, spill_iters=8, spill_lanes=16)),
-                       ("spill-4x64-defer", dict(inline_lanes=1, defer_from=4, lanes=[4, 8, 16, 32, 32],
-                                                 spill_iters=4, spill_lanes=64))]:
-        _log(f"config3 {name}")
+    # the random workload has few similar pairs: its whole candidate list is
+    # also verified at lower thresholds (11 pass at t = 1/10), pinned in the
+    # manifest, in every plan
+    for name, plan in LONG_PLANS:
         set_plan(S, ctx, plan)
+        _log(f"config3 {name}")
         got = run_host(S, ctx, h, cand, tn, td)
         assert got.shape[0] == m["n_result"] and oracle.result_digest(got) == m["result_sha256"], name
-    # the random workload has few similar pairs; also check pass decisions at
-    # lower thresholds on a sample of its candidates
-    sub = cand[::7]
-    for (tn2, td2) in [(1, 10), (1, 5), (3, 10)]:
-        want = want_of(c, sub, tn2, td2)
-        set_plan(S, ctx, None)
-        assert np.array_equal(run_host(S, ctx, h, sub, tn2, td2), want)
+        for key, v in man["verify_at"].items():
+            if key == "candidates":
+                continue
+            vn, vd = (int(x) for x in key.split("/"))
+            got = run_device(S, ctx, h, cand, vn, vd)
+            assert got.shape[0] == v["n_result"] and oracle.result_digest(got) == v["result_sha256"], \
+                (name, key)
     S.ssj_free_collection(ctx, h)
+
+
+# Long-set plans: every mapping family plus the plans the autotuner picks on
+# the long-set workload (thread per pair with a step budget and the longest
+# class on 64 lanes; the staged kernel with a round budget).
+LONG_PLANS = [("default", None), ("inline-16", dict(inline_lanes=16, defer_from=5)),
+              ("inline-64", dict(inline_lanes=64, defer_from=5)),
+              ("deferred-all-256", dict(inline_lanes=4, defer_from=0, lanes=[256] * 5)),
+              ("deferred-long", dict(inline_lanes=1, defer_from=2, lanes=[4, 8, 16, 64, 256])),
+              ("spill-8x16", dict(inline_lanes=1, defer_from=5, spill_iters=8, spill_lanes=16)),
+              ("spill-4x64-defer", dict(inline_lanes=1, defer_from=4, lanes=[4, 8, 16, 32, 32],
+                                        spill_iters=4, spill_lanes=64)),
+              ("tuned-s32x16w4", dict(inline_lanes=1, defer_from=4, lanes=[4, 4, 8, 16, 64],
+                                      spill_iters=32, spill_lanes=16, wg_per_cu=4)),
+              ("staged", dict(inline_lanes=1, defer_from=5, staged=1)),
+              ("staged-s6x16", dict(inline_lanes=1, defer_from=5, staged=1, spill_iters=6, spill_lanes=16)),
+              ("staged-s4x64-defer", dict(inline_lanes=1, defer_from=4, lanes=[4, 8, 16, 32, 64], staged=1,
+                                          spill_iters=4, spill_lanes=64)),
+              ("staged-s8x16-wg2", dict(inline_lanes=1, defer_from=5, staged=1, spill_iters=8,
+                                        spill_lanes=16, wg_per_cu=2))]
+
+
+def test_long_near_duplicates_all_plans(S, ctx):
+    """Long sets (10 to 600 tokens, Zipf(0.9) over 1,000,000 tokens as in the
+    long-set workload) of which each appears three times with 8% of its tokens
+    changed: thousands of passing long pairs, in every long-set plan."""
+    rng = np.random.default_rng(31)
+    c = synth.near_duplicate_collection(rng, n_base=1500, copies=3, max_size=600, universe=1_000_000,
+                                        change_frac=0.08, min_size=10, zipf_s=0.9)
+    h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+    try:
+        for (tn, td) in [(7, 10), (1, 2)]:
+            cand = cfilter.candidates(c.offsets, c.tokens, tn, td)
+            want = want_of(c, cand, tn, td)
+            assert want.shape[0] > 1000
+            for name, plan in LONG_PLANS:
+                _log(f"long near-dup t={tn}/{td} {name} n={cand.shape[0]}")
+                set_plan(S, ctx, plan)
+                assert np.array_equal(run_device(S, ctx, h, cand, tn, td), want), (name, tn, td)
+    finally:
+        S.ssj_free_collection(ctx, h)
 
 
 def test_extreme_tokens_and_very_long_sets(S, ctx):
