@@ -64,16 +64,19 @@ typedef struct {
 
 typedef struct {
     int device;           /* HIP device ordinal */
-    uint64_t hbm_budget;  /* device bytes for candidate chunks and their
-                             worst-case output (the paper's M_c, Sec. 3.3.1);
-                             0 selects 4 GiB */
+    uint64_t hbm_budget;  /* device bytes for the uploaded collections plus
+                             the candidate chunks of each call and their
+                             worst-case output (the paper's M_c, Sec. 3.3.1):
+                             collections must fit it together, and what they
+                             leave bounds the chunks; 0 selects 4 GiB */
     int n_slots;          /* concurrent stream requests on the device (0 -> 4) */
     int queue_depth;      /* stream requests accepted but not yet admitted (0 -> 64) */
 } ssj_opts;
 
 /* Creates a context on opts->device (opts may be NULL for defaults).
- * Allocates device scratch and streams.  SSJ_EINVAL for a bad device or
- * option, SSJ_EDEVICE if HIP fails. */
+ * Allocates small device scratch and streams (candidate buffers are sized on
+ * first use, within the budget).  SSJ_EINVAL for a bad device or option,
+ * SSJ_EDEVICE if HIP fails. */
 int ssj_init(const ssj_opts* opts, ssj_ctx** out);
 
 /* Waits for in-flight stream work, releases everything the context owns
@@ -90,9 +93,11 @@ const char* ssj_last_error(ssj_ctx* ctx);
  * Checks on the host: every set non-empty, tokens strictly increasing inside
  * a set, 0 <= token < 2^31, n_sets < 2^31, n_tokens < 2^32  (else
  * SSJ_EINVAL).  The library copies both arrays; the caller keeps ownership.
- * The device copy is the token array plus one {start, length} descriptor per
- * set.  The handle is valid until ssj_free_collection / ssj_shutdown.
- * (The paper transfers each collection once, Sec. 3.3.1.)
+ * The device copy is the token array (each set padded to a multiple of 4
+ * tokens) plus a 32-byte record per set.  SSJ_ENOMEM when that copy and the
+ * context's resident collections together exceed hbm_budget (nothing is
+ * uploaded then).  The handle is valid until ssj_free_collection /
+ * ssj_shutdown.  (The paper transfers each collection once, Sec. 3.3.1.)
  */
 int ssj_upload_collection(ssj_ctx* ctx, const int64_t* offsets, int64_t n_sets,
                           const int32_t* tokens, int64_t n_tokens, ssj_coll** out);
@@ -295,6 +300,14 @@ int ssj_stream_poll(ssj_ctx* ctx, uint64_t ticket, int wait, ssj_pair* out, int6
  * Does not retire the ticket.  SSJ_ENOTFOUND for an unknown ticket. */
 int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, int wait, uint64_t* t_submit,
                      uint64_t* t_admit, uint64_t* t_done);
+
+/* Holds (pause != 0) or resumes (pause == 0) admission of stream requests:
+ * while held, requests already on the device finish and submits still queue
+ * up to queue_depth (then block, or SSJ_EAGAIN when non-blocking), but no
+ * queued request is admitted.  For draining a device (and for tests of the
+ * queue limits).  ssj_shutdown resumes admission first.  SSJ_EINVAL for a
+ * context without a stream engine. */
+int ssj_stream_pause(ssj_ctx* ctx, int pause);
 
 /*
  * Execution plan.  Verification runs as one or two kernels per launch:

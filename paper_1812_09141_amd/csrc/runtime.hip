@@ -53,6 +53,8 @@ constexpr size_t kBytesPerPair = 8 + 8 + 4 * ssj::kQueues;
 // buffers of kRingPiece pairs, at most kMaxPieces pieces per device batch
 constexpr int64_t kRingPiece = (int64_t)1 << 20;
 constexpr int64_t kMaxPieces = 64;
+// a stream slot may always hold this many pairs, whatever the budget leaves
+constexpr int64_t kSlotFloor = 1024;
 
 // Threshold range of a similarity function (SSJ_SIM_*): 0 < t_den < 2^31,
 // 0 <= t_num < 2^31, and t <= 1 for the normalised functions.
@@ -154,6 +156,7 @@ struct ssj_coll {
     int64_t n_sets = 0;
     int64_t n_tokens = 0;
     int64_t max_len = 0;
+    uint64_t dev_bytes = 0;  // device bytes of its tokens and set records
     mutable std::atomic<int> inflight{0};  // stream requests not yet finished
 };
 
@@ -162,6 +165,7 @@ struct StreamEngine;
 struct ssj_ctx {
     int device = 0;
     uint64_t budget = kDefaultBudget;
+    std::atomic<uint64_t> resident{0};  // device bytes of the uploaded collections (within budget)
     int n_slots = 4;
     int queue_depth = 64;
     int n_cu = 0;
@@ -171,7 +175,12 @@ struct ssj_ctx {
     int occ_deferred2[2] = {0};  // [cosine]
     ssj_plan plan{};
     std::mutex mu;  // default scratch, host staging, collections, plan, graphs
+    // also held while the plan changes (after mu), so that the stream engine,
+    // which holds its own lock, can read the plan without taking mu (the
+    // lock order is mu, then the engine's lock)
+    std::mutex plan_mu;
     hipStream_t stream = nullptr;  // the context's own stream (host-buffer calls)
+    hipStream_t copy_stream = nullptr;  // host-to-device copies of the host-buffer path's pieces
     Scratch def;
     // host-buffer verify staging
     int2* d_cand = nullptr;
@@ -181,7 +190,8 @@ struct ssj_ctx {
     long long* d_count = nullptr;
     long long* h_count = nullptr;  // pinned
     // the pinned ring of the host-buffer path (allocated on first use), one
-    // event per buffer (its last copy to the device), per-piece counts
+    // event per buffer (its last copy to the device, on copy_stream),
+    // per-piece counts
     int2* h_ring[2] = {nullptr, nullptr};
     hipEvent_t ring_ev[2] = {nullptr, nullptr};
     long long* d_counts = nullptr;  // kMaxPieces
@@ -326,6 +336,7 @@ int check_req(const Req& r) {
     if (r.n < 0) return set_error(SSJ_EINVAL, "negative candidate count");
     if (r.out_cap < 0) return set_error(SSJ_EINVAL, "negative output capacity");
     if (!r.d_count || (r.n > 0 && !r.d_cand)) return set_error(SSJ_EINVAL, "null device buffer");
+    if (r.out_cap > 0 && !r.d_out) return set_error(SSJ_EINVAL, "out_cap > 0 with a null output buffer");
     return SSJ_OK;
 }
 
@@ -495,6 +506,12 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     return SSJ_OK;
 }
 
+// Budget bytes left for candidate buffers next to the resident collections.
+uint64_t free_budget(const ssj_ctx* ctx) {
+    const uint64_t r = ctx->resident.load();
+    return r < ctx->budget ? ctx->budget - r : 0u;
+}
+
 int check_ctx(ssj_ctx* ctx) {
     if (!ctx) return set_error(SSJ_EINVAL, "null context");
     if (ctx->failed) return set_error(SSJ_EDEVICE, "context failed after a HIP error");
@@ -538,8 +555,12 @@ struct SlotPart {
     StreamReq* req;
     int64_t off, n;         // range of the request's candidates
     int64_t dev_off;        // offset in the slot's device buffers
+    int64_t res_off;        // offset of its results in the slot's pinned result buffer
 };
 
+// A slot: a stream and the device buffers of one launch in flight.  The
+// buffers are sized on demand (to the largest batch the slot has taken) within
+// the part of the HBM budget that the collections and the other slots leave.
 struct StreamSlot {
     hipStream_t stream = nullptr;
     Scratch sc;
@@ -547,8 +568,11 @@ struct StreamSlot {
     int2* d_out = nullptr;
     long long* d_count = nullptr;
     long long* h_count = nullptr;    // pinned, kMaxReq entries
-    int2* h_out = nullptr;           // pinned, cap pairs
-    int64_t cap = 0;                 // pairs
+    int2* h_out = nullptr;           // pinned results of the batch, h_cap pairs (grown on demand)
+    int64_t h_cap = 0;
+    size_t cand_cap = 0, out_cap = 0;  // pairs d_cand and d_out hold
+    int64_t cap = 0;                 // pairs all device buffers hold
+    uint64_t held = 0;               // device bytes of d_cand, d_out and the queues
     hipEvent_t ev = nullptr;
     int state = 0;                   // 0 idle, 1 running, 2 reading results, 3 results on host
     std::vector<SlotPart> parts;
@@ -560,10 +584,13 @@ struct StreamEngine {
     std::mutex mu;
     std::condition_variable cv_work, cv_space, cv_done;
     std::deque<StreamReq*> pending;     // not fully admitted
+    int reserved = 0;                   // queue places taken by submits still copying their candidates
     std::unordered_map<uint64_t, StreamReq*> table;
     std::vector<StreamSlot> slots;
+    uint64_t held = 0;                  // device bytes held by all slots' buffers
     uint64_t next_ticket = 1;
     bool stop = false;
+    bool paused = false;                // ssj_stream_pause: admit nothing (until stop)
     std::thread worker;
     // pinned staging pool by size class (powers of two)
     std::map<size_t, std::vector<void*>> pool;
@@ -619,11 +646,48 @@ void fail_slot(StreamEngine* E, StreamSlot& s) {
 
 // Called with E->mu held.  Fills idle slot s with parts of pending requests
 // and enqueues their copies, one launch, and the count read-back.
+// Grows slot s's device buffers to hold at least n pairs (the slot is idle;
+// grow() synchronises the device before it releases an old buffer).
+bool slot_grow(StreamEngine* E, StreamSlot& s, int64_t n) {
+    E->held -= s.held;
+    s.held = 0;
+    s.cap = 0;
+    if (grow(s.d_cand, s.cand_cap, (size_t)n) != hipSuccess) return false;
+    if (grow(s.d_out, s.out_cap, (size_t)n) != hipSuccess) return false;
+    if (grow(s.sc.d_queues, s.sc.q_cap, (size_t)ssj::kQueues * (size_t)n) != hipSuccess) return false;
+    s.cap = (int64_t)std::min({s.cand_cap, s.out_cap, s.sc.q_cap / (size_t)ssj::kQueues});
+    s.held = (uint64_t)(s.cand_cap + s.out_cap) * sizeof(int2) + (uint64_t)s.sc.q_cap * sizeof(uint32_t);
+    E->held += s.held;
+    return true;
+}
+
 bool admit(StreamEngine* E, StreamSlot& s) {
     ssj_ctx* ctx = E->ctx;
     s.parts.clear();
     if (E->pending.empty()) return true;
     s.coll = E->pending.front()->coll;
+    // pairs this slot may hold: its own buffers plus the budget that the
+    // collections and the other slots' buffers leave (at least kSlotFloor)
+    const uint64_t others = E->held - s.held;
+    const uint64_t spare = free_budget(ctx);
+    const int64_t room = std::min<int64_t>(
+        kMaxLaunchPairs,
+        std::max<int64_t>(kSlotFloor, (int64_t)((spare > others ? spare - others : 0) / kBytesPerPair)));
+    int64_t want = 0;
+    {
+        int k = 0;
+        for (StreamReq* r : E->pending) {
+            if (r->coll != s.coll || k++ >= ssj::kMaxReq || want >= room) break;
+            want += r->n - r->next_part_off;
+        }
+        want = std::min(want, room);
+    }
+    if (want > s.cap) {
+        // to the batch's size, or twice the old size when that fits (fewer
+        // regrowths while batch sizes vary)
+        const int64_t n = std::min(room, std::max(want, 2 * s.cap));
+        if (!slot_grow(E, s, n)) return false;
+    }
     int64_t used = 0;
     while (!E->pending.empty() && (int)s.parts.size() < ssj::kMaxReq) {
         StreamReq* r = E->pending.front();
@@ -632,7 +696,7 @@ bool admit(StreamEngine* E, StreamSlot& s) {
         const int64_t take = std::min(left, s.cap - used);
         if (take <= 0 && left > 0) break;
         if (r->t_admit == 0) r->t_admit = now_ns();
-        s.parts.push_back(SlotPart{r, r->next_part_off, take, used});
+        s.parts.push_back(SlotPart{r, r->next_part_off, take, used, 0});
         r->parts_admitted += 1;
         r->next_part_off += take;
         used += take;
@@ -651,7 +715,7 @@ bool admit(StreamEngine* E, StreamSlot& s) {
     }
     ssj_plan plan;
     {
-        std::lock_guard<std::mutex> g(ctx->mu);
+        std::lock_guard<std::mutex> g(ctx->plan_mu);
         plan = ctx->plan;
     }
     if (enqueue_launch(ctx, s.coll, s.sc, reqs.data(), (int)reqs.size(), s.stream, plan, false) != SSJ_OK)
@@ -665,14 +729,32 @@ bool admit(StreamEngine* E, StreamSlot& s) {
 }
 
 // Called with E->mu held; slot state 1 and its event complete: copy back the
-// passing pairs (their number is now known).
+// passing pairs (their number is now known) into the slot's pinned result
+// buffer, part after part.
 bool read_counts(StreamSlot& s) {
+    int64_t total = 0;
+    for (size_t k = 0; k < s.parts.size(); ++k) {
+        s.parts[k].res_off = total;
+        total += std::max<long long>(0, s.h_count[k]);
+    }
+    if (total > s.h_cap) {
+        // results are usually few; the buffer grows to the largest batch result
+        const int64_t n = std::max<int64_t>(total, 2 * s.h_cap);
+        if (s.h_out) (void)hipHostFree(s.h_out);
+        s.h_out = nullptr;
+        s.h_cap = 0;
+        if (hipHostMalloc((void**)&s.h_out, (size_t)n * sizeof(int2), hipHostMallocDefault) != hipSuccess) {
+            s.h_out = nullptr;
+            return false;
+        }
+        s.h_cap = n;
+    }
     bool any = false;
     for (size_t k = 0; k < s.parts.size(); ++k) {
         const long long c = s.h_count[k];
         if (c > 0) {
-            if (hipMemcpyAsync(s.h_out + s.parts[k].dev_off, s.d_out + s.parts[k].dev_off,
-                               (size_t)c * 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
+            if (hipMemcpyAsync(s.h_out + s.parts[k].res_off, s.d_out + s.parts[k].dev_off, (size_t)c * 8,
+                               hipMemcpyDeviceToHost, s.stream) != hipSuccess)
                 return false;
             any = true;
         }
@@ -695,7 +777,7 @@ void complete_slot(StreamEngine* E, StreamSlot& s) {
         if (c < 0) {
             r->bad_id = true;
         } else if (c > 0) {
-            r->result.insert(r->result.end(), s.h_out + p.dev_off, s.h_out + p.dev_off + c);
+            r->result.insert(r->result.end(), s.h_out + p.res_off, s.h_out + p.res_off + c);
         }
         ++r->parts_done;
         maybe_finish(E, r);
@@ -729,7 +811,7 @@ void engine_loop(StreamEngine* E) {
                 }
             }
             if (s.state == 3) complete_slot(E, s);
-            if (s.state == 0 && !E->pending.empty() && !E->ctx->failed) {
+            if (s.state == 0 && !E->pending.empty() && !E->ctx->failed && (!E->paused || E->stop)) {
                 if (!admit(E, s)) {
                     fail_slot(E, s);
                 } else if (s.state == 1) {
@@ -765,22 +847,15 @@ int engine_start(ssj_ctx* ctx) {
     auto E = std::make_unique<StreamEngine>();
     E->ctx = ctx;
     E->slots.resize((size_t)ctx->n_slots);
-    const int64_t cap = std::max<int64_t>(
-        1024, (int64_t)(ctx->budget / ((uint64_t)ctx->n_slots * kBytesPerPair)));
+    // per slot: a stream, counters and count buffers; the candidate, output
+    // and queue buffers are sized by the first batches the slot admits
     for (auto& s : E->slots) {
-        s.cap = std::min<int64_t>(cap, kMaxLaunchPairs);
         HIP_OR_FAIL(ctx, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
         int rc = scratch_init(ctx, s.sc);
         if (rc != SSJ_OK) return rc;
-        HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_cand, (size_t)s.cap * 8));
-        HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_out, (size_t)s.cap * 8));
         HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_count, sizeof(long long) * ssj::kMaxReq));
         HIP_OR_FAIL(ctx, hipHostMalloc((void**)&s.h_count, sizeof(long long) * ssj::kMaxReq, hipHostMallocDefault));
-        HIP_OR_FAIL(ctx, hipHostMalloc((void**)&s.h_out, (size_t)s.cap * 8, hipHostMallocDefault));
         HIP_OR_FAIL(ctx, hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
-        size_t qc = 0;
-        HIP_OR_FAIL(ctx, grow(s.sc.d_queues, qc, (size_t)ssj::kQueues * (size_t)s.cap));
-        s.sc.q_cap = qc;
     }
     StreamEngine* raw = E.get();
     ctx->engine = std::move(E);
@@ -916,10 +991,12 @@ int ssj_shutdown(ssj_ctx* ctx) {
             if (q) (void)hipFree(q);
         if (ctx->d_count) (void)hipFree(ctx->d_count);
         if (ctx->h_count) (void)hipHostFree(ctx->h_count);
+        if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
         for (int k = 0; k < 2; ++k) {
             if (ctx->h_ring[k]) (void)hipHostFree(ctx->h_ring[k]);
             if (ctx->ring_ev[k]) (void)hipEventDestroy(ctx->ring_ev[k]);
         }
+        if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
         if (ctx->d_counts) (void)hipFree(ctx->d_counts);
         if (ctx->h_counts) (void)hipHostFree(ctx->h_counts);
         for (auto& kv : ctx->graphs) {
@@ -988,9 +1065,18 @@ int ssj_upload_collection(ssj_ctx* ctx, const int64_t* offsets, int64_t n_sets,
         return set_error(SSJ_ENOMEM, "host allocation failed");
     }
     std::lock_guard<std::mutex> g(ctx->mu);
+    // the collections resident at once must fit the HBM budget (what is left
+    // of it bounds the candidate buffers of each call)
+    const uint64_t bytes = (uint64_t)padded.size() * 4u + (uint64_t)std::max<int64_t>(n_sets, 1) * 32u;
+    if (ctx->resident.load() + bytes > ctx->budget)
+        return set_error(SSJ_ENOMEM, "the collection (" + std::to_string(bytes) + " device bytes) does not fit "
+                                     "the HBM budget next to the resident collections (" +
+                                     std::to_string(ctx->resident.load()) + " of " + std::to_string(ctx->budget) +
+                                     " bytes)");
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
     ssj_coll* c = new (std::nothrow) ssj_coll();
     if (!c) return set_error(SSJ_ENOMEM, "host allocation failed");
+    c->dev_bytes = bytes;
     c->ctx = ctx;
     c->n_sets = n_sets;
     c->n_tokens = n_tokens;
@@ -1018,7 +1104,12 @@ int ssj_upload_collection(ssj_ctx* ctx, const int64_t* offsets, int64_t n_sets,
         if (e == hipErrorOutOfMemory) return set_error(SSJ_ENOMEM, "device allocation failed");
         return hip_fail(ctx, "upload", e);
     }
-    ctx->colls.push_back(c);
+    {
+        std::unique_lock<std::mutex> ek;
+        if (ctx->engine) ek = std::unique_lock<std::mutex>(ctx->engine->mu);
+        ctx->colls.push_back(c);
+        ctx->resident += bytes;
+    }
     *out = c;
     return SSJ_OK;
 }
@@ -1027,11 +1118,19 @@ int ssj_free_collection(ssj_ctx* ctx, ssj_coll* coll) {
     int rc = check_ctx(ctx);
     if (rc != SSJ_OK) return rc;
     if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
-    if (coll->inflight.load() != 0) return set_error(SSJ_EAGAIN, "collection has requests in flight");
     std::lock_guard<std::mutex> g(ctx->mu);
-    auto it = std::find(ctx->colls.begin(), ctx->colls.end(), coll);
-    if (it == ctx->colls.end()) return set_error(SSJ_EINVAL, "unknown collection");
-    ctx->colls.erase(it);
+    {
+        // submits take their place in flight under the engine's lock, so a
+        // request is either counted here or submitted after the collection is
+        // gone from ctx->colls (and then refused by the submit's lookup)
+        std::unique_lock<std::mutex> ek;
+        if (ctx->engine) ek = std::unique_lock<std::mutex>(ctx->engine->mu);
+        if (coll->inflight.load() != 0) return set_error(SSJ_EAGAIN, "collection has requests in flight");
+        auto it = std::find(ctx->colls.begin(), ctx->colls.end(), coll);
+        if (it == ctx->colls.end()) return set_error(SSJ_EINVAL, "unknown collection");
+        ctx->colls.erase(it);
+        ctx->resident -= coll->dev_bytes;
+    }
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (coll->d_tok) (void)hipFree(coll->d_tok);
@@ -1065,6 +1164,7 @@ int ssj_set_plan(ssj_ctx* ctx, const ssj_plan* plan) {
                                      "hard_lanes 0; wg_per_cu in [0, 64]; staged 0 or 1, "
                                      "1 only with 1 lane and hard_lanes 0");
     std::lock_guard<std::mutex> g(ctx->mu);
+    std::lock_guard<std::mutex> gp(ctx->plan_mu);
     ctx->plan = *plan;
     return SSJ_OK;
 }
@@ -1192,6 +1292,7 @@ int ssj_verify_groups_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_col
         return set_error(SSJ_EINVAL, "n_cand and n_groups must be below 2^31 per device call");
     if (!d_count || (n_cand > 0 && !d_cand) || (n_groups > 0 && !d_groups))
         return set_error(SSJ_EINVAL, "null device buffer");
+    if (out_cap > 0 && !d_out) return set_error(SSJ_EINVAL, "out_cap > 0 with a null output buffer");
     std::lock_guard<std::mutex> g(ctx->mu);
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
     return enqueue_groups(ctx, coll_r, coll_s, reinterpret_cast<const int2*>(d_groups), n_groups, d_cand,
@@ -1215,6 +1316,7 @@ int ssj_verify_groups_batch_device(ssj_ctx* ctx, const ssj_coll* coll_r, const s
         if (q.n_groups > kMaxLaunchPairs) return set_error(SSJ_EINVAL, "n_groups must be below 2^31");
         if (!q.d_count || (q.n_cand > 0 && !q.d_cand) || (q.n_groups > 0 && !q.d_groups))
             return set_error(SSJ_EINVAL, "null device buffer");
+        if (q.out_cap > 0 && !q.d_out) return set_error(SSJ_EINVAL, "out_cap > 0 with a null output buffer");
         total += q.n_cand;
         if (total > kMaxLaunchPairs) return set_error(SSJ_EINVAL, "a batch must hold fewer than 2^31 candidates");
     }
@@ -1431,6 +1533,7 @@ hipError_t ring_init(ssj_ctx* ctx) {
             e = hipHostMalloc((void**)&ctx->h_ring[k], (size_t)kRingPiece * sizeof(int2), hipHostMallocDefault);
         if (e == hipSuccess && !ctx->ring_ev[k]) e = hipEventCreateWithFlags(&ctx->ring_ev[k], hipEventDisableTiming);
     }
+    if (e == hipSuccess && !ctx->copy_stream) e = hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking);
     if (e == hipSuccess && !ctx->d_counts) e = hipMalloc((void**)&ctx->d_counts, sizeof(long long) * kMaxPieces);
     if (e == hipSuccess && !ctx->h_counts)
         e = hipHostMalloc((void**)&ctx->h_counts, sizeof(long long) * kMaxPieces, hipHostMallocDefault);
@@ -1439,11 +1542,12 @@ hipError_t ring_init(ssj_ctx* ctx) {
 
 // Host-buffer verification.  Each device batch (bounded by the HBM budget)
 // of more than kRingPiece pairs is sent in pieces of kRingPiece pairs through
-// two pinned buffers: while the device copies piece k and verifies it (one
-// launch per piece, its own count slot), the host fills the other buffer with
-// piece k + 1.  A batch of one piece is copied straight from the caller's
-// buffer.  The counts of a batch come back in one copy, then each piece's
-// passing pairs.
+// two pinned buffers: the host fills one buffer with piece k + 1 while piece k
+// is copied to the device on the copy stream and piece k - 1 is verified on
+// the launch stream (one launch per piece, its own count slot, started once
+// its piece's copy is done), so copies and kernels overlap.  A batch of one
+// piece is copied straight from the caller's buffer.  The counts of a batch
+// come back in one copy, then each piece's passing pairs.
 int verify_host(ssj_ctx* ctx, const ssj_coll* coll, const ssj_coll* coll_s, const ssj_pair* cand,
                 int64_t n_cand, int sim, int64_t t_num, int64_t t_den, ssj_pair* out, int64_t out_cap,
                 int64_t* out_n) {
@@ -1461,7 +1565,7 @@ int verify_host(ssj_ctx* ctx, const ssj_coll* coll, const ssj_coll* coll_s, cons
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
     HIP_OR_FAIL(ctx, ring_init(ctx));
     hipStream_t st = ctx->stream;
-    int64_t chunk = (int64_t)std::max<uint64_t>(1, ctx->budget / kBytesPerPair);
+    int64_t chunk = (int64_t)std::max<uint64_t>(1, free_budget(ctx) / kBytesPerPair);
     chunk = std::min<int64_t>({chunk, kMaxLaunchPairs, kRingPiece * kMaxPieces});
     int64_t total = 0, done = 0;
     bool bad_id = false;
@@ -1485,8 +1589,11 @@ int verify_host(ssj_ctx* ctx, const ssj_coll* coll, const ssj_coll* coll_s, cons
             HIP_OR_FAIL(ctx, hipEventSynchronize(ctx->ring_ev[slot]));
             host_copy(ctx->h_ring[slot], cand + done + off, (size_t)m * sizeof(int2));
             HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->d_cand + off, ctx->h_ring[slot], (size_t)m * sizeof(int2),
-                                            hipMemcpyHostToDevice, st));
-            HIP_OR_FAIL(ctx, hipEventRecord(ctx->ring_ev[slot], st));
+                                            hipMemcpyHostToDevice, ctx->copy_stream));
+            // the event both releases the pinned buffer to the host (two
+            // pieces later) and starts the piece's launch
+            HIP_OR_FAIL(ctx, hipEventRecord(ctx->ring_ev[slot], ctx->copy_stream));
+            HIP_OR_FAIL(ctx, hipStreamWaitEvent(st, ctx->ring_ev[slot], 0));
             Req r{ctx->d_cand + off, m, t_num, t_den, ctx->d_out + off, m, ctx->d_counts + k, sim};
             rc = enqueue_launch(ctx, coll, ctx->def, &r, 1, st, ctx->plan, true, coll_s);
             if (rc != SSJ_OK) return rc;
@@ -1557,7 +1664,7 @@ int ssj_verify_groups(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll
     // batches of whole groups (a group larger than a batch is split), each
     // copied as its s ids and its groups with ends relative to the batch
     const size_t per_cand = 4 + kBytesPerPair;
-    int64_t chunk = (int64_t)std::max<uint64_t>(1, ctx->budget / per_cand);
+    int64_t chunk = (int64_t)std::max<uint64_t>(1, free_budget(ctx) / per_cand);
     chunk = std::min<int64_t>(chunk, kMaxLaunchPairs);
     std::vector<ssj_group> bg;
     int64_t total = 0, c0 = 0, g = 0;
@@ -1772,7 +1879,10 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
     if (rc != SSJ_OK) return rc;
     if (best) *best = cur;
     if (best_ms) *best_ms = cur_ms;
-    if (apply) ctx->plan = cur;
+    if (apply) {
+        std::lock_guard<std::mutex> gp(ctx->plan_mu);
+        ctx->plan = cur;
+    }
     return SSJ_OK;
 }
 
@@ -1795,15 +1905,24 @@ int ssj_stream_submit_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* ca
     StreamEngine* E = ctx->engine.get();
     if (!E) return set_error(SSJ_EINVAL, "streaming engine not running");
     std::unique_lock<std::mutex> lk(E->mu);
-    auto room = [&]() { return (int)E->pending.size() < ctx->queue_depth; };
+    auto room = [&]() { return (int)E->pending.size() + E->reserved < ctx->queue_depth; };
     if (!room()) {
         if (nonblocking) return set_error(SSJ_EAGAIN, "stream queue full");
         E->cv_space.wait(lk, [&]() { return room() || E->stop || ctx->failed.load(); });
         if (E->stop) return set_error(SSJ_EINVAL, "context is shutting down");
         if (ctx->failed) return set_error(SSJ_EDEVICE, "context failed after a HIP error");
     }
+    // the collection list changes only under this lock too: a collection
+    // freed since check_coll is refused here, before anything refers to it
+    if (std::find(ctx->colls.begin(), ctx->colls.end(), coll) == ctx->colls.end())
+        return set_error(SSJ_EINVAL, "unknown collection");
     StreamReq* r = new (std::nothrow) StreamReq();
     if (!r) return set_error(SSJ_ENOMEM, "host allocation failed");
+    // the request holds its collection and its queue place from here on: a
+    // free of the collection sees it in flight, and concurrent submitters see
+    // the place taken while this one copies its candidates
+    coll->inflight.fetch_add(1);
+    ++E->reserved;
     r->ticket = E->next_ticket++;
     r->coll = coll;
     r->t_num = t_num;
@@ -1818,6 +1937,11 @@ int ssj_stream_submit_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* ca
     if (!r->h_cand) {
         void* p = nullptr;
         if (hipHostMalloc(&p, r->h_cand_bytes, hipHostMallocDefault) != hipSuccess || !p) {
+            lk.lock();
+            --E->reserved;
+            coll->inflight.fetch_sub(1);
+            lk.unlock();
+            E->cv_space.notify_all();
             delete r;
             return set_error(SSJ_ENOMEM, "pinned staging allocation failed");
         }
@@ -1825,11 +1949,23 @@ int ssj_stream_submit_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* ca
     }
     if (n_cand > 0) std::memcpy(r->h_cand, cand, (size_t)n_cand * 8);
     lk.lock();
-    coll->inflight.fetch_add(1);
+    --E->reserved;
     E->table.emplace(r->ticket, r);
     E->pending.push_back(r);
     *ticket = r->ticket;
     lk.unlock();
+    E->cv_work.notify_all();
+    return SSJ_OK;
+}
+
+int ssj_stream_pause(ssj_ctx* ctx, int pause) {
+    if (!ctx) return set_error(SSJ_EINVAL, "null context");
+    StreamEngine* E = ctx->engine.get();
+    if (!E) return set_error(SSJ_EINVAL, "streaming engine not running");
+    {
+        std::lock_guard<std::mutex> g(E->mu);
+        E->paused = pause != 0;
+    }
     E->cv_work.notify_all();
     return SSJ_OK;
 }

@@ -49,7 +49,7 @@ EXPORTED = (
     "ssj_autotune", "ssj_verify_sim", "ssj_verify_device_sim", "ssj_stream_submit_sim",
     "ssj_verify_rs", "ssj_verify_rs_device", "ssj_verify_groups", "ssj_verify_groups_device",
     "ssj_verify_groups_batch_device",
-    "ssj_candidates_device", "ssj_join_device", "ssj_join",
+    "ssj_candidates_device", "ssj_join_device", "ssj_join", "ssj_stream_pause",
 )
 
 _NAMES = {
@@ -127,6 +127,7 @@ def load_library(path: str = LIB_PATH):
         "ssj_stream_submit": ([p, p, p, i64, i64, i64, c_int, P(u64)], c_int),
         "ssj_stream_poll": ([p, u64, c_int, p, i64, P(i64)], c_int),
         "ssj_stream_times": ([p, u64, c_int, P(u64), P(u64), P(u64)], c_int),
+        "ssj_stream_pause": ([p, c_int], c_int),
         "ssj_get_plan": ([p, P(ssj_plan)], c_int),
         "ssj_set_plan": ([p, P(ssj_plan)], c_int),
         "ssj_collection_info": ([p, P(i64), P(i64), P(i64)], c_int),
@@ -479,6 +480,13 @@ def ssj_stream_poll(ctx, ticket: int, wait: bool = True, out_cap: int = 0):
     if rc != SSJ_OK:
         _err(ctx, rc, out_n.value)
     return out[:out_n.value].copy()
+
+
+def ssj_stream_pause(ctx, pause: bool = True) -> None:
+    """Holds (True) or resumes (False) admission of queued stream requests."""
+    rc = load_library().ssj_stream_pause(ctx, int(bool(pause)))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
 
 
 def ssj_stream_times(ctx, ticket: int, wait: bool = False):

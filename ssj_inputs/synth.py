@@ -308,6 +308,14 @@ def near_duplicate_collection(rng: np.random.Generator, n_base: int, copies: int
     return canonical_order(offsets, ids[order].astype(np.int32))
 
 
+def device_bytes(c: Collection) -> int:
+    """Device bytes of a collection in the verification library's layout
+    (each set padded to a multiple of 4 int32 tokens, a 32-byte record per
+    set): what an upload takes from a context's HBM budget."""
+    padded = int(((np.diff(c.offsets) + 3) // 4 * 4).sum())
+    return 4 * max(padded, 4) + 32 * max(c.n_sets, 1)
+
+
 def collection_from_sets(sets) -> Collection:
     """CSR from an explicit list of token lists (each sorted and unique)."""
     sizes = np.array([len(s) for s in sets], dtype=np.int64)

@@ -241,7 +241,8 @@ def test_host_ring_batches_pieces_errors(S, golden_dir):
     c = synth.workload_collection(2)
     cand = cfilter.workload_candidates(2, 3, 5)
     m = man["thresholds"]["3/5"]
-    ctx = S.ssj_init(0, hbm_budget=40 * 2_500_000)
+    # the collection's own device bytes (8.6 MB), then 2.5M pairs per batch
+    ctx = S.ssj_init(0, hbm_budget=synth.device_bytes(c) + 40 * 2_500_000)
     try:
         h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
         S.ssj_set_plan(ctx, S.make_plan(inline_lanes=1, defer_from=5))
@@ -423,12 +424,13 @@ def test_upload_validation(S, ctx):
 
 
 def test_chunked_budget(S):
-    # a budget of a few KiB forces many chunks inside one ssj_verify call
-    ctx = S.ssj_init(0, hbm_budget=36 * 1000)
+    # a budget of a few KiB beyond the collection's own device bytes forces
+    # many chunks inside one ssj_verify call
+    rng = np.random.default_rng(9)
+    c = synth.near_duplicate_collection(rng, n_base=100, copies=4, max_size=30, universe=2000,
+                                        change_frac=0.1)
+    ctx = S.ssj_init(0, hbm_budget=synth.device_bytes(c) + 36 * 1000)
     try:
-        rng = np.random.default_rng(9)
-        c = synth.near_duplicate_collection(rng, n_base=100, copies=4, max_size=30, universe=2000,
-                                            change_frac=0.1)
         h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
         cand = np.concatenate([cfilter.candidates(c.offsets, c.tokens, 1, 2),
                                rng.integers(0, c.n_sets, size=(20000, 2)).astype(np.int32)])

@@ -206,7 +206,7 @@ def test_groups_split_across_batches(S):
     """A budget of a few KiB splits the candidates into many batches, with
     groups cut at batch borders."""
     rng, R, Sc = _two(5, 20)
-    ctx = S.ssj_init(0, hbm_budget=44 * 1000)
+    ctx = S.ssj_init(0, hbm_budget=synth.device_bytes(R) + synth.device_bytes(Sc) + 44 * 1000)
     try:
         hr = S.ssj_upload_collection(ctx, R.offsets, R.tokens)
         hs = S.ssj_upload_collection(ctx, Sc.offsets, Sc.tokens)

@@ -233,8 +233,9 @@ def test_stream_alone_equals_mix(S, data):
 
 def test_stream_tiny_budget_splits_and_queues(S, data):
     c, reqs = data
-    # 4 slots of ~2600 pairs: every request is split into several parts
-    ctx = S.ssj_init(0, hbm_budget=4 * 2600 * 36, n_slots=4, queue_depth=4)
+    # beyond the collection, room for 4 slots of ~2600 pairs: every request is
+    # split into several parts
+    ctx = S.ssj_init(0, hbm_budget=synth.device_bytes(c) + 4 * 2600 * 40, n_slots=4, queue_depth=4)
     try:
         h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
         tickets = [(i, S.ssj_stream_submit(ctx, h, cand, tn, td)) for i, (cand, tn, td, _) in
@@ -281,33 +282,103 @@ def test_stream_poll_states(S, data):
             S.ssj_stream_collect(ctx, tb)
         assert e.value.code == S.SSJ_EINVAL
         assert np.array_equal(_collect(S, ctx, tg), want)
-        # non-blocking submit on a full queue: EAGAIN (fill it faster than it drains)
-        saw_again = False
-        tickets = []
+        # with admission held, queue_depth (2) requests queue, the next
+        # non-blocking submit is refused, and the collection cannot be freed
+        S.ssj_stream_pause(ctx, True)
         big = np.concatenate([cand] * 20)
-        for _ in range(40):
-            try:
-                tickets.append(S.ssj_stream_submit(ctx, h, big, tn, td, nonblocking=True))
-            except S.SsjError as e:
-                assert e.code == S.SSJ_EAGAIN
-                saw_again = True
-                break
-        for t in tickets:
-            S.ssj_stream_collect(ctx, t)
-        _log(f"non-blocking submit saw EAGAIN: {saw_again} after {len(tickets)} submits")
-        # a collection with requests in flight cannot be freed
-        t = S.ssj_stream_submit(ctx, h, big, tn, td)
-        try:
+        held = [S.ssj_stream_submit(ctx, h, big, tn, td, nonblocking=True) for _ in range(2)]
+        with pytest.raises(S.SsjError) as e:
+            S.ssj_stream_submit(ctx, h, big, tn, td, nonblocking=True)
+        assert e.value.code == S.SSJ_EAGAIN
+        with pytest.raises(S.SsjError) as e:
             S.ssj_free_collection(ctx, h)
-            freed = True
-        except S.SsjError as e:
-            assert e.code == S.SSJ_EAGAIN
-            freed = False
-        if not freed:
-            S.ssj_stream_collect(ctx, t)
-            S.ssj_free_collection(ctx, h)
+        assert e.value.code == S.SSJ_EAGAIN
+        time.sleep(0.05)
+        assert all(S.ssj_stream_poll(ctx, t, wait=False) is None for t in held)  # still queued
+        # a blocking submit waits for a queue place, which resuming frees
+        got = []
+        th = threading.Thread(target=lambda: got.append(S.ssj_stream_submit(ctx, h, cand, tn, td)))
+        th.start()
+        time.sleep(0.05)
+        assert not got
+        S.ssj_stream_pause(ctx, False)
+        th.join(timeout=60)
+        assert len(got) == 1
+        want_big = oracle.sort_pairs(np.concatenate([want] * 20))
+        for t in held:
+            assert np.array_equal(oracle.sort_pairs(S.ssj_stream_collect(ctx, t)), want_big)
+        assert np.array_equal(_collect(S, ctx, got[0]), want)
+        # nothing in flight: the collection is freed
+        S.ssj_free_collection(ctx, h)
     finally:
         S.ssj_shutdown(ctx)
+
+
+def test_stream_shutdown_while_paused(S, data):
+    """Shutdown resumes a held engine and finishes its queued requests."""
+    c, reqs = data
+    ctx = S.ssj_init(0, n_slots=1, queue_depth=4)
+    h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+    cand, tn, td, want = reqs[1]
+    S.ssj_stream_pause(ctx, True)
+    S.ssj_stream_submit(ctx, h, cand, tn, td)
+    S.ssj_shutdown(ctx)
+
+
+def test_upload_over_budget_is_enomem(S):
+    """Collections must fit the context's HBM budget together: an upload that
+    would pass it returns SSJ_ENOMEM and uploads nothing; after a free it fits."""
+    rng = np.random.default_rng(4)
+    c = synth.random_collection(rng, 2000, 60, 50000)
+    one = synth.device_bytes(c)                          # device bytes of one copy
+    ctx = S.ssj_init(0, hbm_budget=one + one // 2)
+    try:
+        h1 = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+        with pytest.raises(S.SsjError) as e:
+            S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+        assert e.value.code == S.SSJ_ENOMEM
+        # verification still works within what is left of the budget
+        cand = rng.integers(0, c.n_sets, size=(5000, 2)).astype(np.int32)
+        want = oracle.sort_pairs(oracle.select(c.offsets, c.tokens, cand, 1, 10))
+        assert np.array_equal(oracle.sort_pairs(S.ssj_verify(ctx, h1, cand, 1, 10)), want)
+        S.ssj_free_collection(ctx, h1)
+        h2 = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+        assert np.array_equal(oracle.sort_pairs(S.ssj_verify(ctx, h2, cand, 1, 10)), want)
+    finally:
+        S.ssj_shutdown(ctx)
+
+
+def test_null_output_with_capacity_is_einval(S, ctx, data):
+    """out_cap > 0 with no output buffer is refused before anything is
+    enqueued (single, batched and grouped device calls); the count keeps its
+    value."""
+    import torch
+    c, reqs = data
+    h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+    try:
+        cand, tn, td, want = reqs[0]
+        d_cand = _dev(torch, cand)
+        d_cnt = torch.full((1,), -7, dtype=torch.int64, device="cuda:0")
+        lib = S.load_library()
+        rc = lib.ssj_verify_device(ctx, h, d_cand.data_ptr(), cand.shape[0], tn, td, None, 10,
+                                   d_cnt.data_ptr(), None)
+        assert rc == S.SSJ_EINVAL
+        req = S.ssj_request(d_cand.data_ptr(), cand.shape[0], tn, td, None, 10, d_cnt.data_ptr(), 0)
+        assert lib.ssj_verify_batch_device(ctx, h, ctypes_ref(req), 1, None) == S.SSJ_EINVAL
+        g, si = S.groups_of(cand)
+        d_g, d_si = _dev(torch, g), _dev(torch, si)
+        rc = lib.ssj_verify_groups_device(ctx, h, h, d_g.data_ptr(), g.shape[0], d_si.data_ptr(), si.shape[0],
+                                          0, tn, td, None, 10, d_cnt.data_ptr(), None)
+        assert rc == S.SSJ_EINVAL
+        torch.cuda.synchronize()
+        assert int(d_cnt.item()) == -7
+    finally:
+        S.ssj_free_collection(ctx, h)
+
+
+def ctypes_ref(x):
+    import ctypes
+    return ctypes.byref(x)
 
 
 def test_stream_64_tickets_8_threads(S, data):
