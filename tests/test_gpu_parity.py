@@ -132,7 +132,7 @@ def test_config1_all_plans(S, ctx, golden_dir):
         cand = cfilter.workload_candidates(1, tn, td)
         assert cand.shape[0] == m["n_candidates"]
         want = want_of(c, cand, tn, td)
-        assert want.tolist() == sorted(brute.brute_join(c.offsets, c.tokens, tn, td))
+        assert [tuple(x) for x in want.tolist()] == sorted(brute.brute_join(c.offsets, c.tokens, tn, td))
         assert want.shape[0] == m["n_result"] and oracle.result_digest(want) == m["result_sha256"]
         for name, plan in plans():
             _log(f"config1 t={key} {name}")
