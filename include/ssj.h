@@ -161,6 +161,27 @@ int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand
                       int64_t n_cand, int64_t t_num, int64_t t_den, ssj_pair* d_out,
                       int64_t out_cap, int64_t* d_count, void* hip_stream);
 
+/*
+ * ssj_verify_device for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * verification, arguments, ordering and results, but the call allocates
+ * nothing -- no hipMalloc / hipFree, no graph, no timing events.  Its
+ * counters and deferral queues live in a fixed device array that the library
+ * holds on each device from ssj_init until the process ends
+ * (SSJ_NOALLOC_SCRATCH_BYTES: a 256-byte counter block plus 6 queue words per
+ * pair for SSJ_NOALLOC_MAX_PAIRS pairs, about 24 MiB).
+ * n_cand above SSJ_NOALLOC_MAX_PAIRS returns SSJ_EINVAL without enqueuing
+ * anything (split larger inputs into several calls).  Every call on one
+ * device, from any context, shares that array: calls that overlap on one
+ * device race and must be ordered by the caller (one stream, or events).
+ * Each launch leaves the counters zeroed for the next.
+ */
+#define SSJ_NOALLOC_MAX_PAIRS (1 << 20)
+#define SSJ_NOALLOC_SCRATCH_BYTES (256 + 6 * 4 * SSJ_NOALLOC_MAX_PAIRS)
+int ssj_verify_device_noalloc(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand,
+                              int64_t n_cand, int64_t t_num, int64_t t_den, ssj_pair* d_out,
+                              int64_t out_cap, int64_t* d_count, void* hip_stream);
+
 /* ssj_verify_device with the similarity function sim (SSJ_SIM_*, paper
  * Table 1). */
 int ssj_verify_device_sim(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand,

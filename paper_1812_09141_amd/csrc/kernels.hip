@@ -1297,6 +1297,11 @@ __global__ void k_expand_groups(const int2* __restrict__ groups, uint32_t n_grou
     }
 }
 
+// Zeroes n 32-bit words (a fill kernel: usable where a memset node is not).
+__global__ void k_clear_words(uint32_t* __restrict__ p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
 // Set records from the set lengths (CSR offsets of the caller's layout) and
 // the start of each set in the device token array (16-byte aligned).
 __global__ void k_build_heads(const int64_t* __restrict__ off, const uint32_t* __restrict__ start,
@@ -1406,6 +1411,13 @@ hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st) {
     LaunchArgs args = a;
     void* params[] = {&args};
     return hipLaunchKernel(f, dim3((unsigned)grid), dim3(kBlock), params, tiles_lds_bytes(a), st);
+}
+
+hipError_t launch_clear_words(uint32_t* d_words, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const size_t b = std::min<size_t>((n + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL(k_clear_words, dim3((unsigned)b), dim3(kBlock), 0, st, d_words, (uint32_t)n);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st) {

@@ -43,6 +43,11 @@ uint64_t now_ns() {
 }
 
 constexpr uint64_t kDefaultBudget = 4ull << 30;
+// The allocation-free entry point's device scratch: a counter block, then the
+// deferral queues for up to SSJ_NOALLOC_MAX_PAIRS pairs.
+constexpr size_t kNoAllocQueueWords = (size_t)ssj::kQueues * SSJ_NOALLOC_MAX_PAIRS;
+constexpr size_t kNoAllocBytes = sizeof(ssj::Counters) + kNoAllocQueueWords * sizeof(uint32_t);
+constexpr int kMaxDevices = 64;
 constexpr int64_t kMaxLaunchPairs = ((int64_t)1 << 31) - 1;  // pairs per launch
 constexpr int kMaxSpillIters = 1 << 20;
 constexpr int kMaxWgPerCu = 64;
@@ -149,6 +154,19 @@ struct GraphEntry {
 
 }  // namespace
 
+// Scratch of ssj_verify_device_noalloc, one copy per device for the life of
+// the process.  Host code never passes this name to a kernel: it takes the
+// array's device address from hipGetSymbolAddress (noalloc_scratch) and
+// uses that.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};  // device address of scratch, per device (null: not set up)
+
+}  // namespace
+
 struct ssj_coll {
     ssj_ctx* ctx = nullptr;
     int32_t* d_tok = nullptr;
@@ -231,6 +249,7 @@ struct ssj_ctx {
     double t_inorder_ms = 0.0, t_deferred_ms = 0.0;
     int64_t t_launches = 0;
     std::unique_ptr<StreamEngine> engine;
+    Scratch noalloc;  // views into this device's copy of scratch (owned by nobody)
 };
 
 namespace {
@@ -422,7 +441,7 @@ int launch_graph(ssj_ctx* ctx, const ssj::LaunchArgs& a, int g1, int g2, bool tw
 // r ids index coll, s ids coll_s (null: coll, a self-join).
 int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* reqs, int n_req,
                    hipStream_t st, const ssj_plan& plan, bool allow_graph = true,
-                   const ssj_coll* coll_s = nullptr) {
+                   const ssj_coll* coll_s = nullptr, bool allow_timing = true) {
     const ssj_coll* cs = coll_s ? coll_s : coll;
     ssj::LaunchArgs a{};
     a.tok = coll->d_tok;
@@ -476,7 +495,7 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
 
     std::array<hipEvent_t, 4> ev{nullptr, nullptr, nullptr, nullptr};
     const int period = ctx->timing_period.load();
-    const bool timing = period > 0 && (ctx->timing_tick.fetch_add(1) % (uint64_t)period) == 0;
+    const bool timing = allow_timing && period > 0 && (ctx->timing_tick.fetch_add(1) % (uint64_t)period) == 0;
     if (timing) {
         // marker events right before and after each verification kernel (the
         // finalize kernel is not timed)
@@ -843,6 +862,32 @@ void engine_loop(StreamEngine* E) {
     }
 }
 
+// Takes this device's address of scratch (once per device, with the device
+// current) and clears its counter block with a fill kernel; the context
+// keeps views of it.  Every launch's finalize kernel leaves the counters at
+// zero again.
+int noalloc_setup(ssj_ctx* ctx) {
+    if (ctx->device >= kMaxDevices) return set_error(SSJ_EINVAL, "device ordinal too large");
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        if (!g_scratch_ptr[ctx->device]) {
+            HIP_OR_FAIL(ctx, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr) return hip_fail(ctx, "hipGetSymbolAddress", hipErrorInvalidSymbol);
+            HIP_OR_FAIL(ctx, ssj::launch_clear_words(reinterpret_cast<uint32_t*>(ptr),
+                                                     sizeof(ssj::Counters) / sizeof(uint32_t), ctx->stream));
+            HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+            g_scratch_ptr[ctx->device] = ptr;
+        }
+        ptr = g_scratch_ptr[ctx->device];
+    }
+    ctx->noalloc.d_ctr = reinterpret_cast<ssj::Counters*>(ptr);
+    ctx->noalloc.d_queues = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(ptr) +
+                                                        sizeof(ssj::Counters));
+    ctx->noalloc.q_cap = kNoAllocQueueWords;
+    return SSJ_OK;
+}
+
 int engine_start(ssj_ctx* ctx) {
     auto E = std::make_unique<StreamEngine>();
     E->ctx = ctx;
@@ -951,6 +996,7 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
         if (rc != SSJ_OK) break;
         if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) { rc = hip_fail(ctx, "hipStreamCreate", e); break; }
         if ((rc = scratch_init(ctx, ctx->def)) != SSJ_OK) break;
+        if ((rc = noalloc_setup(ctx)) != SSJ_OK) break;
         if ((e = hipMalloc((void**)&ctx->d_count, sizeof(long long))) != hipSuccess) { rc = hip_fail(ctx, "hipMalloc", e); break; }
         if ((e = hipHostMalloc((void**)&ctx->h_count, sizeof(long long), hipHostMallocDefault)) != hipSuccess) { rc = hip_fail(ctx, "hipHostMalloc", e); break; }
         rc = engine_start(ctx);
@@ -1493,6 +1539,26 @@ int ssj_verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand
                       int64_t* d_count, void* hip_stream) {
     return ssj_verify_device_sim(ctx, coll, d_cand, n_cand, SSJ_SIM_JACCARD, t_num, t_den, d_out,
                                  out_cap, d_count, hip_stream);
+}
+
+int ssj_verify_device_noalloc(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
+                              int64_t t_num, int64_t t_den, ssj_pair* d_out, int64_t out_cap, int64_t* d_count,
+                              void* hip_stream) {
+    int rc = check_ctx(ctx);
+    if (rc != SSJ_OK) return rc;
+    if ((rc = check_coll(ctx, coll)) != SSJ_OK) return rc;
+    Req r{reinterpret_cast<const int2*>(d_cand), n_cand, t_num, t_den, reinterpret_cast<int2*>(d_out),
+          out_cap, reinterpret_cast<long long*>(d_count), SSJ_SIM_JACCARD};
+    if ((rc = check_req(r)) != SSJ_OK) return rc;
+    if (n_cand > SSJ_NOALLOC_MAX_PAIRS)
+        return set_error(SSJ_EINVAL, "ssj_verify_device_noalloc takes at most SSJ_NOALLOC_MAX_PAIRS (2^20) "
+                                     "candidates per call");
+    if (!ctx->noalloc.d_ctr) return set_error(SSJ_EDEVICE, "no scratch on this device");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    // no graph (building one allocates) and no timing sample (event creation)
+    return enqueue_launch(ctx, coll, ctx->noalloc, &r, 1, (hipStream_t)hip_stream, ctx->plan, false, nullptr,
+                          false);
 }
 
 namespace {

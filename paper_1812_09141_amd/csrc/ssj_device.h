@@ -103,6 +103,8 @@ hipError_t launch_verify_deferred(const LaunchArgs& a, int grid, hipStream_t st)
 size_t tiles_lds_bytes(const LaunchArgs& a);
 // Publishes the request counts and resets the counters (always last).
 hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st);
+// Zeroes n 32-bit words of device memory with a fill kernel.
+hipError_t launch_clear_words(uint32_t* d_words, size_t n, hipStream_t st);
 
 // The in-order kernel of a mapping: lanes per pair and hard lanes, or the
 // staged thread-per-pair kernel (staged, lanes 1, hard_lanes 0).

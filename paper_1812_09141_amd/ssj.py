@@ -40,6 +40,7 @@ SIMS = {"jaccard": SSJ_SIM_JACCARD, "cosine": SSJ_SIM_COSINE, "dice": SSJ_SIM_DI
 SSJ_N_CLASSES = 5
 SSJ_CLASS_BOUNDS = (32, 128, 512, 2048, 0x7FFFFFFF)
 SSJ_MAX_BATCH = 16
+SSJ_NOALLOC_MAX_PAIRS = 1 << 20
 
 EXPORTED = (
     "ssj_init", "ssj_shutdown", "ssj_last_error", "ssj_upload_collection",
@@ -50,6 +51,7 @@ EXPORTED = (
     "ssj_verify_rs", "ssj_verify_rs_device", "ssj_verify_groups", "ssj_verify_groups_device",
     "ssj_verify_groups_batch_device",
     "ssj_candidates_device", "ssj_join_device", "ssj_join", "ssj_stream_pause",
+    "ssj_verify_device_noalloc",
 )
 
 _NAMES = {
@@ -124,6 +126,7 @@ def load_library(path: str = LIB_PATH):
         "ssj_free_collection": ([p, p], c_int),
         "ssj_verify": ([p, p, p, i64, i64, i64, p, i64, P(i64)], c_int),
         "ssj_verify_device": ([p, p, p, i64, i64, i64, p, i64, p, p], c_int),
+        "ssj_verify_device_noalloc": ([p, p, p, i64, i64, i64, p, i64, p, p], c_int),
         "ssj_stream_submit": ([p, p, p, i64, i64, i64, c_int, P(u64)], c_int),
         "ssj_stream_poll": ([p, u64, c_int, p, i64, P(i64)], c_int),
         "ssj_stream_times": ([p, u64, c_int, P(u64), P(u64), P(u64)], c_int),
@@ -454,6 +457,24 @@ def ssj_verify_device(ctx, coll, d_cand: "torch.Tensor", t_num: int, t_den: int,
     rc = load_library().ssj_verify_device(ctx, coll, d_cand.data_ptr() if n else None, n,
                                           int(t_num), int(t_den), d_out.data_ptr() if cap else None,
                                           cap, d_count.data_ptr(), ctypes.c_void_p(st.cuda_stream))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+
+
+def ssj_verify_device_noalloc(ctx, coll, d_cand: "torch.Tensor", t_num: int, t_den: int,
+                              d_out: "torch.Tensor", d_count: "torch.Tensor", stream=None) -> None:
+    """ssj_verify_device through the allocation-free entry point (at most
+    SSJ_NOALLOC_MAX_PAIRS pairs; the library's fixed per-device scratch)."""
+    assert d_cand.is_cuda and d_cand.dtype == torch.int32 and d_cand.is_contiguous()
+    if d_out is not None:
+        assert d_out.is_cuda and d_out.dtype == torch.int32 and d_out.is_contiguous()
+    assert d_count.is_cuda and d_count.dtype == torch.int64 and d_count.numel() >= 1
+    n = d_cand.numel() // 2
+    cap = d_out.numel() // 2 if d_out is not None else 0
+    st = stream if stream is not None else torch.cuda.current_stream(d_cand.device)
+    rc = load_library().ssj_verify_device_noalloc(ctx, coll, d_cand.data_ptr() if n else None, n,
+                                                  int(t_num), int(t_den), d_out.data_ptr() if cap else None,
+                                                  cap, d_count.data_ptr(), ctypes.c_void_p(st.cuda_stream))
     if rc != SSJ_OK:
         _err(ctx, rc)
 
