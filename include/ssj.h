@@ -35,6 +35,7 @@ extern "C" {
 enum {
     SSJ_OK = 0,
     SSJ_PENDING = 1,     /* stream request not finished yet */
+    SSJ_CACHED = 2,      /* ssj_autotune: the plan came from the tuning cache */
     SSJ_EINVAL = -1,     /* bad argument, malformed collection, id out of range */
     SSJ_ENOMEM = -2,     /* device or host allocation failed / over the HBM budget */
     SSJ_ETRUNC = -3,     /* result larger than out_cap; *out_n holds the size needed */
@@ -218,8 +219,9 @@ int ssj_verify_rs_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* c
  * covers, make *d_count -1, like an id out of range (checked on the device
  * over every group; with n_cand = 0 the ends are not checked and *d_count
  * is 0).
- * The groups are expanded into flat pairs in the context's scratch before the
- * usual launch, so device calls on one context must not overlap.
+ * The verification kernels read the groups in place (a pre-pass kernel
+ * first notes the group of every 64th candidate in the context's scratch),
+ * so device calls on one context must not overlap.
  */
 int ssj_verify_groups(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s,
                       const ssj_group* groups, int64_t n_groups, const int32_t* cand, int64_t n_cand,
@@ -248,9 +250,9 @@ typedef struct {
 
 /*
  * Batched grouped verification (Sec. 3.3.1 C / C_O per request): up to
- * SSJ_MAX_BATCH requests over one pair of collections, each expanded into
- * flat pairs in the context's scratch, then verified together by one launch
- * on hip_stream (as ssj_verify_batch_device).  Each d_count receives its
+ * SSJ_MAX_BATCH requests over one pair of collections, verified together by
+ * one launch on hip_stream (as ssj_verify_batch_device) after one pre-pass
+ * kernel over the groups of all requests.  Each d_count receives its
  * request's count, or -1 when that request's groups are malformed (the
  * rules of ssj_verify_groups_device) or an id is out of range; the other
  * requests are unaffected.  The candidates of all requests together must
@@ -416,10 +418,28 @@ int ssj_verify_batch_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_reques
  * mappings suited to their lengths), then step budgets (spill_iters) on the
  * best thread-per-pair plan, then refines the mapping of each deferred class
  * of the best plan, one class at a time, and last the in-order grid size.
- * Synchronous.
+ * Synchronous.  With a tuning cache (ssj_set_tune_cache) it first looks the
+ * workload up there and, on a hit, returns the stored plan and time without
+ * measuring anything (SSJ_CACHED instead of SSJ_OK); a tuned result is
+ * appended to the cache.
  */
 int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
                  int64_t t_num, int64_t t_den, int apply, ssj_plan* best, double* best_ms);
+
+/*
+ * Tuning cache of ssj_autotune: a text file of one JSON object per line,
+ * {"key": ..., "kernel_ms": ..., "plan": [inline_lanes, hard_lanes,
+ * defer_from, lanes[0..4], use_graph, spill_iters, spill_lanes, wg_per_cu,
+ * staged]}, keyed by the device (architecture, name, compute units) and the
+ * workload (the collection's set count, token count and longest set, the
+ * candidate count and the threshold in lowest terms).  The last entry of a
+ * key wins; lines that do not parse, and plans the library no longer
+ * supports, are ignored.  path NULL or "" turns the cache off (the default).
+ * The file is read and appended to by ssj_autotune only, under the
+ * context's lock; appends are single writes, so several processes may share
+ * one file.
+ */
+int ssj_set_tune_cache(ssj_ctx* ctx, const char* path);
 
 /*
  * Kernel timing, for measurement.  With period > 0, every period-th launch

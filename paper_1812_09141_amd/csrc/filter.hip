@@ -32,7 +32,8 @@
 // pieces per position, and two passes over them (count, then fill at the
 // exclusive prefix sum of the counts) write the candidates in probe order --
 // the order of the CPU filters -- with no atomics.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "ssj_device.h"
 #include "filter.h"
@@ -204,6 +205,23 @@ __global__ void k_probe(const uint4* __restrict__ heads, const int32_t* __restri
     }
 }
 
+// Exclusive prefix sum of n values (rocPRIM's device scan; a null d_temp
+// only reports the scratch size in *temp_bytes).
+template <class T>
+hipError_t scan_exclusive(void* d_temp, size_t* temp_bytes, const T* d_in, T* d_out, uint64_t n,
+                          hipStream_t st) {
+    return rocprim::exclusive_scan(d_temp, *temp_bytes, d_in, d_out, T(0), (size_t)n, rocprim::plus<T>(), st);
+}
+
+// Index entries sorted by their 64-bit key (token << 32 | set), positions
+// moved with them (rocPRIM's device radix sort over all 64 key bits).
+hipError_t sort_entries(void* d_temp, size_t* temp_bytes, const unsigned long long* d_keys,
+                        unsigned long long* d_keys_out, const uint32_t* d_pos, uint32_t* d_pos_out, uint32_t m,
+                        hipStream_t st) {
+    return rocprim::radix_sort_pairs(d_temp, *temp_bytes, d_keys, d_keys_out, d_pos, d_pos_out, (size_t)m, 0u,
+                                     64u, st);
+}
+
 int blocks_for(uint64_t n) {
     return (int)std::max<uint64_t>(1, std::min<uint64_t>((n + kBlock - 1) / kBlock, 65536));
 }
@@ -213,7 +231,7 @@ int blocks_for(uint64_t n) {
 hipError_t filter_prefix_lengths(const uint4* d_heads, uint32_t n, uint64_t num, uint64_t den,
                                  uint32_t* d_plen, uint32_t* d_pre, void* d_temp, size_t* temp_bytes,
                                  hipStream_t st) {
-    if (!d_temp) return hipcub::DeviceScan::ExclusiveSum(nullptr, *temp_bytes, d_plen, d_pre, n + 1, st);
+    if (!d_temp) return scan_exclusive(nullptr, temp_bytes, d_plen, d_pre, n + 1, st);
     hipLaunchKernelGGL(k_prefix_len, dim3(blocks_for(n)), dim3(kBlock), 0, st, d_heads, n, Thr{num, den},
                        d_plen);
     hipError_t e = hipGetLastError();
@@ -221,7 +239,7 @@ hipError_t filter_prefix_lengths(const uint4* d_heads, uint32_t n, uint64_t num,
     // d_plen[n] is 0, so d_pre[n] is the number of index entries
     e = hipMemsetAsync(d_plen + n, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return e;
-    return hipcub::DeviceScan::ExclusiveSum(d_temp, *temp_bytes, d_plen, d_pre, n + 1, st);
+    return scan_exclusive(d_temp, temp_bytes, d_plen, d_pre, n + 1, st);
 }
 
 hipError_t filter_build_index(const uint4* d_heads, const int32_t* d_tok, uint32_t n, uint32_t m,
@@ -229,28 +247,26 @@ hipError_t filter_build_index(const uint4* d_heads, const int32_t* d_tok, uint32
                               uint32_t* d_pos, unsigned long long* d_keys2, uint32_t* d_pos2, uint2* d_probes,
                               void* d_temp, size_t* temp_bytes, hipStream_t st) {
     if (!d_temp)
-        return hipcub::DeviceRadixSort::SortPairs(nullptr, *temp_bytes, d_keys, d_keys2, d_pos, d_pos2, m, 0,
-                                                  64, st);
+        return sort_entries(nullptr, temp_bytes, d_keys, d_keys2, d_pos, d_pos2, m, st);
     hipLaunchKernelGGL(k_prefix_entries, dim3(blocks_for(n)), dim3(kBlock), 0, st, d_heads, d_tok, n, d_plen,
                        d_pre, d_keys, d_pos, d_probes);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return hipcub::DeviceRadixSort::SortPairs(d_temp, *temp_bytes, d_keys, d_keys2, d_pos, d_pos2, m, 0, 64,
-                                              st);
+    return sort_entries(d_temp, temp_bytes, d_keys, d_keys2, d_pos, d_pos2, m, st);
 }
 
 hipError_t filter_probe_items(const uint4* d_heads, const int32_t* d_tok, const uint2* d_probes, uint32_t m,
                               const unsigned long long* d_keys, uint2* d_range, unsigned long long* d_items,
                               unsigned long long* d_istart, void* d_temp, size_t* temp_bytes, hipStream_t st) {
     // d_items[m] is 0, so d_istart[m] is the number of work items
-    if (!d_temp) return hipcub::DeviceScan::ExclusiveSum(nullptr, *temp_bytes, d_items, d_istart, m + 1, st);
+    if (!d_temp) return scan_exclusive(nullptr, temp_bytes, d_items, d_istart, m + 1, st);
     hipLaunchKernelGGL(k_probe_ranges, dim3(blocks_for(m)), dim3(kBlock), 0, st, d_heads, d_tok, d_probes, m,
                        d_keys, d_range, d_items);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemsetAsync(d_items + m, 0, sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
-    return hipcub::DeviceScan::ExclusiveSum(d_temp, *temp_bytes, d_items, d_istart, m + 1, st);
+    return scan_exclusive(d_temp, temp_bytes, d_items, d_istart, m + 1, st);
 }
 
 hipError_t filter_probe(const uint4* d_heads, const int32_t* d_tok, const uint2* d_probes, uint32_t m,
@@ -282,10 +298,10 @@ hipError_t filter_probe(const uint4* d_heads, const int32_t* d_tok, const uint2*
 hipError_t filter_scan_counts(unsigned long long* d_counts, unsigned long long* d_off, uint32_t n, void* d_temp,
                               size_t* temp_bytes, hipStream_t st) {
     // d_counts[n] is 0, so d_off[n] is the number of candidates
-    if (!d_temp) return hipcub::DeviceScan::ExclusiveSum(nullptr, *temp_bytes, d_counts, d_off, n + 1, st);
+    if (!d_temp) return scan_exclusive(nullptr, temp_bytes, d_counts, d_off, n + 1, st);
     hipError_t e = hipMemsetAsync(d_counts + n, 0, sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
-    return hipcub::DeviceScan::ExclusiveSum(d_temp, *temp_bytes, d_counts, d_off, n + 1, st);
+    return scan_exclusive(d_temp, temp_bytes, d_counts, d_off, n + 1, st);
 }
 
 }  // namespace ssj

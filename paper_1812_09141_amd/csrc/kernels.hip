@@ -406,11 +406,93 @@ __device__ __forceinline__ void chunk_origin(const LaunchArgs& a, uint32_t T, in
     *kb = (T - a.tile_off[q]) * (uint32_t)kWave;
 }
 
-// The lane's pair of a chunk (clamped to the request; validity is re-derived
-// from the index when it is used).
-__device__ __forceinline__ int2 lane_pair(const Request& R, uint32_t kb, int lane) {
+// ---------------------------------------------------------------------------
+// Candidates of a chunk of a flat or a grouped request.  Loading and finding
+// the pair are separate steps, so that a pipeline can issue a chunk's loads
+// one iteration before it needs its pairs.  A grouped chunk's lanes load
+// their s ids and a window of 64 consecutive groups from the chunk's first
+// group (chunk_g); each lane then finds its group among them.
+
+// The loads of a lane's candidate: the pair (flat), or the s id in p.y and
+// the lane's entry of the chunk's group window, groups[g0 + lane] (clamped
+// to the last group), in gw (grouped).
+struct CandLoad {
+    int2 p;
+    int2 gw;
+    uint32_t g0;  // the window's first group (wave-uniform)
+};
+
+// Issues the loads of the lane's candidate of the chunk at candidate kb of
+// request R.  chunk_g entries of a request with malformed groups may be stale
+// (that request reports an error): g0 is clamped, so every load stays inside
+// the request's buffers.
+__device__ __forceinline__ CandLoad issue_cand(const LaunchArgs& a, const Request& R, uint32_t kb, int lane) {
+    CandLoad c;
     const uint32_t k = kb + (uint32_t)lane;
-    return load_pair(R.cand, k < R.n ? k : R.n - 1);
+    const uint32_t kc = k < R.n ? k : R.n - 1u;
+    if (!a.grouped) {
+        c.p = load_pair(R.cand, kc);
+        c.gw = make_int2(0, 0);
+        c.g0 = 0u;
+        return c;
+    }
+    const uint32_t g0 = min(R.chunk_g[kb / (uint32_t)kWave], R.n_groups);
+    c.g0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)g0);
+    c.p = make_int2(0, R.sids[kc]);
+    c.gw = R.n_groups != 0u ? R.groups[min(c.g0 + (uint32_t)lane, R.n_groups - 1u)] : make_int2(-1, -1);
+    return c;
+}
+
+// The lane's pair from its loads (all lanes of the wavefront call it
+// together: cross-lane permutes).  The group of candidate k is the first one
+// whose end exceeds k; in a window of ends that do not decrease it is the
+// window's group at the number of ends <= k, unless all 64 are <= k, when the
+// next window is searched.  A candidate no group covers gets probe id -1 (an
+// id error).
+__device__ __forceinline__ int2 resolve_cand(const LaunchArgs& a, const Request& R, uint32_t kb, int lane,
+                                             const CandLoad& c) {
+    if (!a.grouped) return c.p;
+    const uint32_t k = kb + (uint32_t)lane;
+    const bool valid = k < R.n;
+    uint32_t w0 = c.g0;
+    int2 e = c.gw;
+    int32_t probe = -1;
+    bool found = false;
+    while (w0 < R.n_groups) {
+        const uint32_t ek = w0 + (uint32_t)lane < R.n_groups ? (uint32_t)e.y : 0xffffffffu;
+        uint32_t pos = 0;
+#pragma unroll
+        for (uint32_t step = kWave / 2; step >= 1; step >>= 1) {
+            const uint32_t v = (uint32_t)bperm((int)ek, (int)(pos + step - 1u));
+            pos += (v <= k) ? step : 0u;
+        }
+        const bool beyond = (uint32_t)bperm((int)ek, kWave - 1) <= k;
+        const int32_t pp = bperm(e.x, (int)pos);
+        if (!found && !beyond && w0 + pos < R.n_groups) {
+            probe = pp;
+            found = true;
+        }
+        if (ballot(valid && !found) == 0ull) break;
+        w0 += (uint32_t)kWave;
+        if (w0 < R.n_groups) e = R.groups[min(w0 + (uint32_t)lane, R.n_groups - 1u)];
+    }
+    return make_int2(probe, c.p.y);
+}
+
+// A queued pair (global pair index gi of request r) in the deferred kernel:
+// from the request's pairs, or for a grouped launch its s id and the probe id
+// that the in-order kernel stored when it queued the pair.
+__device__ __forceinline__ int2 queued_pair(const LaunchArgs& a, uint32_t gi, int r) {
+    const Request& R = a.req[r];
+    const uint32_t k = gi - a.pair_off[r];
+    if (a.grouped) return make_int2((int32_t)a.probes[gi], R.sids[k]);
+    return load_pair(R.cand, k);
+}
+
+// Records the probe id of a pair that the in-order kernel queues (grouped
+// launches only; the deferred kernel reads it back by global pair index).
+__device__ __forceinline__ void note_queued(const LaunchArgs& a, bool queued, int2 pr, uint32_t gi) {
+    if (a.grouped && queued) a.probes[gi] = (uint32_t)pr.x;
 }
 
 // Set records of a lane's pair: four 16-byte loads (first and second word of
@@ -595,7 +677,10 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
         hcnt += (uint32_t)__popcll(m);
     }
     stage_pass(pass, pr, w_out, ocnt, R.cap == 0);
-    if (deferring) defer_pass(a, defer, cls, spill, a.pair_off[r] + k, w_defer, dc);
+    if (deferring) {
+        defer_pass(a, defer, cls, spill, a.pair_off[r] + k, w_defer, dc);
+        note_queued(a, defer || spill, pr, a.pair_off[r] + k);
+    }
 }
 
 // Finishes the wavefront's h hard pairs: groups of G lanes resume their
@@ -673,7 +758,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     // chunk T + nw and the pairs of chunk T + 2 nw are in flight (memory
     // operations complete in issue order, so the records of T, issued one
     // iteration earlier, are waited for without draining the newer loads).
-    int2 p0 = make_int2(0, 0), p1 = make_int2(0, 0);
+    int2 p0 = make_int2(0, 0);
+    CandLoad c1{};
     LaneRecords rec0{}, rec1{};
     int r_cur = 0, r1 = 0;
     uint32_t kb_cur = 0, kb1 = 0;
@@ -682,10 +768,10 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
         if constexpr (G == 1) {
             // loads beyond the last chunk are clamped to it (results unused),
             // so every iteration issues the same loads in the same order
-            p0 = lane_pair(a.req[r_cur], kb_cur, lane);
+            p0 = resolve_cand(a, a.req[r_cur], kb_cur, lane, issue_cand(a, a.req[r_cur], kb_cur, lane));
             issue_records(a, p0, rec0);
             chunk_origin(a, min(first + nw, n_chunks - 1), &r1, &kb1);
-            p1 = lane_pair(a.req[r1], kb1, lane);
+            c1 = issue_cand(a, a.req[r1], kb1, lane);
         }
     }
     const uint32_t share = first < n_chunks ? (n_chunks - 1u - first) / nw + 1u : 1u;
@@ -698,11 +784,12 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
         const uint32_t Tn = T + nw;
         const Request& R = a.req[r];
         if constexpr (G == 1) {
+            const int2 p1 = resolve_cand(a, a.req[r1], kb1, lane, c1);
             issue_records(a, p1, rec1);
             int r2 = 0;
             uint32_t kb2 = 0;
             chunk_origin(a, min(Tn + nw, n_chunks - 1), &r2, &kb2);
-            const int2 p2 = lane_pair(a.req[r2], kb2, lane);
+            const CandLoad c2 = issue_cand(a, a.req[r2], kb2, lane);
             chunk_thread_pairs<F, C>(a, R, r, kb, p0, rec0, deferring, w_defer, dc, w_out, ocnt,
                                   w_hpr, w_hst, hcnt);
             if constexpr (F > 0) {
@@ -713,7 +800,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
             }
             // rotate the pipeline
             p0 = p1;
-            p1 = p2;
+            c1 = c2;
             rec0 = rec1;
             r_cur = r1;
             kb_cur = kb1;
@@ -725,8 +812,14 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
             // is merged, the first tiles of s + 1, the set descriptors of s + 2
             // and the pair of s + 3 are in flight (clamped, unconditional loads
             // keep the issue order fixed)
+            // a grouped chunk's pairs are found once, lane k holding pair
+            // kb + k, and handed to the groups by permutes
+            int2 cp = make_int2(0, 0);
+            if (a.grouped) cp = resolve_cand(a, R, kb, lane, issue_cand(a, R, kb, lane));
             auto pair_at = [&](int sub) -> int2 {
-                const uint32_t k = kb + (uint32_t)(min(sub, G - 1) * GPW + grp);
+                const int src = min(sub, G - 1) * GPW + grp;
+                if (a.grouped) return make_int2(bperm(cp.x, src), bperm(cp.y, src));
+                const uint32_t k = kb + (uint32_t)src;
                 return load_pair(R.cand, k < R.n ? k : R.n - 1);
             };
             auto desc_of = [&](int2 pq, uint2* dr, uint2* ds) {
@@ -766,7 +859,10 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                     }
                 }
                 stage_pass(pass && g == 0, pq, w_out, ocnt, R.cap == 0);
-                if (deferring) defer_pass(a, defer && g == 0, cls, false, a.pair_off[r] + k, w_defer, dc);
+                if (deferring) {
+                    defer_pass(a, defer && g == 0, cls, false, a.pair_off[r] + k, w_defer, dc);
+                    note_queued(a, defer && g == 0, pq, a.pair_off[r] + k);
+                }
                 pq0 = pq1;
                 pq1 = pq2;
                 pq2 = pq3;
@@ -928,7 +1024,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_staged(LaunchArgs a) {
     const uint32_t first = blockIdx.x * kWaves + (uint32_t)w;
     // pipeline as in the in-order kernel: while chunk T is verified, the
     // records of chunk T + nw and the pairs of chunk T + 2 nw are in flight
-    int2 p0 = make_int2(0, 0), p1 = make_int2(0, 0);
+    int2 p0 = make_int2(0, 0);
+    CandLoad c1{};
     uint4 ra0 = make_uint4(0u, 0u, 0u, 0u), rb0 = ra0, ra1 = ra0, rb1 = ra0;
     int r_cur = 0, r1 = 0;
     uint32_t kb_cur = 0, kb1 = 0;
@@ -939,10 +1036,10 @@ __global__ __launch_bounds__(kBlock) void k_verify_staged(LaunchArgs a) {
     };
     if (first < n_chunks) {
         chunk_origin(a, first, &r_cur, &kb_cur);
-        p0 = lane_pair(a.req[r_cur], kb_cur, lane);
+        p0 = resolve_cand(a, a.req[r_cur], kb_cur, lane, issue_cand(a, a.req[r_cur], kb_cur, lane));
         records(p0, ra0, rb0);
         chunk_origin(a, min(first + nw, n_chunks - 1), &r1, &kb1);
-        p1 = lane_pair(a.req[r1], kb1, lane);
+        c1 = issue_cand(a, a.req[r1], kb1, lane);
     }
     const uint32_t share = first < n_chunks ? (n_chunks - 1u - first) / nw + 1u : 1u;
     uint32_t done = 0, level = 3;
@@ -953,11 +1050,12 @@ __global__ __launch_bounds__(kBlock) void k_verify_staged(LaunchArgs a) {
         const uint32_t kb = kb_cur;
         const uint32_t Tn = T + nw;
         const Request& R = a.req[r];
+        const int2 p1 = resolve_cand(a, a.req[r1], kb1, lane, c1);
         records(p1, ra1, rb1);
         int r2 = 0;
         uint32_t kb2 = 0;
         chunk_origin(a, min(Tn + nw, n_chunks - 1), &r2, &kb2);
-        const int2 p2 = lane_pair(a.req[r2], kb2, lane);
+        const CandLoad c2 = issue_cand(a, a.req[r2], kb2, lane);
 
         const int2 pr = p0;
         const uint32_t k = kb + (uint32_t)lane;
@@ -1017,10 +1115,13 @@ __global__ __launch_bounds__(kBlock) void k_verify_staged(LaunchArgs a) {
         }
         if (ballot(valid && !ok) != 0ull && lane == 0) atomicOr(&a.ctr->err[r], 1u);
         stage_pass(pass, pr, w_out, ocnt, R.cap == 0);
-        if (deferring) defer_pass(a, defer, cls, spill, a.pair_off[r] + k, w_defer, dc);
+        if (deferring) {
+            defer_pass(a, defer, cls, spill, a.pair_off[r] + k, w_defer, dc);
+            note_queued(a, defer || spill, pr, a.pair_off[r] + k);
+        }
         // rotate the pipeline
         p0 = p1;
-        p1 = p2;
+        c1 = c2;
         ra0 = ra1;
         rb0 = rb1;
         r_cur = r1;
@@ -1091,7 +1192,7 @@ __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
     };
     auto pair_of = [&](uint32_t gi, int* r) -> int2 {
         *r = request_of_pair(gi, a);
-        return load_pair(a.req[*r].cand, gi - a.pair_off[*r]);
+        return queued_pair(a, gi, *r);
     };
     uint32_t e3;
     int2 p0, p1, p2;
@@ -1175,7 +1276,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
             const uint32_t gi = queue[t];
             const int r = request_of_pair(gi, a);
             const Request& R = a.req[r];
-            const int2 pr = load_pair(R.cand, gi - a.pair_off[r]);
+            const int2 pr = queued_pair(a, gi, r);
             const uint2 dr = set_desc(a, pr.x);
             const uint2 ds = set_desc_s(a, pr.y);
             const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok_s + ds.x, ds.y,
@@ -1202,98 +1303,38 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
 // ---------------------------------------------------------------------------
 // Grouped candidates (the interleaved C_O / C form of Sec. 3.3.1): group g is
 // {probe id, exclusive end}, and its candidates are the s ids
-// cand[end(g-1) .. end(g)) with end(-1) = 0.  They are expanded into flat
-// pairs before verification.
+// sids[end(g-1) .. end(g)) with end(-1) = 0.  The verification kernels read
+// them in place (issue_cand / resolve_cand); this pre-pass gives each chunk
+// of kWave candidates its first group.
 
-__device__ __forceinline__ uint32_t group_end(const int2* groups, uint32_t g) {
-    return (uint32_t)reinterpret_cast<const int32_t*>(groups)[2u * g + 1u];
+__device__ __forceinline__ int32_t group_end(const int2* groups, uint32_t g) {
+    return reinterpret_cast<const int32_t*>(groups)[2u * g + 1u];
 }
 
-// Least g with end(g) > c0 (n_groups when none) for ends not decreasing, by a
-// 64-way search: each round the lanes read 64 evenly spaced ends of the
-// range [lo, hi] that holds the answer and keep the stretch before the first
-// end above c0, until at most kWave groups remain; the caller then scans
-// from lo.  Wave-uniform; with malformed ends it still returns some
-// lo <= n_groups.
-__device__ uint32_t first_group_above(const int2* __restrict__ groups, uint32_t n_groups, uint32_t c0,
-                                      int lane) {
-    uint32_t lo = 0, hi = n_groups;
-    while (hi - lo > (uint32_t)kWave) {
-        const uint32_t step = (hi - lo + (uint32_t)kWave - 1u) / (uint32_t)kWave;
-        const uint64_t p = (uint64_t)lo + (uint64_t)(lane + 1) * step - 1u;  // sample of lane k
-        const bool above = p >= hi || group_end(groups, (uint32_t)p) > c0;
-        const unsigned long long m = ballot(above);
-        if (m == 0ull) {  // every sampled end is at or below c0: the answer is hi
-            lo = hi;
-            break;
+// One thread per group of all requests of the launch (requests located by
+// the prefix sums group_off): checks the group's end against its
+// predecessor's and the request's size, and writes chunk_g[t] = g for every
+// chunk start t * kWave inside the group's candidates.  With ends that do not
+// decrease, end above n or a last end other than n, the request's error flag
+// is set; only in-range entries of chunk_g are ever written.
+__global__ void k_group_chunks(LaunchArgs a) {
+    const uint32_t total = a.group_off[a.n_req];
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
+        int r = 0;
+        for (int q = 1; q < a.n_req; ++q) r += (x >= a.group_off[q]) ? 1 : 0;
+        const Request& R = a.req[r];
+        const uint32_t g = x - a.group_off[r];
+        const int32_t e = group_end(R.groups, g);
+        const int32_t pv = g > 0u ? group_end(R.groups, g - 1u) : 0;
+        const bool bad = e < pv || (uint32_t)e > R.n || (g + 1u == R.n_groups && (uint32_t)e != R.n);
+        if (bad) {
+            atomicOr(&a.ctr->err[r], 1u);
+            continue;
         }
-        const uint32_t f = (uint32_t)__builtin_ctzll(m);
-        const uint64_t pf = (uint64_t)lo + (uint64_t)(f + 1u) * step - 1u;
-        const uint32_t nlo = f == 0u ? lo : (uint32_t)((uint64_t)lo + (uint64_t)f * step);
-        hi = pf < hi ? (uint32_t)pf : hi;
-        lo = nlo;
-    }
-    return lo;
-}
-
-// Flat pairs (probe, s) of grouped candidates.  A wavefront expands a run of
-// `run` consecutive chunks of kWave candidates: it finds the first
-// group of the run, and for each chunk the lanes load the ends of 64 groups
-// from the current group, each lane's group being the number of those ends
-// at or below its candidate index (binary search across the lanes; a lane
-// past all 64 takes the next 64); the next chunk starts from the group of
-// this chunk's last candidate, so a chunk costs one dependent load.  A
-// candidate that no group covers gets probe id -1, which the verification
-// reports as an id error.  Every thread also checks a share of the ends (not
-// decreasing, none above n, the last one n) and flags request req of ctr on
-// a violation.
-__global__ void k_expand_groups(const int2* __restrict__ groups, uint32_t n_groups,
-                                const int32_t* __restrict__ cand, uint32_t n, uint32_t run,
-                                int2* __restrict__ pairs, Counters* __restrict__ ctr, int req) {
-    const int lane = lane_id();
-    bool bad = false;
-    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_groups; g += gridDim.x * blockDim.x) {
-        const int32_t e = (int32_t)group_end(groups, g);
-        const int32_t prev = g > 0u ? (int32_t)group_end(groups, g - 1u) : 0;
-        bad |= e < prev || (uint32_t)e > n || (g + 1u == n_groups && (uint32_t)e != n);
-    }
-    if (ballot(bad) != 0ull && lane == 0) atomicOr(&ctr->err[req], 1u);
-
-    const uint32_t n_chunks = (n + (uint32_t)kWave - 1u) / (uint32_t)kWave;
-    const uint32_t n_runs = (n_chunks + run - 1u) / run;
-    const uint32_t waves = gridDim.x * (blockDim.x / (uint32_t)kWave);
-    for (uint32_t R = (blockIdx.x * blockDim.x + threadIdx.x) / (uint32_t)kWave; R < n_runs; R += waves) {
-        const uint32_t T0 = R * run, T1 = min(T0 + run, n_chunks);
-        uint32_t g0 = first_group_above(groups, n_groups, T0 * (uint32_t)kWave, lane);
-        for (uint32_t T = T0; T < T1; ++T) {
-            const uint32_t c = T * (uint32_t)kWave + (uint32_t)lane;
-            const bool valid = c < n;
-            const int32_t sv = valid ? cand[c] : 0;
-            uint32_t g = 0xffffffffu;  // the lane's group once found
-            // all lanes take part in every permute (a permute reads nothing
-            // from an inactive lane); the window moves past at most kWave
-            // empty groups per round
-            uint32_t w0 = g0;
-            while (w0 < n_groups) {
-                const uint32_t gk = w0 + (uint32_t)lane;
-                const uint32_t ek = gk < n_groups ? group_end(groups, gk) : 0xffffffffu;
-                uint32_t pos = 0;
-#pragma unroll
-                for (uint32_t step = kWave / 2; step >= 1; step >>= 1) {
-                    const uint32_t v = (uint32_t)bperm((int)ek, (int)(pos + step - 1u));
-                    pos += (v <= c) ? step : 0u;
-                }
-                const bool beyond = (uint32_t)bperm((int)ek, kWave - 1) <= c;
-                if (g == 0xffffffffu && !beyond) g = w0 + pos;
-                if (ballot(valid && g == 0xffffffffu) == 0ull) break;
-                w0 += (uint32_t)kWave;
-            }
-            if (valid) pairs[c] = make_int2(g < n_groups ? groups[g].x : -1, sv);
-            // the next chunk's first group is at or after this chunk's last
-            // candidate's group (ends not decreasing; any start keeps the
-            // search in bounds otherwise)
-            g0 = min((uint32_t)__builtin_amdgcn_readlane((int)g, kWave - 1), n_groups);
-        }
+        // 0 <= max(pv, 0) <= e <= n: every t written is below the request's chunk count
+        const uint32_t lo = (uint32_t)max(pv, 0), hi = (uint32_t)e;
+        for (uint32_t t = (lo + (uint32_t)kWave - 1u) / (uint32_t)kWave; t * (uint32_t)kWave < hi; ++t)
+            R.chunk_g[t] = g;
     }
 }
 
@@ -1370,18 +1411,11 @@ const void* kernel_verify_deferred(bool cosine) {
     return cosine ? (const void*)&k_verify_deferred<true> : (const void*)&k_verify_deferred<false>;
 }
 
-hipError_t launch_expand_groups(const int2* d_groups, int64_t n_groups, const int32_t* d_cand, int64_t n,
-                                Counters* d_ctr, int req, int2* d_pairs, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    const int64_t n_chunks = (n + kWave - 1) / kWave;
-    // chunks per wavefront: one while the chunks alone fill the device (every
-    // chunk then waits for its own search in parallel), up to 8 beyond that
-    // (later chunks of a run skip the search but wait for the chunk before)
-    const int64_t run = std::min<int64_t>(8, std::max<int64_t>(1, (n_chunks + 8191) / 8192));
-    const int64_t n_runs = (n_chunks + run - 1) / run;
-    const int64_t b = std::min<int64_t>((n_runs + kBlock / kWave - 1) / (kBlock / kWave), 65536);
-    hipLaunchKernelGGL(k_expand_groups, dim3((unsigned)b), dim3(kBlock), 0, st, d_groups,
-                       (uint32_t)n_groups, d_cand, (uint32_t)n, (uint32_t)run, d_pairs, d_ctr, req);
+hipError_t launch_group_chunks(const LaunchArgs& a, hipStream_t st) {
+    const uint32_t total = a.group_off[a.n_req];
+    if (total == 0) return hipSuccess;
+    const uint32_t b = std::min<uint32_t>((total + kBlock - 1) / kBlock, 65536u);
+    hipLaunchKernelGGL(k_group_chunks, dim3(b), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 

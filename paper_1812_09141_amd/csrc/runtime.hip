@@ -131,6 +131,10 @@ struct Scratch {
     ssj::Counters* d_ctr = nullptr;
     uint32_t* d_queues = nullptr;
     size_t q_cap = 0;  // entries (kQueues x per-queue capacity)
+    uint32_t* d_chunk_g = nullptr;  // grouped launches: first group of every chunk
+    size_t chunk_cap = 0;
+    uint32_t* d_probes = nullptr;   // grouped launches that defer: probe id per queued pair
+    size_t probes_cap = 0;
 };
 
 struct GraphKey {
@@ -182,6 +186,8 @@ struct StreamEngine;
 
 struct ssj_ctx {
     int device = 0;
+    std::string device_key;   // architecture, name and compute units (tuning cache key)
+    std::string tune_cache;   // tuning cache file ("" = none)
     uint64_t budget = kDefaultBudget;
     std::atomic<uint64_t> resident{0};  // device bytes of the uploaded collections (within budget)
     int n_slots = 4;
@@ -294,6 +300,8 @@ int scratch_init(ssj_ctx* ctx, Scratch& s) {
 void scratch_free(Scratch& s) {
     if (s.d_ctr) (void)hipFree(s.d_ctr);
     if (s.d_queues) (void)hipFree(s.d_queues);
+    if (s.d_chunk_g) (void)hipFree(s.d_chunk_g);
+    if (s.d_probes) (void)hipFree(s.d_probes);
     s = Scratch{};
 }
 
@@ -348,6 +356,11 @@ struct Req {
     int64_t out_cap;
     long long* d_count;
     int sim = SSJ_SIM_JACCARD;
+    // grouped request (d_cand unused): s ids and groups {probe id, end}
+    const int32_t* d_sids = nullptr;
+    const int2* d_groups = nullptr;
+    int64_t n_groups = 0;
+    bool grouped = false;
 };
 
 int check_req(const Req& r) {
@@ -466,11 +479,14 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
         a.bounds[q] = bounds[q];
         a.lanes[q] = plan.lanes[q];
     }
-    uint64_t tiles = 0, pairs = 0;
+    // a launch is grouped when its requests are (callers never mix the two)
+    a.grouped = n_req > 0 && reqs[0].grouped ? 1u : 0u;
+    uint64_t tiles = 0, pairs = 0, groups = 0;
     for (int r = 0; r < n_req; ++r) {
         const Req& q = reqs[r];
         a.tile_off[r] = (uint32_t)tiles;
         a.pair_off[r] = (uint32_t)pairs;
+        a.group_off[r] = (uint32_t)groups;
         ssj::Request& R = a.req[r];
         R.cand = q.d_cand;
         R.out = q.d_out;
@@ -479,14 +495,31 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
         overlap_rule(q.sim, q.t_num, q.t_den, R);
         if (R.rule == ssj::kCosine) a.cosine = 1u;
         R.n = (uint32_t)q.n;
+        if (a.grouped) {
+            // a request without candidates has nothing to verify: its groups
+            // are not read (nor checked)
+            R.sids = q.d_sids;
+            R.groups = q.d_groups;
+            R.n_groups = q.n > 0 ? (uint32_t)q.n_groups : 0u;
+            groups += R.n_groups;
+        }
         tiles += ((uint64_t)q.n + tile_pairs - 1) / tile_pairs;
         pairs += (uint64_t)q.n;
     }
     a.tile_off[n_req] = (uint32_t)tiles;
     a.pair_off[n_req] = (uint32_t)pairs;
+    a.group_off[n_req] = (uint32_t)groups;
     const bool two = plan_two_kernels(plan);
     if (two) {
         HIP_OR_FAIL(ctx, grow(sc.d_queues, sc.q_cap, (size_t)ssj::kQueues * std::max<uint64_t>(pairs, 1)));
+    }
+    if (a.grouped) {
+        HIP_OR_FAIL(ctx, grow(sc.d_chunk_g, sc.chunk_cap, (size_t)std::max<uint64_t>(tiles, 1)));
+        for (int r = 0; r < n_req; ++r) a.req[r].chunk_g = sc.d_chunk_g + a.tile_off[r];
+        if (two) {
+            HIP_OR_FAIL(ctx, grow(sc.d_probes, sc.probes_cap, (size_t)std::max<uint64_t>(pairs, 1)));
+            a.probes = sc.d_probes;
+        }
     }
     a.queues = sc.d_queues;
     a.qcap = (uint32_t)(sc.q_cap / ssj::kQueues);
@@ -504,7 +537,10 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
             if (!ev[k]) return hip_fail(ctx, "hipEventCreate", hipErrorOutOfMemory);
         }
     }
-    if (plan.use_graph && allow_graph && !timing) {
+    // grouped launches start with the group pre-pass (outside the graph and
+    // the timing events, which cover the verification kernels)
+    if (a.grouped) HIP_OR_FAIL(ctx, ssj::launch_group_chunks(a, st));
+    if (plan.use_graph && allow_graph && !timing && !a.grouped) {
         int rc = launch_graph(ctx, a, g1, g2, two, st);
         if (rc != SSJ_OK) return rc;
     } else {
@@ -968,6 +1004,9 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
         hipDeviceProp_t prop;
         if ((e = hipGetDeviceProperties(&prop, ctx->device)) != hipSuccess) { rc = hip_fail(ctx, "hipGetDeviceProperties", e); break; }
         ctx->n_cu = prop.multiProcessorCount;
+        ctx->device_key = std::string(prop.gcnArchName) + "/" + prop.name + "/" + std::to_string(ctx->n_cu) + "cu";
+        for (char& ch : ctx->device_key)
+            if (ch == '"' || ch == '\\' || ch == '|' || (unsigned char)ch < 32) ch = '_';
         for (int k = 0; k < 4 * kMappings && rc == SSJ_OK; ++k) {
             const bool deferring = (k & 1) != 0;
             const void* f = ssj::kernel_verify_tiles(kInlineLanes[k / 4], kInlineHard[k / 4],
@@ -1295,15 +1334,23 @@ int verify_device(ssj_ctx* ctx, const ssj_coll* coll, const ssj_coll* coll_s, co
     return enqueue_launch(ctx, coll, ctx->def, &r, 1, (hipStream_t)hip_stream, ctx->plan, true, coll_s);
 }
 
-// Expands grouped candidates already on the device into ctx->d_pairs and
-// enqueues their verification (ctx->mu held).
+// A grouped request (candidates read in place by the verification kernels).
+void grouped_req(Req& r, const int2* d_groups, int64_t n_groups, const int32_t* d_sids, int64_t n_cand, int sim,
+                 int64_t t_num, int64_t t_den, int2* d_out, int64_t out_cap, long long* d_count) {
+    r = Req{nullptr, n_cand, t_num, t_den, d_out, out_cap, d_count, sim};
+    r.d_sids = d_sids;
+    r.d_groups = d_groups;
+    r.n_groups = n_groups;
+    r.grouped = true;
+}
+
+// Enqueues the verification of grouped candidates already on the device
+// (ctx->mu held).
 int enqueue_groups(ssj_ctx* ctx, const ssj_coll* R, const ssj_coll* S, const int2* d_groups,
                    int64_t n_groups, const int32_t* d_sids, int64_t n_cand, int sim, int64_t t_num,
                    int64_t t_den, int2* d_out, int64_t out_cap, long long* d_count, hipStream_t st) {
-    HIP_OR_FAIL(ctx, grow(ctx->d_pairs, ctx->pairs_cap, (size_t)std::max<int64_t>(n_cand, 1)));
-    HIP_OR_FAIL(ctx, ssj::launch_expand_groups(d_groups, n_groups, d_sids, n_cand, ctx->def.d_ctr, 0,
-                                               ctx->d_pairs, st));
-    Req r{ctx->d_pairs, n_cand, t_num, t_den, d_out, out_cap, d_count, sim};
+    Req r;
+    grouped_req(r, d_groups, n_groups, d_sids, n_cand, sim, t_num, t_den, d_out, out_cap, d_count);
     return enqueue_launch(ctx, R, ctx->def, &r, 1, st, ctx->plan, true, S);
 }
 
@@ -1354,12 +1401,14 @@ int ssj_verify_groups_batch_device(ssj_ctx* ctx, const ssj_coll* coll_r, const s
     if ((rc = check_coll(ctx, coll_s)) != SSJ_OK) return rc;
     if (n_reqs < 0 || n_reqs > ssj::kMaxReq || (n_reqs > 0 && !reqs))
         return set_error(SSJ_EINVAL, "n_reqs must be in [0, SSJ_MAX_BATCH]");
-    int64_t total = 0;
+    int64_t total = 0, total_groups = 0;
     for (int i = 0; i < n_reqs; ++i) {
         const ssj_group_request& q = reqs[i];
         if (!valid_threshold(q.sim, q.t_num, q.t_den)) return set_error(SSJ_EINVAL, kThresholdError);
         if (q.n_groups < 0 || q.n_cand < 0 || q.out_cap < 0) return set_error(SSJ_EINVAL, "negative size");
-        if (q.n_groups > kMaxLaunchPairs) return set_error(SSJ_EINVAL, "n_groups must be below 2^31");
+        total_groups += q.n_groups;
+        if (q.n_groups > kMaxLaunchPairs || total_groups > kMaxLaunchPairs)
+            return set_error(SSJ_EINVAL, "the groups of a batch must stay below 2^31");
         if (!q.d_count || (q.n_cand > 0 && !q.d_cand) || (q.n_groups > 0 && !q.d_groups))
             return set_error(SSJ_EINVAL, "null device buffer");
         if (q.out_cap > 0 && !q.d_out) return set_error(SSJ_EINVAL, "out_cap > 0 with a null output buffer");
@@ -1370,17 +1419,12 @@ int ssj_verify_groups_batch_device(ssj_ctx* ctx, const ssj_coll* coll_r, const s
     std::lock_guard<std::mutex> g(ctx->mu);
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)hip_stream;
-    HIP_OR_FAIL(ctx, grow(ctx->d_pairs, ctx->pairs_cap, (size_t)std::max<int64_t>(total, 1)));
     std::vector<Req> v((size_t)n_reqs);
-    int64_t off = 0;
     for (int i = 0; i < n_reqs; ++i) {
         const ssj_group_request& q = reqs[i];
-        // request i's expansion flags malformed groups in request i's error word
-        HIP_OR_FAIL(ctx, ssj::launch_expand_groups(reinterpret_cast<const int2*>(q.d_groups), q.n_groups, q.d_cand,
-                                                   q.n_cand, ctx->def.d_ctr, i, ctx->d_pairs + off, st));
-        v[i] = Req{ctx->d_pairs + off, q.n_cand, q.t_num, q.t_den, reinterpret_cast<int2*>(q.d_out), q.out_cap,
-                   reinterpret_cast<long long*>(q.d_count), q.sim};
-        off += q.n_cand;
+        grouped_req(v[i], reinterpret_cast<const int2*>(q.d_groups), q.n_groups, q.d_cand, q.n_cand, q.sim,
+                    q.t_num, q.t_den, reinterpret_cast<int2*>(q.d_out), q.out_cap,
+                    reinterpret_cast<long long*>(q.d_count));
     }
     return enqueue_launch(ctx, coll_r, ctx->def, v.data(), n_reqs, st, ctx->plan, true, coll_s);
 }
@@ -1785,6 +1829,80 @@ int ssj_verify(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* cand, int64_t
                           out_n);
 }
 
+}  // extern "C"
+
+namespace {
+
+int64_t gcd64(int64_t a, int64_t b) {
+    while (b != 0) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Tuning cache key of a workload on the context's device.
+std::string tune_key(const ssj_ctx* ctx, const ssj_coll* coll, int64_t n_cand, int64_t t_num, int64_t t_den) {
+    const int64_t g = std::max<int64_t>(1, gcd64(t_num, t_den));
+    return ctx->device_key + "|sets=" + std::to_string(coll->n_sets) + ",tokens=" + std::to_string(coll->n_tokens) +
+           ",max_len=" + std::to_string(coll->max_len) + "|cand=" + std::to_string(n_cand) + "|t=" +
+           std::to_string(t_num / g) + "/" + std::to_string(t_den / g);
+}
+
+// The last well-formed entry of key in the cache file.
+bool tune_lookup(const std::string& path, const std::string& key, ssj_plan* plan, double* ms) {
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    const std::string want = "{\"key\": \"" + key + "\", ";
+    bool found = false;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::strncmp(line, want.c_str(), want.size()) != 0) continue;
+        ssj_plan p{};
+        double t = 0.0;
+        const int n = std::sscanf(line + want.size(),
+                                  "\"kernel_ms\": %lf, \"plan\": [%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d]}",
+                                  &t, &p.inline_lanes, &p.hard_lanes, &p.defer_from, &p.lanes[0], &p.lanes[1],
+                                  &p.lanes[2], &p.lanes[3], &p.lanes[4], &p.use_graph, &p.spill_iters,
+                                  &p.spill_lanes, &p.wg_per_cu, &p.staged);
+        if (n == 14 && plan_valid(p)) {
+            *plan = p;
+            *ms = t;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+// Appends an entry (one write of the whole line).
+void tune_store(const std::string& path, const std::string& key, const ssj_plan& p, double ms) {
+    char buf[1024];
+    const int n = std::snprintf(buf, sizeof buf,
+                                "{\"key\": \"%s\", \"kernel_ms\": %.6f, \"plan\": [%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d]}\n",
+                                key.c_str(), ms, p.inline_lanes, p.hard_lanes, p.defer_from, p.lanes[0], p.lanes[1],
+                                p.lanes[2], p.lanes[3], p.lanes[4], p.use_graph, p.spill_iters, p.spill_lanes,
+                                p.wg_per_cu, p.staged);
+    if (n <= 0 || n >= (int)sizeof buf) return;
+    FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fwrite(buf, 1, (size_t)n, f);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssj_set_tune_cache(ssj_ctx* ctx, const char* path) {
+    int rc = check_ctx(ctx);
+    if (rc != SSJ_OK) return rc;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->tune_cache = path ? path : "";
+    return SSJ_OK;
+}
+
 int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int64_t n_cand,
                  int64_t t_num, int64_t t_den, int apply, ssj_plan* best, double* best_ms) {
     int rc = check_ctx(ctx);
@@ -1794,6 +1912,20 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
     if (n_cand <= 0 || n_cand > kMaxLaunchPairs || !d_cand)
         return set_error(SSJ_EINVAL, "autotuning needs 1 .. 2^31-1 device candidates");
     std::lock_guard<std::mutex> g(ctx->mu);
+    const std::string key = tune_key(ctx, coll, n_cand, t_num, t_den);
+    if (!ctx->tune_cache.empty()) {
+        ssj_plan p{};
+        double ms = 0.0;
+        if (tune_lookup(ctx->tune_cache, key, &p, &ms)) {
+            if (best) *best = p;
+            if (best_ms) *best_ms = ms;
+            if (apply) {
+                std::lock_guard<std::mutex> gp(ctx->plan_mu);
+                ctx->plan = p;
+            }
+            return SSJ_CACHED;
+        }
+    }
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     HIP_OR_FAIL(ctx, grow(ctx->d_out, ctx->out_cap, (size_t)n_cand));
@@ -1943,6 +2075,7 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SSJ_OK) return rc;
+    if (!ctx->tune_cache.empty()) tune_store(ctx->tune_cache, key, cur, cur_ms);
     if (best) *best = cur;
     if (best_ms) *best_ms = cur_ms;
     if (apply) {

@@ -33,6 +33,17 @@ struct Request {
     unsigned long long den;
     uint32_t n;                // pairs
     uint32_t rule;             // OverlapRule
+    // A grouped request (the C / C_O layout of paper Sec. 3.3.1) has no
+    // cand: its candidates are the s ids sids[0..n), and group g = {probe id,
+    // exclusive end into sids} covers sids[end(g-1) .. end(g)) with end(-1)
+    // = 0.  chunk_g[t] is the first group whose end exceeds t * kWave (the
+    // group of the chunk's first candidate), written by the launch's group
+    // pre-pass.
+    const int32_t* sids;
+    const int2* groups;
+    uint32_t* chunk_g;
+    uint32_t n_groups;
+    uint32_t pad;
 };
 
 // Per-launch device counters.  Every launch leaves them zeroed again (its
@@ -70,6 +81,10 @@ struct LaunchArgs {
     uint32_t staged;                     // != 0: thread-per-pair merges over token blocks staged
                                          // in LDS (k_verify_staged); spill_iters then counts
                                          // block rounds
+    uint32_t grouped;                    // != 0: every request of the launch is grouped
+    uint32_t* probes;                    // grouped launches that defer: the probe id of every
+                                         // queued pair, by global pair index
+    uint32_t group_off[kMaxReq + 1];     // grouped launches: prefix sums of per-request groups
     uint32_t tile_off[kMaxReq + 1];      // prefix sums of per-request chunks (of kWave pairs)
     uint32_t pair_off[kMaxReq + 1];      // prefix sums of per-request pairs
     uint32_t bounds[kClasses];           // inclusive upper bound of |r|+|s| per class
@@ -84,14 +99,12 @@ struct LaunchArgs {
 // array.
 hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start, const int32_t* d_tok,
                               uint4* d_heads, int64_t n_sets, hipStream_t st);
-// Flat pairs d_pairs[0..n) from grouped candidates: groups {probe id,
-// exclusive end into d_cand} and s ids d_cand (n > 0).  Candidates no group
-// covers get probe id -1; malformed ends (decreasing, above n, the last one
-// not n) set the error flag of request req in d_ctr, which the launch that
-// verifies d_pairs as its request req with these counters then reports and
-// clears.
-hipError_t launch_expand_groups(const int2* d_groups, int64_t n_groups, const int32_t* d_cand, int64_t n,
-                                Counters* d_ctr, int req, int2* d_pairs, hipStream_t st);
+// Group pre-pass of a grouped launch (a.grouped): writes every request's
+// chunk_g and checks its group ends (not decreasing, none above n, the last
+// one n); malformed ends set the request's error flag, which the launch's
+// finalize kernel reports.  Candidates no group covers are verified with
+// probe id -1, an id error.
+hipError_t launch_group_chunks(const LaunchArgs& a, hipStream_t st);
 // The in-order kernel: every pair of a class below defer_from is verified
 // with inline_lanes lanes; the others are queued for launch_verify_deferred,
 // and so is every thread-per-pair merge still undecided after spill_iters

@@ -22,6 +22,7 @@ LIB_PATH = os.environ.get("SSJ_LIB") or os.path.join(_PKG, "libssj.so")
 
 SSJ_OK = 0
 SSJ_PENDING = 1
+SSJ_CACHED = 2
 SSJ_EINVAL = -1
 SSJ_ENOMEM = -2
 SSJ_ETRUNC = -3
@@ -51,11 +52,11 @@ EXPORTED = (
     "ssj_verify_rs", "ssj_verify_rs_device", "ssj_verify_groups", "ssj_verify_groups_device",
     "ssj_verify_groups_batch_device",
     "ssj_candidates_device", "ssj_join_device", "ssj_join", "ssj_stream_pause",
-    "ssj_verify_device_noalloc",
+    "ssj_verify_device_noalloc", "ssj_set_tune_cache",
 )
 
 _NAMES = {
-    SSJ_OK: "SSJ_OK", SSJ_PENDING: "SSJ_PENDING", SSJ_EINVAL: "SSJ_EINVAL",
+    SSJ_OK: "SSJ_OK", SSJ_PENDING: "SSJ_PENDING", SSJ_CACHED: "SSJ_CACHED", SSJ_EINVAL: "SSJ_EINVAL",
     SSJ_ENOMEM: "SSJ_ENOMEM", SSJ_ETRUNC: "SSJ_ETRUNC", SSJ_EAGAIN: "SSJ_EAGAIN",
     SSJ_EDEVICE: "SSJ_EDEVICE", SSJ_ENOTFOUND: "SSJ_ENOTFOUND",
 }
@@ -138,6 +139,7 @@ def load_library(path: str = LIB_PATH):
         "ssj_timing_read": ([p, c_int, P(ctypes.c_double), P(ctypes.c_double), P(i64)], c_int),
         "ssj_verify_batch_device": ([p, p, P(ssj_request), c_int, p], c_int),
         "ssj_autotune": ([p, p, p, i64, i64, i64, c_int, P(ssj_plan), P(ctypes.c_double)], c_int),
+        "ssj_set_tune_cache": ([p, ctypes.c_char_p], c_int),
         "ssj_verify_sim": ([p, p, p, i64, c_int, i64, i64, p, i64, P(i64)], c_int),
         "ssj_verify_device_sim": ([p, p, p, i64, c_int, i64, i64, p, i64, p, p], c_int),
         "ssj_stream_submit_sim": ([p, p, p, i64, c_int, i64, i64, c_int, P(u64)], c_int),
@@ -577,16 +579,27 @@ def ssj_verify_batch_device(ctx, coll, requests, stream=None) -> None:
         _err(ctx, rc)
 
 
-def ssj_autotune(ctx, coll, d_cand: "torch.Tensor", t_num: int, t_den: int, apply: bool = True):
-    """Best plan for the given device candidates and its kernel time (ms)."""
+def ssj_autotune(ctx, coll, d_cand: "torch.Tensor", t_num: int, t_den: int, apply: bool = True,
+                 with_status: bool = False):
+    """Best plan for the given device candidates and its kernel time (ms);
+    with_status also returns whether it came from the tuning cache."""
     p = ssj_plan()
     ms = ctypes.c_double()
     n = d_cand.numel() // 2
     rc = load_library().ssj_autotune(ctx, coll, d_cand.data_ptr(), n, int(t_num), int(t_den),
                                      int(bool(apply)), ctypes.byref(p), ctypes.byref(ms))
+    if rc not in (SSJ_OK, SSJ_CACHED):
+        _err(ctx, rc)
+    if with_status:
+        return p, ms.value, rc == SSJ_CACHED
+    return p, ms.value
+
+
+def ssj_set_tune_cache(ctx, path) -> None:
+    """Tuning cache file of ssj_autotune (None turns it off)."""
+    rc = load_library().ssj_set_tune_cache(ctx, os.fsencode(path) if path else None)
     if rc != SSJ_OK:
         _err(ctx, rc)
-    return p, ms.value
 
 
 def ssj_timing_enable(ctx, period: int = 1) -> None:

@@ -390,3 +390,80 @@ def test_groups_batch_one_launch(S, ctx, golden_dir):
             S.ssj_verify_groups_batch_device(ctx, h, h, [reqs[0]] * 17)
     finally:
         S.ssj_free_collection(ctx, h)
+
+
+# Every mapping family on grouped candidates: the in-order kernel's
+# thread-per-pair pipeline, its lane groups (pairs handed on by permutes),
+# the staged kernel, and the deferred kernel, which reads the probe ids
+# that the in-order kernel stored for the pairs it queued.
+GROUP_PLANS = PLANS + [
+    ("inline-1h16-defer", dict(inline_lanes=1, hard_lanes=16, defer_from=1, lanes=[4, 16, 32, 64, 256])),
+    ("inline-32", dict(inline_lanes=32, defer_from=5)),
+    ("inline-64", dict(inline_lanes=64, defer_from=5)),
+    ("deferred-1", dict(inline_lanes=4, defer_from=0, lanes=[1] * 5)),
+    ("deferred-64", dict(inline_lanes=16, defer_from=0, lanes=[64] * 5)),
+    ("spill-2x1-defer", dict(inline_lanes=1, defer_from=2, lanes=[4, 8, 32, 64, 256], spill_iters=2,
+                             spill_lanes=1)),
+    ("spill-1x256", dict(inline_lanes=1, defer_from=5, spill_iters=1, spill_lanes=256)),
+    ("staged", dict(inline_lanes=1, defer_from=5, staged=1)),
+    ("staged-spill-1x16", dict(inline_lanes=1, defer_from=5, staged=1, spill_iters=1, spill_lanes=16)),
+    ("staged-defer", dict(inline_lanes=1, defer_from=2, lanes=[4, 8, 32, 64, 256], staged=1)),
+    ("graph", dict(inline_lanes=8, defer_from=2, lanes=[4, 16, 16, 64, 256], use_graph=1)),
+    ("inline-1-wg1", dict(inline_lanes=1, defer_from=5, wg_per_cu=1)),
+]
+
+
+def test_groups_every_mapping(S, ctx):
+    """Grouped candidates over long near-duplicate sets (merges past the set
+    records, deferred classes, spilled merges) with empty groups, runs of more
+    than 64 empty groups inside one chunk, one-candidate groups and a group of
+    thousands, in every mapping; two grouped requests of one batched launch."""
+    import torch
+    rng, R, Sc = _two(8, 400)
+    hr = S.ssj_upload_collection(ctx, R.offsets, R.tokens)
+    hs = S.ssj_upload_collection(ctx, Sc.offsets, Sc.tokens)
+    try:
+        sizes = ([0, 3, 0] + [0] * 150 + [2, 1] + [0] * 70 + [1] * 130 + [64, 65, 63, 0, 2500]
+                 + list(rng.integers(0, 40, 80)) + [0] * 65 + [7] + list(rng.integers(0, 3, 300)) + [0])
+        groups = _uneven_groups(rng, R.n_sets, sizes)
+        n = int(groups[-1, 1])
+        sids = rng.integers(0, Sc.n_sets, n).astype(np.int32)
+        flat = np.stack([np.repeat(groups[:, 0], sizes), sids], axis=1).astype(np.int32)
+        dev = torch.device("cuda:0")
+        d_g = torch.from_numpy(groups).to(dev)
+        d_s = torch.from_numpy(sids).to(dev)
+        # the second request: the first half of the groups, cut to end where they end
+        half = groups.shape[0] // 2
+        g2 = groups[:half].copy()
+        n2 = int(g2[-1, 1])
+        d_g2 = torch.from_numpy(g2).to(dev)
+        d_s2 = d_s[:n2].contiguous()
+        wants = {}
+        for tn, td in [(1, 4), (3, 5)]:
+            wants[(tn, td)] = oracle.sort_pairs(oracle.select_rs(R.offsets, R.tokens, Sc.offsets, Sc.tokens,
+                                                                 flat, tn, td))
+        want2 = oracle.sort_pairs(oracle.select_rs(R.offsets, R.tokens, Sc.offsets, Sc.tokens, flat[:n2], 1, 2))
+        assert wants[(3, 5)].shape[0] > 50 and want2.shape[0] > 50
+        d_out = torch.empty((n, 2), dtype=torch.int32, device=dev)
+        d_out2 = torch.empty((n2, 2), dtype=torch.int32, device=dev)
+        d_cnt = torch.zeros(2, dtype=torch.int64, device=dev)
+        for name, plan in GROUP_PLANS:
+            S.ssj_set_plan(ctx, S.make_plan(**plan))
+            for (tn, td), want in wants.items():
+                _log(f"groups every mapping {name} t={tn}/{td} n={n}")
+                S.ssj_verify_groups_device(ctx, hr, hs, d_g, d_s, "jaccard", tn, td, d_out, d_cnt[:1])
+                torch.cuda.synchronize()
+                k = int(d_cnt[0].item())
+                assert k == want.shape[0], (name, tn, td)
+                assert np.array_equal(oracle.sort_pairs(d_out[:k].cpu().numpy()), want), (name, tn, td)
+            _log(f"groups every mapping {name}: two grouped requests in one launch")
+            S.ssj_verify_groups_batch_device(ctx, hr, hs, [(d_g, d_s, 3, 5, d_out, d_cnt[0:1]),
+                                                          (d_g2, d_s2, 1, 2, d_out2, d_cnt[1:2])])
+            torch.cuda.synchronize()
+            k1, k2 = (int(x) for x in d_cnt.cpu().numpy())
+            assert k1 == wants[(3, 5)].shape[0] and k2 == want2.shape[0], name
+            assert np.array_equal(oracle.sort_pairs(d_out[:k1].cpu().numpy()), wants[(3, 5)]), name
+            assert np.array_equal(oracle.sort_pairs(d_out2[:k2].cpu().numpy()), want2), name
+    finally:
+        S.ssj_free_collection(ctx, hr)
+        S.ssj_free_collection(ctx, hs)

@@ -140,6 +140,52 @@ def test_autotune_plan_is_correct(S, ctx, data):
     S.ssj_free_collection(ctx, h)
 
 
+def test_autotune_cache(S, ctx, data, tmp_path):
+    """The tuning cache: a tuned workload is stored and then served without
+    measuring (SSJ_CACHED, same plan and time), also to another context; a
+    different threshold misses; lines that do not parse are ignored."""
+    import torch
+    c, reqs = data
+    path = str(tmp_path / "tune.jsonl")
+    with open(path, "w") as f:
+        f.write("not json\n{\"key\": \"broken\n")
+    h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+    try:
+        S.ssj_set_tune_cache(ctx, path)
+        cand, tn, td, want = reqs[0]
+        d_cand = _dev(torch, cand)
+        p1, ms1, hit1 = S.ssj_autotune(ctx, h, d_cand, tn, td, apply=True, with_status=True)
+        assert not hit1 and ms1 > 0
+        p2, ms2, hit2 = S.ssj_autotune(ctx, h, d_cand, tn, td, apply=False, with_status=True)
+        assert hit2 and p2.as_dict() == p1.as_dict() and abs(ms2 - ms1) < 1e-5
+        got = oracle.sort_pairs(S.ssj_verify(ctx, h, cand, tn, td))
+        assert np.array_equal(got, want)
+        lines = open(path).read().splitlines()
+        assert len(lines) == 3 and lines[-1].startswith('{"key": "') and "|t=" in lines[-1]
+        # the same workload in a second context reads the same file
+        ctx2 = S.ssj_init(0)
+        try:
+            S.ssj_set_tune_cache(ctx2, path)
+            h2 = S.ssj_upload_collection(ctx2, c.offsets, c.tokens)
+            p3, ms3, hit3 = S.ssj_autotune(ctx2, h2, d_cand, tn, td, apply=True, with_status=True)
+            assert hit3 and p3.as_dict() == p1.as_dict()
+            assert S.ssj_get_plan(ctx2).as_dict() == p1.as_dict()
+            S.ssj_free_collection(ctx2, h2)
+        finally:
+            S.ssj_shutdown(ctx2)
+        # another threshold is another workload
+        cand_b, tn_b, td_b, _ = reqs[1]
+        if (tn_b, td_b) != (tn, td):
+            _, _, hit4 = S.ssj_autotune(ctx, h, _dev(torch, cand_b), tn_b, td_b, apply=False, with_status=True)
+            assert not hit4
+        S.ssj_set_tune_cache(ctx, None)
+        _, _, hit5 = S.ssj_autotune(ctx, h, d_cand, tn, td, apply=False, with_status=True)
+        assert not hit5
+    finally:
+        S.ssj_set_tune_cache(ctx, None)
+        S.ssj_free_collection(ctx, h)
+
+
 def test_timing_counts_launches(S, ctx, data):
     import torch
     c, reqs = data
