@@ -85,9 +85,8 @@ def parse(argv=None):
 
 def plan_of(S, spec):
     """auto | inline:M | defer:M,D,l0,l1,l2,l3,l4 with M = L[b][hF][sI[xG]][wW] (L lanes per pair,
-    b the staged kernel (token blocks in LDS), F hard lanes, I window steps (staged: block
-    rounds) before a merge spills to G lanes, W in-order workgroups per compute unit, D first
-    deferred class)"""
+    b the window ring (L = 1), F hard lanes, I window steps before a merge spills to G lanes,
+    W in-order workgroups per compute unit, D first deferred class)"""
     if spec == "auto":
         return None
     kind, _, rest = spec.partition(":")
@@ -144,14 +143,13 @@ def kernel_source_hash():
 
 
 def kernel_name_of(plan):
-    """The verification kernels a plan runs (as rocprofv3 names their instances)."""
+    """The verification kernels a plan runs (as rocprofv3 names their instances,
+    flat launches)."""
     deferred = plan.defer_from < 5 or plan.spill_iters > 0
-    if plan.staged:
-        first = f"k_verify_staged<{'true' if deferred else 'false'},false>"
-    else:
-        first = (f"k_verify_tiles<{plan.inline_lanes},{plan.hard_lanes},"
-                 f"{'true' if deferred else 'false'},false>")
-    return first + (" + k_verify_deferred<false>" if deferred else "")
+    tf = lambda v: "true" if v else "false"  # noqa: E731
+    first = (f"k_verify_tiles<{plan.inline_lanes},{plan.hard_lanes},{tf(deferred)},false,"
+             f"{tf(plan.staged)},false>")
+    return first + (" + k_verify_deferred<false,false>" if deferred else "")
 
 
 def copy_gbs(torch, mib=1024, reps=5):
@@ -659,7 +657,10 @@ def stream_phase(S, ctx, args):
     # staging pool holds buffers of every size class (steady state)
     for name in ("warmup", "saturated", "offered_load_0.8"):
         rate = 0.8 * runs["saturated"]["pairs_per_s"] if name == "offered_load_0.8" else None
+        S.ssj_stream_stats(ctx, reset=True)
         r = serving.run_stream(S, ctx, h5, batches, rate, seed=1 if rate else 0, n_submitters=subs, results=res)
+        # buffer regrowths and the longest engine pass during this run
+        r["engine"] = S.ssj_stream_stats(ctx, reset=True)
         if pinned:
             ok &= all(x is not None and x.shape[0] == p["n_result"] and pairs_digest(x) == p["result_sha256"]
                       for x, p in zip(res, pins["batches"]))

@@ -221,7 +221,8 @@ int ssj_verify_rs_device(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* c
  * is 0).
  * The verification kernels read the groups in place (a pre-pass kernel
  * first notes the group of every 64th candidate in the context's scratch),
- * so device calls on one context must not overlap.
+ * so no expanded pairs are written.  Device calls on one context must not
+ * overlap.
  */
 int ssj_verify_groups(ssj_ctx* ctx, const ssj_coll* coll_r, const ssj_coll* coll_s,
                       const ssj_group* groups, int64_t n_groups, const int32_t* cand, int64_t n_cand,
@@ -333,6 +334,24 @@ int ssj_stream_times(ssj_ctx* ctx, uint64_t ticket, int wait, uint64_t* t_submit
 int ssj_stream_pause(ssj_ctx* ctx, int pause);
 
 /*
+ * Statistics of the streaming engine since it started (or the last reset):
+ * how often slots regrew their device buffers (stream-ordered reallocations
+ * on the slot's idle stream) and their pinned result buffers, the host time
+ * spent doing so, and the longest pass of the engine loop over its slots
+ * (host time, with the engine lock held: a long pass delays every request's
+ * admission and completion).  reset != 0 zeroes them after reading.
+ * SSJ_EINVAL without a running engine.
+ */
+typedef struct {
+    uint64_t slot_grows;
+    double slot_grow_ms;
+    uint64_t result_grows;
+    double result_grow_ms;
+    double longest_pass_ms;
+} ssj_stream_stats_t;
+int ssj_stream_stats(ssj_ctx* ctx, ssj_stream_stats_t* out, int reset);
+
+/*
  * Execution plan.  Verification runs as one or two kernels per launch:
  *  1. an in-order kernel in which every wavefront walks chunks of 64
  *     consecutive pairs and verifies each pair with inline_lanes lanes (1 =
@@ -353,11 +372,11 @@ int ssj_stream_pause(ssj_ctx* ctx, int pause);
  *     pair still undecided then is queued and verified again from its start
  *     by the kernel of (2), with spill_lanes lanes per pair.  This keeps a
  *     few long merges from holding up their wavefronts.  0: no bound.
- *  4. staged != 0 (with one thread per pair and no hard lanes) runs (1) as
- *     the staged kernel for long sets: each lane merges its pair from 16-token
- *     blocks of both sets held in LDS, which the wavefront loads together
- *     (four lanes per 64-byte block) whenever merges leave their blocks;
- *     spill_iters then bounds the rounds of block loads per chunk of 64 pairs.
+ *  4. staged != 0 (with one thread per pair and no hard lanes) stages the
+ *     4-token windows of the thread-per-pair merges of (1) in a ring of LDS
+ *     slots per lane, so that each window is requested two merge steps
+ *     before it is needed instead of one (for long sets, whose merges wait
+ *     on their window loads); spill_iters counts window steps as in (3).
  * use_graph != 0 replays the launch through a captured hipGraph whose kernel
  * parameters are updated per call.  wg_per_cu sizes the in-order kernel's
  * grid (its wavefronts split the chunks evenly; more workgroups than fit at

@@ -422,36 +422,72 @@ struct CandLoad {
     uint32_t g0;  // the window's first group (wave-uniform)
 };
 
+// First groups of a wavefront's upcoming chunks, one per lane: lane L holds
+// chunk_g of the wavefront's chunk with ordinal base + L (its chunk
+// first + (base + L) * nw, clamped to the last chunk as the pipelines clamp
+// their chunks), so that a grouped chunk's first group is in a register
+// before its loads are issued (one vector load per 64 chunks of a wavefront).
+template <bool GR>
+__device__ __forceinline__ uint32_t load_chunk_groups(const LaunchArgs& a, uint32_t first, uint32_t nw,
+                                                      uint32_t n_chunks, uint32_t base, int lane) {
+    if constexpr (!GR) return 0u;
+    const unsigned long long c = (unsigned long long)first + (unsigned long long)(base + (uint32_t)lane) * nw;
+    return a.chunk_g[c < n_chunks ? (uint32_t)c : n_chunks - 1u];
+}
+
 // Issues the loads of the lane's candidate of the chunk at candidate kb of
-// request R.  chunk_g entries of a request with malformed groups may be stale
-// (that request reports an error): g0 is clamped, so every load stays inside
-// the request's buffers.
-__device__ __forceinline__ CandLoad issue_cand(const LaunchArgs& a, const Request& R, uint32_t kb, int lane) {
+// request R, whose first group is g0 (chunk_g; unused for a flat request).
+// chunk_g entries of a request with malformed groups may be stale (that
+// request reports an error): g0 is clamped, so every load stays inside the
+// request's buffers.
+template <bool GR>
+__device__ __forceinline__ CandLoad issue_cand(const LaunchArgs& a, const Request& R, uint32_t kb, int lane,
+                                               uint32_t g0) {
     CandLoad c;
     const uint32_t k = kb + (uint32_t)lane;
     const uint32_t kc = k < R.n ? k : R.n - 1u;
-    if (!a.grouped) {
+    if constexpr (!GR) {
         c.p = load_pair(R.cand, kc);
         c.gw = make_int2(0, 0);
         c.g0 = 0u;
         return c;
     }
-    const uint32_t g0 = min(R.chunk_g[kb / (uint32_t)kWave], R.n_groups);
-    c.g0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)g0);
+    c.g0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(g0, R.n_groups));
     c.p = make_int2(0, R.sids[kc]);
     c.gw = R.n_groups != 0u ? R.groups[min(c.g0 + (uint32_t)lane, R.n_groups - 1u)] : make_int2(-1, -1);
     return c;
 }
 
+// Maximum of v over lanes 0 .. lane of the wavefront (v >= 0): within each
+// row of 16 lanes by shifted maxima (DPP row shifts), then across rows from
+// the rows' last lanes.
+__device__ __forceinline__ uint32_t wave_max_scan(uint32_t v, int lane) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+    const int row = lane >> 4;
+    const uint32_t below = row == 0 ? 0u : row == 1 ? r0 : row == 2 ? max(r0, r1) : max(max(r0, r1), r2);
+    return max(v, below);
+}
+
 // The lane's pair from its loads (all lanes of the wavefront call it
-// together: cross-lane permutes).  The group of candidate k is the first one
-// whose end exceeds k; in a window of ends that do not decrease it is the
-// window's group at the number of ends <= k, unless all 64 are <= k, when the
-// next window is searched.  A candidate no group covers gets probe id -1 (an
-// id error).
+// together: cross-lane operations); marks is the wavefront's 64-word LDS
+// scratch.  The group of candidate kb + k is the first one whose end exceeds
+// it, so its index in a window of ends that do not decrease is the number of
+// window groups ending at or before kb + k.  Each window group marks the
+// chunk position its end falls on (the largest group index + 1 per
+// position, by an LDS maximum), and a running maximum over the positions
+// gives every lane that number at once.  A lane past all 64 ends searches
+// the next window; a candidate no group covers gets probe id -1 (an id
+// error).
+template <bool GR>
 __device__ __forceinline__ int2 resolve_cand(const LaunchArgs& a, const Request& R, uint32_t kb, int lane,
-                                             const CandLoad& c) {
-    if (!a.grouped) return c.p;
+                                             const CandLoad& c, uint32_t* marks) {
+    if constexpr (!GR) return c.p;
     const uint32_t k = kb + (uint32_t)lane;
     const bool valid = k < R.n;
     uint32_t w0 = c.g0;
@@ -460,15 +496,16 @@ __device__ __forceinline__ int2 resolve_cand(const LaunchArgs& a, const Request&
     bool found = false;
     while (w0 < R.n_groups) {
         const uint32_t ek = w0 + (uint32_t)lane < R.n_groups ? (uint32_t)e.y : 0xffffffffu;
-        uint32_t pos = 0;
-#pragma unroll
-        for (uint32_t step = kWave / 2; step >= 1; step >>= 1) {
-            const uint32_t v = (uint32_t)bperm((int)ek, (int)(pos + step - 1u));
-            pos += (v <= k) ? step : 0u;
-        }
-        const bool beyond = (uint32_t)bperm((int)ek, kWave - 1) <= k;
-        const int32_t pp = bperm(e.x, (int)pos);
-        if (!found && !beyond && w0 + pos < R.n_groups) {
+        // chunk candidates before the end of the lane's window group (0 .. 64)
+        const uint32_t cpos = ek <= kb ? 0u : min(ek - kb, (uint32_t)kWave);
+        marks[lane] = 0u;
+        wave_sync();
+        if (cpos < (uint32_t)kWave) atomicMax(&marks[cpos], (uint32_t)lane + 1u);
+        wave_sync();
+        const uint32_t cnt = wave_max_scan(marks[lane], lane);
+        wave_sync();  // the marks are cleared again by the next use
+        const int32_t pp = bperm(e.x, (int)min(cnt, (uint32_t)kWave - 1u));
+        if (!found && cnt < (uint32_t)kWave && w0 + cnt < R.n_groups) {
             probe = pp;
             found = true;
         }
@@ -482,17 +519,21 @@ __device__ __forceinline__ int2 resolve_cand(const LaunchArgs& a, const Request&
 // A queued pair (global pair index gi of request r) in the deferred kernel:
 // from the request's pairs, or for a grouped launch its s id and the probe id
 // that the in-order kernel stored when it queued the pair.
+template <bool GR>
 __device__ __forceinline__ int2 queued_pair(const LaunchArgs& a, uint32_t gi, int r) {
     const Request& R = a.req[r];
     const uint32_t k = gi - a.pair_off[r];
-    if (a.grouped) return make_int2((int32_t)a.probes[gi], R.sids[k]);
+    if constexpr (GR) return make_int2((int32_t)a.probes[gi], R.sids[k]);
     return load_pair(R.cand, k);
 }
 
 // Records the probe id of a pair that the in-order kernel queues (grouped
 // launches only; the deferred kernel reads it back by global pair index).
+template <bool GR>
 __device__ __forceinline__ void note_queued(const LaunchArgs& a, bool queued, int2 pr, uint32_t gi) {
-    if (a.grouped && queued) a.probes[gi] = (uint32_t)pr.x;
+    if constexpr (GR) {
+        if (queued) a.probes[gi] = (uint32_t)pr.x;
+    }
 }
 
 // Set records of a lane's pair: four 16-byte loads (first and second word of
@@ -630,20 +671,135 @@ __device__ __forceinline__ bool merge_windows(const int32_t* __restrict__ tok_a,
     }
 }
 
+// One window step of the tile merge on the current 4-token windows va (of
+// the r side, tokens 4*(i/4).. of a set of na tokens) and vb (s side): the
+// side whose window ends lower is consumed whole, the other up to that end
+// (both on equal ends); equal tokens inside the unconsumed parts are matches.
+// Same rule as the steps of merge_windows.
+__device__ __forceinline__ void window_step(uint4 va, uint4 vb, uint32_t na, uint32_t nb, uint32_t& i,
+                                            uint32_t& j, uint32_t& o) {
+    const int32_t a[4] = {(int32_t)va.x, (int32_t)va.y, (int32_t)va.z, (int32_t)va.w};
+    const int32_t b[4] = {(int32_t)vb.x, (int32_t)vb.y, (int32_t)vb.z, (int32_t)vb.w};
+    const uint32_t ba = i & ~3u, bb = j & ~3u;
+    const uint32_t ea = min(na - ba, 4u), eb = min(nb - bb, 4u);
+    int32_t amax = a[0], bmax = b[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        amax = ((uint32_t)k < ea) ? a[k] : amax;
+        bmax = ((uint32_t)k < eb) ? b[k] : bmax;
+    }
+    uint32_t hits = 0, na_le = 0, nb_le = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool va_k = ba + k >= i && (uint32_t)k < ea;
+        const bool vb_k = bb + k >= j && (uint32_t)k < eb;
+        bool hit = false;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) hit |= (bb + t >= j && (uint32_t)t < eb) && a[k] == b[t];
+        hits += (va_k && hit) ? 1u : 0u;
+        na_le += (va_k && a[k] <= bmax) ? 1u : 0u;
+        nb_le += (vb_k && b[k] <= amax) ? 1u : 0u;
+    }
+    i = bmax < amax ? i + na_le : ba + ea;
+    j = amax < bmax ? j + nb_le : bb + eb;
+    o += hits;
+}
+
+// Entries of the wavefront's window ring (merge_ring): three 16-byte slots per
+// side and lane, slot s of side d of lane l at ring[(3 d + s) * kWave + l]
+// (so that a wavefront's accesses to one slot are consecutive).
+constexpr uint32_t kRingSlots = 6u * (uint32_t)kWave;
+
+// The merge of merge_windows (same steps, same step budget) with the loads
+// two steps ahead instead of one.  Each side's windows pass through a ring of
+// three LDS slots of the lane (window w in slot w % 3).  After every step the
+// lane requests the window two past its new current one of each side into
+// one of two register sets, which is written to the ring two steps later; a
+// step reads its two windows from the ring.  The current window of a side
+// moves by at most one per step, so every window a step can need has been
+// written, and no written window is still needed when its slot is reused; a
+// load has two steps to arrive before anything waits for it.  Windows past a
+// set's last one are loaded clamped (and never read).
+__device__ __forceinline__ bool merge_ring(const int32_t* __restrict__ tok_a, uint32_t sa, uint32_t na,
+                                           const int32_t* __restrict__ tok_b, uint32_t sb, uint32_t nb,
+                                           uint32_t alpha, uint32_t i, uint32_t j, uint32_t o, uint32_t budget,
+                                           bool* spilled, uint4* ring, int lane) {
+    const uint4* __restrict__ t4a = reinterpret_cast<const uint4*>(tok_a);
+    const uint4* __restrict__ t4b = reinterpret_cast<const uint4*>(tok_b);
+    const uint32_t qa = sa >> 2, qb = sb >> 2;              // first window of each set
+    const uint32_t la = (na - 1u) >> 2, lb = (nb - 1u) >> 2;  // last window index
+    uint4* ra = ring + lane;
+    uint4* rb = ring + 3 * kWave + lane;
+    auto slot = [](uint32_t w) { return (w % 3u) * (uint32_t)kWave; };
+    uint32_t wa = i >> 2, wb = j >> 2;
+    ra[slot(wa)] = t4a[qa + wa];
+    ra[slot(wa + 1u)] = t4a[qa + min(wa + 1u, la)];
+    rb[slot(wb)] = t4b[qb + wb];
+    rb[slot(wb + 1u)] = t4b[qb + min(wb + 1u, lb)];
+    // set x: the windows two past the first step's (written before step 3)
+    uint32_t xwa = wa + 2u, xwb = wb + 2u;
+    uint4 xa = t4a[qa + min(xwa, la)], xb = t4b[qb + min(xwb, lb)];
+    uint32_t ywa, ywb;
+    uint4 ya, yb;
+    uint32_t step = 0;
+    // one step on the ring: 0 undecided, 1 similar, 2 not similar, 3 cut off
+    auto merge_step = [&]() -> int {
+        ++step;
+        wave_sync();
+        const uint4 va = ra[slot(i >> 2)], vb = rb[slot(j >> 2)];
+        window_step(va, vb, na, nb, i, j, o);
+        if (o >= alpha) return 1;
+        if (o + min(na - i, nb - j) < alpha) return 2;
+        if (step >= budget) return 3;
+        return 0;
+    };
+    auto finish = [&](int st) {
+        if (st == 3) *spilled = true;
+        return st == 1;
+    };
+    int st = merge_step();
+    if (st != 0) return finish(st);
+    ywa = (i >> 2) + 2u;
+    ywb = (j >> 2) + 2u;
+    ya = t4a[qa + min(ywa, la)];
+    yb = t4b[qb + min(ywb, lb)];
+    st = merge_step();
+    if (st != 0) return finish(st);
+    for (;;) {
+        ra[slot(xwa)] = xa;
+        rb[slot(xwb)] = xb;
+        xwa = (i >> 2) + 2u;
+        xwb = (j >> 2) + 2u;
+        xa = t4a[qa + min(xwa, la)];
+        xb = t4b[qb + min(xwb, lb)];
+        st = merge_step();
+        if (st != 0) return finish(st);
+        ra[slot(ywa)] = ya;
+        rb[slot(ywb)] = yb;
+        ywa = (i >> 2) + 2u;
+        ywb = (j >> 2) + 2u;
+        ya = t4a[qa + min(ywa, la)];
+        yb = t4b[qb + min(ywb, lb)];
+        st = merge_step();
+        if (st != 0) return finish(st);
+    }
+}
+
 // Thread-per-pair verification of the lane's pair (chunk index kb + lane)
 // from its records: first the head tiles (head_tiles), which decide most
 // pairs; a pair still undecided continues from that merge state.  F == 0: it
 // continues in the same lane over 16-byte windows of the token array
-// (merge_windows).  F > 0: it is appended, with
+// (merge_windows, or with S merge_ring, its loads two steps ahead through
+// the wavefront's window ring).  F > 0: it is appended, with
 // its merge state, to the wavefront's list of hard pairs (hcnt entries), which
 // groups of F lanes finish (finish_hard), so that no lane walks the token
 // array alone while the rest of its wavefront waits.
-template <int F, bool C>
+template <int F, bool C, bool S, bool GR>
 __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Request& R, int r,
                                                    uint32_t kb, int2 pr, const LaneRecords& rec,
                                                    bool deferring, uint32_t* w_defer,
                                                    unsigned long long& dc, int2* w_out, uint32_t& ocnt,
-                                                   int2* w_hpr, uint32_t* w_hst, uint32_t& hcnt) {
+                                                   int2* w_hpr, uint32_t* w_hst, uint32_t& hcnt, uint4* ring) {
     const int lane = lane_id();
     const uint32_t k = kb + (uint32_t)lane;
     const bool valid = k < R.n;
@@ -660,9 +816,14 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
     bool act = run && !pass && o + min(na - i, nb - j) >= alpha;
     bool spill = false;
     if constexpr (F == 0) {
-        if (act)
-            pass = merge_windows(a.tok, rec.ra0.x, na, a.tok_s, rec.rb0.x, nb, alpha, i, j, o,
-                                 deferring ? a.spill_iters : 0xffffffffu, &spill);
+        const uint32_t budget = deferring ? a.spill_iters : 0xffffffffu;
+        if constexpr (S) {
+            if (act)
+                pass = merge_ring(a.tok, rec.ra0.x, na, a.tok_s, rec.rb0.x, nb, alpha, i, j, o, budget, &spill,
+                                  ring, lane);
+        } else {
+            if (act) pass = merge_windows(a.tok, rec.ra0.x, na, a.tok_s, rec.rb0.x, nb, alpha, i, j, o, budget, &spill);
+        }
     }
     // (after the merges: atomics count with loads, so none sits between the
     // record loads in flight and their use)
@@ -679,7 +840,7 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
     stage_pass(pass, pr, w_out, ocnt, R.cap == 0);
     if (deferring) {
         defer_pass(a, defer, cls, spill, a.pair_off[r] + k, w_defer, dc);
-        note_queued(a, defer || spill, pr, a.pair_off[r] + k);
+        note_queued<GR>(a, defer || spill, pr, a.pair_off[r] + k);
     }
 }
 
@@ -718,8 +879,10 @@ __device__ __forceinline__ void finish_hard(const LaunchArgs& a, const Request& 
 // of one request, grid-stride over all wavefronts of the grid.  G == 1: a
 // lane per pair.  G > 1: 64/G pairs at a time, G lanes each.  D: whether
 // the instance can defer length classes (an instance without that code needs
-// fewer registers).
-template <int G, int F, bool D, bool C>
+// fewer registers).  S (G == 1, F == 0): merges through the window ring
+// (merge_ring).  GR: a grouped launch (every request's candidates read in
+// place from its groups and s ids).
+template <int G, int F, bool D, bool C, bool S, bool GR>
 __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     constexpr int GPW = kWave / G;
     constexpr uint32_t kWaves = (uint32_t)(kBlock / kWave);
@@ -749,6 +912,12 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     __shared__ uint32_t s_hst[F > 0 ? kWaves * kWave : 1];
     int2* w_hpr = s_hpr + (F > 0 ? wl * kWave : 0u);
     uint32_t* w_hst = s_hst + (F > 0 ? wl * kWave : 0u);
+    // group search scratch of grouped launches (resolve_cand)
+    __shared__ uint32_t s_marks[GR ? kWaves * kWave : 1];
+    uint32_t* w_marks = s_marks + (GR ? wl * kWave : 0u);
+    // the window rings of merge_ring
+    __shared__ uint4 s_ring[S ? kWaves * kRingSlots : 1];
+    uint4* w_ring = s_ring + (S ? wl * kRingSlots : 0u);
     uint32_t ocnt = 0, hcnt = 0;
     unsigned long long dc = 0ull;  // deferred queue fill counts (dcount)
     const uint32_t n_chunks = a.tile_off[a.n_req];
@@ -763,15 +932,28 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     LaneRecords rec0{}, rec1{};
     int r_cur = 0, r1 = 0;
     uint32_t kb_cur = 0, kb1 = 0;
+    // grouped: first groups of this wavefront's chunks with ordinals
+    // vbase .. vbase + 63, one per lane
+    uint32_t vbase = 0, vg = 0;
+    auto group_of_ord = [&](uint32_t q) -> uint32_t {
+        if constexpr (!GR) return 0u;
+        if (q - vbase >= (uint32_t)kWave) {
+            vbase = q;
+            vg = load_chunk_groups<GR>(a, first, nw, n_chunks, vbase, lane);
+        }
+        return (uint32_t)__builtin_amdgcn_readlane((int)vg, (int)(q - vbase));
+    };
     if (first < n_chunks) {
         chunk_origin(a, first, &r_cur, &kb_cur);
         if constexpr (G == 1) {
             // loads beyond the last chunk are clamped to it (results unused),
             // so every iteration issues the same loads in the same order
-            p0 = resolve_cand(a, a.req[r_cur], kb_cur, lane, issue_cand(a, a.req[r_cur], kb_cur, lane));
+            vg = load_chunk_groups<GR>(a, first, nw, n_chunks, 0u, lane);
+            p0 = resolve_cand<GR>(a, a.req[r_cur], kb_cur, lane,
+                                  issue_cand<GR>(a, a.req[r_cur], kb_cur, lane, group_of_ord(0u)), w_marks);
             issue_records(a, p0, rec0);
             chunk_origin(a, min(first + nw, n_chunks - 1), &r1, &kb1);
-            c1 = issue_cand(a, a.req[r1], kb1, lane);
+            c1 = issue_cand<GR>(a, a.req[r1], kb1, lane, group_of_ord(1u));
         }
     }
     const uint32_t share = first < n_chunks ? (n_chunks - 1u - first) / nw + 1u : 1u;
@@ -784,14 +966,14 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
         const uint32_t Tn = T + nw;
         const Request& R = a.req[r];
         if constexpr (G == 1) {
-            const int2 p1 = resolve_cand(a, a.req[r1], kb1, lane, c1);
+            const int2 p1 = resolve_cand<GR>(a, a.req[r1], kb1, lane, c1, w_marks);
             issue_records(a, p1, rec1);
             int r2 = 0;
             uint32_t kb2 = 0;
             chunk_origin(a, min(Tn + nw, n_chunks - 1), &r2, &kb2);
-            const CandLoad c2 = issue_cand(a, a.req[r2], kb2, lane);
-            chunk_thread_pairs<F, C>(a, R, r, kb, p0, rec0, deferring, w_defer, dc, w_out, ocnt,
-                                  w_hpr, w_hst, hcnt);
+            const CandLoad c2 = issue_cand<GR>(a, a.req[r2], kb2, lane, group_of_ord(done + 1u));
+            chunk_thread_pairs<F, C, S, GR>(a, R, r, kb, p0, rec0, deferring, w_defer, dc, w_out, ocnt,
+                                            w_hpr, w_hst, hcnt, w_ring);
             if constexpr (F > 0) {
                 if (hcnt > 0) {
                     finish_hard<F, C>(a, R, hcnt, w_hpr, w_hst, w_out, ocnt);
@@ -815,10 +997,10 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
             // a grouped chunk's pairs are found once, lane k holding pair
             // kb + k, and handed to the groups by permutes
             int2 cp = make_int2(0, 0);
-            if (a.grouped) cp = resolve_cand(a, R, kb, lane, issue_cand(a, R, kb, lane));
+            if constexpr (GR) cp = resolve_cand<GR>(a, R, kb, lane, issue_cand<GR>(a, R, kb, lane, a.chunk_g[T]), w_marks);
             auto pair_at = [&](int sub) -> int2 {
                 const int src = min(sub, G - 1) * GPW + grp;
-                if (a.grouped) return make_int2(bperm(cp.x, src), bperm(cp.y, src));
+                if constexpr (GR) return make_int2(bperm(cp.x, src), bperm(cp.y, src));
                 const uint32_t k = kb + (uint32_t)src;
                 return load_pair(R.cand, k < R.n ? k : R.n - 1);
             };
@@ -861,7 +1043,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
                 stage_pass(pass && g == 0, pq, w_out, ocnt, R.cap == 0);
                 if (deferring) {
                     defer_pass(a, defer && g == 0, cls, false, a.pair_off[r] + k, w_defer, dc);
-                    note_queued(a, defer && g == 0, pq, a.pair_off[r] + k);
+                    note_queued<GR>(a, defer && g == 0, pq, a.pair_off[r] + k);
                 }
                 pq0 = pq1;
                 pq1 = pq2;
@@ -900,256 +1082,6 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// Staged thread-per-pair kernel (long sets).  One lane per pair as in the
-// in-order kernel with G == 1, but a lane never loads its own tokens: each
-// side of its pair has a 64-byte block (16 tokens, aligned to 16 tokens from
-// the set's start) in the wavefront's LDS, and the blocks are filled by the
-// whole wavefront together, four lanes per block, so that one load
-// instruction fetches 16 whole blocks instead of 64 scattered 16-byte
-// windows.  A chunk of 64 pairs then alternates between
-//   * a refill round: every undecided lane whose merge position on a side
-//     has left the block it holds posts a request for the block holding that
-//     position (a list in LDS, ranked by ballot), and the wavefront serves
-//     the list with coalesced loads;
-//   * a merge phase: every undecided lane whose two current windows lie in
-//     its blocks takes window steps from LDS (the step of merge_windows)
-//     until it is decided or a window leaves its block.
-// With a step budget (spill_iters), pairs still undecided after that many
-// refill rounds are queued whole for the deferred kernel.
-constexpr uint32_t kBlkTok = 16;                    // tokens per staged block
-constexpr uint32_t kLaneBuf = 80;                   // LDS bytes per lane and side: a block plus
-                                                    // 16 bytes, so that lanes 1..15 apart start
-                                                    // on distinct banks
-constexpr uint32_t kStagedTok = 2u * kWave * kLaneBuf;  // both sides' blocks of one wavefront
-constexpr uint32_t kStagedReq = 2u * kWave;         // block requests per round (two per lane)
-constexpr uint32_t kStagedOut = 2u * kWave;         // staged output pairs per wavefront
-constexpr uint32_t kStagedFixed = kStagedTok + kStagedReq * 8u + kStagedOut * 8u;
-
-// One window step of the tile merge on the current 4-token windows va (of
-// the r side, tokens 4*(i/4).. of a set of na tokens) and vb (s side): the
-// side whose window ends lower is consumed whole, the other up to that end
-// (both on equal ends); equal tokens inside the unconsumed parts are matches.
-// Same rule as the steps of merge_windows.
-__device__ __forceinline__ void window_step(uint4 va, uint4 vb, uint32_t na, uint32_t nb, uint32_t& i,
-                                            uint32_t& j, uint32_t& o) {
-    const int32_t a[4] = {(int32_t)va.x, (int32_t)va.y, (int32_t)va.z, (int32_t)va.w};
-    const int32_t b[4] = {(int32_t)vb.x, (int32_t)vb.y, (int32_t)vb.z, (int32_t)vb.w};
-    const uint32_t ba = i & ~3u, bb = j & ~3u;
-    const uint32_t ea = min(na - ba, 4u), eb = min(nb - bb, 4u);
-    int32_t amax = a[0], bmax = b[0];
-#pragma unroll
-    for (int k = 1; k < 4; ++k) {
-        amax = ((uint32_t)k < ea) ? a[k] : amax;
-        bmax = ((uint32_t)k < eb) ? b[k] : bmax;
-    }
-    uint32_t hits = 0, na_le = 0, nb_le = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const bool va_k = ba + k >= i && (uint32_t)k < ea;
-        const bool vb_k = bb + k >= j && (uint32_t)k < eb;
-        bool hit = false;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) hit |= (bb + t >= j && (uint32_t)t < eb) && a[k] == b[t];
-        hits += (va_k && hit) ? 1u : 0u;
-        na_le += (va_k && a[k] <= bmax) ? 1u : 0u;
-        nb_le += (vb_k && b[k] <= amax) ? 1u : 0u;
-    }
-    i = bmax < amax ? i + na_le : ba + ea;
-    j = amax < bmax ? j + nb_le : bb + eb;
-    o += hits;
-}
-
-// Serves the wavefront's r block requests in w_req: request k = {first
-// token of the block in its side's token array, LDS byte offset of the
-// destination | side << 16 | 16-byte parts to copy << 17}.  Part p of the
-// list (request p / 4, quarter p % 4) is copied by lane p % 64, four
-// lanes per block, up to four parts per lane in flight.  Parts past the
-// end of a set's (16-byte padded) tokens are not read.
-__device__ __forceinline__ void serve_blocks(const LaunchArgs& a, const uint2* w_req, uint32_t r,
-                                             unsigned char* w_tok) {
-    wave_sync();
-    const int lane = lane_id();
-    const uint4* __restrict__ t4a = reinterpret_cast<const uint4*>(a.tok);
-    const uint4* __restrict__ t4b = reinterpret_cast<const uint4*>(a.tok_s);
-    const uint32_t parts = 4u * r;
-    for (uint32_t p0 = 0; p0 < parts; p0 += 4u * kWave) {
-        uint4 v[4];
-        uint32_t dst[4];
-        bool ok[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t p = p0 + (uint32_t)u * kWave + (uint32_t)lane;
-            ok[u] = false;
-            dst[u] = 0;
-            v[u] = make_uint4(0u, 0u, 0u, 0u);
-            if (p < parts) {
-                const uint2 e = w_req[p >> 2];
-                const uint32_t q = p & 3u;
-                ok[u] = q < ((e.y >> 17) & 7u);
-                dst[u] = (e.y & 0xffffu) + q * 16u;
-                if (ok[u]) v[u] = ((e.y >> 16) & 1u) ? t4b[(e.x >> 2) + q] : t4a[(e.x >> 2) + q];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (ok[u]) *reinterpret_cast<uint4*>(w_tok + dst[u]) = v[u];
-    }
-    wave_sync();
-}
-
-template <bool D, bool C>
-__global__ __launch_bounds__(kBlock) void k_verify_staged(LaunchArgs a) {
-    constexpr uint32_t kWaves = (uint32_t)(kBlock / kWave);
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const uint32_t wl = threadIdx.x >> 6;
-    const int lane = lane_id();
-    // dynamic LDS, per wavefront: the token blocks (r side of lanes 0..63,
-    // then the s side), the request list, the staged output pairs, then
-    // defer_cap entries per deferred queue
-    extern __shared__ uint4 s_dyn[];
-    const bool deferring = D && (a.defer_from < kClasses || spilling(a));
-    const uint32_t wave_bytes =
-        kStagedFixed + (deferring ? (uint32_t)wave_queues(a.defer_from, spilling(a)) * a.defer_cap * 4u : 0u);
-    unsigned char* w_tok = reinterpret_cast<unsigned char*>(s_dyn) + wl * wave_bytes;
-    uint2* w_req = reinterpret_cast<uint2*>(w_tok + kStagedTok);
-    int2* w_out = reinterpret_cast<int2*>(w_req + kStagedReq);
-    uint32_t* w_defer = reinterpret_cast<uint32_t*>(w_out + kStagedOut);
-    const uint32_t dst_a = (uint32_t)lane * kLaneBuf;                   // this lane's r block
-    const uint32_t dst_b = (uint32_t)(kWave + lane) * kLaneBuf;         // and its s block
-    uint32_t ocnt = 0;
-    unsigned long long dc = 0ull;
-    const uint32_t n_chunks = a.tile_off[a.n_req];
-    const uint32_t nw = gridDim.x * kWaves;
-    const uint32_t first = blockIdx.x * kWaves + (uint32_t)w;
-    // pipeline as in the in-order kernel: while chunk T is verified, the
-    // records of chunk T + nw and the pairs of chunk T + 2 nw are in flight
-    int2 p0 = make_int2(0, 0);
-    CandLoad c1{};
-    uint4 ra0 = make_uint4(0u, 0u, 0u, 0u), rb0 = ra0, ra1 = ra0, rb1 = ra0;
-    int r_cur = 0, r1 = 0;
-    uint32_t kb_cur = 0, kb1 = 0;
-    auto records = [&](int2 pr, uint4& ra, uint4& rb) {
-        const bool ok = ids_ok(pr, a);
-        ra = a.heads[2 * (ok ? pr.x : 0)];
-        rb = a.heads_s[2 * (ok ? pr.y : 0)];
-    };
-    if (first < n_chunks) {
-        chunk_origin(a, first, &r_cur, &kb_cur);
-        p0 = resolve_cand(a, a.req[r_cur], kb_cur, lane, issue_cand(a, a.req[r_cur], kb_cur, lane));
-        records(p0, ra0, rb0);
-        chunk_origin(a, min(first + nw, n_chunks - 1), &r1, &kb1);
-        c1 = issue_cand(a, a.req[r1], kb1, lane);
-    }
-    const uint32_t share = first < n_chunks ? (n_chunks - 1u - first) / nw + 1u : 1u;
-    uint32_t done = 0, level = 3;
-    __builtin_amdgcn_s_setprio(3);
-    for (uint32_t T = first; T < n_chunks; T += nw) {
-        progress_priority(done++, share, level);
-        const int r = r_cur;
-        const uint32_t kb = kb_cur;
-        const uint32_t Tn = T + nw;
-        const Request& R = a.req[r];
-        const int2 p1 = resolve_cand(a, a.req[r1], kb1, lane, c1);
-        records(p1, ra1, rb1);
-        int r2 = 0;
-        uint32_t kb2 = 0;
-        chunk_origin(a, min(Tn + nw, n_chunks - 1), &r2, &kb2);
-        const CandLoad c2 = issue_cand(a, a.req[r2], kb2, lane);
-
-        const int2 pr = p0;
-        const uint32_t k = kb + (uint32_t)lane;
-        const bool valid = k < R.n;
-        const bool ok = valid && ids_ok(pr, a);
-        const uint32_t sa = ra0.x, na = ra0.y, sb = rb0.x, nb = rb0.y;
-        const int cls = deferring ? class_of(na + nb, a) : 0;
-        const bool defer = ok && deferring && cls >= a.defer_from;
-        const bool run = ok && !defer;
-        const uint32_t alpha = run ? required_overlap<C>(na, nb, R) : 0u;
-        bool pass = run && alpha == 0u;
-        bool act = run && !pass && min(na, nb) >= alpha;
-        bool spill = false;
-        uint32_t i = 0, j = 0, o = 0;
-        uint32_t blk_a = 0xffffffffu, blk_b = 0xffffffffu;  // blocks held (none yet)
-        for (uint32_t round = 0;; ++round) {
-            if (ballot(act) == 0ull) break;
-            if (deferring && round >= a.spill_iters) {
-                spill = act;
-                act = false;
-                break;
-            }
-            // requests for the blocks holding positions i and j
-            const bool need_a = act && (i / kBlkTok) != blk_a;
-            const bool need_b = act && (j / kBlkTok) != blk_b;
-            const unsigned long long ma = ballot(need_a), mb = ballot(need_b);
-            const uint32_t n_a = (uint32_t)__popcll(ma);
-            if (need_a) {
-                const uint32_t t0 = i & ~(kBlkTok - 1u);
-                const uint32_t np = min(4u, (na - t0 + 3u) >> 2);
-                w_req[mbcnt(ma)] = make_uint2(sa + t0, dst_a | (np << 17));
-                blk_a = i / kBlkTok;
-            }
-            if (need_b) {
-                const uint32_t t0 = j & ~(kBlkTok - 1u);
-                const uint32_t np = min(4u, (nb - t0 + 3u) >> 2);
-                w_req[n_a + mbcnt(mb)] = make_uint2(sb + t0, dst_b | (1u << 16) | (np << 17));
-                blk_b = j / kBlkTok;
-            }
-            serve_blocks(a, w_req, n_a + (uint32_t)__popcll(mb), w_tok);
-            // merge phase
-            for (;;) {
-                const bool can = act && (i / kBlkTok) == blk_a && (j / kBlkTok) == blk_b;
-                if (ballot(can) == 0ull) break;
-                if (can) {
-                    const uint4 va = *reinterpret_cast<const uint4*>(w_tok + dst_a + ((i >> 2) & 3u) * 16u);
-                    const uint4 vb = *reinterpret_cast<const uint4*>(w_tok + dst_b + ((j >> 2) & 3u) * 16u);
-                    window_step(va, vb, na, nb, i, j, o);
-                    if (o >= alpha) {
-                        pass = true;
-                        act = false;
-                    } else if (o + min(na - i, nb - j) < alpha) {
-                        act = false;
-                    }
-                }
-            }
-        }
-        if (ballot(valid && !ok) != 0ull && lane == 0) atomicOr(&a.ctr->err[r], 1u);
-        stage_pass(pass, pr, w_out, ocnt, R.cap == 0);
-        if (deferring) {
-            defer_pass(a, defer, cls, spill, a.pair_off[r] + k, w_defer, dc);
-            note_queued(a, defer || spill, pr, a.pair_off[r] + k);
-        }
-        // rotate the pipeline
-        p0 = p1;
-        c1 = c2;
-        ra0 = ra1;
-        rb0 = rb1;
-        r_cur = r1;
-        kb_cur = kb1;
-        r1 = r2;
-        kb1 = kb2;
-        const bool same_next = Tn < n_chunks && r_cur == r;
-        if (ocnt > 0 && ((R.cap != 0 && ocnt > kStagedOut - kWave) || !same_next)) {
-            wave_flush_out(a, r, ocnt, w_out);
-            ocnt = 0;
-        }
-        if (deferring) {
-            for (int q = a.defer_from; q < queue_end(a); ++q) {
-                const uint32_t c = dcount(dc, q);
-                if (c > a.defer_cap - kWave) {
-                    wave_flush_deferred(a, q, c, w_defer);
-                    dc &= ~(0xffull << (8 * q));
-                }
-            }
-        }
-    }
-    if (deferring) {
-        for (int q = a.defer_from; q < queue_end(a); ++q) {
-            if (dcount(dc, q) > 0) wave_flush_deferred(a, q, dcount(dc, q), w_defer);
-        }
-    }
-}
-
 // Publishes each request's count (-1 after an id error) and returns the
 // counters to zero for the next launch.  One workgroup, after the verify
 // kernels of the launch (the kernel boundary makes their atomics visible).
@@ -1172,7 +1104,7 @@ __global__ void k_finalize(LaunchArgs a) {
 // Deferred classes.  Workgroup-mapped classes (lanes == kBlock) are taken one
 // pair per workgroup by work stealing; the others are split statically over
 // all wavefronts of the grid.
-template <int G, bool C>
+template <int G, bool C, bool GR>
 __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
     constexpr int GPW = kWave / G;
     const int lane = lane_id();
@@ -1192,7 +1124,7 @@ __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
     };
     auto pair_of = [&](uint32_t gi, int* r) -> int2 {
         *r = request_of_pair(gi, a);
-        return queued_pair(a, gi, *r);
+        return queued_pair<GR>(a, gi, *r);
     };
     uint32_t e3;
     int2 p0, p1, p2;
@@ -1254,7 +1186,7 @@ __device__ __forceinline__ int lanes_of_queue(const LaunchArgs& a, int q) {
 
 // Queues are drained from the spill queue (the longest merges) down to the
 // first deferred class.
-template <bool C>
+template <bool C, bool GR>
 __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
     __shared__ int32_t sb[kBlock];
     __shared__ uint32_t red[16];
@@ -1276,7 +1208,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
             const uint32_t gi = queue[t];
             const int r = request_of_pair(gi, a);
             const Request& R = a.req[r];
-            const int2 pr = queued_pair(a, gi, r);
+            const int2 pr = queued_pair<GR>(a, gi, r);
             const uint2 dr = set_desc(a, pr.x);
             const uint2 ds = set_desc_s(a, pr.y);
             const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok_s + ds.x, ds.y,
@@ -1289,12 +1221,12 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
         const uint32_t cnt = load_relaxed(&a.ctr->tail[q]);
         if (cnt == 0) continue;
         switch (lanes_of_queue(a, q)) {
-            case 1: drain_static<1, C>(a, q, cnt); break;
-            case 4: drain_static<4, C>(a, q, cnt); break;
-            case 8: drain_static<8, C>(a, q, cnt); break;
-            case 16: drain_static<16, C>(a, q, cnt); break;
-            case 32: drain_static<32, C>(a, q, cnt); break;
-            case 64: drain_static<64, C>(a, q, cnt); break;
+            case 1: drain_static<1, C, GR>(a, q, cnt); break;
+            case 4: drain_static<4, C, GR>(a, q, cnt); break;
+            case 8: drain_static<8, C, GR>(a, q, cnt); break;
+            case 16: drain_static<16, C, GR>(a, q, cnt); break;
+            case 32: drain_static<32, C, GR>(a, q, cnt); break;
+            case 64: drain_static<64, C, GR>(a, q, cnt); break;
             default: break;
         }
     }
@@ -1369,46 +1301,49 @@ bool lanes_supported(int lanes) {
 }
 
 bool inline_supported(int lanes, int hard_lanes, bool staged) {
-    return kernel_verify_tiles(lanes, hard_lanes, staged, false, false) != nullptr;
+    return kernel_verify_tiles(lanes, hard_lanes, staged, false, false, false) != nullptr;
 }
 
-template <bool D, bool C>
-const void* verify_tiles_instance(int lanes, int hard_lanes) {
+template <bool D, bool C, bool GR>
+const void* verify_tiles_instance(int lanes, int hard_lanes, bool staged) {
     if (lanes == 1) {
+        if (staged) return hard_lanes == 0 ? (const void*)&k_verify_tiles<1, 0, D, C, true, GR> : nullptr;
         switch (hard_lanes) {
-            case 0: return (const void*)&k_verify_tiles<1, 0, D, C>;
-            case 8: return (const void*)&k_verify_tiles<1, 8, D, C>;
-            case 16: return (const void*)&k_verify_tiles<1, 16, D, C>;
+            case 0: return (const void*)&k_verify_tiles<1, 0, D, C, false, GR>;
+            case 8: return (const void*)&k_verify_tiles<1, 8, D, C, false, GR>;
+            case 16: return (const void*)&k_verify_tiles<1, 16, D, C, false, GR>;
             default: return nullptr;
         }
     }
-    if (hard_lanes != 0) return nullptr;
+    if (hard_lanes != 0 || staged) return nullptr;
     switch (lanes) {
-        case 4: return (const void*)&k_verify_tiles<4, 0, D, C>;
-        case 8: return (const void*)&k_verify_tiles<8, 0, D, C>;
-        case 16: return (const void*)&k_verify_tiles<16, 0, D, C>;
-        case 32: return (const void*)&k_verify_tiles<32, 0, D, C>;
-        case 64: return (const void*)&k_verify_tiles<64, 0, D, C>;
+        case 4: return (const void*)&k_verify_tiles<4, 0, D, C, false, GR>;
+        case 8: return (const void*)&k_verify_tiles<8, 0, D, C, false, GR>;
+        case 16: return (const void*)&k_verify_tiles<16, 0, D, C, false, GR>;
+        case 32: return (const void*)&k_verify_tiles<32, 0, D, C, false, GR>;
+        case 64: return (const void*)&k_verify_tiles<64, 0, D, C, false, GR>;
         default: return nullptr;
     }
 }
 
-const void* kernel_verify_tiles(int lanes, int hard_lanes, bool staged, bool deferring, bool cosine) {
-    if (staged) {
-        if (lanes != 1 || hard_lanes != 0) return nullptr;
-        if (cosine)
-            return deferring ? (const void*)&k_verify_staged<true, true> : (const void*)&k_verify_staged<false, true>;
-        return deferring ? (const void*)&k_verify_staged<true, false> : (const void*)&k_verify_staged<false, false>;
-    }
+template <bool GR>
+const void* verify_tiles_by_flags(int lanes, int hard_lanes, bool staged, bool deferring, bool cosine) {
     if (cosine)
-        return deferring ? verify_tiles_instance<true, true>(lanes, hard_lanes)
-                         : verify_tiles_instance<false, true>(lanes, hard_lanes);
-    return deferring ? verify_tiles_instance<true, false>(lanes, hard_lanes)
-                     : verify_tiles_instance<false, false>(lanes, hard_lanes);
+        return deferring ? verify_tiles_instance<true, true, GR>(lanes, hard_lanes, staged)
+                         : verify_tiles_instance<false, true, GR>(lanes, hard_lanes, staged);
+    return deferring ? verify_tiles_instance<true, false, GR>(lanes, hard_lanes, staged)
+                     : verify_tiles_instance<false, false, GR>(lanes, hard_lanes, staged);
 }
 
-const void* kernel_verify_deferred(bool cosine) {
-    return cosine ? (const void*)&k_verify_deferred<true> : (const void*)&k_verify_deferred<false>;
+const void* kernel_verify_tiles(int lanes, int hard_lanes, bool staged, bool deferring, bool cosine, bool grouped) {
+    return grouped ? verify_tiles_by_flags<true>(lanes, hard_lanes, staged, deferring, cosine)
+                   : verify_tiles_by_flags<false>(lanes, hard_lanes, staged, deferring, cosine);
+}
+
+const void* kernel_verify_deferred(bool cosine, bool grouped) {
+    if (grouped)
+        return cosine ? (const void*)&k_verify_deferred<true, true> : (const void*)&k_verify_deferred<false, true>;
+    return cosine ? (const void*)&k_verify_deferred<true, false> : (const void*)&k_verify_deferred<false, false>;
 }
 
 hipError_t launch_group_chunks(const LaunchArgs& a, hipStream_t st) {
@@ -1430,17 +1365,16 @@ hipError_t launch_build_heads(const int64_t* d_offsets, const uint32_t* d_start,
 }
 
 size_t tiles_lds_bytes(const LaunchArgs& a) {
-    // per wavefront: kWaveStage staged output pairs (the staged kernel: its
-    // token blocks, block requests and kStagedOut output pairs), then
-    // defer_cap entries per queue (a multiple of 16 bytes)
-    const size_t stage = a.staged ? (size_t)kStagedFixed : (size_t)kWaveStage * sizeof(int2);
+    // per wavefront: kWaveStage staged output pairs, then defer_cap entries
+    // per queue (a multiple of 16 bytes)
+    const size_t stage = (size_t)kWaveStage * sizeof(int2);
     const size_t defer = (size_t)wave_queues(a.defer_from, spilling(a)) * a.defer_cap * 4u;
     return (size_t)(kBlock / kWave) * (stage + defer);
 }
 
 hipError_t launch_verify_tiles(const LaunchArgs& a, int grid, hipStream_t st) {
     const void* f = kernel_verify_tiles(a.inline_lanes, a.hard_lanes, a.staged != 0,
-                                        a.defer_from < kClasses || spilling(a), a.cosine != 0);
+                                        a.defer_from < kClasses || spilling(a), a.cosine != 0, a.grouped != 0);
     if (!f) return hipErrorInvalidValue;
     LaunchArgs args = a;
     void* params[] = {&args};
@@ -1462,7 +1396,7 @@ hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st) {
 const void* kernel_finalize() { return (const void*)&k_finalize; }
 
 hipError_t launch_verify_deferred(const LaunchArgs& a, int grid, hipStream_t st) {
-    const void* f = kernel_verify_deferred(a.cosine != 0);
+    const void* f = kernel_verify_deferred(a.cosine != 0, a.grouped != 0);
     LaunchArgs args = a;
     void* params[] = {&args};
     return hipLaunchKernel(f, dim3((unsigned)grid), dim3(kBlock), params, 0, st);

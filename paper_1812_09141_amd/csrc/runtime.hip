@@ -60,6 +60,7 @@ constexpr int64_t kRingPiece = (int64_t)1 << 20;
 constexpr int64_t kMaxPieces = 64;
 // a stream slot may always hold this many pairs, whatever the budget leaves
 constexpr int64_t kSlotFloor = 1024;
+constexpr int64_t kSlotResults = (int64_t)1 << 16;  // pinned result pairs per slot at start
 
 // Threshold range of a similarity function (SSJ_SIM_*): 0 < t_den < 2^31,
 // 0 <= t_num < 2^31, and t <= 1 for the normalised functions.
@@ -195,8 +196,9 @@ struct ssj_ctx {
     int n_cu = 0;
     // in-order kernel workgroups per CU, limited by registers and by its
     // dynamic LDS: [4 * mapping index + 2 * cosine + deferring][deferred classes]
-    int occ_tiles[4 * 9][ssj::kQueues + 1] = {};  // [mapping][LDS queues per wavefront]
-    int occ_deferred2[2] = {0};  // [cosine]
+    // [8 * mapping + 4 * grouped + 2 * cosine + deferring][LDS queues per wavefront]
+    int occ_tiles[8 * 9][ssj::kQueues + 1] = {};
+    int occ_deferred2[4] = {0};  // [2 * grouped + cosine]
     ssj_plan plan{};
     std::mutex mu;  // default scratch, host staging, collections, plan, graphs
     // also held while the plan changes (after mu), so that the stream engine,
@@ -285,7 +287,8 @@ int inline_index(int lanes, int hard_lanes, int staged) {
     }
 }
 
-constexpr int kMappings = 9;  // in-order mappings: by lanes, hard lanes and staging
+// in-order mappings: by lanes, hard lanes and staging (the window ring)
+constexpr int kMappings = 9;
 const int kInlineLanes[kMappings] = {1, 4, 8, 16, 32, 64, 1, 1, 1};
 const int kInlineHard[kMappings] = {0, 0, 0, 0, 0, 0, 8, 16, 0};
 const int kInlineStaged[kMappings] = {0, 0, 0, 0, 0, 0, 0, 0, 1};
@@ -386,24 +389,24 @@ int vgpr_limited_blocks(const void* f) {
 
 // Workgroups of the in-order kernel that the device holds at once per
 // compute unit.
-int tiles_occupancy(const ssj_ctx* ctx, const ssj_plan& plan, bool cosine) {
+int tiles_occupancy(const ssj_ctx* ctx, const ssj_plan& plan, bool cosine, bool grouped = false) {
     const bool deferring = plan_two_kernels(plan);
     const int nq = ssj::wave_queues(plan.defer_from, plan.spill_iters > 0);
-    return std::max(1, ctx->occ_tiles[4 * inline_index(plan.inline_lanes, plan.hard_lanes, plan.staged) + (cosine ? 2 : 0) +
-                                      (deferring ? 1 : 0)][nq]);
+    return std::max(1, ctx->occ_tiles[8 * inline_index(plan.inline_lanes, plan.hard_lanes, plan.staged) +
+                                      (grouped ? 4 : 0) + (cosine ? 2 : 0) + (deferring ? 1 : 0)][nq]);
 }
 
 // Workgroups of the in-order kernel: one per kBlock / kWave chunks, at most
 // plan.wg_per_cu per compute unit, or what the device holds at once.
-int grid_tiles(const ssj_ctx* ctx, const ssj_plan& plan, bool cosine, int64_t n_chunks) {
-    const int per_cu = plan.wg_per_cu > 0 ? plan.wg_per_cu : tiles_occupancy(ctx, plan, cosine);
+int grid_tiles(const ssj_ctx* ctx, const ssj_plan& plan, bool cosine, bool grouped, int64_t n_chunks) {
+    const int per_cu = plan.wg_per_cu > 0 ? plan.wg_per_cu : tiles_occupancy(ctx, plan, cosine, grouped);
     const int64_t cap = (int64_t)ctx->n_cu * per_cu;
     const int64_t per_wg = ssj::kBlock / ssj::kWave;
     return (int)std::max<int64_t>(1, std::min<int64_t>((n_chunks + per_wg - 1) / per_wg, cap));
 }
 
-int grid_deferred(const ssj_ctx* ctx, bool cosine) {
-    return ctx->n_cu * std::max(1, ctx->occ_deferred2[cosine ? 1 : 0]);
+int grid_deferred(const ssj_ctx* ctx, bool cosine, bool grouped) {
+    return ctx->n_cu * std::max(1, ctx->occ_deferred2[(grouped ? 2 : 0) + (cosine ? 1 : 0)]);
 }
 
 int launch_graph(ssj_ctx* ctx, const ssj::LaunchArgs& a, int g1, int g2, bool two,
@@ -416,9 +419,10 @@ int launch_graph(ssj_ctx* ctx, const ssj::LaunchArgs& a, int g1, int g2, bool tw
     if (it == ctx->graphs.end()) {
         GraphEntry ge;
         HIP_OR_FAIL(ctx, hipGraphCreate(&ge.graph, 0));
+        // (grouped launches do not use graphs)
         const void* funcs[3] = {ssj::kernel_verify_tiles(a.inline_lanes, a.hard_lanes, a.staged != 0, two,
-                                                         a.cosine != 0),
-                                ssj::kernel_verify_deferred(a.cosine != 0), ssj::kernel_finalize()};
+                                                         a.cosine != 0, false),
+                                ssj::kernel_verify_deferred(a.cosine != 0, false), ssj::kernel_finalize()};
         const int grids[3] = {g1, g2, 1};
         const int blocks[3] = {ssj::kBlock, ssj::kBlock, ssj::kWave};
         for (int k = 0; k < 3; ++k) {
@@ -515,6 +519,7 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     }
     if (a.grouped) {
         HIP_OR_FAIL(ctx, grow(sc.d_chunk_g, sc.chunk_cap, (size_t)std::max<uint64_t>(tiles, 1)));
+        a.chunk_g = sc.d_chunk_g;
         for (int r = 0; r < n_req; ++r) a.req[r].chunk_g = sc.d_chunk_g + a.tile_off[r];
         if (two) {
             HIP_OR_FAIL(ctx, grow(sc.d_probes, sc.probes_cap, (size_t)std::max<uint64_t>(pairs, 1)));
@@ -523,8 +528,8 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     }
     a.queues = sc.d_queues;
     a.qcap = (uint32_t)(sc.q_cap / ssj::kQueues);
-    const int g1 = grid_tiles(ctx, plan, a.cosine != 0, (int64_t)tiles);
-    const int g2 = grid_deferred(ctx, a.cosine != 0);
+    const int g1 = grid_tiles(ctx, plan, a.cosine != 0, a.grouped != 0, (int64_t)tiles);
+    const int g2 = grid_deferred(ctx, a.cosine != 0, a.grouped != 0);
 
     std::array<hipEvent_t, 4> ev{nullptr, nullptr, nullptr, nullptr};
     const int period = ctx->timing_period.load();
@@ -649,6 +654,12 @@ struct StreamEngine {
     std::thread worker;
     // pinned staging pool by size class (powers of two)
     std::map<size_t, std::vector<void*>> pool;
+    // pinned result buffers outgrown by their slot: freed at stop (a
+    // hipHostFree would wait for the whole device inside the engine loop)
+    std::vector<void*> retired_host;
+    // statistics (ssj_stream_stats)
+    uint64_t slot_grows = 0, result_grows = 0;
+    double slot_grow_ms = 0.0, result_grow_ms = 0.0, longest_pass_ms = 0.0;
 };
 
 namespace {
@@ -703,16 +714,43 @@ void fail_slot(StreamEngine* E, StreamSlot& s) {
 // and enqueues their copies, one launch, and the count read-back.
 // Grows slot s's device buffers to hold at least n pairs (the slot is idle;
 // grow() synchronises the device before it releases an old buffer).
+// A slot buffer of at least need elements from the device's stream-ordered
+// pool, on the slot's stream.  The slot is idle when it grows, so its old
+// buffer goes back to the pool in stream order; neither step waits for the
+// other slots' work (hipFree and hipDeviceSynchronize would), and once the
+// pool holds the memory (it keeps what is freed) neither reaches the driver.
+template <class T>
+hipError_t slot_realloc(T*& p, size_t& cap, size_t need, hipStream_t st) {
+    if (need <= cap && p) return hipSuccess;
+    if (p) {
+        const hipError_t e = hipFreeAsync(p, st);
+        p = nullptr;
+        cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    const hipError_t e = hipMallocAsync((void**)&p, need * sizeof(T), st);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+    }
+    cap = need;
+    return hipSuccess;
+}
+
 bool slot_grow(StreamEngine* E, StreamSlot& s, int64_t n) {
+    const auto t0 = std::chrono::steady_clock::now();
     E->held -= s.held;
     s.held = 0;
     s.cap = 0;
-    if (grow(s.d_cand, s.cand_cap, (size_t)n) != hipSuccess) return false;
-    if (grow(s.d_out, s.out_cap, (size_t)n) != hipSuccess) return false;
-    if (grow(s.sc.d_queues, s.sc.q_cap, (size_t)ssj::kQueues * (size_t)n) != hipSuccess) return false;
+    if (slot_realloc(s.d_cand, s.cand_cap, (size_t)n, s.stream) != hipSuccess) return false;
+    if (slot_realloc(s.d_out, s.out_cap, (size_t)n, s.stream) != hipSuccess) return false;
+    if (slot_realloc(s.sc.d_queues, s.sc.q_cap, (size_t)ssj::kQueues * (size_t)n, s.stream) != hipSuccess)
+        return false;
     s.cap = (int64_t)std::min({s.cand_cap, s.out_cap, s.sc.q_cap / (size_t)ssj::kQueues});
     s.held = (uint64_t)(s.cand_cap + s.out_cap) * sizeof(int2) + (uint64_t)s.sc.q_cap * sizeof(uint32_t);
     E->held += s.held;
+    E->slot_grows += 1;
+    E->slot_grow_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return true;
 }
 
@@ -786,16 +824,18 @@ bool admit(StreamEngine* E, StreamSlot& s) {
 // Called with E->mu held; slot state 1 and its event complete: copy back the
 // passing pairs (their number is now known) into the slot's pinned result
 // buffer, part after part.
-bool read_counts(StreamSlot& s) {
+bool read_counts(StreamEngine* E, StreamSlot& s) {
     int64_t total = 0;
     for (size_t k = 0; k < s.parts.size(); ++k) {
         s.parts[k].res_off = total;
         total += std::max<long long>(0, s.h_count[k]);
     }
     if (total > s.h_cap) {
-        // results are usually few; the buffer grows to the largest batch result
+        // results are usually few (the buffer starts at kSlotResults pairs);
+        // it grows to the largest batch result, the old one retired
+        const auto t0 = std::chrono::steady_clock::now();
         const int64_t n = std::max<int64_t>(total, 2 * s.h_cap);
-        if (s.h_out) (void)hipHostFree(s.h_out);
+        if (s.h_out) E->retired_host.push_back(s.h_out);
         s.h_out = nullptr;
         s.h_cap = 0;
         if (hipHostMalloc((void**)&s.h_out, (size_t)n * sizeof(int2), hipHostMallocDefault) != hipSuccess) {
@@ -803,6 +843,9 @@ bool read_counts(StreamSlot& s) {
             return false;
         }
         s.h_cap = n;
+        E->result_grows += 1;
+        E->result_grow_ms +=
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     bool any = false;
     for (size_t k = 0; k < s.parts.size(); ++k) {
@@ -850,6 +893,7 @@ void engine_loop(StreamEngine* E) {
     (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     std::unique_lock<std::mutex> lk(E->mu);
     for (;;) {
+        const auto t_pass = std::chrono::steady_clock::now();
         bool busy = false;
         for (auto& s : E->slots) {
             if (s.state == 1 || s.state == 2) {
@@ -857,7 +901,7 @@ void engine_loop(StreamEngine* E) {
                 const hipError_t q = hipEventQuery(s.ev);
                 if (q == hipSuccess) {
                     if (s.state == 1) {
-                        if (!read_counts(s)) fail_slot(E, s);
+                        if (!read_counts(E, s)) fail_slot(E, s);
                     } else {
                         s.state = 3;
                     }
@@ -887,6 +931,9 @@ void engine_loop(StreamEngine* E) {
             E->cv_done.notify_all();
             E->cv_space.notify_all();
         }
+        E->longest_pass_ms = std::max(
+            E->longest_pass_ms,
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_pass).count());
         if (E->stop && !busy && E->pending.empty()) break;
         if (busy) {
             lk.unlock();
@@ -928,6 +975,13 @@ int engine_start(ssj_ctx* ctx) {
     auto E = std::make_unique<StreamEngine>();
     E->ctx = ctx;
     E->slots.resize((size_t)ctx->n_slots);
+    // the slots' device buffers come from the device's stream-ordered pool,
+    // which keeps freed memory for later allocations instead of returning it
+    // to the driver
+    hipMemPool_t pool = nullptr;
+    HIP_OR_FAIL(ctx, hipDeviceGetDefaultMemPool(&pool, ctx->device));
+    uint64_t keep = UINT64_MAX;
+    HIP_OR_FAIL(ctx, hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
     // per slot: a stream, counters and count buffers; the candidate, output
     // and queue buffers are sized by the first batches the slot admits
     for (auto& s : E->slots) {
@@ -936,6 +990,8 @@ int engine_start(ssj_ctx* ctx) {
         if (rc != SSJ_OK) return rc;
         HIP_OR_FAIL(ctx, hipMalloc((void**)&s.d_count, sizeof(long long) * ssj::kMaxReq));
         HIP_OR_FAIL(ctx, hipHostMalloc((void**)&s.h_count, sizeof(long long) * ssj::kMaxReq, hipHostMallocDefault));
+        HIP_OR_FAIL(ctx, hipHostMalloc((void**)&s.h_out, sizeof(int2) * kSlotResults, hipHostMallocDefault));
+        s.h_cap = kSlotResults;
         HIP_OR_FAIL(ctx, hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
     }
     StreamEngine* raw = E.get();
@@ -955,10 +1011,14 @@ void engine_stop(ssj_ctx* ctx) {
     E->cv_space.notify_all();
     if (E->worker.joinable()) E->worker.join();
     for (auto& s : E->slots) {
-        if (s.stream) (void)hipStreamSynchronize(s.stream);
+        if (s.stream) {
+            if (s.d_cand) (void)hipFreeAsync(s.d_cand, s.stream);
+            if (s.d_out) (void)hipFreeAsync(s.d_out, s.stream);
+            if (s.sc.d_queues) (void)hipFreeAsync(s.sc.d_queues, s.stream);
+            s.sc.d_queues = nullptr;
+            (void)hipStreamSynchronize(s.stream);
+        }
         scratch_free(s.sc);
-        if (s.d_cand) (void)hipFree(s.d_cand);
-        if (s.d_out) (void)hipFree(s.d_out);
         if (s.d_count) (void)hipFree(s.d_count);
         if (s.h_count) (void)hipHostFree(s.h_count);
         if (s.h_out) (void)hipHostFree(s.h_out);
@@ -971,6 +1031,7 @@ void engine_stop(ssj_ctx* ctx) {
     }
     for (auto& kv : E->pool)
         for (void* p : kv.second) (void)hipHostFree(p);
+    for (void* p : E->retired_host) (void)hipHostFree(p);
     ctx->engine.reset();
 }
 
@@ -1007,10 +1068,11 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
         ctx->device_key = std::string(prop.gcnArchName) + "/" + prop.name + "/" + std::to_string(ctx->n_cu) + "cu";
         for (char& ch : ctx->device_key)
             if (ch == '"' || ch == '\\' || ch == '|' || (unsigned char)ch < 32) ch = '_';
-        for (int k = 0; k < 4 * kMappings && rc == SSJ_OK; ++k) {
+        for (int k = 0; k < 8 * kMappings && rc == SSJ_OK; ++k) {
             const bool deferring = (k & 1) != 0;
-            const void* f = ssj::kernel_verify_tiles(kInlineLanes[k / 4], kInlineHard[k / 4],
-                                                     kInlineStaged[k / 4] != 0, deferring, (k & 2) != 0);
+            const void* f = ssj::kernel_verify_tiles(kInlineLanes[k / 8], kInlineHard[k / 8],
+                                                     kInlineStaged[k / 8] != 0, deferring, (k & 2) != 0,
+                                                     (k & 4) != 0);
             // by the number of LDS queues per wavefront (deferred classes,
             // plus the spill queue)
             for (int nd = deferring ? 1 : 0; nd <= (deferring ? ssj::kQueues : 0) && rc == SSJ_OK; ++nd) {
@@ -1018,7 +1080,8 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
                 la.defer_from = nd <= ssj::kClasses ? ssj::kClasses - nd : 0;
                 la.spill_iters = nd <= ssj::kClasses ? 0xffffffffu : 1u;
                 la.defer_cap = 2 * ssj::kWave;
-                la.staged = (uint32_t)kInlineStaged[k / 4];
+                la.staged = (uint32_t)kInlineStaged[k / 8];
+                la.inline_lanes = kInlineLanes[k / 8];
                 int occ = 0;
                 if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, ssj::kBlock, ssj::tiles_lds_bytes(la))) != hipSuccess)
                     rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
@@ -1026,11 +1089,12 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
             }
         }
         if (rc != SSJ_OK) break;
-        for (int k = 0; k < 2 && rc == SSJ_OK; ++k) {
+        for (int k = 0; k < 4 && rc == SSJ_OK; ++k) {
             int occ = 0;
-            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ssj::kernel_verify_deferred(k != 0), ssj::kBlock, 0)) != hipSuccess)
+            const void* f = ssj::kernel_verify_deferred((k & 1) != 0, (k & 2) != 0);
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, ssj::kBlock, 0)) != hipSuccess)
                 rc = hip_fail(ctx, "hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
-            ctx->occ_deferred2[k] = std::min(occ, vgpr_limited_blocks(ssj::kernel_verify_deferred(k != 0)));
+            ctx->occ_deferred2[k] = std::min(occ, vgpr_limited_blocks(f));
         }
         if (rc != SSJ_OK) break;
         if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) { rc = hip_fail(ctx, "hipStreamCreate", e); break; }
@@ -1959,7 +2023,7 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
     double cur_ms = 1e30;
     ssj_plan thread_best = ctx->plan;  // best plan with one thread per pair, no hard lanes
     double thread_ms = 1e30;
-    ssj_plan staged_best = ctx->plan;  // best staged plan
+    ssj_plan staged_best = ctx->plan;  // best plan with the window ring
     double staged_ms = 1e30;
     for (int k = 0; k < kMappings && rc == SSJ_OK; ++k) {
         for (int d = ssj::kClasses; d >= 1 && rc == SSJ_OK; --d) {
@@ -1985,7 +2049,7 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
                     thread_ms = ms;
                     thread_best = p;
                 }
-                if (kInlineStaged[k] && ms < staged_ms) {
+                if (kInlineStaged[k] && kInlineLanes[k] == 1 && ms < staged_ms) {
                     staged_ms = ms;
                     staged_best = p;
                 }
@@ -1994,35 +2058,24 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
     }
     // 2) thread-per-pair merges cut off after a budget of window steps (the
     //    rest of such a merge goes to the deferred kernel), tried on the best
-    //    thread-per-pair plan with and without its deferred classes
+    //    thread-per-pair plan and the best window-ring plan, each with and
+    //    without its deferred classes
     static const int kSpillIters[6] = {4, 8, 12, 16, 24, 32};
-    for (int nodefer = 0; nodefer < 2 && rc == SSJ_OK; ++nodefer) {
-        if (nodefer && thread_best.defer_from == ssj::kClasses) break;
-        for (int it : kSpillIters) {
-            ssj_plan p = thread_best;
-            if (nodefer) p.defer_from = ssj::kClasses;
-            p.spill_iters = it;
-            p.spill_lanes = 16;
-            double ms = 0;
-            if ((rc = measure(p, &ms)) != SSJ_OK) break;
-            if (ms < cur_ms * 0.99) {
-                cur_ms = ms;
-                cur = p;
+    for (const ssj_plan& base : {thread_best, staged_best}) {
+        for (int nodefer = 0; nodefer < 2 && rc == SSJ_OK; ++nodefer) {
+            if (nodefer && base.defer_from == ssj::kClasses) break;
+            for (int it : kSpillIters) {
+                ssj_plan p = base;
+                if (nodefer) p.defer_from = ssj::kClasses;
+                p.spill_iters = it;
+                p.spill_lanes = 16;
+                double ms = 0;
+                if ((rc = measure(p, &ms)) != SSJ_OK) break;
+                if (ms < cur_ms * 0.99) {
+                    cur_ms = ms;
+                    cur = p;
+                }
             }
-        }
-    }
-    // the staged kernel's budget counts rounds of block loads per chunk
-    static const int kStagedRounds[4] = {4, 6, 8, 12};
-    for (int it : kStagedRounds) {
-        if (rc != SSJ_OK) break;
-        ssj_plan p = staged_best;
-        p.spill_iters = it;
-        p.spill_lanes = 16;
-        double ms = 0;
-        if ((rc = measure(p, &ms)) != SSJ_OK) break;
-        if (ms < cur_ms * 0.99) {
-            cur_ms = ms;
-            cur = p;
         }
     }
     if (cur.spill_iters > 0 && rc == SSJ_OK) {
@@ -2198,6 +2251,24 @@ int ssj_stream_poll(ssj_ctx* ctx, uint64_t ticket, int wait, ssj_pair* out, int6
     }
     E->table.erase(it);
     delete r;
+    return SSJ_OK;
+}
+
+int ssj_stream_stats(ssj_ctx* ctx, ssj_stream_stats_t* out, int reset) {
+    if (!ctx) return set_error(SSJ_EINVAL, "null context");
+    if (!out) return set_error(SSJ_EINVAL, "null output");
+    StreamEngine* E = ctx->engine.get();
+    if (!E) return set_error(SSJ_EINVAL, "streaming engine not running");
+    std::lock_guard<std::mutex> g(E->mu);
+    out->slot_grows = E->slot_grows;
+    out->slot_grow_ms = E->slot_grow_ms;
+    out->result_grows = E->result_grows;
+    out->result_grow_ms = E->result_grow_ms;
+    out->longest_pass_ms = E->longest_pass_ms;
+    if (reset) {
+        E->slot_grows = E->result_grows = 0;
+        E->slot_grow_ms = E->result_grow_ms = E->longest_pass_ms = 0.0;
+    }
     return SSJ_OK;
 }
 

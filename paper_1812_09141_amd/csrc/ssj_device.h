@@ -78,12 +78,14 @@ struct LaunchArgs {
                                          // in-order kernel before it is queued whole for the
                                          // deferred kernel (0xffffffff: no limit)
     int spill_lanes;                     // lanes per pair of the spill queue
-    uint32_t staged;                     // != 0: thread-per-pair merges over token blocks staged
-                                         // in LDS (k_verify_staged); spill_iters then counts
-                                         // block rounds
+    uint32_t staged;                     // != 0: thread-per-pair merges through the window
+                                         // ring in LDS, their loads two steps ahead
+                                         // (merge_ring); spill_iters counts window steps
     uint32_t grouped;                    // != 0: every request of the launch is grouped
     uint32_t* probes;                    // grouped launches that defer: the probe id of every
                                          // queued pair, by global pair index
+    const uint32_t* chunk_g;             // grouped launches: every request's chunk_g, by global
+                                         // chunk index (req[r].chunk_g = chunk_g + tile_off[r])
     uint32_t group_off[kMaxReq + 1];     // grouped launches: prefix sums of per-request groups
     uint32_t tile_off[kMaxReq + 1];      // prefix sums of per-request chunks (of kWave pairs)
     uint32_t pair_off[kMaxReq + 1];      // prefix sums of per-request pairs
@@ -120,9 +122,10 @@ hipError_t launch_finalize(const LaunchArgs& a, hipStream_t st);
 hipError_t launch_clear_words(uint32_t* d_words, size_t n, hipStream_t st);
 
 // The in-order kernel of a mapping: lanes per pair and hard lanes, or the
-// staged thread-per-pair kernel (staged, lanes 1, hard_lanes 0).
-const void* kernel_verify_tiles(int lanes, int hard_lanes, bool staged, bool deferring, bool cosine);
-const void* kernel_verify_deferred(bool cosine);
+// window-ring thread-per-pair merge (staged, lanes 1, hard_lanes 0); for a
+// flat or a grouped launch.
+const void* kernel_verify_tiles(int lanes, int hard_lanes, bool staged, bool deferring, bool cosine, bool grouped);
+const void* kernel_verify_deferred(bool cosine, bool grouped);
 const void* kernel_finalize();
 
 // LDS queues of a wavefront of the in-order kernel: one per deferred class,

@@ -52,7 +52,7 @@ EXPORTED = (
     "ssj_verify_rs", "ssj_verify_rs_device", "ssj_verify_groups", "ssj_verify_groups_device",
     "ssj_verify_groups_batch_device",
     "ssj_candidates_device", "ssj_join_device", "ssj_join", "ssj_stream_pause",
-    "ssj_verify_device_noalloc", "ssj_set_tune_cache",
+    "ssj_verify_device_noalloc", "ssj_set_tune_cache", "ssj_stream_stats",
 )
 
 _NAMES = {
@@ -106,6 +106,12 @@ class ssj_group_request(ctypes.Structure):
                 ("d_count", ctypes.c_void_p), ("sim", ctypes.c_int32)]
 
 
+class ssj_stream_stats_t(ctypes.Structure):
+    _fields_ = [("slot_grows", ctypes.c_uint64), ("slot_grow_ms", ctypes.c_double),
+                ("result_grows", ctypes.c_uint64), ("result_grow_ms", ctypes.c_double),
+                ("longest_pass_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -131,6 +137,7 @@ def load_library(path: str = LIB_PATH):
         "ssj_stream_submit": ([p, p, p, i64, i64, i64, c_int, P(u64)], c_int),
         "ssj_stream_poll": ([p, u64, c_int, p, i64, P(i64)], c_int),
         "ssj_stream_times": ([p, u64, c_int, P(u64), P(u64), P(u64)], c_int),
+        "ssj_stream_stats": ([p, P(ssj_stream_stats_t), c_int], c_int),
         "ssj_stream_pause": ([p, c_int], c_int),
         "ssj_get_plan": ([p, P(ssj_plan)], c_int),
         "ssj_set_plan": ([p, P(ssj_plan)], c_int),
@@ -522,6 +529,17 @@ def ssj_stream_times(ctx, ticket: int, wait: bool = False):
     if rc != SSJ_OK:
         _err(ctx, rc)
     return a.value, b.value, c.value
+
+
+def ssj_stream_stats(ctx, reset: bool = False) -> dict:
+    """The streaming engine's buffer regrowths and longest engine-loop pass."""
+    st = ssj_stream_stats_t()
+    rc = load_library().ssj_stream_stats(ctx, ctypes.byref(st), int(bool(reset)))
+    if rc != SSJ_OK:
+        _err(ctx, rc)
+    return {"slot_grows": st.slot_grows, "slot_grow_ms": round(st.slot_grow_ms, 4),
+            "result_grows": st.result_grows, "result_grow_ms": round(st.result_grow_ms, 4),
+            "longest_pass_ms": round(st.longest_pass_ms, 4)}
 
 
 def ssj_get_plan(ctx) -> ssj_plan:

@@ -62,12 +62,13 @@ def test_traffic_lookup_requires_matching_source():
 def test_kernel_names_follow_the_plan():
     """The kernel names the bench reports (and looks traffic up by) are the
     instances a plan launches."""
-    assert bench.kernel_name_of(bench.plan_of(S, "inline:1w5")) == "k_verify_tiles<1,0,false,false>"
+    assert bench.kernel_name_of(bench.plan_of(S, "inline:1w5")) == \
+        "k_verify_tiles<1,0,false,false,false,false>"
     assert bench.kernel_name_of(bench.plan_of(S, "inline:1bs6x16")) == \
-        "k_verify_staged<true,false> + k_verify_deferred<false>"
-    assert bench.kernel_name_of(bench.plan_of(S, "inline:1b")) == "k_verify_staged<false,false>"
+        "k_verify_tiles<1,0,true,false,true,false> + k_verify_deferred<false,false>"
+    assert bench.kernel_name_of(bench.plan_of(S, "inline:1b")) == "k_verify_tiles<1,0,false,false,true,false>"
     assert bench.kernel_name_of(bench.plan_of(S, "defer:16,3,4,8,16,32,64")) == \
-        "k_verify_tiles<16,0,true,false> + k_verify_deferred<false>"
+        "k_verify_tiles<16,0,true,false,false,false> + k_verify_deferred<false,false>"
 
 
 def test_default_workloads_lead_with_the_largest():

@@ -68,9 +68,10 @@ def plans():
                                       spill_iters=2, spill_lanes=32)))
     out.append(("spill-graph", dict(inline_lanes=1, defer_from=3, lanes=[4, 8, 16, 32, 256],
                                     spill_iters=1, spill_lanes=8, use_graph=1)))
-    # the staged kernel (token blocks in LDS): alone, cut off after one or two
-    # rounds of block loads (the rest verified again by the deferred
-    # kernel), with deferred classes, in a graph and on a one-workgroup grid
+    # the window ring (thread-per-pair merges with their window loads two
+    # steps ahead): alone, cut off after one or two window steps (the rest
+    # verified again by the deferred kernel), with deferred classes, in a
+    # graph and on a one-workgroup grid
     out.append(("staged", dict(inline_lanes=1, defer_from=5, staged=1)))
     for I, G in [(1, 16), (2, 1), (1, 256)]:
         out.append((f"staged-spill-{I}x{G}", dict(inline_lanes=1, defer_from=5, staged=1, spill_iters=I,
@@ -296,7 +297,7 @@ def test_config3_long_sets(S, ctx, golden_dir):
 
 # Long-set plans: every mapping family plus the plans the autotuner picks on
 # the long-set workload (thread per pair with a step budget and the longest
-# class on 64 lanes; the staged kernel with a round budget).
+# class on 64 lanes; the window ring with a step budget).
 LONG_PLANS = [("default", None), ("inline-16", dict(inline_lanes=16, defer_from=5)),
               ("inline-64", dict(inline_lanes=64, defer_from=5)),
               ("deferred-all-256", dict(inline_lanes=4, defer_from=0, lanes=[256] * 5)),
@@ -307,7 +308,7 @@ LONG_PLANS = [("default", None), ("inline-16", dict(inline_lanes=16, defer_from=
               ("tuned-s32x16w4", dict(inline_lanes=1, defer_from=4, lanes=[4, 4, 8, 16, 64],
                                       spill_iters=32, spill_lanes=16, wg_per_cu=4)),
               ("staged", dict(inline_lanes=1, defer_from=5, staged=1)),
-              ("staged-s6x16", dict(inline_lanes=1, defer_from=5, staged=1, spill_iters=6, spill_lanes=16)),
+              ("staged-s24x16", dict(inline_lanes=1, defer_from=5, staged=1, spill_iters=24, spill_lanes=16)),
               ("staged-s4x64-defer", dict(inline_lanes=1, defer_from=4, lanes=[4, 8, 16, 32, 64], staged=1,
                                           spill_iters=4, spill_lanes=64)),
               ("staged-s8x16-wg2", dict(inline_lanes=1, defer_from=5, staged=1, spill_iters=8,

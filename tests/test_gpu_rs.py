@@ -24,6 +24,7 @@ PLANS = [
     ("inline-8", dict(inline_lanes=8, defer_from=5)),
     ("deferred-4", dict(inline_lanes=4, defer_from=0, lanes=[4] * 5)),
     ("deferred-256", dict(inline_lanes=4, defer_from=0, lanes=[256] * 5)),
+    ("ring", dict(inline_lanes=1, defer_from=5, staged=1)),
 ]
 
 
@@ -427,8 +428,18 @@ def test_groups_every_mapping(S, ctx):
                  + list(rng.integers(0, 40, 80)) + [0] * 65 + [7] + list(rng.integers(0, 3, 300)) + [0])
         groups = _uneven_groups(rng, R.n_sets, sizes)
         n = int(groups[-1, 1])
+        # half of each probe's candidates among the S sets similar to it at
+        # t = 1/2 (found by the oracle over all cross pairs), so that many pass
+        cross = _cross(R.n_sets, Sc.n_sets)
+        close = oracle.select_rs(R.offsets, R.tokens, Sc.offsets, Sc.tokens, cross, 1, 2)
+        near = [close[close[:, 0] == r, 1] for r in range(R.n_sets)]
+        probe_of = np.repeat(groups[:, 0], sizes)
         sids = rng.integers(0, Sc.n_sets, n).astype(np.int32)
-        flat = np.stack([np.repeat(groups[:, 0], sizes), sids], axis=1).astype(np.int32)
+        for k in range(n):
+            nb = near[probe_of[k]]
+            if nb.shape[0] and rng.random() < 0.5:
+                sids[k] = nb[rng.integers(0, nb.shape[0])]
+        flat = np.stack([probe_of, sids], axis=1).astype(np.int32)
         dev = torch.device("cuda:0")
         d_g = torch.from_numpy(groups).to(dev)
         d_s = torch.from_numpy(sids).to(dev)

@@ -273,6 +273,12 @@ def test_stream_alone_equals_mix(S, data):
             assert len(outs) == 16
             for got in outs:
                 assert np.array_equal(got, alone[i]), i
+        # the engine's statistics: slots grew their buffers, and a reset zeroes them
+        st = S.ssj_stream_stats(ctx, reset=True)
+        _log(f"engine statistics: {st}")
+        assert st["slot_grows"] >= 1 and st["slot_grow_ms"] >= 0.0 and st["longest_pass_ms"] > 0.0
+        st = S.ssj_stream_stats(ctx)
+        assert st["slot_grows"] == 0 and st["result_grows"] == 0 and st["longest_pass_ms"] < 1e3
     finally:
         S.ssj_shutdown(ctx)
 

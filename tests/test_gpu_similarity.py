@@ -42,6 +42,9 @@ PLANS = [
     ("spill-1x16", dict(inline_lanes=1, defer_from=5, spill_iters=1, spill_lanes=16)),
     ("spill-2x1-defer", dict(inline_lanes=1, defer_from=3, lanes=[4, 8, 16, 32, 256],
                              spill_iters=2, spill_lanes=1)),
+    ("ring", dict(inline_lanes=1, defer_from=5, staged=1)),
+    ("ring-spill-2x16-defer", dict(inline_lanes=1, defer_from=2, lanes=[4, 8, 32, 64, 256], staged=1,
+                                   spill_iters=2, spill_lanes=16)),
 ]
 
 

@@ -1,7 +1,7 @@
 """The allocation-free entry point (ssj_verify_device_noalloc) against
 ssj_verify_device, the entry point it varies, on the same inputs: identical
 result multisets and counts (tolerance 0), two calls in a row with the second
-smaller, under plans that use its deferral queues and the staged kernel."""
+smaller, under plans that use its deferral queues and the window ring."""
 import json
 import os
 import sys
