@@ -36,6 +36,8 @@ PEAK_HBM_GBS = 8000.0
 TIMING_PERIOD = 5
 WORKLOAD_CFG = {"offline": 2, "tiny": 1, "longsets": 3, "heavytail": 4}
 DEFAULT_WORKLOADS = "heavytail,longsets,offline"
+# plans the autotuner chose on MI355X for these workloads (ssj_set_tune_cache)
+TUNE_CACHE = os.path.join(ROOT, "paper_1812_09141_amd", "tuned_plans.jsonl")
 
 
 def log(msg):
@@ -60,6 +62,9 @@ def parse(argv=None):
     ap.add_argument("--stream-batches", type=int, default=200,
                     help="streamed-serving phase: batches drawn from the 1,000,000-set "
                          "collection (0 disables it)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="tuning cache file of the autotuner (plans by device and workload; a workload "
+                         "found there is not re-tuned; '' turns the cache off)")
     ap.add_argument("--sweep", default="",
                     help="semicolon-separated plan specs to time as well (reported under 'sweep')")
     ap.add_argument("--ppjoin", type=int, default=1,
@@ -299,9 +304,11 @@ def measure(W, args, src_hash):
     if plan is None:
         big = max(range(len(W.cands)), key=lambda i: W.cands[i].shape[0])
         tn, td = W.w.thresholds[big]
-        plan, tuned_ms = S.ssj_autotune(ctx, W.h, W.d_cands[big], tn, td, apply=False)
+        S.ssj_set_tune_cache(ctx, args.tune_cache or None)
+        plan, tuned_ms, cached = S.ssj_autotune(ctx, W.h, W.d_cands[big], tn, td, apply=False, with_status=True)
+        S.ssj_set_tune_cache(ctx, None)
         tuned = {"plan": plan.as_dict(), "kernel_ms": round(tuned_ms, 5),
-                 "tuned_on": f"t={tn}/{td}, {W.cands[big].shape[0]} pairs"}
+                 "tuned_on": f"t={tn}/{td}, {W.cands[big].shape[0]} pairs", "from_cache": bool(cached)}
         log(f"{W.name}: autotuned plan: {tuned}")
     S.ssj_set_plan(ctx, plan)
     # every TIMING_PERIOD-th launch is bracketed by HIP events on the launch
