@@ -449,7 +449,7 @@ int ssj_autotune(ssj_ctx* ctx, const ssj_coll* coll, const ssj_pair* d_cand, int
  * Tuning cache of ssj_autotune: a text file of one JSON object per line,
  * {"key": ..., "kernel_ms": ..., "plan": [inline_lanes, hard_lanes,
  * defer_from, lanes[0..4], use_graph, spill_iters, spill_lanes, wg_per_cu,
- * staged]}, keyed by the device (architecture, name, compute units) and the
+ * staged]}, keyed by the device (architecture and compute units) and the
  * workload (the collection's set count, token count and longest set, the
  * candidate count and the threshold in lowest terms).  The last entry of a
  * key wins; lines that do not parse, and plans the library no longer

@@ -1065,7 +1065,9 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
         hipDeviceProp_t prop;
         if ((e = hipGetDeviceProperties(&prop, ctx->device)) != hipSuccess) { rc = hip_fail(ctx, "hipGetDeviceProperties", e); break; }
         ctx->n_cu = prop.multiProcessorCount;
-        ctx->device_key = std::string(prop.gcnArchName) + "/" + prop.name + "/" + std::to_string(ctx->n_cu) + "cu";
+        // architecture and compute units: the marketing name is not part of
+        // it (it reads empty under some profiling tools)
+        ctx->device_key = std::string(prop.gcnArchName) + "/" + std::to_string(ctx->n_cu) + "cu";
         for (char& ch : ctx->device_key)
             if (ch == '"' || ch == '\\' || ch == '|' || (unsigned char)ch < 32) ch = '_';
         for (int k = 0; k < 8 * kMappings && rc == SSJ_OK; ++k) {
