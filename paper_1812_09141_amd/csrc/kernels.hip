@@ -80,7 +80,16 @@ __device__ __forceinline__ uint32_t required_overlap(uint32_t na, uint32_t nb, c
     }
     if (R.rule == kConstant) return (uint32_t)R.num;
     const unsigned long long L = (unsigned long long)na + nb;
-    return (uint32_t)((R.num * L + R.den - 1ull) / R.den);
+    const unsigned long long x = R.num * L + R.den - 1ull;
+    if ((x >> 32) == 0ull) {
+        // ceil(num L / den) = floor(x / den) by a multiply with the request's
+        // precomputed magic number (the round-up method for unsigned division
+        // by an invariant integer of Granlund and Montgomery, PLDI 1994)
+        const uint32_t n = (uint32_t)x;
+        const uint32_t t = __umulhi(R.dmagic, n);
+        return (t + ((n - t) >> (R.dshift & 0xffu))) >> (R.dshift >> 8);
+    }
+    return (uint32_t)(x / R.den);
 }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
@@ -552,34 +561,38 @@ __device__ __forceinline__ void issue_records(const LaunchArgs& a, int2 pr, Lane
     rec.rb1 = a.heads_s[2 * is + 1];
 }
 
-// Merge state after the first tile of one side is consumed, with the six
-// record tokens of each side as the tiles (the tile merge of merge_group,
+// Merge state after the first tile of one side is consumed, with the first
+// H record tokens of each side as the tiles (the tile merge of merge_group,
 // done by one lane in straight-line code): with m the smaller of the two
 // tile ends, the merge has consumed every token <= m of both tiles, and the
 // overlap so far is the number of equal tokens in the two tiles (all of them
 // are <= m).  Record slots past the end of a set hold -1; tokens are >= 0, so
-// unsigned comparisons with m >= 0 leave those slots out of both counts.
+// unsigned comparisons with m >= 0 leave those slots out of both counts (sets
+// are not empty, so m >= 0).  A larger H gives a state at least as far along
+// the same merge.
+template <int H>
 __device__ __forceinline__ void head_tiles(uint4 a0, uint4 a1, uint4 b0, uint4 b1, uint32_t* i,
                                            uint32_t* j, uint32_t* o) {
+    static_assert(H >= 1 && H <= kHeadTokens, "head tiles come from the record tokens");
     const int32_t A[kHeadTokens] = {(int32_t)a0.z, (int32_t)a0.w, (int32_t)a1.x,
                                     (int32_t)a1.y, (int32_t)a1.z, (int32_t)a1.w};
     const int32_t B[kHeadTokens] = {(int32_t)b0.z, (int32_t)b0.w, (int32_t)b1.x,
                                     (int32_t)b1.y, (int32_t)b1.z, (int32_t)b1.w};
     int32_t am = A[0], bm = B[0];
 #pragma unroll
-    for (int x = 1; x < kHeadTokens; ++x) {
+    for (int x = 1; x < H; ++x) {
         am = max(am, A[x]);
         bm = max(bm, B[x]);
     }
     const uint32_t m = (uint32_t)min(am, bm);
     uint32_t ci = 0, cj = 0, co = 0;
 #pragma unroll
-    for (int x = 0; x < kHeadTokens; ++x) {
+    for (int x = 0; x < H; ++x) {
         ci += ((uint32_t)A[x] <= m) ? 1u : 0u;
         cj += ((uint32_t)B[x] <= m) ? 1u : 0u;
         bool hit = false;
 #pragma unroll
-        for (int y = 0; y < kHeadTokens; ++y) hit |= A[x] == B[y];
+        for (int y = 0; y < H; ++y) hit |= A[x] == B[y];
         co += (hit && A[x] >= 0) ? 1u : 0u;
     }
     *i = ci;
@@ -787,7 +800,8 @@ __device__ __forceinline__ bool merge_ring(const int32_t* __restrict__ tok_a, ui
 
 // Thread-per-pair verification of the lane's pair (chunk index kb + lane)
 // from its records: first the head tiles (head_tiles), which decide most
-// pairs; a pair still undecided continues from that merge state.  F == 0: it
+// pairs (with try4, four tokens per side first: see the caller); a pair
+// still undecided continues from that merge state.  F == 0: it
 // continues in the same lane over 16-byte windows of the token array
 // (merge_windows, or with S merge_ring, its loads two steps ahead through
 // the wavefront's window ring).  F > 0: it is appended, with
@@ -799,7 +813,8 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
                                                    uint32_t kb, int2 pr, const LaneRecords& rec,
                                                    bool deferring, uint32_t* w_defer,
                                                    unsigned long long& dc, int2* w_out, uint32_t& ocnt,
-                                                   int2* w_hpr, uint32_t* w_hst, uint32_t& hcnt, uint4* ring) {
+                                                   int2* w_hpr, uint32_t* w_hst, uint32_t& hcnt, uint4* ring,
+                                                   bool try4, bool& need6) {
     const int lane = lane_id();
     const uint32_t k = kb + (uint32_t)lane;
     const bool valid = k < R.n;
@@ -810,10 +825,26 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
     const bool defer = ok && deferring && cls >= a.defer_from;
     const bool run = ok && !defer;
     const uint32_t alpha = run ? required_overlap<C>(na, nb, R) : 0u;
-    uint32_t i, j, o;
-    head_tiles(rec.ra0, rec.ra1, rec.rb0, rec.rb1, &i, &j, &o);
-    bool pass = run && o >= alpha;
-    bool act = run && !pass && o + min(na - i, nb - j) >= alpha;
+    uint32_t i = 0, j = 0, o = 0;
+    bool pass = false, act = false;
+    auto decide = [&]() {
+        pass = run && o >= alpha;
+        act = run && !pass && o + min(na - i, nb - j) >= alpha;
+    };
+    // with try4 (wave-uniform) the head step first takes four record tokens
+    // per side, and the six only when that left some lane of the chunk
+    // undecided (need6); the six-token state supersedes the four-token one
+    bool full = true;
+    if (try4) {
+        head_tiles<4>(rec.ra0, rec.ra1, rec.rb0, rec.rb1, &i, &j, &o);
+        decide();
+        full = ballot(act) != 0ull;
+        need6 = full;
+    }
+    if (full) {
+        head_tiles<kHeadTokens>(rec.ra0, rec.ra1, rec.rb0, rec.rb1, &i, &j, &o);
+        decide();
+    }
     bool spill = false;
     if constexpr (F == 0) {
         const uint32_t budget = deferring ? a.spill_iters : 0xffffffffu;
@@ -958,6 +989,13 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     }
     const uint32_t share = first < n_chunks ? (n_chunks - 1u - first) / nw + 1u : 1u;
     uint32_t done = 0, level = 3;
+    // thread-per-pair head step: four tokens per side first while that
+    // decides whole chunks often enough.  h4est tracks 256 times the share of
+    // recent tries that still needed the six-token step; the four-token step
+    // costs about 60% of the six-token one, so trying it first pays while
+    // that share stays below about 3/8, and it is tried again on every
+    // eighth chunk
+    uint32_t h4est = 96u;
     __builtin_amdgcn_s_setprio(3);
     for (uint32_t T = first; T < n_chunks; T += nw) {
         progress_priority(done++, share, level);
@@ -972,8 +1010,14 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
             uint32_t kb2 = 0;
             chunk_origin(a, min(Tn + nw, n_chunks - 1), &r2, &kb2);
             const CandLoad c2 = issue_cand<GR>(a, a.req[r2], kb2, lane, group_of_ord(done + 1u));
+            // (only in the plain thread-per-pair instances: with the deferral
+            // code it spills scalar registers, with the window ring it costs
+            // a wavefront per SIMD)
+            const bool try4 = !D && !S && (h4est < 96u || ((done - 1u) & 7u) == 0u);
+            bool need6 = false;
             chunk_thread_pairs<F, C, S, GR>(a, R, r, kb, p0, rec0, deferring, w_defer, dc, w_out, ocnt,
-                                            w_hpr, w_hst, hcnt, w_ring);
+                                            w_hpr, w_hst, hcnt, w_ring, try4, need6);
+            if (try4) h4est = h4est - (h4est >> 3) + (need6 ? 32u : 0u);
             if constexpr (F > 0) {
                 if (hcnt > 0) {
                     finish_hard<F, C>(a, R, hcnt, w_hpr, w_hst, w_out, ocnt);

@@ -79,6 +79,20 @@ const char* kThresholdError =
 //   Dice     ceil(t_num (|r|+|s|) / (2 t_den))
 //   Cosine   least o with o^2 t_den^2 >= t_num^2 |r| |s|
 //   Overlap  ceil(t_num / t_den)
+// Magic number and shifts for dividing 32-bit dividends by d (1 <= d <
+// 2^32) with one high multiply (Granlund and Montgomery, "Division by
+// Invariant Integers using Multiplication", PLDI 1994, the unsigned round-up
+// method): l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, then
+// floor(x / d) = (t + ((x - t) >> min(l, 1))) >> max(l - 1, 0) with t the
+// high word of m x.
+void division_magic(unsigned long long d, ssj::Request& R) {
+    int l = 0;
+    while (l < 32 && (1ull << l) < d) ++l;
+    const unsigned __int128 num = ((unsigned __int128)1 << 32) * (((unsigned __int128)1 << l) - d);
+    R.dmagic = (uint32_t)(num / d + 1u);
+    R.dshift = (uint32_t)std::min(l, 1) | ((uint32_t)std::max(l - 1, 0) << 8);
+}
+
 void overlap_rule(int sim, int64_t t_num, int64_t t_den, ssj::Request& R) {
     switch (sim) {
         case SSJ_SIM_DICE:
@@ -102,6 +116,8 @@ void overlap_rule(int sim, int64_t t_num, int64_t t_den, ssj::Request& R) {
             R.den = (unsigned long long)(t_num + t_den);
             break;
     }
+    // every den here is below 2^32 (thresholds below 2^31)
+    division_magic(R.den, R);
 }
 
 template <class T>

@@ -43,6 +43,10 @@ struct Request {
     const int2* groups;
     uint32_t* chunk_g;
     uint32_t n_groups;
+    // division by den without a divide (kLinear, dividends below 2^32):
+    // q = (t + ((x - t) >> (dshift & 0xff))) >> (dshift >> 8), t = mulhi(dmagic, x)
+    uint32_t dmagic;
+    uint32_t dshift;
     uint32_t pad;
 };
 
