@@ -182,6 +182,36 @@ def test_cosine_long_sets(S, ctx):
         S.ssj_free_collection(ctx, h)
 
 
+def test_required_overlap_large_terms(S, ctx):
+    """Thresholds whose terms reach 2^31 - 1: the required overlap
+    ceil(num (|r| + |s|) / den) with divisors up to 2^32 - 2, with dividends
+    on both sides of 2^32 (the kernels divide the smaller ones by a
+    per-request magic number and the larger ones exactly), and one-token up
+    to 2,000-token sets, in every mapping."""
+    rng = np.random.default_rng(9300)
+    c = synth.near_duplicate_collection(rng, n_base=30, copies=4, max_size=2000, universe=8000,
+                                        change_frac=0.05)
+    sets = [c.tokens[c.offsets[i]:c.offsets[i + 1]].tolist() for i in range(c.n_sets)]
+    # exact copies (similarity 1, so they pass thresholds just below 1) and tiny sets
+    c = synth.collection_from_sets(sets + [sets[0], sets[7], sets[50], [5], [5, 9], [1, 2, 3], [5, 9]])
+    cand = _all_pairs(c.n_sets)
+    top = (1 << 31) - 1
+    cases = [("jaccard", 1, top), ("jaccard", top - 1, top), ("jaccard", 1 << 30, top),
+             ("jaccard", 999999937, 1000000007), ("jaccard", 65537, 131071), ("jaccard", 1, 2),
+             ("dice", 1, top), ("dice", top - 1, top), ("dice", 999999937, 1000000007)]
+    h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
+    try:
+        for sim, tn, td in cases:
+            want = oracle.sort_pairs(oracle.select(c.offsets, c.tokens, cand, tn, td, sim=sim))
+            for name, plan in PLANS:
+                _log(f"large terms {sim} t={tn}/{td} plan={name}")
+                S.ssj_set_plan(ctx, S.make_plan(**plan))
+                got = oracle.sort_pairs(S.ssj_verify_sim(ctx, h, cand, sim, tn, td))
+                assert np.array_equal(got, want), (sim, tn, td, name)
+    finally:
+        S.ssj_free_collection(ctx, h)
+
+
 def test_similarity_threshold_errors(S, ctx):
     c, cand = _case(5, 10)
     h = S.ssj_upload_collection(ctx, c.offsets, c.tokens)
