@@ -369,9 +369,11 @@ int ssj_stream_stats(ssj_ctx* ctx, ssj_stream_stats_t* out, int reset);
  *     the in-order kernel alone.
  *  3. with one thread per pair and no hard lanes, spill_iters > 0 bounds the
  *     merge of each pair in (1) to that many steps over 4-token windows: a
- *     pair still undecided then is queued and verified again from its start
- *     by the kernel of (2), with spill_lanes lanes per pair.  This keeps a
- *     few long merges from holding up their wavefronts.  0: no bound.
+ *     pair still undecided then is queued and finished by the kernel of (2),
+ *     with spill_lanes lanes per pair, from the merge state where it stopped
+ *     (from its start in the calls of the stream engine and in
+ *     ssj_verify_device_noalloc, which keep no per-pair state).  This keeps
+ *     a few long merges from holding up their wavefronts.  0: no bound.
  *  4. staged != 0 (with one thread per pair and no hard lanes) stages the
  *     4-token windows of the thread-per-pair merges of (1) in a ring of LDS
  *     slots per lane, so that each window is requested two merge steps

@@ -615,13 +615,14 @@ __device__ __forceinline__ void head_tiles(uint4 a0, uint4 a1, uint4 b0, uint4 b
 // load ends up in a temporary register plus a copy that waits for it).  The
 // scheduling barrier keeps those loads after the selects that read the
 // registers they refill, for the same reason.  The pair must be undecided at (i, j, o), so
-// i < na and j < nb.  After budget steps a merge still undecided stops with
-// *spilled set (all lanes enter together, so the step count is the same in
-// every lane and the cut is a wave-uniform branch).
+// i < na and j < nb; (i, j, o) hold the state where the merge stopped.  After
+// budget steps a merge still undecided stops with *spilled set (all lanes
+// enter together, so the step count is the same in every lane and the cut is
+// a wave-uniform branch).
 __device__ __forceinline__ bool merge_windows(const int32_t* __restrict__ tok_a, uint32_t sa,
                                               uint32_t na, const int32_t* __restrict__ tok_b,
-                                              uint32_t sb, uint32_t nb, uint32_t alpha, uint32_t i,
-                                              uint32_t j, uint32_t o, uint32_t budget, bool* spilled) {
+                                              uint32_t sb, uint32_t nb, uint32_t alpha, uint32_t& i,
+                                              uint32_t& j, uint32_t& o, uint32_t budget, bool* spilled) {
     const uint4* __restrict__ t4a = reinterpret_cast<const uint4*>(tok_a);
     const uint4* __restrict__ t4b = reinterpret_cast<const uint4*>(tok_b);
     const uint32_t qa = sa >> 2, qb = sb >> 2;              // first window of each set
@@ -735,7 +736,7 @@ constexpr uint32_t kRingSlots = 6u * (uint32_t)kWave;
 // set's last one are loaded clamped (and never read).
 __device__ __forceinline__ bool merge_ring(const int32_t* __restrict__ tok_a, uint32_t sa, uint32_t na,
                                            const int32_t* __restrict__ tok_b, uint32_t sb, uint32_t nb,
-                                           uint32_t alpha, uint32_t i, uint32_t j, uint32_t o, uint32_t budget,
+                                           uint32_t alpha, uint32_t& i, uint32_t& j, uint32_t& o, uint32_t budget,
                                            bool* spilled, uint4* ring, int lane) {
     const uint4* __restrict__ t4a = reinterpret_cast<const uint4*>(tok_a);
     const uint4* __restrict__ t4b = reinterpret_cast<const uint4*>(tok_b);
@@ -856,6 +857,9 @@ __device__ __forceinline__ void chunk_thread_pairs(const LaunchArgs& a, const Re
             if (act) pass = merge_windows(a.tok, rec.ra0.x, na, a.tok_s, rec.rb0.x, nb, alpha, i, j, o, budget, &spill);
         }
     }
+    // a spilled merge leaves its state (i, j, o) for the deferred kernel
+    if (deferring && spill && a.spill_state != nullptr)
+        a.spill_state[a.pair_off[r] + k] = make_uint4(i, j, o, 0u);
     // (after the merges: atomics count with loads, so none sits between the
     // record loads in flight and their use)
     if (ballot(valid && !ok) != 0ull && lane == 0) atomicOr(&a.ctr->err[r], 1u);
@@ -1166,54 +1170,67 @@ __device__ void drain_static(const LaunchArgs& a, int q, uint32_t cnt) {
         const uint32_t k = t0 + s * stride + (uint32_t)grp;
         return queue[min(k, cnt - 1u)];
     };
-    auto pair_of = [&](uint32_t gi, int* r) -> int2 {
+    // spilled merges resume from the state the in-order kernel left (the
+    // merge of the unconsumed suffixes against alpha - o decides the pair the
+    // same way: no consumed token matches an unconsumed one)
+    const bool resume = q == kSpillQ && a.spill_state != nullptr;
+    auto pair_of = [&](uint32_t gi, int* r, uint4* st) -> int2 {
         *r = request_of_pair(gi, a);
+        *st = resume ? a.spill_state[gi] : make_uint4(0u, 0u, 0u, 0u);
         return queued_pair<GR>(a, gi, *r);
     };
+    // a set's descriptor without its first c tokens
+    auto suffix = [](uint2 d, uint32_t c) { return make_uint2(d.x + c, d.y - c); };
     uint32_t e3;
     int2 p0, p1, p2;
     int r0, r1, r2;
+    uint4 st0, st1, st2;
     uint2 dr0, ds0, dr1, ds1;
     int32_t wa0, wb0;
     {
         const uint32_t e0 = entry_at(0), e1 = entry_at(1), e2 = entry_at(2);
         e3 = entry_at(3);
-        p0 = pair_of(e0, &r0);
-        p1 = pair_of(e1, &r1);
-        p2 = pair_of(e2, &r2);
+        p0 = pair_of(e0, &r0, &st0);
+        p1 = pair_of(e1, &r1, &st1);
+        p2 = pair_of(e2, &r2, &st2);
         dr0 = set_desc(a, p0.x);
         ds0 = set_desc_s(a, p0.y);
         dr1 = set_desc(a, p1.x);
         ds1 = set_desc_s(a, p1.y);
-        wa0 = first_tile_token(a.tok, dr0, g);
-        wb0 = first_tile_token(a.tok_s, ds0, g);
+        wa0 = first_tile_token(a.tok, suffix(dr0, st0.x), g);
+        wb0 = first_tile_token(a.tok_s, suffix(ds0, st0.y), g);
     }
     for (uint32_t t = t0, s = 0; t < cnt; t += stride, ++s) {
         const uint32_t e4 = entry_at(s + 4);
         int r3;
-        const int2 p3 = pair_of(e3, &r3);
+        uint4 st3;
+        const int2 p3 = pair_of(e3, &r3, &st3);
         const uint2 dr2 = set_desc(a, p2.x);
         const uint2 ds2 = set_desc_s(a, p2.y);
-        const int32_t wa1 = first_tile_token(a.tok, dr1, g);
-        const int32_t wb1 = first_tile_token(a.tok_s, ds1, g);
+        const int32_t wa1 = first_tile_token(a.tok, suffix(dr1, st1.x), g);
+        const int32_t wb1 = first_tile_token(a.tok_s, suffix(ds1, st1.y), g);
         if (t + (uint32_t)grp < cnt) {
             const Request& R = a.req[r0];
-            const uint32_t alpha = required_overlap<C>(dr0.y, ds0.y, R);
+            const uint32_t alpha = required_overlap<C>(dr0.y, ds0.y, R) - st0.z;
+            const uint2 ar = suffix(dr0, st0.x), as = suffix(ds0, st0.y);
             bool pass;
             if constexpr (G == 1)
-                pass = merge_thread(a.tok + dr0.x, dr0.y, a.tok_s + ds0.x, ds0.y, alpha);
+                pass = merge_thread(a.tok + ar.x, ar.y, a.tok_s + as.x, as.y, alpha);
             else
-                pass = merge_group_first<G>(a.tok + dr0.x, dr0.y, a.tok_s + ds0.x, ds0.y, alpha, g,
-                                            gbase, wa0, wb0);
+                pass = merge_group_first<G>(a.tok + ar.x, ar.y, a.tok_s + as.x, as.y, alpha, g, gbase, wa0,
+                                            wb0);
             if (pass && g == 0) append_one(p0, R, &a.ctr->out_count[r0]);
         }
         e3 = e4;
         p0 = p1;
         r0 = r1;
+        st0 = st1;
         p1 = p2;
         r1 = r2;
+        st1 = st2;
         p2 = p3;
         r2 = r3;
+        st2 = st3;
         dr0 = dr1;
         ds0 = ds1;
         dr1 = dr2;
@@ -1255,8 +1272,11 @@ __global__ __launch_bounds__(kBlock) void k_verify_deferred(LaunchArgs a) {
             const int2 pr = queued_pair<GR>(a, gi, r);
             const uint2 dr = set_desc(a, pr.x);
             const uint2 ds = set_desc_s(a, pr.y);
-            const bool pass = merge_block(a.tok + dr.x, dr.y, a.tok_s + ds.x, ds.y,
-                                          required_overlap<C>(dr.y, ds.y, R), sb, red);
+            // a spilled merge resumes from its state (as in drain_static)
+            const uint4 st = q == kSpillQ && a.spill_state != nullptr ? a.spill_state[gi]
+                                                                       : make_uint4(0u, 0u, 0u, 0u);
+            const bool pass = merge_block(a.tok + dr.x + st.x, dr.y - st.x, a.tok_s + ds.x + st.y, ds.y - st.y,
+                                          required_overlap<C>(dr.y, ds.y, R) - st.z, sb, red);
             if (threadIdx.x == 0 && pass) append_one(pr, R, &a.ctr->out_count[r]);
         }
     }

@@ -152,6 +152,13 @@ struct Scratch {
     size_t chunk_cap = 0;
     uint32_t* d_probes = nullptr;   // grouped launches that defer: probe id per queued pair
     size_t probes_cap = 0;
+    // launches whose merges spill: the merge state of every spilled pair, so
+    // that the deferred kernel resumes it (only where resume is set: the
+    // context's own scratch; stream slots and the allocation-free entry point
+    // restart spilled merges instead of holding 16 bytes per pair)
+    bool resume = false;
+    uint4* d_spill = nullptr;
+    size_t spill_cap = 0;
 };
 
 struct GraphKey {
@@ -321,6 +328,7 @@ void scratch_free(Scratch& s) {
     if (s.d_queues) (void)hipFree(s.d_queues);
     if (s.d_chunk_g) (void)hipFree(s.d_chunk_g);
     if (s.d_probes) (void)hipFree(s.d_probes);
+    if (s.d_spill) (void)hipFree(s.d_spill);
     s = Scratch{};
 }
 
@@ -532,6 +540,10 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
     const bool two = plan_two_kernels(plan);
     if (two) {
         HIP_OR_FAIL(ctx, grow(sc.d_queues, sc.q_cap, (size_t)ssj::kQueues * std::max<uint64_t>(pairs, 1)));
+    }
+    if (two && sc.resume && ssj::spilling(a)) {
+        HIP_OR_FAIL(ctx, grow(sc.d_spill, sc.spill_cap, (size_t)std::max<uint64_t>(pairs, 1)));
+        a.spill_state = sc.d_spill;
     }
     if (a.grouped) {
         HIP_OR_FAIL(ctx, grow(sc.d_chunk_g, sc.chunk_cap, (size_t)std::max<uint64_t>(tiles, 1)));
@@ -1117,6 +1129,7 @@ int ssj_init(const ssj_opts* opts, ssj_ctx** out) {
         if (rc != SSJ_OK) break;
         if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) { rc = hip_fail(ctx, "hipStreamCreate", e); break; }
         if ((rc = scratch_init(ctx, ctx->def)) != SSJ_OK) break;
+        ctx->def.resume = true;
         if ((rc = noalloc_setup(ctx)) != SSJ_OK) break;
         if ((e = hipMalloc((void**)&ctx->d_count, sizeof(long long))) != hipSuccess) { rc = hip_fail(ctx, "hipMalloc", e); break; }
         if ((e = hipHostMalloc((void**)&ctx->h_count, sizeof(long long), hipHostMallocDefault)) != hipSuccess) { rc = hip_fail(ctx, "hipHostMalloc", e); break; }

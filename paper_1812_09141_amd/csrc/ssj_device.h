@@ -79,8 +79,8 @@ struct LaunchArgs {
     uint32_t defer_cap;                  // LDS queue entries per deferred class and wavefront (>= 2 chunks)
     uint32_t cosine;                     // != 0: some request uses the Cosine rule
     uint32_t spill_iters;                // window steps a thread-per-pair merge may take in the
-                                         // in-order kernel before it is queued whole for the
-                                         // deferred kernel (0xffffffff: no limit)
+                                         // in-order kernel before it is queued for the deferred
+                                         // kernel (0xffffffff: no limit)
     int spill_lanes;                     // lanes per pair of the spill queue
     uint32_t staged;                     // != 0: thread-per-pair merges through the window
                                          // ring in LDS, their loads two steps ahead
@@ -88,6 +88,9 @@ struct LaunchArgs {
     uint32_t grouped;                    // != 0: every request of the launch is grouped
     uint32_t* probes;                    // grouped launches that defer: the probe id of every
                                          // queued pair, by global pair index
+    uint4* spill_state;                  // launches whose merges spill: {i, j, o, 0} of every
+                                         // spilled merge by global pair index, from which the
+                                         // deferred kernel resumes it (nullptr: it restarts)
     const uint32_t* chunk_g;             // grouped launches: every request's chunk_g, by global
                                          // chunk index (req[r].chunk_g = chunk_g + tile_off[r])
     uint32_t group_off[kMaxReq + 1];     // grouped launches: prefix sums of per-request groups
