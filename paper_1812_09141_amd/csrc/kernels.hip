@@ -600,6 +600,39 @@ __device__ __forceinline__ void head_tiles(uint4 a0, uint4 a1, uint4 b0, uint4 b
     *o = co;
 }
 
+// One window step on the current 4-token windows a (set positions ba ..
+// ba + 3 of A) and b (bb .. bb + 3 of B), with i and j tokens consumed
+// (ba <= i < min(ba + 4, na), the same for j): the window with the lower
+// last token is consumed whole, the other up to that token (both on equal
+// ones), and o counts the matches among the unconsumed tokens.  Consumed
+// tokens are exactly those up to the last consumption point, and slots past
+// a set's end hold -1 (the smallest signed, the largest unsigned value), so:
+// a window's largest token is the largest of its four slots; an unconsumed
+// real token of A is one at a position >= i that is <= bmax as unsigned
+// (larger ones cannot match and are not consumed); and such a token can only
+// equal an unconsumed token of B, so its matches need no test on b's side.
+__device__ __forceinline__ void step_windows(const int32_t (&a)[4], const int32_t (&b)[4], uint32_t ba,
+                                             uint32_t bb, uint32_t na, uint32_t nb, uint32_t& i, uint32_t& j,
+                                             uint32_t& o) {
+    const int32_t amax = max(max(a[0], a[1]), max(a[2], a[3]));
+    const int32_t bmax = max(max(b[0], b[1]), max(b[2], b[3]));
+    uint32_t hits = 0, na_le = 0, nb_le = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool va = ba + k >= i && (uint32_t)a[k] <= (uint32_t)bmax;
+        const bool vb = bb + k >= j && (uint32_t)b[k] <= (uint32_t)amax;
+        bool hit = false;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) hit |= a[k] == b[t];
+        hits += (va && hit) ? 1u : 0u;
+        na_le += va ? 1u : 0u;
+        nb_le += vb ? 1u : 0u;
+    }
+    i = bmax < amax ? i + na_le : min(ba + 4u, na);
+    j = amax < bmax ? j + nb_le : min(bb + 4u, nb);
+    o += hits;
+}
+
 // One lane's merge continued from state (i, j, o) over 16-byte windows of
 // the two token lists (A from slot sa of tok_a, B from slot sb of tok_b;
 // every set starts on a 16-byte boundary of its token array): window w of a
@@ -643,28 +676,7 @@ __device__ __forceinline__ bool merge_windows(const int32_t* __restrict__ tok_a,
     unpack(t4b[qb + min(wb + 1u, lb)], bn);
     for (uint32_t step = 1;; ++step) {
         const uint32_t ba = wa << 2, bb = wb << 2;
-        const uint32_t ea = min(na - ba, 4u), eb = min(nb - bb, 4u);  // tokens in the windows
-        int32_t amax = a[0], bmax = b[0];
-#pragma unroll
-        for (int k = 1; k < 4; ++k) {
-            amax = ((uint32_t)k < ea) ? a[k] : amax;
-            bmax = ((uint32_t)k < eb) ? b[k] : bmax;
-        }
-        uint32_t hits = 0, na_le = 0, nb_le = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const bool va = ba + k >= i && (uint32_t)k < ea;
-            const bool vb = bb + k >= j && (uint32_t)k < eb;
-            bool hit = false;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) hit |= (bb + t >= j && (uint32_t)t < eb) && a[k] == b[t];
-            hits += (va && hit) ? 1u : 0u;
-            na_le += (va && a[k] <= bmax) ? 1u : 0u;
-            nb_le += (vb && b[k] <= amax) ? 1u : 0u;
-        }
-        i = bmax < amax ? i + na_le : ba + ea;
-        j = amax < bmax ? j + nb_le : bb + eb;
-        o += hits;
+        step_windows(a, b, ba, bb, na, nb, i, j, o);
         if (o >= alpha) return true;
         if (o + min(na - i, nb - j) < alpha) return false;
         if (step >= budget) {
@@ -694,29 +706,7 @@ __device__ __forceinline__ void window_step(uint4 va, uint4 vb, uint32_t na, uin
                                             uint32_t& j, uint32_t& o) {
     const int32_t a[4] = {(int32_t)va.x, (int32_t)va.y, (int32_t)va.z, (int32_t)va.w};
     const int32_t b[4] = {(int32_t)vb.x, (int32_t)vb.y, (int32_t)vb.z, (int32_t)vb.w};
-    const uint32_t ba = i & ~3u, bb = j & ~3u;
-    const uint32_t ea = min(na - ba, 4u), eb = min(nb - bb, 4u);
-    int32_t amax = a[0], bmax = b[0];
-#pragma unroll
-    for (int k = 1; k < 4; ++k) {
-        amax = ((uint32_t)k < ea) ? a[k] : amax;
-        bmax = ((uint32_t)k < eb) ? b[k] : bmax;
-    }
-    uint32_t hits = 0, na_le = 0, nb_le = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const bool va_k = ba + k >= i && (uint32_t)k < ea;
-        const bool vb_k = bb + k >= j && (uint32_t)k < eb;
-        bool hit = false;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) hit |= (bb + t >= j && (uint32_t)t < eb) && a[k] == b[t];
-        hits += (va_k && hit) ? 1u : 0u;
-        na_le += (va_k && a[k] <= bmax) ? 1u : 0u;
-        nb_le += (vb_k && b[k] <= amax) ? 1u : 0u;
-    }
-    i = bmax < amax ? i + na_le : ba + ea;
-    j = amax < bmax ? j + nb_le : bb + eb;
-    o += hits;
+    step_windows(a, b, i & ~3u, j & ~3u, na, nb, i, j, o);
 }
 
 // Entries of the wavefront's window ring (merge_ring): three 16-byte slots per
