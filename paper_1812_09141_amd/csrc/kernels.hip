@@ -393,9 +393,13 @@ __device__ void wave_flush_deferred(const LaunchArgs& a, int q, uint32_t c, cons
 // the oldest wavefronts among those of equal priority, so with equal shares
 // of chunks the youngest ones would otherwise finish long after the rest and
 // leave the end of the launch to a few wavefronts; a wavefront that is ahead
-// now yields to one that is behind.  done, total and level are wave-uniform.
-__device__ __forceinline__ void progress_priority(uint32_t done, uint32_t total, uint32_t& level) {
-    const uint32_t l = 3u - min(3u, (4u * done) / total);
+// now yields to one that is behind.  quarter[k - 1] = ceil(k share / 4) for
+// k = 1, 2, 3 (share: the wavefront's chunk count), so that done chunks are
+// past the k-th quarter when done >= quarter[k - 1], without a division per
+// chunk.  done, quarter and level are wave-uniform.
+__device__ __forceinline__ void progress_priority(uint32_t done, const uint32_t (&quarter)[3], uint32_t& level) {
+    const uint32_t l = 3u - (done >= quarter[0] ? 1u : 0u) - (done >= quarter[1] ? 1u : 0u) -
+                       (done >= quarter[2] ? 1u : 0u);
     if (l == level) return;
     level = l;
     switch (l) {
@@ -409,6 +413,11 @@ __device__ __forceinline__ void progress_priority(uint32_t done, uint32_t total,
 // Request and first pair index of chunk T (prefix sums in tile_off, in
 // chunks of kWave pairs).
 __device__ __forceinline__ void chunk_origin(const LaunchArgs& a, uint32_t T, int* r, uint32_t* kb) {
+    if (a.n_req == 1) {  // the common launch of one request: no search
+        *r = 0;
+        *kb = T * (uint32_t)kWave;
+        return;
+    }
     int q = 0;
     while (q + 1 < a.n_req && a.tile_off[q + 1] <= T) ++q;
     *r = q;
@@ -982,6 +991,9 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
         }
     }
     const uint32_t share = first < n_chunks ? (n_chunks - 1u - first) / nw + 1u : 1u;
+    const uint32_t quarter[3] = {(uint32_t)__builtin_amdgcn_readfirstlane((int)((share + 3u) / 4u)),
+                                 (uint32_t)__builtin_amdgcn_readfirstlane((int)((2u * share + 3u) / 4u)),
+                                 (uint32_t)__builtin_amdgcn_readfirstlane((int)((3u * share + 3u) / 4u))};
     uint32_t done = 0, level = 3;
     // thread-per-pair head step: four tokens per side first while that
     // decides whole chunks often enough.  h4est tracks 256 times the share of
@@ -992,7 +1004,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(LaunchArgs a) {
     uint32_t h4est = 96u;
     __builtin_amdgcn_s_setprio(3);
     for (uint32_t T = first; T < n_chunks; T += nw) {
-        progress_priority(done++, share, level);
+        progress_priority(done++, quarter, level);
         const int r = r_cur;
         const uint32_t kb = kb_cur;
         const uint32_t Tn = T + nw;
