@@ -379,6 +379,8 @@ int ssj_stream_stats(ssj_ctx* ctx, ssj_stream_stats_t* out, int reset);
  *     slots per lane, so that each window is requested two merge steps
  *     before it is needed instead of one (for long sets, whose merges wait
  *     on their window loads); spill_iters counts window steps as in (3).
+ *     Grouped launches (ssj_verify_groups*) ignore it: their merges take the
+ *     plain windows of (1), which run faster there.
  * use_graph != 0 replays the launch through a captured hipGraph whose kernel
  * parameters are updated per call.  wg_per_cu sizes the in-order kernel's
  * grid (its wavefronts split the chunks evenly; more workgroups than fit at

@@ -507,8 +507,10 @@ int enqueue_launch(ssj_ctx* ctx, const ssj_coll* coll, Scratch& sc, const Req* r
         a.bounds[q] = bounds[q];
         a.lanes[q] = plan.lanes[q];
     }
-    // a launch is grouped when its requests are (callers never mix the two)
+    // a launch is grouped when its requests are (callers never mix the two);
+    // grouped launches have no window-ring instance
     a.grouped = n_req > 0 && reqs[0].grouped ? 1u : 0u;
+    if (a.grouped) a.staged = 0u;
     uint64_t tiles = 0, pairs = 0, groups = 0;
     for (int r = 0; r < n_req; ++r) {
         const Req& q = reqs[r];

@@ -130,7 +130,8 @@ hipError_t launch_clear_words(uint32_t* d_words, size_t n, hipStream_t st);
 
 // The in-order kernel of a mapping: lanes per pair and hard lanes, or the
 // window-ring thread-per-pair merge (staged, lanes 1, hard_lanes 0); for a
-// flat or a grouped launch.
+// flat or a grouped launch (grouped launches have no window-ring instance:
+// staged selects the plain one).
 const void* kernel_verify_tiles(int lanes, int hard_lanes, bool staged, bool deferring, bool cosine, bool grouped);
 const void* kernel_verify_deferred(bool cosine, bool grouped);
 const void* kernel_finalize();
